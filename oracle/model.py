@@ -1,0 +1,191 @@
+"""The equivariant interaction model, energy, forces and loss gradients (oracle).
+
+§4 of the paper: its backend speeds up the Clebsch-Gordan tensor product
+that MACE and NequIP use inside message passing. The paper gives no model
+equations; the model below is the reading, each step anchored to the
+Appendix F hyperparameter tables:
+
+  geometry     d_e = r_j - r_i + n.cell for edge e = (i <- j, n); r_e = |d_e|
+  harmonics    Y_e = real_sh(d_e), l <= l_max                       (sh.py)
+  basis        B_e = radial_basis(r_e)                               (basis.py)
+  embedding    h0_i = W_emb[z_i] (scalars only)
+  layer t      R_e = W3^T silu(W2^T silu(W1^T B_e)), no biases, one weight
+                   per (path, channel)   (NequIP table: 2 hidden layers of 64, swish)
+               A_i[p,k,m3] = 1/nu sum_{e in in(i)} R_e[p,k]
+                                sum_{m1,m2} C^p[m1,m2,m3] h_j[k,l1,m1] Y_e[l2,m2]
+               h~_i[l3] = sum_{p: l3(p)=l3} A_i[p] W_{l3}[p] + h_i[l3] S_{l3}
+               gate (MACE table: gate_nodes): h[0] = silu(h~[0]),
+                    h[l>0] = h~[l] * sigmoid(h~[0])
+  readout      E_i = w2^T silu(W_r^T h_i[0]) + E0[z_i]   (MACE table:
+                   readout irreps 16x0e -> 0e; §5.3 readout with one head)
+  energy       E_s = sum_{i in s} E_i
+  forces       F = -dE/dr (§5.2: the Hessian is minus the position
+                   derivative of the forces, i.e. forces are -dE/dr)
+
+nu is a fixed constant of the model (the nominal neighbour count). Every
+layer outputs all orders l <= l_max. Computation is FP64 throughout.
+
+The neighbour sum may be evaluated over edge chunks, each recomputed in the
+backward pass, which only bounds memory; the arithmetic per edge is the
+definition above.
+"""
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+import torch
+from torch.utils.checkpoint import checkpoint
+
+from . import basis, cg
+from .sh import real_sh, sl
+
+
+def silu(x):
+    return x * torch.sigmoid(x)
+
+
+class Model:
+    def __init__(self, cfg, weights: Dict[str, np.ndarray]):
+        self.cfg = cfg
+        self.w = {k: torch.tensor(np.asarray(v), dtype=torch.float64) for k, v in weights.items()}
+        self.layer_paths: List[List[Tuple[int, int, int]]] = []
+        for t in range(1, cfg.layers + 1):
+            l_in = [0] if t == 1 else list(range(cfg.lmax + 1))
+            self.layer_paths.append(cg.paths(l_in, cfg.lmax))
+        self.cg = {}
+        for ps in self.layer_paths:
+            for p in ps:
+                if p not in self.cg:
+                    self.cg[p] = torch.tensor(cg.real_cg(*p))
+
+    def parameters(self) -> Dict[str, torch.Tensor]:
+        return self.w
+
+    # -- one layer's neighbour sum over a set of edges --------------------
+    def _messages(self, t: int, h_flat: torch.Tensor, B: torch.Tensor, Y: torch.Tensor,
+                  src: torch.Tensor, dst: torch.Tensor, n_atoms: int) -> torch.Tensor:
+        """Returns A as [N, C, sum_p (2 l3 + 1)] (paths concatenated)."""
+        cfg, w = self.cfg, self.w
+        C = cfg.channels
+        paths = self.layer_paths[t - 1]
+        R = silu(silu(B @ w[f"rad1_{t}"]) @ w[f"rad2_{t}"]) @ w[f"rad3_{t}"]
+        R = R.view(-1, len(paths), C)
+        hj = h_flat[src]                                   # [E, C, (lmax+1)^2]
+        out = []
+        for pi, (l1, l2, l3) in enumerate(paths):
+            Tp = torch.einsum("abc,eka,eb->ekc", self.cg[(l1, l2, l3)], hj[:, :, sl(l1)], Y[:, sl(l2)])
+            msg = R[:, pi, :, None] * Tp
+            out.append(torch.zeros(n_atoms, C, 2 * l3 + 1, dtype=msg.dtype).index_add(0, dst, msg))
+        return torch.cat(out, dim=2) / cfg.avg_neighbors
+
+    def node_energies(self, pos: torch.Tensor, species: torch.Tensor, dst: torch.Tensor,
+                      src: torch.Tensor, shift_vec: torch.Tensor, edge_chunk: Optional[int] = None,
+                      features: Optional[list] = None) -> torch.Tensor:
+        """E_i for every atom. pos [N,3] FP64 (may require grad), shift_vec [E,3]
+        the Cartesian image displacement of each edge."""
+        cfg, w = self.cfg, self.w
+        N, C, L = pos.shape[0], cfg.channels, cfg.lmax
+        nc = (L + 1) ** 2
+        d = pos[src] - pos[dst] + shift_vec
+        r = torch.linalg.norm(d, dim=-1)
+        Y = real_sh(d, L)
+        B = basis.radial_basis(r, cfg.cutoff, cfg.n_basis, cfg.envelope_p)
+        h = torch.cat([w["emb"][species][:, :, None], torch.zeros(N, C, nc - 1, dtype=torch.float64)], 2)
+        for t in range(1, cfg.layers + 1):
+            paths = self.layer_paths[t - 1]
+            if edge_chunk is None or edge_chunk >= len(src):
+                A = self._messages(t, h, B, Y, src, dst, N)
+            else:
+                A = None
+                for a in range(0, len(src), edge_chunk):
+                    b = min(a + edge_chunk, len(src))
+                    part = checkpoint(self._messages, t, h, B[a:b], Y[a:b], src[a:b], dst[a:b], N,
+                                      use_reentrant=False)
+                    A = part if A is None else A + part
+            # split A per path
+            Ap, off = [], 0
+            for (_, _, l3) in paths:
+                Ap.append(A[:, :, off:off + 2 * l3 + 1])
+                off += 2 * l3 + 1
+            l_in = [0] if t == 1 else list(range(L + 1))
+            ht = []
+            for l3 in range(L + 1):
+                acc = torch.zeros(N, C, 2 * l3 + 1, dtype=torch.float64)
+                Wm = w[f"mix_{t}_{l3}"]
+                q = 0
+                for pi, (_, _, pl3) in enumerate(paths):
+                    if pl3 != l3:
+                        continue
+                    acc = acc + torch.einsum("nkm,kq->nqm", Ap[pi], Wm[q * C:(q + 1) * C])
+                    q += 1
+                if l3 in l_in:
+                    acc = acc + torch.einsum("nkm,kq->nqm", h[:, :, sl(l3)], w[f"self_{t}_{l3}"])
+                ht.append(acc)
+            g = torch.sigmoid(ht[0])                       # [N, C, 1]
+            h = torch.cat([silu(ht[0])] + [ht[l] * g for l in range(1, L + 1)], dim=2)
+            if features is not None:
+                features.append(h)
+        e = silu(h[:, :, 0] @ w["read1"]) @ w["read2"]
+        return e[:, 0] + w["e0"][species]
+
+
+def structure_energies(e_atom: torch.Tensor, offsets: np.ndarray) -> torch.Tensor:
+    """E_s = sum over the atoms of structure s."""
+    owner = torch.from_numpy(np.repeat(np.arange(len(offsets) - 1), np.diff(offsets)))
+    return torch.zeros(len(offsets) - 1, dtype=e_atom.dtype).index_add(0, owner, e_atom)
+
+
+def _edges(batch, cutoff):
+    from .neighbours import neighbour_list, shift_vectors
+    dst, src, sh = neighbour_list(batch.pos, batch.cell, batch.pbc, batch.offsets, cutoff)
+    return (torch.from_numpy(dst), torch.from_numpy(src),
+            torch.from_numpy(shift_vectors(sh, dst, batch.cell, batch.offsets)))
+
+
+def energy_forces(model: Model, batch, edge_chunk: Optional[int] = None, edges=None,
+                  features: Optional[list] = None):
+    """(E_s [S], F [N,3], E_i [N]) in FP64. F = -dE/dr by autograd."""
+    dst, src, shv = edges if edges is not None else _edges(batch, model.cfg.cutoff)
+    pos = torch.tensor(batch.pos, dtype=torch.float64, requires_grad=True)
+    species = torch.from_numpy(np.asarray(batch.species, dtype=np.int64))
+    e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk, features)
+    E = structure_energies(e_atom, batch.offsets)
+    (g,) = torch.autograd.grad(E.sum(), pos)
+    return E.detach().numpy(), (-g).numpy(), e_atom.detach().numpy()
+
+
+def energy(model: Model, batch, edges=None, edge_chunk: Optional[int] = None) -> np.ndarray:
+    dst, src, shv = edges if edges is not None else _edges(batch, model.cfg.cutoff)
+    pos = torch.tensor(batch.pos, dtype=torch.float64)
+    species = torch.from_numpy(np.asarray(batch.species, dtype=np.int64))
+    with torch.no_grad():
+        e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk)
+    return structure_energies(e_atom, batch.offsets).numpy()
+
+
+def loss_and_grads(model: Model, batch, e_ref: np.ndarray, f_ref: np.ndarray,
+                   w_energy: float = 1.0, w_forces: float = 1.0, edges=None,
+                   edge_chunk: Optional[int] = None):
+    """loss = w_E mean_s (E_s - E_ref)^2 + w_F sum (F - F_ref)^2 / (3 N),
+    and its gradient with respect to every weight tensor (second order
+    through the forces)."""
+    dst, src, shv = edges if edges is not None else _edges(batch, model.cfg.cutoff)
+    params = model.parameters()
+    for v in params.values():
+        v.requires_grad_(True)
+    try:
+        pos = torch.tensor(batch.pos, dtype=torch.float64, requires_grad=True)
+        species = torch.from_numpy(np.asarray(batch.species, dtype=np.int64))
+        e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk)
+        E = structure_energies(e_atom, batch.offsets)
+        (g,) = torch.autograd.grad(E.sum(), pos, create_graph=True)
+        F = -g
+        loss = (w_energy * torch.mean((E - torch.from_numpy(e_ref)) ** 2)
+                + w_forces * torch.sum((F - torch.from_numpy(f_ref)) ** 2) / F.numel())
+        names = list(params.keys())
+        grads = torch.autograd.grad(loss, [params[k] for k in names], allow_unused=True)
+        out = {k: (torch.zeros_like(params[k]) if gk is None else gk).detach().numpy()
+               for k, gk in zip(names, grads)}
+        return float(loss.detach()), out
+    finally:
+        for v in params.values():
+            v.requires_grad_(False)

@@ -1,0 +1,64 @@
+"""Pins of the oracle's velocity-Verlet integrator."""
+import math
+
+import numpy as np
+
+import synth
+from oracle import md
+from oracle import model as om
+
+
+def test_harmonic_oscillator_matches_exact_solution():
+    k, mass, x0 = 2.0, 12.0, 0.3
+    omega = math.sqrt(k * md.ACCEL_UNIT / mass)
+
+    def force(x):
+        return np.zeros(1), -k * x
+    dt, n = 0.5, 400
+    x, v, _ = md.velocity_verlet(force, np.array([[x0, 0, 0]]), np.zeros((1, 3)), np.array([mass]), dt, n)
+    # Velocity Verlet on a harmonic oscillator is a rotation in phase space
+    # with the modified frequency 2/dt asin(omega dt / 2).
+    om_mod = 2.0 / dt * math.asin(omega * dt / 2.0)
+    assert abs(x[0, 0] - x0 * math.cos(om_mod * n * dt)) < 1e-12
+    assert abs(x[0, 0] - x0 * math.cos(omega * n * dt)) < 1e-3 * x0
+
+
+def _model_system():
+    cfg = synth.ModelConfig(lmax=2, channels=8, layers=2, n_species=4, cutoff=5.0, avg_neighbors=10.0)
+    m = om.Model(cfg, synth.model_weights(cfg, 21))
+    b = synth.jittered_lattice(16, 0.1, 0.3, 4, np.random.default_rng(22))
+    v = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(23))
+
+    def force(x):
+        E, F, _ = om.energy_forces(m, synth.Batch(x, b.species, b.cell, b.pbc, b.offsets))
+        return E, F
+    return b, v, force, synth.SPECIES_MASS[b.species]
+
+
+def test_reversible_and_momentum_conserving():
+    b, v, force, mass = _model_system()
+    x1, v1, _ = md.velocity_verlet(force, b.pos, v, mass, 0.5, 10)
+    p0 = (mass[:, None] * v).sum(0)
+    p1 = (mass[:, None] * v1).sum(0)
+    np.testing.assert_allclose(p1, p0, atol=1e-13)
+    x2, v2, _ = md.velocity_verlet(force, x1, -v1, mass, 0.5, 10)
+    np.testing.assert_allclose(x2, b.pos, atol=1e-11)
+    np.testing.assert_allclose(-v2, v, atol=1e-12)
+
+
+def test_energy_conservation():
+    b, v, force, mass = _model_system()
+    E0, _ = force(b.pos)
+    tot0 = E0[0] + md.kinetic_energy(v, mass)
+    x, v1, Es = md.velocity_verlet(force, b.pos, v, mass, 0.25, 40)
+    tot1 = Es[-1][0] + md.kinetic_energy(v1, mass)
+    assert abs(tot1 - tot0) < 1e-3 * max(1e-3, md.kinetic_energy(v, mass))
+
+
+def test_maxwell_boltzmann_temperature():
+    b = synth.jittered_lattice(2000, 0.1, 0.3, 5, np.random.default_rng(1))
+    v = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(2))
+    ke = md.kinetic_energy(v, synth.SPECIES_MASS[b.species])
+    T = 2 * ke / (3 * b.n_atoms * synth.KB_EV)
+    assert abs(T - 300.0) < 15.0
+    np.testing.assert_allclose((synth.SPECIES_MASS[b.species][:, None] * v).sum(0), 0, atol=1e-12)
