@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the equivariant interaction on one MI355X.
+
+A step is one velocity-Verlet MD step of the whole hot path on a 3,000-atom
+periodic box (0.1 atoms/A^3, jittered lattice, 4 species, r_c 5 A, l_max 3,
+128 channels, 2 layers, FP32): half kick, drift, edge selection inside the
+cutoff from the skin list, radial MLP, tensor product + neighbour sum,
+channel mix, gate, readout, FP64 energy sum, the full adjoint to forces, half
+kick; the neighbour lists are rebuilt on the device every 20 steps (skin 1 A).
+Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line: atom-steps/s, the roofline position of the dominant
+kernel (timed live with HIP events on the launch stream), and the FP64 CPU
+oracle timed on a bounded sample on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12        # bytes/s
+PEAK_FP32_MFMA = 157.3e12
+PEAK_FP32_VALU = 157.3e12
+KAPPA = 0.009648533
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cg_nnz():
+    """Nonzeros per path of the compiled CG table (for the algorithmic flop model)."""
+    text = open(os.path.join(ROOT, "paper_2605_22698_amd", "csrc", "cg_tables.inc")).read()
+
+    def arr(name):
+        m = re.search(name + r"\[[^\]]*\] = \{([^}]*)\}", text)
+        return [int(x) for x in m.group(1).split(",")]
+    b = arr("kNzBegin")
+    return arr("kL1"), arr("kL2"), arr("kL3"), [b[i + 1] - b[i] for i in range(len(b) - 1)]
+
+
+def layer_paths(cfg, t):
+    L1, L2, L3, NZ = cg_nnz()
+    l1max = 0 if t == 1 else cfg.lmax
+    l3max = 0 if t == cfg.layers else cfg.lmax
+    return [(L1[g], L2[g], L3[g], NZ[g]) for g in range(len(L1))
+            if L1[g] <= l1max and L2[g] <= cfg.lmax and L3[g] <= l3max]
+
+
+def work_model(cfg, t, E, N):
+    """Algorithmic (flops, HBM bytes) of one launch of each stage of layer t."""
+    C = cfg.channels
+    ps = layer_paths(cfg, t)
+    PC = len(ps) * C
+    nc_in = 1 if t == 1 else (cfg.lmax + 1) ** 2
+    nout = sum(2 * l3 + 1 for (_, _, l3, _) in ps)
+    H = cfg.radial_hidden
+    mlp_hidden = 2 * (cfg.n_basis * H + H * H)
+    tp_flops = 2 * C * sum(nz + 2 * l3 + 1 for (_, _, l3, nz) in ps)
+    out = {}
+    # radial MLP: flops on the matrix cores; bytes = edge vectors in, R out
+    out["radial_fwd"] = (E * (mlp_hidden + 2 * H * PC), E * (16 + 4 * PC))
+    # adjoint: recompute hidden layers, dR W3^T, dH2 W2^T, dH1 W1^T; dR and dY in, g read+write
+    out["radial_bwd"] = (E * (mlp_hidden + 2 * H * PC + 2 * H * H + 2 * H * cfg.n_basis),
+                         E * (16 + 4 * PC + 64 + 32))
+    # tensor product + neighbour sum: R streamed once, h read and A written once per atom
+    out["tp_fwd"] = (E * tp_flops, E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
+    out["tp_bwd_edge"] = (E * (tp_flops + 2 * C * sum(nz for *_, nz in ps) + 2 * C * nout),
+                          E * (8 * PC + 16 + 4 + 64) + N * 4 * C * (nc_in + nout))
+    out["tp_bwd_node"] = (E * 2 * C * sum(nz + 2 * l3 + 1 for (_, _, l3, nz) in ps),
+                          E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--atoms", type=int, default=3000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-atoms", type=int, default=400)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_22698_amd as e3
+    import synth
+
+    dev = torch.device("cuda:0")
+    cfg, b = synth.single_config(n=args.atoms)
+    w = synth.flatten_weights(cfg, synth.model_weights(cfg, 2))
+    m = e3.Model(cfg.to_json(), w, device=dev)
+    vel = synth.maxwell_boltzmann(b, 300.0, synth.seed_for(2, 9))
+    pos_d = torch.tensor(b.pos, dtype=torch.float64, device=dev)
+    vel_d = torch.tensor(vel, dtype=torch.float64, device=dev)
+    sp_d = torch.tensor(b.species, dtype=torch.int32, device=dev)
+    masses = synth.SPECIES_MASS[:cfg.n_species]
+    skin, rebuild_every, dt = 1.0, 20, 0.5
+    md = e3.MD(m, b.offsets, pos_d, vel_d, sp_d, masses, b.cell, b.pbc, cfg.cutoff, skin, rebuild_every)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    md.step(args.warmup, dt, energy)
+    torch.cuda.synchronize()
+
+    # ---- timed region ----
+    m.profile(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for k in range(args.steps):
+        md.step(1, dt, energy)
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    gpu_ms = float(step_ms.sum())
+    m.profile(False)
+    stages = ["prune", "embed", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd", "mix_bwd",
+              "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build"]
+    stage_ms = {}
+    for s in stages:
+        tot, n = m.stage_time(s)
+        stage_ms[s] = (tot, n)
+    steps_done, rebuilds, violations = md.stats()
+    n_edges = md_edges = None
+    # exact edge count at the final configuration (same graph the steps used)
+    g_pos, _, _ = md.state()
+    g = m.build_graph(b.offsets, g_pos, sp_d, b.cell, b.pbc, cfg.cutoff, 0.0)
+    m.energy_forces(g, g_pos)
+    n_edges = g.last_edge_count()
+    E_now = energy.item()
+
+    value = b.n_atoms * args.steps / (wall)
+    ms_per_step = 1e3 * wall / args.steps
+
+    # ---- roofline of the dominant kernel ----
+    best = None
+    for t in range(1, cfg.layers + 1):
+        wm = work_model(cfg, t, n_edges, b.n_atoms)
+        for s, (flops, nbytes) in wm.items():
+            tot, n = m.stage_time(f"{s}@{t}")
+            if n == 0:
+                continue
+            if best is None or tot > best[0]:
+                best = (tot, n, s, t, flops, nbytes)
+    tot, n, s, t, flops, nbytes = best
+    avg_s = tot / n / 1e3
+    peak_flop = PEAK_FP32_MFMA if s.startswith("radial") else PEAK_FP32_VALU
+    t_hbm, t_flop = nbytes / PEAK_HBM, flops / peak_flop
+    if t_flop >= t_hbm:
+        bound = "mfma" if s.startswith("radial") else "alu"
+        roof = {"bound": bound, "achieved": flops / avg_s / 1e12, "peak": peak_flop / 1e12, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"{s} (layer {t})"
+    roof["avg_launch_ms"] = tot / n
+    roof["algorithmic_per_launch"] = {"flops": flops, "bytes": nbytes, "edges": n_edges}
+
+    # ---- oracle on the host cores (bounded sample) ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        import torch as _t
+        from oracle import model as om
+        _t.set_num_threads(min(os.cpu_count() or 1, 64))
+        cfg_s, bs = synth.single_config(n=args.cpu_sample_atoms, seed_key=12)
+        om_model = om.Model(cfg_s, synth.model_weights(cfg_s, 2))
+        edges = om._edges(bs, cfg_s.cutoff)
+        om.energy_forces(om_model, synth.Batch(bs.pos[:8], bs.species[:8], bs.cell, bs.pbc,
+                                               np.array([0, 8])))  # warm caches
+        tc = time.perf_counter()
+        om.energy_forces(om_model, bs, edges=edges, edge_chunk=8192)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": bs.n_atoms / tcpu, "unit": "atom-steps/s", "cores": _t.get_num_threads(), "kind": "oracle",
+               "sample": f"one FP64 energy+forces evaluation of a {bs.n_atoms}-atom periodic box of the same "
+                         f"recipe and model (neighbour list excluded), {tcpu:.1f} s"}
+
+    out = {
+        "metric": "atom-steps/s (energy+forces)",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"MD step, {b.n_atoms}-atom periodic box, 0.1 atoms/A^3, 4 species, r_c 5 A, "
+                               f"l_max 3, 128 channels, 2 layers, last layer scalar outputs only",
+                   "n_atoms": b.n_atoms, "n_edges": n_edges, "dt_fs": dt, "skin": skin,
+                   "rebuild_every": rebuild_every, "precision": "fp32"},
+        "p50_ms": float(np.percentile(step_ms, 50)),
+        "p99_ms": float(np.percentile(step_ms, 99)),
+        "gpu_ms_per_step": gpu_ms / args.steps,
+        "stage_ms_per_step": {k: v[0] / args.steps for k, v in stage_ms.items()},
+        "rebuilds": rebuilds,
+        "skin_violations": violations,
+        "energy_eV": E_now,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * e3mi — equivariant message-passing interaction on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library. It evaluates the energy and forces of an equivariant
+ * interatomic potential whose hot loop is the Clebsch-Gordan tensor product
+ * that the paper's backend accelerates (Section 4, "Accelerating equivariant
+ * operations"; Appendix F, MACE and NequIP hyperparameter tables), and runs
+ * velocity-Verlet molecular dynamics on it (Section 1: batched MD; Appendix H,
+ * table of ms per MD step).
+ *
+ * Problem statement (Section 3.2 and Appendix A: a chemical system — positions,
+ * atomic numbers, cell — is turned into a graph with a cutoff radius and the
+ * force field returns its energy, with forces by default): several structures
+ * are packed along the atom axis by `atom_offsets`; structure s owns atoms
+ * atom_offsets[s] .. atom_offsets[s+1]-1.
+ *
+ * Units: angstrom, eV, fs, amu. Forces are -dE/dr (Section 5.2 defines the
+ * Hessian as minus the derivative of the forces, i.e. forces are -dE/dr).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers documented as "device" must be device (HBM) addresses; "host"
+ *    pointers are ordinary CPU memory read during the call only.
+ *  - The caller owns every array it passes. The library owns the opaque
+ *    handles and their device buffers, obtained from the allocator given at
+ *    e3mi_model_create (or hipMalloc when none is given).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *    Outputs are valid once the stream has been synchronised. Calls that
+ *    must learn a size from the device (graph building) synchronise the
+ *    stream themselves, as documented.
+ *  - A model handle holds one scratch workspace: calls that use the same
+ *    model must be ordered (same stream, or externally synchronised).
+ *  - Every function returns an e3mi_status. No exception crosses the ABI.
+ *    On error, outputs are unspecified, handles stay valid, and
+ *    e3mi_last_error() describes the failure (thread-local).
+ */
+#ifndef E3MI_H
+#define E3MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct e3mi_model e3mi_model; /* weights + workspace */
+typedef struct e3mi_graph e3mi_graph; /* neighbour lists of a packed batch */
+typedef struct e3mi_md e3mi_md;       /* MD state: x, v (FP64), forces, graph */
+
+typedef enum e3mi_status {
+  E3MI_OK = 0,
+  E3MI_EINVAL = -1,      /* bad argument (null pointer, inconsistent sizes, bad config) */
+  E3MI_ENOMEM = -2,      /* the allocator returned NULL */
+  E3MI_EDEVICE = -3,     /* a HIP runtime call failed */
+  E3MI_EOVERFLOW = -4,   /* an image index or an edge count does not fit its type */
+  E3MI_ENAN = -5,        /* non-finite positions or energies */
+  E3MI_EUNSUPPORTED = -6 /* valid input the library does not handle (e.g. triclinic cell) */
+} e3mi_status;
+
+typedef enum e3mi_precision {
+  E3MI_FP32 = 0,    /* every contraction in FP32 */
+  E3MI_BF16_MIX = 1 /* radial-MLP and channel-mix GEMM inputs rounded to BF16, FP32 accumulation;
+                       tensor product FP32; energy reduction and MD update FP64 */
+} e3mi_precision;
+
+/* Device allocator callbacks: alloc returns `bytes` of device memory aligned to
+ * 256 bytes, or NULL; free releases a pointer alloc returned. */
+typedef void* (*e3mi_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*e3mi_free_fn)(void* ptr, void* ctx);
+
+/* Model configuration (JSON object, all keys required):
+ *   lmax (2 or 3), channels (C, a multiple of 32), layers (T >= 1),
+ *   n_species, cutoff (r_c, angstrom), avg_neighbors (nu, the constant the
+ *   neighbour sum is divided by), n_basis (8), envelope_p, radial_hidden (64),
+ *   readout_hidden (16).
+ * Readings of the paper behind each key: Appendix F tables (l_max, channels,
+ * layers, num_rbf 8, radial net of 2 hidden layers of 64 with swish,
+ * polynomial envelope, gate nonlinearity, readout 16x0e -> 0e, cutoff 5 A).
+ *
+ * Weights: one host FP64 vector, row-major tensors concatenated in this order
+ * (P_t = number of natural-parity paths (l1,l2,l3) of layer t, ordered by
+ * (l3, l1, l2); l1 runs over the layer's input orders — {0} for t = 1,
+ * 0..lmax after — and l2, l3 over 0..lmax; P_{t,l3} those with output l3):
+ *   emb [n_species, C]
+ *   for t = 1..T: rad1 [n_basis, H], rad2 [H, H], rad3 [H, P_t*C] (column p*C + k),
+ *                 mix_l3 [P_{t,l3}*C, C] for l3 = 0..lmax (row q*C + k),
+ *                 self_l3 [C, C] for each l3 among the layer's input orders
+ *   read1 [C, readout_hidden], read2 [readout_hidden, 1], e0 [n_species]
+ */
+
+/* Number of FP64 weights the configuration expects. */
+int e3mi_weight_count(const char* config_json, size_t* n_weights);
+
+/* Create a model. weights_host: n_weights FP64 values (host). precision: an
+ * e3mi_precision. alloc/free may be NULL (then hipMalloc/hipFree are used);
+ * ctx is passed to them unchanged. Synchronous (uploads weights). */
+int e3mi_model_create(const char* config_json, const double* weights_host, size_t n_weights,
+                      int precision, e3mi_alloc_fn alloc, e3mi_free_fn free_fn, void* ctx,
+                      e3mi_model** out);
+int e3mi_model_destroy(e3mi_model* model);
+
+/* Build the neighbour lists of a packed batch (Section 3.2: graph from a
+ * chemical system and a cutoff radius). Lists every directed edge i <- j with
+ * integer image vector n (zero along non-periodic axes) such that
+ *   0 < |r_j - r_i + n . cell| < cutoff + skin,
+ * per structure (edges never join structures), stored in CSR by receiver i and
+ * sorted by (j, n) within a receiver; each edge knows its reverse (j <- i, -n).
+ *   n_structures   S >= 1
+ *   atom_offsets   host int64 [S+1], non-decreasing, atom_offsets[0] = 0
+ *   pos            device FP64 [N, 3]
+ *   species        device int32 [N], values in [0, n_species)
+ *   cell           host FP64 [S, 3, 3], rows are lattice vectors; must be
+ *                  diagonal (orthorhombic) on periodic axes, else EUNSUPPORTED
+ *   pbc            host uint8 [S, 3], periodic flags
+ *   cutoff         >= the model's cutoff; skin >= 0
+ * Synchronises `stream` twice (to size the cell grid and the edge arrays).
+ * The graph stays valid while every atom stays within skin/2 of its position
+ * at build time; energy_forces re-selects the edges inside the model cutoff on
+ * every call. */
+int e3mi_build_graph(e3mi_model* model, int n_structures, const int64_t* atom_offsets,
+                     const double* pos, const int32_t* species, const double* cell,
+                     const uint8_t* pbc, double cutoff, double skin, void* stream,
+                     e3mi_graph** out);
+int e3mi_graph_destroy(e3mi_graph* graph);
+
+/* Sizes of a graph: atoms N and edges of the skin list. */
+int e3mi_graph_info(const e3mi_graph* graph, int64_t* n_atoms, int64_t* n_skin_edges);
+
+/* Copy the skin neighbour list to caller device buffers: row_ptr int32 [N+1],
+ * src int32 [E], shift int32 [E, 3] (image vector n), rev int32 [E] (index of
+ * the reverse edge). Any output may be NULL. Asynchronous on `stream`. */
+int e3mi_graph_copy_edges(const e3mi_graph* graph, int32_t* row_ptr, int32_t* src, int32_t* shift,
+                          int32_t* rev, void* stream);
+
+/* Energy and forces of every structure (Section 4 hot path; Section 5.3 readout
+ * E = sum_i [R(h_i) + E0(z_i)] with one head). pos: device FP64 [N, 3] (the
+ * same atoms as the graph). energy: device FP64 [S] (per-structure sums in a
+ * fixed order). forces: device FP32 [N, 3]. atom_energy: device FP64 [N] or
+ * NULL. Asynchronous on `stream`. */
+int e3mi_energy_forces(e3mi_model* model, e3mi_graph* graph, const double* pos, double* energy,
+                       float* forces, double* atom_energy, void* stream);
+
+/* Number of edges inside the model cutoff at the last energy_forces call on
+ * this graph. Synchronises `stream`. */
+int e3mi_graph_last_edge_count(const e3mi_graph* graph, int64_t* n_edges, void* stream);
+
+/* Velocity-Verlet NVE molecular dynamics on a packed batch (Section 1: batched
+ * MD; Appendix H: ms per MD step). The state (positions and velocities in
+ * FP64, forces, neighbour lists) stays on the device. Inputs as for
+ * e3mi_build_graph plus: vel device FP64 [N, 3] (angstrom/fs), masses host
+ * FP64 [n_species] (amu), rebuild_every >= 1 (steps between neighbour
+ * rebuilds). Positions are wrapped into the cell at every rebuild. The device
+ * tracks each atom's displacement since the last rebuild; when a scheduled
+ * rebuild finds that some atom moved more than skin/2 in the interval, it is
+ * counted as a skin violation and the interval is halved from then on.
+ * pos/vel are copied; the caller's buffers are not referenced afterwards.
+ * Synchronises `stream`. */
+int e3mi_md_create(e3mi_model* model, int n_structures, const int64_t* atom_offsets,
+                   const double* pos, const double* vel, const int32_t* species,
+                   const double* masses, const double* cell, const uint8_t* pbc, double cutoff,
+                   double skin, int rebuild_every, void* stream, e3mi_md** out);
+
+/* Advance n_steps steps of dt_fs:
+ *   v += dt/2 * kappa F/m;  x += dt v;  F = F(x);  v += dt/2 * kappa F/m
+ * with kappa = 0.009648533 A/fs^2 per (eV/A)/amu, positions and velocities in
+ * FP64. energy_out: device FP64 [S], potential energy after the last step, or
+ * NULL. Synchronises `stream` when a neighbour rebuild is due (every
+ * rebuild_every steps). */
+int e3mi_md_step(e3mi_md* md, int n_steps, double dt_fs, double* energy_out, void* stream);
+
+/* Copy the current state to caller device buffers (any may be NULL):
+ * pos, vel FP64 [N, 3], forces FP32 [N, 3]. Asynchronous on `stream`. */
+int e3mi_md_state(const e3mi_md* md, double* pos, double* vel, float* forces, void* stream);
+
+/* Counters of an MD state (any output may be NULL): steps taken, neighbour
+ * rebuilds done, skin violations detected. */
+int e3mi_md_stats(const e3mi_md* md, int64_t* steps, int64_t* rebuilds, int64_t* skin_violations);
+int e3mi_md_destroy(e3mi_md* md);
+
+/* Device bytes an energy_forces call needs for n_atoms atoms and n_edges skin
+ * edges (graph + workspace), for admission control by a caller that packs
+ * several systems. */
+size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_edges);
+
+/* Per-stage timing with HIP events recorded on the launch stream, for
+ * measuring kernels in place (Appendix H reports ms per MD step; this splits
+ * a step into its stages). enable != 0 resets the counters and starts
+ * recording; 0 stops. Stages: prune, embed, radial_fwd, tp_fwd, mix_fwd,
+ * gate_fwd, readout, gate_bwd, mix_bwd, tp_bwd_edge, radial_bwd, tp_bwd_node,
+ * forces, md_update, graph_build; "name@t" selects interaction layer t.
+ * e3mi_profile_query waits for the recorded events and returns the summed
+ * milliseconds and the number of timed launches of a stage. */
+int e3mi_profile_enable(e3mi_model* model, int enable);
+int e3mi_profile_query(e3mi_model* model, const char* stage, double* total_ms, int64_t* launches);
+
+/* Thread-local description of the last error ("" if none). */
+const char* e3mi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* E3MI_H */

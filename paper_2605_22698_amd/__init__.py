@@ -1,0 +1,200 @@
+"""e3mi: equivariant message-passing interaction on MI355X (gfx950 HIP kernels).
+
+Python face of libe3mi.so. Each class owns one opaque handle of the C ABI
+(include/e3mi.h) and only marshals arguments: the neighbour lists, the
+interaction, its adjoint and the MD integrator all run in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import BF16_MIX, FP32, E3miError, check, lib, ptr
+
+__all__ = ["Model", "Graph", "MD", "E3miError", "FP32", "BF16_MIX", "weight_count"]
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def weight_count(config_json: str) -> int:
+    n = ctypes.c_size_t()
+    check(lib().e3mi_weight_count(config_json.encode(), ctypes.byref(n)))
+    return n.value
+
+
+class Model:
+    """Weights on the device plus the evaluation workspace.
+
+    config_json: the model configuration (see include/e3mi.h); weights: FP64
+    vector in the documented order; precision: FP32 or BF16_MIX.
+    """
+
+    def __init__(self, config_json: str, weights: np.ndarray, precision: int = FP32, device="cuda",
+                 torch_allocator: bool = True):
+        import torch
+        self.device = torch.device(device)
+        self.config_json = config_json
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        self._alloc = _lib.TorchAllocator(self.device) if torch_allocator else None
+        h = ctypes.c_void_p()
+        a = self._alloc.alloc_cb if self._alloc else _lib.ALLOC_FN()
+        f = self._alloc.free_cb if self._alloc else _lib.FREE_FN()
+        with torch.cuda.device(self.device):
+            check(lib().e3mi_model_create(config_json.encode(), w.ctypes.data, w.size, precision, a, f, None,
+                                          ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().e3mi_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool = True):
+        """Start (resetting counters) or stop per-stage HIP-event timing."""
+        check(lib().e3mi_profile_enable(self.handle, 1 if enable else 0))
+
+    def stage_time(self, stage: str):
+        """(total ms, launches) of a timed stage, e.g. "radial_fwd" or "tp_fwd@2"."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(lib().e3mi_profile_query(self.handle, stage.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def footprint_bytes(self, n_atoms: int, n_edges: int) -> int:
+        return int(lib().e3mi_footprint_bytes(self.handle, n_atoms, n_edges))
+
+    def build_graph(self, offsets, pos, species, cell, pbc, cutoff: float, skin: float = 0.0,
+                    stream=None) -> "Graph":
+        return Graph(self, offsets, pos, species, cell, pbc, cutoff, skin, stream)
+
+    def energy_forces(self, graph: "Graph", pos, atom_energy: bool = False, stream=None):
+        """(E [S] FP64, F [N,3] FP32, E_i [N] FP64 or None) as device tensors."""
+        import torch
+        S, N = graph.n_structures, graph.n_atoms
+        E = torch.empty(S, dtype=torch.float64, device=self.device)
+        F = torch.empty((N, 3), dtype=torch.float32, device=self.device)
+        Ei = torch.empty(N, dtype=torch.float64, device=self.device) if atom_energy else None
+        pos = pos.contiguous()
+        assert pos.dtype == torch.float64 and pos.shape == (N, 3)
+        check(lib().e3mi_energy_forces(self.handle, graph.handle, ptr(pos), ptr(E), ptr(F), ptr(Ei),
+                                       _stream(stream)))
+        return E, F, Ei
+
+
+class Graph:
+    """Neighbour lists (skin list + per-call cutoff selection) of a packed batch."""
+
+    def __init__(self, model: Model, offsets, pos, species, cell, pbc, cutoff, skin, stream=None):
+        import torch
+        self.model = model
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        cell = np.ascontiguousarray(cell, dtype=np.float64).reshape(-1, 3, 3)
+        pbc = np.ascontiguousarray(pbc, dtype=np.uint8).reshape(-1, 3)
+        self.n_structures = len(off) - 1
+        self.n_atoms = int(off[-1])
+        assert cell.shape[0] == self.n_structures and pbc.shape[0] == self.n_structures
+        pos = pos.contiguous()
+        self._species = species.to(torch.int32).contiguous()
+        assert pos.dtype == torch.float64 and pos.shape == (self.n_atoms, 3)
+        h = ctypes.c_void_p()
+        check(lib().e3mi_build_graph(model.handle, self.n_structures, off.ctypes.data, ptr(pos),
+                                     ptr(self._species), cell.ctypes.data, pbc.ctypes.data, cutoff, skin,
+                                     _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().e3mi_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_skin_edges(self) -> int:
+        e = ctypes.c_int64()
+        check(lib().e3mi_graph_info(self.handle, None, ctypes.byref(e)))
+        return e.value
+
+    def last_edge_count(self, stream=None) -> int:
+        e = ctypes.c_int64()
+        check(lib().e3mi_graph_last_edge_count(self.handle, ctypes.byref(e), _stream(stream)))
+        return e.value
+
+    def edges(self, stream=None):
+        """Skin list as device tensors (row_ptr [N+1], src [E], shift [E,3], rev [E])."""
+        import torch
+        E = self.n_skin_edges
+        dev = self.model.device
+        row_ptr = torch.empty(self.n_atoms + 1, dtype=torch.int32, device=dev)
+        src = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+        shift = torch.empty((max(E, 1), 3), dtype=torch.int32, device=dev)
+        rev = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+        check(lib().e3mi_graph_copy_edges(self.handle, ptr(row_ptr), ptr(src), ptr(shift), ptr(rev),
+                                          _stream(stream)))
+        return row_ptr, src[:E], shift[:E], rev[:E]
+
+
+class MD:
+    """Velocity-Verlet NVE trajectories of a packed batch, state kept on the device."""
+
+    def __init__(self, model: Model, offsets, pos, vel, species, masses, cell, pbc, cutoff: float,
+                 skin: float = 1.0, rebuild_every: int = 20, stream=None):
+        import torch
+        self.model = model
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.n_structures = len(off) - 1
+        self.n_atoms = int(off[-1])
+        cell = np.ascontiguousarray(cell, dtype=np.float64).reshape(-1, 3, 3)
+        pbc = np.ascontiguousarray(pbc, dtype=np.uint8).reshape(-1, 3)
+        masses = np.ascontiguousarray(masses, dtype=np.float64)
+        pos, vel = pos.contiguous(), vel.contiguous()
+        species = species.to(torch.int32).contiguous()
+        h = ctypes.c_void_p()
+        check(lib().e3mi_md_create(model.handle, self.n_structures, off.ctypes.data, ptr(pos), ptr(vel), ptr(species),
+                                   masses.ctypes.data, cell.ctypes.data, pbc.ctypes.data, cutoff, skin, rebuild_every,
+                                   _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def step(self, n_steps: int, dt_fs: float, energy_out=None, stream=None):
+        check(lib().e3mi_md_step(self.handle, n_steps, dt_fs, ptr(energy_out), _stream(stream)))
+
+    def state(self, stream=None):
+        import torch
+        dev = self.model.device
+        x = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=dev)
+        v = torch.empty((self.n_atoms, 3), dtype=torch.float64, device=dev)
+        F = torch.empty((self.n_atoms, 3), dtype=torch.float32, device=dev)
+        check(lib().e3mi_md_state(self.handle, ptr(x), ptr(v), ptr(F), _stream(stream)))
+        return x, v, F
+
+    def stats(self) -> Tuple[int, int, int]:
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib().e3mi_md_stats(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().e3mi_md_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1017 @@
+// Host runtime and C ABI of the e3mi library (declared in include/e3mi.h).
+//
+// Owns the model (FP32 device copies of the weights, plus transposed copies
+// the adjoint GEMMs read), the neighbour-list handles and the MD state, and
+// sequences the kernels of one energy + forces evaluation on the caller's
+// stream:
+//   prune -> embed -> for each layer: radial MLP, tensor product + neighbour
+//   sum, channel mix, gate -> readout -> FP64 energy sum
+//   -> adjoint in reverse layer order -> force assembly.
+// The last layer keeps only its scalar outputs (the readout reads nothing
+// else), which removes its l3 > 0 paths without changing E or F.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "cg_tables.inc"
+#include "common.h"
+#include "runtime.h"
+
+namespace e3mi {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// ---- configuration ---------------------------------------------------------------
+struct Config {
+  int lmax = 0, channels = 0, layers = 0, n_species = 0, n_basis = 0, envelope_p = 0, radial_hidden = 0,
+      readout_hidden = 0;
+  double cutoff = 0, avg_neighbors = 0;
+};
+
+double json_number(const std::string& s, const char* key) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = s.find(k);
+  if (p == std::string::npos) throw Error(E3MI_EINVAL, std::string("config: missing key ") + key);
+  p = s.find(':', p + k.size());
+  if (p == std::string::npos) throw Error(E3MI_EINVAL, std::string("config: malformed value of ") + key);
+  const char* b = s.c_str() + p + 1;
+  char* e = nullptr;
+  const double v = std::strtod(b, &e);
+  if (e == b) throw Error(E3MI_EINVAL, std::string("config: value of ") + key + " is not a number");
+  return v;
+}
+
+Config parse_config(const char* json) {
+  E3MI_REQUIRE(json, E3MI_EINVAL, "config is NULL");
+  const std::string s(json);
+  Config c;
+  c.lmax = (int)json_number(s, "lmax");
+  c.channels = (int)json_number(s, "channels");
+  c.layers = (int)json_number(s, "layers");
+  c.n_species = (int)json_number(s, "n_species");
+  c.cutoff = json_number(s, "cutoff");
+  c.avg_neighbors = json_number(s, "avg_neighbors");
+  c.n_basis = (int)json_number(s, "n_basis");
+  c.envelope_p = (int)json_number(s, "envelope_p");
+  c.radial_hidden = (int)json_number(s, "radial_hidden");
+  c.readout_hidden = (int)json_number(s, "readout_hidden");
+  E3MI_REQUIRE(c.lmax == 2 || c.lmax == 3, E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
+  E3MI_REQUIRE(c.channels >= 32 && c.channels % 32 == 0 && c.channels <= 256, E3MI_EUNSUPPORTED,
+               "channels must be a multiple of 32 in [32, 256]");
+  E3MI_REQUIRE(c.layers >= 1 && c.layers <= 8, E3MI_EINVAL, "layers must be in [1, 8]");
+  E3MI_REQUIRE(c.n_species >= 1, E3MI_EINVAL, "n_species must be >= 1");
+  E3MI_REQUIRE(c.cutoff > 0 && std::isfinite(c.cutoff), E3MI_EINVAL, "cutoff must be positive");
+  E3MI_REQUIRE(c.avg_neighbors > 0, E3MI_EINVAL, "avg_neighbors must be positive");
+  E3MI_REQUIRE(c.n_basis == 8, E3MI_EUNSUPPORTED, "n_basis must be 8");
+  E3MI_REQUIRE(c.envelope_p >= 2 && c.envelope_p <= 16, E3MI_EINVAL, "envelope_p must be in [2, 16]");
+  E3MI_REQUIRE(c.radial_hidden == 64, E3MI_EUNSUPPORTED, "radial_hidden must be 64");
+  E3MI_REQUIRE(c.readout_hidden == 16, E3MI_EUNSUPPORTED, "readout_hidden must be 16");
+  return c;
+}
+
+// Path bookkeeping of layer t (1-based).
+struct LayerPlan {
+  int kind;
+  int l1max;           // highest input order
+  int l3max_used;      // highest output order computed (0 for the last layer)
+  int nc_in, nc_out;   // components of h^{t-1} and of h~^t as stored
+  int p_full;          // paths in the weight tensors of this layer
+  int p_full_l3[4];    // per output order
+  int p_used;          // paths evaluated
+  int p_used_l3[4];
+  long a_per_atom;     // floats of A per atom = sum_l3 (2 l3 + 1) P_l3 C
+};
+
+LayerPlan plan_layer(const Config& c, int t) {
+  LayerPlan L{};
+  const int T = c.layers;
+  L.kind = T == 1 ? 3 : (t == 1 ? 0 : (t == T ? 2 : 1));
+  L.l1max = t == 1 ? 0 : c.lmax;
+  L.l3max_used = t == T ? 0 : c.lmax;
+  L.nc_in = (L.l1max + 1) * (L.l1max + 1);
+  L.nc_out = (L.l3max_used + 1) * (L.l3max_used + 1);
+  for (int l = 0; l < 4; ++l) L.p_full_l3[l] = L.p_used_l3[l] = 0;
+  for (int g = 0; g < e3mi_cg::kNumPaths; ++g) {
+    const int l1 = e3mi_cg::kL1[g], l2 = e3mi_cg::kL2[g], l3 = e3mi_cg::kL3[g];
+    if (l1 > L.l1max || l2 > c.lmax || l3 > c.lmax) continue;
+    L.p_full_l3[l3]++;
+    if (l3 <= L.l3max_used) L.p_used_l3[l3]++;
+  }
+  L.p_full = L.p_used = 0;
+  L.a_per_atom = 0;
+  for (int l = 0; l <= c.lmax; ++l) {
+    L.p_full += L.p_full_l3[l];
+    L.p_used += L.p_used_l3[l];
+    L.a_per_atom += (long)(2 * l + 1) * L.p_used_l3[l] * c.channels;
+  }
+  return L;
+}
+
+size_t weight_count(const Config& c) {
+  const size_t C = c.channels, H = c.radial_hidden;
+  size_t n = (size_t)c.n_species * C;
+  for (int t = 1; t <= c.layers; ++t) {
+    const LayerPlan L = plan_layer(c, t);
+    n += (size_t)c.n_basis * H + H * H + H * (size_t)L.p_full * C;
+    for (int l = 0; l <= c.lmax; ++l) n += (size_t)L.p_full_l3[l] * C * C;
+    n += (size_t)(L.l1max + 1) * C * C;  // self connection per input order
+  }
+  n += C * c.readout_hidden + c.readout_hidden + c.n_species;
+  return n;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Timed stages (per layer where it applies: index = stage * 8 + layer).
+enum Stage : int {
+  kPrune = 0, kEmbed, kRadialFwd, kTpFwd, kMixFwd, kGateFwd, kReadout, kGateBwd, kMixBwd, kTpBwdEdge,
+  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kNumStages
+};
+const char* const kStageNames[kNumStages] = {
+    "prune", "embed", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd", "mix_bwd",
+    "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build"};
+inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
+
+}  // namespace
+
+// ---- model -----------------------------------------------------------------------
+struct LayerWeights {
+  DevBuf rad1, rad2, rad2T, rad3, rad3T;
+  DevBuf mix[4], mixT[4], self_[4], selfT[4];
+};
+
+struct Workspace {
+  std::vector<std::unique_ptr<DevBuf>> h, ht, R;
+  std::unique_ptr<DevBuf> A, dR, dY, g, dh_a, dh_b, dht, e_atom;
+};
+
+}  // namespace e3mi
+
+struct e3mi_model {
+  e3mi::Config cfg;
+  int precision = 0;
+  e3mi::Allocator alloc;
+  std::vector<e3mi::LayerPlan> plans;
+  std::vector<std::unique_ptr<e3mi::LayerWeights>> lw;
+  std::unique_ptr<e3mi::DevBuf> emb, read1, read2, e0;
+  e3mi::Workspace ws;
+  e3mi::Profiler prof;
+};
+
+struct e3mi_graph {
+  e3mi_model* model = nullptr;
+  int S = 0, N = 0;
+  long E = 0;  // skin-list edges
+  double cutoff = 0, skin = 0;
+  std::vector<int64_t> off_h;
+  std::vector<double> box_h;
+  std::vector<uint8_t> pbc_h;
+  std::unique_ptr<e3mi::DevBuf> off_d, owner, box_d, pbc_d, species, row_ptr, src, shift, rev, keys;
+  std::unique_ptr<e3mi::DevBuf> cnt, row_ptr_x, src_x, dvec_x, old_idx, new_idx, rev_x, x_ref;
+};
+
+struct e3mi_md {
+  e3mi_model* model = nullptr;
+  e3mi_graph* graph = nullptr;
+  int S = 0, N = 0;
+  std::vector<int64_t> off_h;
+  std::vector<double> cell_h;
+  std::vector<uint8_t> pbc_h;
+  double cutoff = 0, skin = 0;
+  int rebuild_every = 1, since_build = 0;
+  int64_t steps = 0, rebuilds = 0, skin_violations = 0;
+  std::unique_ptr<e3mi::DevBuf> x, v, F, species, inv_mass, energy, flag;
+};
+
+namespace e3mi {
+namespace {
+
+std::unique_ptr<DevBuf> upload(Allocator* a, const void* host, size_t bytes) {
+  auto b = std::make_unique<DevBuf>(a);
+  b->ensure(bytes);
+  if (bytes) E3MI_HIP(hipMemcpy(b->p, host, bytes, hipMemcpyHostToDevice));
+  return b;
+}
+
+std::unique_ptr<DevBuf> upload_f32(Allocator* a, const std::vector<float>& v) {
+  return upload(a, v.data(), v.size() * sizeof(float));
+}
+
+std::vector<float> transpose(const std::vector<float>& m, int rows, int cols) {
+  std::vector<float> t((size_t)rows * cols);
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) t[(size_t)c * rows + r] = m[(size_t)r * cols + c];
+  return t;
+}
+
+DevBuf& ensure(std::unique_ptr<DevBuf>& b, Allocator* a, size_t bytes) {
+  if (!b) b = std::make_unique<DevBuf>(a);
+  b->ensure(bytes);
+  return *b;
+}
+
+void fill_plan(const Config& c, int S, const std::vector<int64_t>& off, const double* cell, const uint8_t* pbc,
+               const std::vector<double>& bbox, double rc_eff, std::vector<GridPlan>& plans, int& n_cells) {
+  plans.resize(S);
+  n_cells = 0;
+  (void)c;
+  for (int s = 0; s < S; ++s) {
+    GridPlan g{};
+    const long ns = off[s + 1] - off[s];
+    for (int k = 0; k < 3; ++k) {
+      g.periodic[k] = pbc[3 * s + k] ? 1 : 0;
+      if (g.periodic[k]) {
+        const double L = cell[9 * s + 4 * k];
+        g.lo[k] = 0.0;
+        g.len[k] = L;
+        g.nb[k] = std::max(1, (int)std::floor(L / rc_eff));
+        g.inv_cw[k] = g.nb[k] / L;
+      } else {
+        const double lo = ns ? bbox[6 * s + k] : 0.0, hi = ns ? bbox[6 * s + 3 + k] : 0.0;
+        const double ext = hi - lo;
+        g.lo[k] = lo;
+        g.len[k] = 0.0;
+        g.nb[k] = ext > 0 ? std::max(1, (int)std::floor(ext / rc_eff)) : 1;
+        g.inv_cw[k] = ext > 0 ? g.nb[k] / ext : 1.0;
+      }
+    }
+    const long cap = std::max<long>(64, 8 * ns);
+    long cells = (long)g.nb[0] * g.nb[1] * g.nb[2];
+    if (cells > cap) {
+      const double f = std::cbrt((double)cells / (double)cap);
+      for (int k = 0; k < 3; ++k) {
+        const int nb = std::max(1, (int)std::floor(g.nb[k] / f));
+        g.inv_cw[k] *= (double)nb / g.nb[k];
+        g.nb[k] = nb;
+      }
+      cells = (long)g.nb[0] * g.nb[1] * g.nb[2];
+    }
+    g.cell_base = n_cells;
+    n_cells += (int)cells;
+    plans[s] = g;
+  }
+}
+
+void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
+  e3mi_model* M = G->model;
+  Allocator* a = &M->alloc;
+  const int S = G->S, N = G->N;
+  const double rc_eff = G->cutoff + G->skin;
+  // bounding boxes of open axes
+  std::vector<double> bbox((size_t)6 * S, 0.0);
+  bool any_open = false;
+  for (int s = 0; s < S; ++s)
+    for (int k = 0; k < 3; ++k) any_open |= !G->pbc_h[3 * s + k];
+  if (any_open && N) {
+    DevBuf bb(a);
+    bb.ensure(sizeof(double) * 6 * S);
+    launch_bbox(pos, G->off_d->as<int64_t>(), S, bb.as<double>(), st);
+    E3MI_HIP(hipMemcpyAsync(bbox.data(), bb.p, sizeof(double) * 6 * S, hipMemcpyDeviceToHost, st));
+    E3MI_HIP(hipStreamSynchronize(st));
+  }
+  std::vector<double> cell9((size_t)9 * S, 0.0);
+  for (int s = 0; s < S; ++s)
+    for (int k = 0; k < 3; ++k) cell9[9 * s + 4 * k] = G->box_h[3 * s + k];
+  std::vector<GridPlan> plans;
+  int n_cells = 0;
+  fill_plan(M->cfg, S, G->off_h, cell9.data(), G->pbc_h.data(), bbox, rc_eff, plans, n_cells);
+  auto plan_d = upload(a, plans.data(), sizeof(GridPlan) * plans.size());
+
+  DevBuf cell_count(a), cell_start(a), cell_fill(a), cell_atoms(a), atom_cell(a), wrap(a), err(a);
+  cell_count.ensure(sizeof(int) * (n_cells + 1));
+  cell_start.ensure(sizeof(int) * (n_cells + 1));
+  cell_fill.ensure(sizeof(int) * (n_cells + 1));
+  cell_atoms.ensure(sizeof(int) * (N + 1));
+  atom_cell.ensure(sizeof(int) * (N + 1));
+  wrap.ensure(sizeof(int) * 3 * (N + 1));
+  err.ensure(sizeof(int));
+  E3MI_HIP(hipMemsetAsync(cell_count.p, 0, sizeof(int) * (n_cells + 1), st));
+  E3MI_HIP(hipMemsetAsync(cell_fill.p, 0, sizeof(int) * (n_cells + 1), st));
+  E3MI_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
+  launch_bin(pos, G->owner->as<int>(), plan_d->as<GridPlan>(), N, atom_cell.as<int>(), wrap.as<int>(),
+             cell_count.as<int>(), st);
+  launch_exclusive_scan(cell_count.as<int>(), cell_start.as<int>(), n_cells, st);
+  launch_bin_fill(atom_cell.as<int>(), cell_start.as<int>(), N, cell_fill.as<int>(), cell_atoms.as<int>(), st);
+
+  const double rc2 = rc_eff * rc_eff;
+  ensure(G->cnt, a, sizeof(int) * (N + 1));
+  ensure(G->row_ptr, a, sizeof(int) * (N + 1));
+  launch_edges(false, pos, G->owner->as<int>(), plan_d->as<GridPlan>(), atom_cell.as<int>(), wrap.as<int>(),
+               cell_start.as<int>(), cell_atoms.as<int>(), nullptr, N, rc2, G->cnt->as<int>(), nullptr,
+               err.as<int>(), st);
+  launch_exclusive_scan(G->cnt->as<int>(), G->row_ptr->as<int>(), N, st);
+  int E = 0;
+  E3MI_HIP(hipMemcpyAsync(&E, G->row_ptr->as<int>() + N, sizeof(int), hipMemcpyDeviceToHost, st));
+  E3MI_HIP(hipStreamSynchronize(st));
+  E3MI_REQUIRE(E >= 0, E3MI_EOVERFLOW, "edge count overflow");
+  G->E = E;
+  ensure(G->keys, a, sizeof(uint64_t) * (E + 1));
+  ensure(G->src, a, sizeof(int) * (E + 1));
+  ensure(G->shift, a, sizeof(int) * (E + 1));
+  ensure(G->rev, a, sizeof(int) * (E + 1));
+  launch_edges(true, pos, G->owner->as<int>(), plan_d->as<GridPlan>(), atom_cell.as<int>(), wrap.as<int>(),
+               cell_start.as<int>(), cell_atoms.as<int>(), G->row_ptr->as<int>(), N, rc2, nullptr,
+               G->keys->as<uint64_t>(), err.as<int>(), st);
+  launch_sort_rows(G->row_ptr->as<int>(), N, G->keys->as<uint64_t>(), G->src->as<int>(), G->shift->as<int>(), st);
+  launch_rekey(G->src->as<int>(), G->shift->as<int>(), E, G->keys->as<uint64_t>(), st);
+  launch_reverse(G->row_ptr->as<int>(), G->keys->as<uint64_t>(), N, G->rev->as<int>(), err.as<int>(), st);
+  int errh = 0;
+  E3MI_HIP(hipMemcpyAsync(&errh, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  E3MI_HIP(hipStreamSynchronize(st));
+  E3MI_REQUIRE(!(errh & 1), E3MI_EOVERFLOW, "image index beyond +-127 cells: wrap positions into the cell");
+  E3MI_REQUIRE(!(errh & 2), E3MI_EDEVICE, "neighbour list is not symmetric");
+  // pruned-list capacity and the reference positions for the skin check
+  ensure(G->row_ptr_x, a, sizeof(int) * (N + 1));
+  ensure(G->src_x, a, sizeof(int) * (E + 1));
+  ensure(G->dvec_x, a, sizeof(float4) * (E + 1));
+  ensure(G->old_idx, a, sizeof(int) * (E + 1));
+  ensure(G->new_idx, a, sizeof(int) * (E + 1));
+  ensure(G->rev_x, a, sizeof(int) * (E + 1));
+  ensure(G->x_ref, a, sizeof(double) * 3 * (N + 1));
+  if (N) E3MI_HIP(hipMemcpyAsync(G->x_ref->p, pos, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
+}
+
+e3mi_graph* new_graph(e3mi_model* M, int S, const int64_t* off, const double* pos, const int32_t* species,
+                      const double* cell, const uint8_t* pbc, double cutoff, double skin, hipStream_t st) {
+  E3MI_REQUIRE(M && off && cell && pbc, E3MI_EINVAL, "null argument");
+  E3MI_REQUIRE(S >= 1, E3MI_EINVAL, "n_structures must be >= 1");
+  E3MI_REQUIRE(off[0] == 0, E3MI_EINVAL, "atom_offsets[0] must be 0");
+  for (int s = 0; s < S; ++s) E3MI_REQUIRE(off[s + 1] >= off[s], E3MI_EINVAL, "atom_offsets must be non-decreasing");
+  E3MI_REQUIRE(off[S] < (1LL << 30), E3MI_EOVERFLOW, "too many atoms");
+  E3MI_REQUIRE(off[S] == 0 || (pos && species), E3MI_EINVAL, "null positions or species");
+  E3MI_REQUIRE(cutoff >= M->cfg.cutoff && std::isfinite(cutoff), E3MI_EINVAL,
+               "graph cutoff must be at least the model cutoff");
+  E3MI_REQUIRE(skin >= 0 && std::isfinite(skin), E3MI_EINVAL, "skin must be >= 0");
+  auto G = std::make_unique<e3mi_graph>();
+  G->model = M;
+  G->S = S;
+  G->N = (int)off[S];
+  G->cutoff = cutoff;
+  G->skin = skin;
+  G->off_h.assign(off, off + S + 1);
+  G->box_h.assign((size_t)3 * S, 0.0);
+  G->pbc_h.assign(pbc, pbc + 3 * S);
+  for (int s = 0; s < S; ++s) {
+    bool periodic = false;
+    for (int k = 0; k < 3; ++k) periodic |= pbc[3 * s + k] != 0;
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) {
+        const double v = cell[9 * s + 3 * r + k];
+        E3MI_REQUIRE(std::isfinite(v), E3MI_EINVAL, "cell is not finite");
+        if (periodic && r != k && v != 0.0)
+          throw Error(E3MI_EUNSUPPORTED, "periodic cells must be orthorhombic (diagonal)");
+      }
+    for (int k = 0; k < 3; ++k)
+      if (pbc[3 * s + k]) {
+        const double L = cell[9 * s + 4 * k];
+        E3MI_REQUIRE(L > 0, E3MI_EINVAL, "periodic cell length must be positive");
+        G->box_h[3 * s + k] = L;
+      }
+  }
+  Allocator* a = &M->alloc;
+  G->off_d = upload(a, G->off_h.data(), sizeof(int64_t) * (S + 1));
+  G->box_d = upload(a, G->box_h.data(), sizeof(double) * 3 * S);
+  G->pbc_d = upload(a, G->pbc_h.data(), 3 * S);
+  G->owner = std::make_unique<DevBuf>(a);
+  G->owner->ensure(sizeof(int) * (G->N + 1));
+  G->species = std::make_unique<DevBuf>(a);
+  G->species->ensure(sizeof(int) * (G->N + 1));
+  if (G->N) E3MI_HIP(hipMemcpyAsync(G->species->p, species, sizeof(int) * G->N, hipMemcpyDeviceToDevice, st));
+  launch_owner(G->off_d->as<int64_t>(), S, G->owner->as<int>(), st);
+  if (G->N) {
+    DevBuf flag(a);
+    flag.ensure(sizeof(int));
+    E3MI_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+    launch_nonfinite(pos, 3 * G->N, flag.as<int>(), st);
+    int fh = 0;
+    E3MI_HIP(hipMemcpyAsync(&fh, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    E3MI_HIP(hipStreamSynchronize(st));
+    E3MI_REQUIRE(!fh, E3MI_ENAN, "positions are not finite");
+  }
+  build_lists(G.get(), pos, st);
+  return G.release();
+}
+
+// ---- energy + forces ---------------------------------------------------------------
+
+void prune(e3mi_graph* G, const double* pos, hipStream_t st) {
+  const int N = G->N;
+  const double rc2 = G->model->cfg.cutoff * G->model->cfg.cutoff;
+  launch_prune_count(pos, G->owner->as<int>(), G->box_d->as<double>(), G->row_ptr->as<int>(), G->src->as<int>(),
+                     G->shift->as<int>(), N, rc2, G->cnt->as<int>(), st);
+  launch_exclusive_scan(G->cnt->as<int>(), G->row_ptr_x->as<int>(), N, st);
+  launch_prune_compact(pos, G->owner->as<int>(), G->box_d->as<double>(), G->row_ptr->as<int>(), G->src->as<int>(),
+                       G->shift->as<int>(), G->row_ptr_x->as<int>(), N, rc2, G->src_x->as<int>(),
+                       G->dvec_x->as<float4>(), G->old_idx->as<int>(), G->new_idx->as<int>(), st);
+  launch_prune_rev(G->row_ptr_x->as<int>(), N, G->old_idx->as<int>(), G->new_idx->as<int>(), G->rev->as<int>(),
+                   G->rev_x->as<int>(), st);
+}
+
+int cpt_for(const LayerPlan& L, int C) {
+  if (L.kind == 1) return C <= 128 ? 1 : 2;
+  return C <= 64 ? 1 : C / 64;
+}
+
+void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* energy, float* forces,
+                   double* atom_energy, hipStream_t st) {
+  const Config& c = M->cfg;
+  Allocator* a = &M->alloc;
+  const int N = G->N, S = G->S, C = c.channels, T = c.layers;
+  const long Ecap = G->E;
+  const int NC = (c.lmax + 1) * (c.lmax + 1);
+  const float inv_nu = (float)(1.0 / c.avg_neighbors);
+  const float rc = (float)c.cutoff;
+  const int p_env = c.envelope_p;
+  Workspace& w = M->ws;
+  if (N == 0) {
+    E3MI_HIP(hipMemsetAsync(energy, 0, sizeof(double) * S, st));
+    return;
+  }
+  {
+    ProfScope ps(&M->prof, stage_id(kPrune), st);
+    prune(G, pos, st);
+  }
+  const int* row_ptr = G->row_ptr_x->as<int>();
+  const int* src = G->src_x->as<int>();
+  const float4* dvec = G->dvec_x->as<float4>();
+  const int* species = G->species->as<int>();
+
+  // ---- workspace (grows, never shrinks) ----
+  w.h.resize(T + 1);
+  w.ht.resize(T + 1);
+  w.R.resize(T + 1);
+  ensure(w.h[0], a, sizeof(float) * (size_t)N * C);
+  long a_max = 0, pc_max = 0;
+  for (int t = 1; t <= T; ++t) {
+    const LayerPlan& L = M->plans[t - 1];
+    ensure(w.h[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
+    ensure(w.ht[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
+    ensure(w.R[t], a, sizeof(float) * (size_t)(Ecap + 1) * L.p_used * C);
+    a_max = std::max(a_max, L.a_per_atom);
+    pc_max = std::max(pc_max, (long)L.p_used * C);
+  }
+  ensure(w.A, a, sizeof(float) * (size_t)N * a_max);
+  ensure(w.dR, a, sizeof(float) * (size_t)(Ecap + 1) * pc_max);
+  ensure(w.dY, a, sizeof(float) * 16 * (size_t)(Ecap + 1));
+  ensure(w.g, a, sizeof(float4) * (size_t)(Ecap + 1));
+  ensure(w.dh_a, a, sizeof(float) * (size_t)N * NC * C);
+  ensure(w.dh_b, a, sizeof(float) * (size_t)N * NC * C);
+  ensure(w.dht, a, sizeof(float) * (size_t)N * NC * C);
+  ensure(w.e_atom, a, sizeof(double) * (size_t)N);
+  float* A = w.A->as<float>();
+
+  // ---- forward ----
+  {
+    ProfScope ps(&M->prof, stage_id(kEmbed), st);
+    launch_embed(species, M->emb->as<float>(), w.h[0]->as<float>(), N, C, st);
+  }
+  for (int t = 1; t <= T; ++t) {
+    const LayerPlan& L = M->plans[t - 1];
+    LayerWeights& W = *M->lw[t - 1];
+    const float* hin = w.h[t - 1]->as<float>();
+    float* R = w.R[t]->as<float>();
+    const int PCu = L.p_used * C;
+    {
+      ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
+      launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
+                        W.rad3.as<float>(), L.p_full * C, PCu, R, rc, p_env, st);
+    }
+    TpArgs ta{};
+    ta.lmax = c.lmax;
+    ta.kind = L.kind;
+    ta.cpt = cpt_for(L, C);
+    ta.row_ptr = row_ptr;
+    ta.src = src;
+    ta.dvec = dvec;
+    ta.R = R;
+    ta.r_stride = PCu;
+    ta.h = hin;
+    ta.h_nc = L.nc_in;
+    ta.A = A;
+    ta.N = N;
+    ta.C = C;
+    ta.inv_nu = inv_nu;
+    {
+      ProfScope ps(&M->prof, stage_id(kTpFwd, t), st);
+      launch_tp(0, ta, st);
+    }
+    float* ht = w.ht[t]->as<float>();
+    long gbase = 0;
+    ProfScope ps_mix(&M->prof, stage_id(kMixFwd, t), st);
+    for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
+      const int P3 = L.p_used_l3[l3], g = 2 * l3 + 1;
+      GemmArgs ga{};
+      ga.a0 = RowMap{A + gbase, (long)g * P3 * C, (long)P3 * C, g};
+      ga.b0 = W.mix[l3].as<float>();
+      ga.ldb0 = C;
+      ga.k0 = P3 * C;
+      if (l3 <= L.l1max) {
+        ga.a1 = RowMap{const_cast<float*>(hin) + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, g};
+        ga.b1 = W.self_[l3].as<float>();
+        ga.ldb1 = C;
+        ga.k1 = C;
+      }
+      ga.c = RowMap{ht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
+      ga.M = N * g;
+      ga.Nc = C;
+      launch_gemm(ga, st);
+      gbase += (long)N * g * P3 * C;
+    }
+    ProfScope ps_gate(&M->prof, stage_id(kGateFwd, t), st);
+    launch_gate_fwd(ht, w.h[t]->as<float>(), N, L.nc_out, C, st);
+  }
+  float* dcur = w.dh_a->as<float>();
+  float* dother = w.dh_b->as<float>();
+  {
+    ProfScope ps(&M->prof, stage_id(kReadout), st);
+    launch_readout(w.h[T]->as<float>(), M->plans[T - 1].nc_out, species, M->read1->as<float>(),
+                   M->read2->as<float>(), M->e0->as<float>(), N, C, w.e_atom->as<double>(), dcur, st);
+    launch_energy(w.e_atom->as<double>(), G->off_d->as<int64_t>(), S, energy, st);
+  }
+  if (atom_energy)
+    E3MI_HIP(hipMemcpyAsync(atom_energy, w.e_atom->p, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+
+  // ---- adjoint: dE/dr ----
+  float* dht = w.dht->as<float>();
+  float4* g = w.g->as<float4>();
+  for (int t = T; t >= 1; --t) {
+    const LayerPlan& L = M->plans[t - 1];
+    LayerWeights& W = *M->lw[t - 1];
+    const float* hin = w.h[t - 1]->as<float>();
+    const float* R = w.R[t]->as<float>();
+    const int PCu = L.p_used * C;
+    {
+      ProfScope ps(&M->prof, stage_id(kGateBwd, t), st);
+      launch_gate_bwd(w.ht[t]->as<float>(), dcur, dht, N, L.nc_out, C, st);
+    }
+    ProfScope ps_mixb(&M->prof, stage_id(kMixBwd, t), st);
+    long gbase = 0;
+    for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
+      const int P3 = L.p_used_l3[l3], gg = 2 * l3 + 1;
+      GemmArgs ga{};
+      ga.a0 = RowMap{dht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
+      ga.b0 = W.mixT[l3].as<float>();
+      ga.ldb0 = P3 * C;
+      ga.k0 = C;
+      ga.c = RowMap{A + gbase, (long)gg * P3 * C, (long)P3 * C, gg};
+      ga.M = N * gg;
+      ga.Nc = P3 * C;
+      launch_gemm(ga, st);
+      gbase += (long)N * gg * P3 * C;
+    }
+    if (t > 1) {
+      E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+      for (int l3 = 0; l3 <= std::min(L.l3max_used, L.l1max); ++l3) {
+        const int gg = 2 * l3 + 1;
+        GemmArgs ga{};
+        ga.a0 = RowMap{dht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
+        ga.b0 = W.selfT[l3].as<float>();
+        ga.ldb0 = C;
+        ga.k0 = C;
+        ga.c = RowMap{dother + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, gg};
+        ga.M = N * gg;
+        ga.Nc = C;
+        launch_gemm(ga, st);
+      }
+    }
+    TpArgs ta{};
+    ta.lmax = c.lmax;
+    ta.kind = L.kind;
+    ta.cpt = cpt_for(L, C);
+    ta.row_ptr = row_ptr;
+    ta.src = src;
+    ta.dvec = dvec;
+    ta.R = R;
+    ta.r_stride = PCu;
+    ta.h = hin;
+    ta.h_nc = L.nc_in;
+    ta.dA = A;
+    ta.dR = w.dR->as<float>();
+    ta.dY = w.dY->as<float>();
+    ta.N = N;
+    ta.C = C;
+    ta.inv_nu = inv_nu;
+    {
+      ProfScope ps(&M->prof, stage_id(kTpBwdEdge, t), st);
+      launch_tp(1, ta, st);
+    }
+    {
+      ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
+      launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
+                        W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->as<float>(), w.dY->as<float>(), g,
+                        t != T ? 1 : 0, rc, p_env, st);
+    }
+    if (t > 1) {
+      ta.dh = dother;
+      ta.dh_nc = L.nc_in;
+      ProfScope ps(&M->prof, stage_id(kTpBwdNode, t), st);
+      launch_tp(2, ta, st);
+      std::swap(dcur, dother);
+    }
+  }
+  {
+    ProfScope ps(&M->prof, stage_id(kForces), st);
+    launch_forces(row_ptr, G->rev_x->as<int>(), g, N, forces, st);
+  }
+}
+
+size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
+  const Config& c = M->cfg;
+  const size_t N = (size_t)std::max<int64_t>(n_atoms, 0), E = (size_t)std::max<int64_t>(n_edges, 0) + 1;
+  const size_t C = c.channels, NC = (size_t)(c.lmax + 1) * (c.lmax + 1);
+  size_t b = 0;
+  b += E * (8 + 4 * 3) + E * (4 + 16 + 4 + 4 + 4);   // skin list + pruned list
+  b += N * (4 * 4 + 24 + 8) + 64 * 1024;             // per-atom graph data
+  size_t a_max = 0, pc_max = 0;
+  b += N * C * 4;                                    // embedding
+  for (int t = 1; t <= c.layers; ++t) {
+    const LayerPlan& L = M->plans[t - 1];
+    b += 2 * N * L.nc_out * C * 4 + E * L.p_used * C * 4;
+    a_max = std::max(a_max, (size_t)L.a_per_atom);
+    pc_max = std::max(pc_max, (size_t)L.p_used * C);
+  }
+  b += N * a_max * 4 + E * pc_max * 4 + E * (64 + 16) + 3 * N * NC * C * 4 + N * 8;
+  return b;
+}
+
+e3mi_model* new_model(const char* json, const double* wts, size_t n, int precision, e3mi_alloc_fn al,
+                      e3mi_free_fn fr, void* ctx) {
+  auto M = std::make_unique<e3mi_model>();
+  M->cfg = parse_config(json);
+  const Config& c = M->cfg;
+  E3MI_REQUIRE(precision == E3MI_FP32 || precision == E3MI_BF16_MIX, E3MI_EINVAL, "unknown precision");
+  E3MI_REQUIRE(precision == E3MI_FP32, E3MI_EUNSUPPORTED, "BF16 mode is not available in this build");
+  M->precision = precision;
+  E3MI_REQUIRE(wts, E3MI_EINVAL, "weights are NULL");
+  const size_t expect = weight_count(c);
+  E3MI_REQUIRE(n == expect, E3MI_EINVAL,
+               "weight count " + std::to_string(n) + " does not match the configuration (" + std::to_string(expect) + ")");
+  for (size_t i = 0; i < n; ++i) E3MI_REQUIRE(std::isfinite(wts[i]), E3MI_ENAN, "weights are not finite");
+  M->alloc.alloc = al;
+  M->alloc.free_fn = fr;
+  M->alloc.ctx = ctx;
+  Allocator* a = &M->alloc;
+  const int C = c.channels, H = c.radial_hidden;
+  size_t cur = 0;
+  auto take = [&](size_t cnt) {
+    std::vector<float> v(cnt);
+    for (size_t i = 0; i < cnt; ++i) v[i] = (float)wts[cur + i];
+    cur += cnt;
+    return v;
+  };
+  M->emb = upload_f32(a, take((size_t)c.n_species * C));
+  for (int t = 1; t <= c.layers; ++t) {
+    const LayerPlan L = plan_layer(c, t);
+    M->plans.push_back(L);
+    auto W = std::make_unique<LayerWeights>();
+    for (DevBuf* b : {&W->rad1, &W->rad2, &W->rad2T, &W->rad3, &W->rad3T}) b->a = a;
+    for (int l = 0; l < 4; ++l) W->mix[l].a = W->mixT[l].a = W->self_[l].a = W->selfT[l].a = a;
+    auto up = [&](DevBuf& b, const std::vector<float>& v) {
+      b.ensure(v.size() * sizeof(float));
+      E3MI_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
+    };
+    const auto r1 = take((size_t)c.n_basis * H);
+    const auto r2 = take((size_t)H * H);
+    const auto r3 = take((size_t)H * L.p_full * C);
+    up(W->rad1, r1);
+    up(W->rad2, r2);
+    up(W->rad2T, transpose(r2, H, H));
+    up(W->rad3, r3);
+    // transpose of the used columns only: [p_used C, H]
+    std::vector<float> r3t((size_t)L.p_used * C * H);
+    for (int k = 0; k < H; ++k)
+      for (int col = 0; col < L.p_used * C; ++col) r3t[(size_t)col * H + k] = r3[(size_t)k * L.p_full * C + col];
+    up(W->rad3T, r3t);
+    for (int l3 = 0; l3 <= c.lmax; ++l3) {
+      const int P3 = L.p_full_l3[l3];
+      const auto m = take((size_t)P3 * C * C);
+      if (l3 <= L.l3max_used) {
+        up(W->mix[l3], m);
+        up(W->mixT[l3], transpose(m, P3 * C, C));
+      }
+    }
+    for (int l = 0; l <= L.l1max; ++l) {
+      const auto s = take((size_t)C * C);
+      up(W->self_[l], s);
+      up(W->selfT[l], transpose(s, C, C));
+    }
+    M->lw.push_back(std::move(W));
+  }
+  M->read1 = upload_f32(a, take((size_t)C * c.readout_hidden));
+  M->read2 = upload_f32(a, take((size_t)c.readout_hidden));
+  M->e0 = upload_f32(a, take((size_t)c.n_species));
+  E3MI_REQUIRE(cur == n, E3MI_EINVAL, "internal: weight cursor mismatch");
+  return M.release();
+}
+
+// ---- MD -----------------------------------------------------------------------------------
+
+constexpr double kAccelUnit = 0.009648533;  // angstrom/fs^2 per (eV/angstrom)/amu
+
+void md_rebuild(e3mi_md* D, hipStream_t st) {
+  e3mi_graph* G = D->graph;
+  ProfScope ps(&D->model->prof, stage_id(kGraphBuild), st);
+  launch_wrap(D->x->as<double>(), G->owner->as<int>(), G->box_d->as<double>(), G->pbc_d->as<uint8_t>(), D->N, st);
+  build_lists(G, D->x->as<double>(), st);
+  D->since_build = 0;
+  D->rebuilds++;
+}
+
+e3mi_md* new_md(e3mi_model* M, int S, const int64_t* off, const double* pos, const double* vel,
+                const int32_t* species, const double* masses, const double* cell, const uint8_t* pbc, double cutoff,
+                double skin, int rebuild_every, hipStream_t st) {
+  E3MI_REQUIRE(M && masses, E3MI_EINVAL, "null argument");
+  E3MI_REQUIRE(rebuild_every >= 1, E3MI_EINVAL, "rebuild_every must be >= 1");
+  for (int z = 0; z < M->cfg.n_species; ++z)
+    E3MI_REQUIRE(masses[z] > 0 && std::isfinite(masses[z]), E3MI_EINVAL, "masses must be positive");
+  auto D = std::make_unique<e3mi_md>();
+  D->model = M;
+  D->S = S;
+  D->rebuild_every = rebuild_every;
+  D->cutoff = cutoff;
+  D->skin = skin;
+  Allocator* a = &M->alloc;
+  E3MI_REQUIRE(off && S >= 1, E3MI_EINVAL, "bad atom_offsets");
+  D->N = (int)off[S];
+  E3MI_REQUIRE(D->N == 0 || (pos && vel && species), E3MI_EINVAL, "null state arrays");
+  const size_t n3 = sizeof(double) * 3 * (D->N + 1);
+  D->x = std::make_unique<DevBuf>(a);
+  D->x->ensure(n3);
+  D->v = std::make_unique<DevBuf>(a);
+  D->v->ensure(n3);
+  D->F = std::make_unique<DevBuf>(a);
+  D->F->ensure(sizeof(float) * 3 * (D->N + 1));
+  D->species = std::make_unique<DevBuf>(a);
+  D->species->ensure(sizeof(int) * (D->N + 1));
+  if (D->N) {
+    E3MI_HIP(hipMemcpyAsync(D->x->p, pos, sizeof(double) * 3 * D->N, hipMemcpyDeviceToDevice, st));
+    E3MI_HIP(hipMemcpyAsync(D->v->p, vel, sizeof(double) * 3 * D->N, hipMemcpyDeviceToDevice, st));
+    E3MI_HIP(hipMemcpyAsync(D->species->p, species, sizeof(int) * D->N, hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<double> inv((size_t)M->cfg.n_species);
+  for (int z = 0; z < M->cfg.n_species; ++z) inv[z] = 1.0 / masses[z];
+  D->inv_mass = upload(a, inv.data(), sizeof(double) * inv.size());
+  D->energy = std::make_unique<DevBuf>(a);
+  D->energy->ensure(sizeof(double) * S);
+  D->flag = std::make_unique<DevBuf>(a);
+  D->flag->ensure(sizeof(int));
+  E3MI_HIP(hipMemsetAsync(D->flag->p, 0, sizeof(int), st));
+  D->graph = new_graph(M, S, off, D->x->as<double>(), D->species->as<int>(), cell, pbc, cutoff, skin, st);
+  md_rebuild(D.get(), st);  // wrapped positions, lists relative to them
+  D->rebuilds = 0;
+  energy_forces(M, D->graph, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
+  E3MI_HIP(hipStreamSynchronize(st));
+  return D.release();
+}
+
+void md_step(e3mi_md* D, int n_steps, double dt, double* energy_out, hipStream_t st) {
+  E3MI_REQUIRE(n_steps >= 0 && std::isfinite(dt), E3MI_EINVAL, "bad step arguments");
+  e3mi_graph* G = D->graph;
+  const double hk = 0.5 * dt * kAccelUnit;
+  const double lim = 0.5 * D->skin;
+  for (int s = 0; s < n_steps; ++s) {
+    {
+      ProfScope ps(&D->model->prof, stage_id(kMdUpdate), st);
+      launch_kick(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(), hk,
+                  D->N, st);
+      launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), dt, lim * lim, D->N,
+                   D->flag->as<int>(), st);
+    }
+    if (++D->since_build >= D->rebuild_every) {
+      int fh = 0;
+      E3MI_HIP(hipMemcpyAsync(&fh, D->flag->p, sizeof(int), hipMemcpyDeviceToHost, st));
+      E3MI_HIP(hipStreamSynchronize(st));
+      if (fh) {
+        // an atom travelled more than skin/2 within the interval: rebuild more often
+        D->skin_violations++;
+        D->rebuild_every = std::max(1, D->rebuild_every / 2);
+        E3MI_HIP(hipMemsetAsync(D->flag->p, 0, sizeof(int), st));
+      }
+      md_rebuild(D, st);
+    }
+    energy_forces(D->model, G, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
+    {
+      ProfScope ps(&D->model->prof, stage_id(kMdUpdate), st);
+      launch_kick(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(), hk,
+                  D->N, st);
+    }
+    D->steps++;
+  }
+  if (energy_out)
+    E3MI_HIP(hipMemcpyAsync(energy_out, D->energy->p, sizeof(double) * D->S, hipMemcpyDeviceToDevice, st));
+}
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+}  // namespace
+}  // namespace e3mi
+
+// ---- C ABI -----------------------------------------------------------------------------------
+
+#define E3MI_API_BEGIN \
+  e3mi::set_error(""); \
+  try {
+#define E3MI_API_END                                  \
+  }                                                   \
+  catch (const e3mi::Error& e) {                      \
+    e3mi::set_error(e.what());                        \
+    return e.code;                                    \
+  }                                                   \
+  catch (const std::bad_alloc&) {                     \
+    e3mi::set_error("host allocation failed");        \
+    return E3MI_ENOMEM;                               \
+  }                                                   \
+  catch (const std::exception& e) {                   \
+    e3mi::set_error(e.what());                        \
+    return E3MI_EINVAL;                               \
+  }                                                   \
+  return E3MI_OK;
+
+extern "C" {
+
+int e3mi_weight_count(const char* config_json, size_t* n_weights) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(n_weights, E3MI_EINVAL, "null output");
+  *n_weights = e3mi::weight_count(e3mi::parse_config(config_json));
+  E3MI_API_END
+}
+
+int e3mi_model_create(const char* config_json, const double* weights_host, size_t n_weights, int precision,
+                      e3mi_alloc_fn alloc, e3mi_free_fn free_fn, void* ctx, e3mi_model** out) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(out, E3MI_EINVAL, "null output");
+  *out = nullptr;
+  *out = e3mi::new_model(config_json, weights_host, n_weights, precision, alloc, free_fn, ctx);
+  E3MI_API_END
+}
+
+int e3mi_model_destroy(e3mi_model* model) {
+  E3MI_API_BEGIN
+  delete model;
+  E3MI_API_END
+}
+
+int e3mi_build_graph(e3mi_model* model, int n_structures, const int64_t* atom_offsets, const double* pos,
+                     const int32_t* species, const double* cell, const uint8_t* pbc, double cutoff, double skin,
+                     void* stream, e3mi_graph** out) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(out, E3MI_EINVAL, "null output");
+  *out = nullptr;
+  *out = e3mi::new_graph(model, n_structures, atom_offsets, pos, species, cell, pbc, cutoff, skin,
+                         e3mi::as_stream(stream));
+  E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_graph_destroy(e3mi_graph* graph) {
+  E3MI_API_BEGIN
+  delete graph;
+  E3MI_API_END
+}
+
+int e3mi_graph_info(const e3mi_graph* graph, int64_t* n_atoms, int64_t* n_skin_edges) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(graph, E3MI_EINVAL, "null graph");
+  if (n_atoms) *n_atoms = graph->N;
+  if (n_skin_edges) *n_skin_edges = graph->E;
+  E3MI_API_END
+}
+
+int e3mi_graph_copy_edges(const e3mi_graph* graph, int32_t* row_ptr, int32_t* src, int32_t* shift, int32_t* rev,
+                          void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(graph, E3MI_EINVAL, "null graph");
+  hipStream_t st = e3mi::as_stream(stream);
+  const size_t E = (size_t)graph->E, N = (size_t)graph->N;
+  if (row_ptr)
+    E3MI_HIP(hipMemcpyAsync(row_ptr, graph->row_ptr->p, sizeof(int) * (N + 1), hipMemcpyDeviceToDevice, st));
+  if (src && E) E3MI_HIP(hipMemcpyAsync(src, graph->src->p, sizeof(int) * E, hipMemcpyDeviceToDevice, st));
+  if (rev && E) E3MI_HIP(hipMemcpyAsync(rev, graph->rev->p, sizeof(int) * E, hipMemcpyDeviceToDevice, st));
+  if (shift) e3mi::launch_unpack_shift(graph->shift->as<int>(), (int)E, shift, st);
+  E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_energy_forces(e3mi_model* model, e3mi_graph* graph, const double* pos, double* energy, float* forces,
+                       double* atom_energy, void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model && graph && energy && forces, E3MI_EINVAL, "null argument");
+  E3MI_REQUIRE(graph->model == model, E3MI_EINVAL, "graph was built for another model");
+  E3MI_REQUIRE(graph->N == 0 || pos, E3MI_EINVAL, "null positions");
+  e3mi::energy_forces(model, graph, pos, energy, forces, atom_energy, e3mi::as_stream(stream));
+  E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_graph_last_edge_count(const e3mi_graph* graph, int64_t* n_edges, void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(graph && n_edges, E3MI_EINVAL, "null argument");
+  int e = 0;
+  if (graph->N) {
+    hipStream_t st = e3mi::as_stream(stream);
+    E3MI_HIP(hipMemcpyAsync(&e, graph->row_ptr_x->as<int>() + graph->N, sizeof(int), hipMemcpyDeviceToHost, st));
+    E3MI_HIP(hipStreamSynchronize(st));
+  }
+  *n_edges = e;
+  E3MI_API_END
+}
+
+int e3mi_md_create(e3mi_model* model, int n_structures, const int64_t* atom_offsets, const double* pos,
+                   const double* vel, const int32_t* species, const double* masses, const double* cell,
+                   const uint8_t* pbc, double cutoff, double skin, int rebuild_every, void* stream, e3mi_md** out) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(out, E3MI_EINVAL, "null output");
+  *out = nullptr;
+  *out = e3mi::new_md(model, n_structures, atom_offsets, pos, vel, species, masses, cell, pbc, cutoff, skin,
+                      rebuild_every, e3mi::as_stream(stream));
+  E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_md_step(e3mi_md* md, int n_steps, double dt_fs, double* energy_out, void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(md, E3MI_EINVAL, "null md");
+  e3mi::md_step(md, n_steps, dt_fs, energy_out, e3mi::as_stream(stream));
+  E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_md_state(const e3mi_md* md, double* pos, double* vel, float* forces, void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(md, E3MI_EINVAL, "null md");
+  hipStream_t st = e3mi::as_stream(stream);
+  const size_t n = (size_t)md->N;
+  if (n && pos) E3MI_HIP(hipMemcpyAsync(pos, md->x->p, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+  if (n && vel) E3MI_HIP(hipMemcpyAsync(vel, md->v->p, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+  if (n && forces) E3MI_HIP(hipMemcpyAsync(forces, md->F->p, sizeof(float) * 3 * n, hipMemcpyDeviceToDevice, st));
+  E3MI_API_END
+}
+
+int e3mi_md_stats(const e3mi_md* md, int64_t* steps, int64_t* rebuilds, int64_t* skin_violations) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(md, E3MI_EINVAL, "null md");
+  if (steps) *steps = md->steps;
+  if (rebuilds) *rebuilds = md->rebuilds;
+  if (skin_violations) *skin_violations = md->skin_violations;
+  E3MI_API_END
+}
+
+int e3mi_md_destroy(e3mi_md* md) {
+  E3MI_API_BEGIN
+  if (md) delete md->graph;
+  delete md;
+  E3MI_API_END
+}
+
+size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_edges) {
+  if (!model) return 0;
+  return e3mi::footprint(model, n_atoms, n_edges);
+}
+
+int e3mi_profile_enable(e3mi_model* model, int enable) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
+  model->prof.reset();
+  model->prof.on = enable != 0;
+  E3MI_API_END
+}
+
+int e3mi_profile_query(e3mi_model* model, const char* stage, double* total_ms, int64_t* launches) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model && stage && total_ms && launches, E3MI_EINVAL, "null argument");
+  model->prof.drain();
+  std::string name(stage);
+  int layer = -1;
+  const size_t at = name.find('@');
+  if (at != std::string::npos) {
+    layer = std::atoi(name.c_str() + at + 1);
+    name = name.substr(0, at);
+  }
+  int sid = -1;
+  for (int k = 0; k < e3mi::kNumStages; ++k)
+    if (name == e3mi::kStageNames[k]) sid = k;
+  E3MI_REQUIRE(sid >= 0, E3MI_EINVAL, "unknown stage " + name);
+  double ms = 0.0;
+  int64_t n = 0;
+  for (int l = 0; l < 8; ++l) {
+    if (layer >= 0 && l != layer) continue;
+    const size_t idx = (size_t)sid * 8 + l;
+    if (idx < model->prof.ms.size()) {
+      ms += model->prof.ms[idx];
+      n += model->prof.count[idx];
+    }
+  }
+  *total_ms = ms;
+  *launches = n;
+  E3MI_API_END
+}
+
+const char* e3mi_last_error(void) { return e3mi::g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Shared device helpers of the e3mi HIP kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace e3mi {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+__device__ __forceinline__ float siluf(float x) { return x * sigmoidf(x); }
+// d silu / dx = s + x s (1 - s)
+__device__ __forceinline__ float silu_grad(float x) {
+  const float s = sigmoidf(x);
+  return s * (1.0f + x * (1.0f - s));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Real spherical harmonics of a unit vector, component normalised
+// (sum_m Y_lm^2 = 2l + 1), index l*l + m + l. Only orders <= LMAX are written.
+template <int LMAX>
+__device__ __forceinline__ void real_sh(float x, float y, float z, float* Y) {
+  Y[0] = 1.0f;
+  if constexpr (LMAX >= 1) {
+    constexpr float s3 = 1.7320508075688772f;
+    Y[1] = s3 * y;
+    Y[2] = s3 * z;
+    Y[3] = s3 * x;
+  }
+  if constexpr (LMAX >= 2) {
+    constexpr float s15 = 3.872983346207417f, s5h = 1.118033988749895f;
+    Y[4] = s15 * x * y;
+    Y[5] = s15 * y * z;
+    Y[6] = s5h * (3.0f * z * z - 1.0f);
+    Y[7] = s15 * x * z;
+    Y[8] = 0.5f * s15 * (x * x - y * y);
+  }
+  if constexpr (LMAX >= 3) {
+    constexpr float a358 = 2.091650066335189f, s105 = 10.246950765959598f;
+    constexpr float a218 = 1.620185174601965f, s7h = 1.3228756555322954f;
+    Y[9] = a358 * y * (3.0f * x * x - y * y);
+    Y[10] = s105 * x * y * z;
+    Y[11] = a218 * y * (5.0f * z * z - 1.0f);
+    Y[12] = s7h * z * (5.0f * z * z - 3.0f);
+    Y[13] = a218 * x * (5.0f * z * z - 1.0f);
+    Y[14] = 0.5f * s105 * z * (x * x - y * y);
+    Y[15] = a358 * x * (x * x - 3.0f * y * y);
+  }
+}
+
+// G = sum_c dY[c] * grad P_c(x, y, z), where P_c is the polynomial above
+// (the caller projects out the radial part).
+template <int LMAX>
+__device__ __forceinline__ void real_sh_vjp(float x, float y, float z, const float* dY, float& gx,
+                                            float& gy, float& gz) {
+  gx = gy = gz = 0.0f;
+  if constexpr (LMAX >= 1) {
+    constexpr float s3 = 1.7320508075688772f;
+    gy += s3 * dY[1];
+    gz += s3 * dY[2];
+    gx += s3 * dY[3];
+  }
+  if constexpr (LMAX >= 2) {
+    constexpr float s15 = 3.872983346207417f, s5h = 1.118033988749895f;
+    gx += s15 * (y * dY[4] + z * dY[7] + x * dY[8]);
+    gy += s15 * (x * dY[4] + z * dY[5] - y * dY[8]);
+    gz += s15 * (y * dY[5] + x * dY[7]) + 6.0f * s5h * z * dY[6];
+  }
+  if constexpr (LMAX >= 3) {
+    constexpr float a358 = 2.091650066335189f, s105 = 10.246950765959598f;
+    constexpr float a218 = 1.620185174601965f, s7h = 1.3228756555322954f;
+    gx += a358 * (6.0f * x * y * dY[9] + 3.0f * (x * x - y * y) * dY[15]) + s105 * (y * z * dY[10] + x * z * dY[14]) +
+          a218 * (5.0f * z * z - 1.0f) * dY[13];
+    gy += a358 * (3.0f * (x * x - y * y) * dY[9] - 6.0f * x * y * dY[15]) + s105 * (x * z * dY[10] - y * z * dY[14]) +
+          a218 * (5.0f * z * z - 1.0f) * dY[11];
+    gz += s105 * x * y * dY[10] + 10.0f * a218 * z * (y * dY[11] + x * dY[13]) +
+          s7h * (15.0f * z * z - 3.0f) * dY[12] + 0.5f * s105 * (x * x - y * y) * dY[14];
+  }
+}
+
+// Bessel x polynomial-envelope radial basis B_n(r), n = 1..NB, and optionally
+// its derivative dB_n/dr. Zero for r >= rc.
+template <int NB>
+__device__ __forceinline__ void radial_basis(float r, float rc, int p, float* B, float* dB) {
+  const float x = r / rc;
+  if (!(x < 1.0f)) {
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      B[n] = 0.0f;
+      if (dB) dB[n] = 0.0f;
+    }
+    return;
+  }
+  // u(x) = 1 - (p+1)(p+2)/2 x^p + p(p+2) x^(p+1) - p(p+1)/2 x^(p+2)
+  // u'(x) = -p(p+1)(p+2)/2 x^(p-1) (1-x)^2
+  float xp1 = 1.0f;  // x^(p-1)
+  for (int k = 0; k < p - 1; ++k) xp1 *= x;
+  const float xp = xp1 * x;
+  const float fp = (float)p;
+  const float u = 1.0f - 0.5f * (fp + 1.0f) * (fp + 2.0f) * xp + fp * (fp + 2.0f) * xp * x -
+                  0.5f * fp * (fp + 1.0f) * xp * x * x;
+  const float du_dr = -0.5f * fp * (fp + 1.0f) * (fp + 2.0f) * xp1 * (1.0f - x) * (1.0f - x) / rc;
+  const float pref = sqrtf(2.0f / rc);
+  const float inv_r = 1.0f / r;
+  const float w = 3.14159265358979f / rc;
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    float s, c;
+    sincosf((n + 1) * w * r, &s, &c);
+    const float b = pref * s * inv_r;
+    B[n] = b * u;
+    if (dB) {
+      const float db = pref * ((n + 1) * w * c * inv_r - s * inv_r * inv_r);
+      dB[n] = db * u + b * du_dr;
+    }
+  }
+}
+
+}  // namespace e3mi

@@ -1,0 +1,223 @@
+// Per-atom stages of the interaction:
+//   channel mix + self connection (dense contractions on the FP32 matrix cores)
+//     h~[l3] = A[l3] W[l3] + h[l3] S[l3]        rows (atom, m), columns channels
+//   gate (MACE table of Appendix F: gate_nodes):
+//     h[0] = silu(h~[0]),  h[l>0] = h~[l] sigmoid(h~[0])
+//   embedding h0 = W_emb[z];  readout E_i = w2 . silu(W_r^T h[0]) + E0[z_i]
+//   (Section 5.3 readout with one head), fused with its adjoint dE/dh[0]
+//   energy reduction per structure in FP64, fixed summation order
+//   force assembly F_i = sum_{e in in(i)} (g_e - g_rev(e))
+#include "common.h"
+#include "runtime.h"
+
+namespace e3mi {
+
+namespace {
+
+__device__ __forceinline__ long row_off(const RowMap& m, int r) {
+  return (long)(r / m.g) * m.s_atom + (long)(r % m.g) * m.s_m;
+}
+__device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// 64x64 output tile per workgroup, K in steps of 16 staged through LDS, each
+// wave a 32x32 block on v_mfma_f32_32x32x2f32.
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs a) {
+  __shared__ float As[64][17];
+  __shared__ float Bs[16][65];
+  const int bm = blockIdx.x * 64, bn = blockIdx.y * 64;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+  f32x16 acc = {};
+  for (int op = 0; op < 2; ++op) {
+    const RowMap am = op ? a.a1 : a.a0;
+    const float* __restrict__ B = op ? a.b1 : a.b0;
+    const int ldb = op ? a.ldb1 : a.ldb0;
+    const int K = op ? a.k1 : a.k0;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      {
+        const int row = t >> 2, kq = (t & 3) * 4, gr = bm + row;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gr < a.M && k0 + kq < K) v = *reinterpret_cast<const float4*>(am.base + row_off(am, gr) + k0 + kq);
+        As[row][kq] = v.x;
+        As[row][kq + 1] = v.y;
+        As[row][kq + 2] = v.z;
+        As[row][kq + 3] = v.w;
+      }
+      {
+        const int kr = t >> 4, c4 = (t & 15) * 4, gk = k0 + kr, gc = bn + c4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gk < K && gc < a.Nc) v = *reinterpret_cast<const float4*>(B + (long)gk * ldb + gc);
+        Bs[kr][c4] = v.x;
+        Bs[kr][c4 + 1] = v.y;
+        Bs[kr][c4 + 2] = v.z;
+        Bs[kr][c4 + 3] = v.w;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 2)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[rb + (lane & 31)][kk + (lane >> 5)],
+                                                    Bs[kk + (lane >> 5)][cb + (lane & 31)], acc, 0, 0, 0);
+      __syncthreads();
+    }
+  }
+  const int col = bn + cb + (lane & 31);
+  if (col < a.Nc) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = bm + rb + acc_row(r, lane);
+      if (row < a.M) {
+        float* p = a.c.base + row_off(a.c, row) + col;
+        *p = a.accumulate ? *p + acc[r] : acc[r];
+      }
+    }
+  }
+}
+
+__global__ void k_gate_fwd(const float* __restrict__ ht, float* __restrict__ h, int N, int nc, int C) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)N * C) return;
+  const long i = idx / C;
+  const int k = (int)(idx % C);
+  const float* src = ht + i * nc * C + k;
+  float* dst = h + i * nc * C + k;
+  const float s0 = src[0];
+  const float s = sigmoidf(s0);
+  dst[0] = s0 * s;
+  for (int c = 1; c < nc; ++c) dst[(long)c * C] = src[(long)c * C] * s;
+}
+
+__global__ void k_gate_bwd(const float* __restrict__ ht, const float* __restrict__ dh, float* __restrict__ dht,
+                           int N, int nc, int C) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)N * C) return;
+  const long i = idx / C;
+  const int k = (int)(idx % C);
+  const float* x = ht + i * nc * C + k;
+  const float* g = dh + i * nc * C + k;
+  float* o = dht + i * nc * C + k;
+  const float s0 = x[0];
+  const float s = sigmoidf(s0);
+  float acc = 0.0f;
+  for (int c = 1; c < nc; ++c) {
+    acc += g[(long)c * C] * x[(long)c * C];
+    o[(long)c * C] = g[(long)c * C] * s;
+  }
+  o[0] = g[0] * silu_grad(s0) + acc * s * (1.0f - s);
+}
+
+__global__ void k_embed(const int* __restrict__ species, const float* __restrict__ emb, float* __restrict__ h0, int N,
+                        int C) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)N * C) return;
+  const long i = idx / C;
+  const int k = (int)(idx % C);
+  h0[idx] = emb[(long)species[i] * C + k];
+}
+
+// One wave per atom; readout_hidden = 16.
+__global__ void __launch_bounds__(256) k_readout(const float* __restrict__ h, int nc, const int* __restrict__ species,
+                                                 const float* __restrict__ Wr, const float* __restrict__ w2,
+                                                 const float* __restrict__ e0, int N, int C,
+                                                 double* __restrict__ e_atom, float* __restrict__ dh) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;
+  const float* hi = h + (long)i * nc * C;
+  float pre[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) pre[q] = 0.0f;
+  for (int k = lane; k < C; k += 64) {
+    const float x = hi[k];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pre[q] += x * Wr[k * 16 + q];
+  }
+  float e = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    pre[q] = wave_sum(pre[q]);
+    e += w2[q] * siluf(pre[q]);
+  }
+  if (lane == 0) e_atom[i] = (double)e + (double)e0[species[i]];
+  float gq[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) gq[q] = w2[q] * silu_grad(pre[q]);
+  for (int k = lane; k < C; k += 64) {
+    float s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += Wr[k * 16 + q] * gq[q];
+    dh[(long)i * C + k] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_energy(const double* __restrict__ e_atom, const int64_t* __restrict__ off,
+                                                double* __restrict__ energy) {
+  __shared__ double red[256];
+  const int s = blockIdx.x;
+  const int64_t a = off[s], b = off[s + 1];
+  double acc = 0.0;
+  for (int64_t i = a + threadIdx.x; i < b; i += 256) acc += e_atom[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) energy[s] = red[0];
+}
+
+__global__ void k_forces(const int* __restrict__ row_ptr, const int* __restrict__ rev, const float4* __restrict__ g,
+                         int N, float* __restrict__ F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  const int b = row_ptr[i + 1];
+  for (int e = row_ptr[i]; e < b; ++e) {
+    const int re = rev[e];
+    const float4 a = g[e];
+    const float4 r = re >= 0 ? g[re] : make_float4(0.f, 0.f, 0.f, 0.f);
+    fx += a.x - r.x;
+    fy += a.y - r.y;
+    fz += a.z - r.z;
+  }
+  F[3 * i] = fx;
+  F[3 * i + 1] = fy;
+  F[3 * i + 2] = fz;
+}
+
+inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
+
+}  // namespace
+
+void launch_gemm(const GemmArgs& a, hipStream_t st) {
+  if (a.M == 0 || a.Nc == 0) return;
+  if ((a.k0 % 4) || (a.k1 % 4) || (a.Nc % 4) || (a.ldb0 % 4) || (a.k1 && (a.ldb1 % 4)))
+    throw Error(E3MI_EUNSUPPORTED, "GEMM dimensions must be multiples of 4");
+  dim3 grid(blocks(a.M, 64), blocks(a.Nc, 64));
+  k_gemm<<<grid, 256, 0, st>>>(a);
+}
+void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st) {
+  if (N == 0) return;
+  k_gate_fwd<<<blocks((long)N * C, 256), 256, 0, st>>>(ht, h, N, nc, C);
+}
+void launch_gate_bwd(const float* ht, const float* dh, float* dht, int N, int nc, int C, hipStream_t st) {
+  if (N == 0) return;
+  k_gate_bwd<<<blocks((long)N * C, 256), 256, 0, st>>>(ht, dh, dht, N, nc, C);
+}
+void launch_embed(const int* species, const float* emb, float* h0, int N, int C, hipStream_t st) {
+  if (N == 0) return;
+  k_embed<<<blocks((long)N * C, 256), 256, 0, st>>>(species, emb, h0, N, C);
+}
+void launch_readout(const float* h, int nc, const int* species, const float* Wr, const float* w2, const float* e0,
+                    int N, int C, double* e_atom, float* dh, hipStream_t st) {
+  if (N == 0) return;
+  k_readout<<<blocks((long)N * 64, 256), 256, 0, st>>>(h, nc, species, Wr, w2, e0, N, C, e_atom, dh);
+}
+void launch_energy(const double* e_atom, const int64_t* off, int S, double* energy, hipStream_t st) {
+  k_energy<<<S, 256, 0, st>>>(e_atom, off, energy);
+}
+void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st) {
+  if (N == 0) return;
+  k_forces<<<blocks(N, 256), 256, 0, st>>>(row_ptr, rev, g, N, F);
+}
+
+}  // namespace e3mi

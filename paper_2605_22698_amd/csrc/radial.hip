@@ -1,0 +1,245 @@
+// Radial MLP per edge (NequIP table of Appendix F: 8 Bessel functions, a
+// radial net of two hidden layers of 64 with swish, polynomial envelope; one
+// output weight per (path, channel), no biases):
+//   B = bessel(r) u(r/rc);  H1 = silu(B W1);  H2 = silu(H1 W2);  R = H2 W3
+// and its adjoint, which ends in the geometric gradient of every edge:
+//   dr = dR . dR/dr  (through the MLP and the basis),
+//   g_e = dE/dd_e = dr d^ + (I - d^ d^T)/r grad_Y(d^) . dY
+//
+// One workgroup (4 waves) owns a tile of 64 consecutive edges. The 64x64
+// hidden layer and the 64 x (P C) output layer are dense contractions and run
+// on the FP32 matrix cores (v_mfma_f32_32x32x2f32: each wave owns 32x32
+// output blocks). The edge count is read on the device (row_ptr_x[N]); the
+// grid is sized for the skin-list capacity and surplus tiles exit at once.
+//
+// MFMA 32x32x2 operand layout (wave64): lane l supplies A[l%32][l/32] and
+// B[l/32][l%32]; accumulator register r of lane l holds
+// D[8 (r/4) + 4 (l/32) + r%4][l%32].
+#include "common.h"
+#include "runtime.h"
+
+namespace e3mi {
+namespace {
+
+constexpr int kTile = 64;
+constexpr int kH = 64;  // hidden width
+constexpr int kLd = 65; // padded LDS row
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// pre1 = B W1 (K = NB) on the vector ALU; 256 threads x 16 outputs.
+template <int NB>
+__device__ __forceinline__ void layer1(const float (*Bs)[NB + 1], const float* __restrict__ W1, float (*P1)[kLd],
+                                       float (*H1)[kLd]) {
+  const int t = threadIdx.x;
+  const int row = t >> 2, cb = (t & 3) * 16;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    float s = 0.0f;
+#pragma unroll
+    for (int n = 0; n < NB; ++n) s += Bs[row][n] * W1[n * kH + cb + j];
+    if (P1) P1[row][cb + j] = s;
+    H1[row][cb + j] = siluf(s);
+  }
+}
+
+// acc (32x32 block of the wave) = X[rb:rb+32, :] * W[:, cb:cb+32], K = 64,
+// X from LDS, W row-major [64][ldw] from global memory.
+__device__ __forceinline__ f32x16 block_64(const float (*X)[kLd], int rb, const float* __restrict__ W, int ldw, int cb) {
+  const int lane = threadIdx.x & 63;
+  f32x16 acc = {};
+#pragma unroll 8
+  for (int kk = 0; kk < kH; kk += 2) {
+    const float a = X[rb + (lane & 31)][kk + (lane >> 5)];
+    const float b = W[(kk + (lane >> 5)) * ldw + cb + (lane & 31)];
+    acc = mfma32(a, b, acc);
+  }
+  return acc;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
+                                                    int N, const float* __restrict__ W1, const float* __restrict__ W2,
+                                                    const float* __restrict__ W3, int ld3, int PC,
+                                                    float* __restrict__ R, float rc, int p) {
+  __shared__ float Bs[kTile][NB + 1];
+  __shared__ float H[kTile][kLd];
+  const int E = row_ptr_x[N];
+  const int e0 = blockIdx.x * kTile;
+  if (e0 >= E) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t < kTile) {
+    const int e = e0 + t;
+    const float r = e < E ? dvec[e].w : rc;
+    float b[NB];
+    radial_basis<NB>(r, rc, p, b, nullptr);
+#pragma unroll
+    for (int n = 0; n < NB; ++n) Bs[t][n] = b[n];
+  }
+  __syncthreads();
+  layer1<NB>(Bs, W1, nullptr, H);
+  __syncthreads();
+  {
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+    const f32x16 acc = block_64(H, rb, W2, kH, cb);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) H[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(acc[r]);
+  }
+  __syncthreads();
+  for (int cc = w * 32; cc < PC; cc += 128) {
+    f32x16 a0 = {}, a1 = {};
+#pragma unroll 8
+    for (int kk = 0; kk < kH; kk += 2) {
+      const float b = W3[(kk + (lane >> 5)) * ld3 + cc + (lane & 31)];
+      a0 = mfma32(H[lane & 31][kk + (lane >> 5)], b, a0);
+      a1 = mfma32(H[32 + (lane & 31)][kk + (lane >> 5)], b, a1);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = acc_row(r, lane);
+      const int ea = e0 + row, eb = e0 + 32 + row;
+      if (ea < E) R[(long)ea * PC + cc + (lane & 31)] = a0[r];
+      if (eb < E) R[(long)eb * PC + cc + (lane & 31)] = a1[r];
+    }
+  }
+}
+
+template <int NB, int LMAX>
+__global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
+                                                    int N, const float* __restrict__ W1, const float* __restrict__ W2,
+                                                    const float* __restrict__ W2T, const float* __restrict__ W3T,
+                                                    int PC, const float* __restrict__ dR, const float* __restrict__ dY,
+                                                    float4* __restrict__ g, int accumulate, float rc, int p) {
+  __shared__ float Bs[kTile][NB + 1];
+  __shared__ float dBs[kTile][NB + 1];
+  __shared__ float P1[kTile][kLd];
+  __shared__ float P2[kTile][kLd];
+  __shared__ float X[kTile][kLd];
+  __shared__ float Ds[kTile][33];
+  const int E = row_ptr_x[N];
+  const int e0 = blockIdx.x * kTile;
+  if (e0 >= E) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+  if (t < kTile) {
+    const int e = e0 + t;
+    const float r = e < E ? dvec[e].w : rc;
+    float b[NB], db[NB];
+    radial_basis<NB>(r, rc, p, b, db);
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      Bs[t][n] = b[n];
+      dBs[t][n] = db[n];
+    }
+  }
+  __syncthreads();
+  layer1<NB>(Bs, W1, P1, X);  // P1 = pre1, X = H1
+  __syncthreads();
+  {
+    const f32x16 acc = block_64(X, rb, W2, kH, cb);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) P2[rb + acc_row(r, lane)][cb + (lane & 31)] = acc[r];
+  }
+  // dH2 = dR W3^T, K = PC, dR staged through LDS in chunks of 32 columns.
+  f32x16 acc = {};
+  for (int kc = 0; kc < PC; kc += 32) {
+    __syncthreads();
+    {
+      const int row = t >> 2, c8 = (t & 3) * 8;
+      const int e = e0 + row;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) Ds[row][c8 + q] = e < E ? dR[(long)e * PC + kc + c8 + q] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 32; kk += 2) {
+      const float a = Ds[rb + (lane & 31)][kk + (lane >> 5)];
+      const float b = W3T[(kc + kk + (lane >> 5)) * kH + cb + (lane & 31)];
+      acc = mfma32(a, b, acc);
+    }
+  }
+  __syncthreads();
+  // dpre2 = dH2 * silu'(pre2) -> X
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
+    X[row][col] = acc[r] * silu_grad(P2[row][col]);
+  }
+  __syncthreads();
+  {
+    // dH1 = dpre2 W2^T ; dpre1 = dH1 * silu'(pre1) -> P2
+    const f32x16 a2 = block_64(X, rb, W2T, kH, cb);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
+      P2[row][col] = a2[r] * silu_grad(P1[row][col]);
+    }
+  }
+  __syncthreads();
+  if (t < kTile) {
+    const int e = e0 + t;
+    if (e < E) {
+      float dr = 0.0f;
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        float s = 0.0f;
+        for (int q = 0; q < kH; ++q) s += P2[t][q] * W1[n * kH + q];
+        dr += s * dBs[t][n];
+      }
+      const float4 d = dvec[e];
+      const float ir = 1.0f / d.w;
+      const float nx = d.x * ir, ny = d.y * ir, nz = d.z * ir;
+      float gx = dr * nx, gy = dr * ny, gz = dr * nz;
+      if (dY) {
+        float dy[16];
+#pragma unroll
+        for (int q = 0; q < (LMAX + 1) * (LMAX + 1); ++q) dy[q] = dY[(long)e * 16 + q];
+        float Gx, Gy, Gz;
+        real_sh_vjp<LMAX>(nx, ny, nz, dy, Gx, Gy, Gz);
+        const float dot = Gx * nx + Gy * ny + Gz * nz;
+        gx += (Gx - dot * nx) * ir;
+        gy += (Gy - dot * ny) * ir;
+        gz += (Gz - dot * nz) * ir;
+      }
+      if (accumulate) {
+        const float4 o = g[e];
+        g[e] = make_float4(o.x + gx, o.y + gy, o.z + gz, 0.0f);
+      } else {
+        g[e] = make_float4(gx, gy, gz, 0.0f);
+      }
+    }
+  }
+}
+
+inline int tiles(long n) { return (int)((n + kTile - 1) / kTile); }
+
+}  // namespace
+
+void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
+                       const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, hipStream_t st) {
+  if (e_cap == 0) return;
+  if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
+  if (PC % 32) throw Error(E3MI_EUNSUPPORTED, "paths x channels must be a multiple of 32");
+  k_radial_fwd<8><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p);
+}
+
+void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
+                       const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
+                       const float* dY, float4* g, int accumulate, float rc, int p, hipStream_t st) {
+  if (e_cap == 0) return;
+  if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
+  if (lmax == 3)
+    k_radial_bwd<8, 3><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate,
+                                                     rc, p);
+  else if (lmax == 2)
+    k_radial_bwd<8, 2><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate,
+                                                     rc, p);
+  else
+    throw Error(E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
+}
+
+}  // namespace e3mi

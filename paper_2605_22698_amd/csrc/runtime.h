@@ -1,0 +1,260 @@
+// Host-side runtime pieces shared by the library's translation units:
+// error type, allocator wrapper, device buffers, and the launchers each
+// kernel file exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/e3mi.h"
+
+namespace e3mi {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define E3MI_HIP(call)                                                                       \
+  do {                                                                                       \
+    hipError_t e3mi_err_ = (call);                                                           \
+    if (e3mi_err_ != hipSuccess)                                                             \
+      throw ::e3mi::Error(E3MI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e3mi_err_)); \
+  } while (0)
+
+#define E3MI_REQUIRE(cond, code, msg)                  \
+  do {                                                 \
+    if (!(cond)) throw ::e3mi::Error((code), (msg));   \
+  } while (0)
+
+struct Allocator {
+  e3mi_alloc_fn alloc = nullptr;
+  e3mi_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+  void* get(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (alloc) {
+      p = alloc(bytes, ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (!p) throw Error(E3MI_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    if (free_fn) {
+      free_fn(p, ctx);
+    } else if (!alloc) {
+      (void)hipFree(p);
+    }
+  }
+};
+
+// A device allocation that can only grow. Contents are not preserved on growth.
+struct DevBuf {
+  Allocator* a = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(Allocator* al) : a(al) {}
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p && a) a->put(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void* ensure(size_t n) {
+    if (n > bytes || !p) {
+      release();
+      p = a->get(n);
+      bytes = n == 0 ? 256 : n;
+    }
+    return p;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+
+// Optional per-stage timing with HIP events recorded on the launch stream.
+struct Profiler {
+  struct Pending {
+    int stage;
+    hipEvent_t a, b;
+  };
+  bool on = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<double> ms;
+  std::vector<int64_t> count;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    E3MI_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void drain() {
+    for (auto& p : pending) {
+      E3MI_HIP(hipEventSynchronize(p.b));
+      float t = 0.f;
+      E3MI_HIP(hipEventElapsedTime(&t, p.a, p.b));
+      if ((int)ms.size() <= p.stage) {
+        ms.resize(p.stage + 1, 0.0);
+        count.resize(p.stage + 1, 0);
+      }
+      ms[p.stage] += t;
+      count[p.stage] += 1;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    drain();
+    ms.assign(ms.size(), 0.0);
+    count.assign(count.size(), 0);
+  }
+  ~Profiler() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct ProfScope {
+  Profiler* p;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(Profiler* prof, int s, hipStream_t stream) : p(prof), stage(s), st(stream) {
+    if (p && p->on) {
+      a = p->get();
+      E3MI_HIP(hipEventRecord(a, st));
+    }
+  }
+  ~ProfScope() {
+    if (a) {
+      hipEvent_t b = p->get();
+      if (hipEventRecord(b, st) == hipSuccess) p->pending.push_back({stage, a, b});
+    }
+  }
+};
+
+// Per-structure cell-list plan (orthorhombic periodic axes or open axes).
+struct GridPlan {
+  double lo[3];      // grid origin: 0 on periodic axes, bounding-box minimum on open axes
+  double len[3];     // box length on periodic axes
+  double inv_cw[3];  // 1 / cell width
+  int nb[3];         // cells per axis
+  int periodic[3];
+  int cell_base;     // index of the structure's first cell in the global cell array
+  int pad;
+};
+
+// ---- launchers exported by graph.hip -------------------------------------
+void launch_owner(const int64_t* offsets, int S, int* owner, hipStream_t st);
+void launch_bbox(const double* pos, const int64_t* offsets, int S, double* bbox, hipStream_t st);
+void launch_exclusive_scan(const int* in, int* out, int n, hipStream_t st);
+void launch_bin(const double* pos, const int* owner, const GridPlan* plan, int N, int* atom_cell,
+                int* wrap, int* cell_count, hipStream_t st);
+void launch_bin_fill(const int* atom_cell, const int* cell_start, int N, int* cell_fill,
+                     int* cell_atoms, hipStream_t st);
+void launch_edges(bool fill, const double* pos, const int* owner, const GridPlan* plan,
+                  const int* atom_cell, const int* wrap, const int* cell_start, const int* cell_atoms,
+                  const int* row_ptr, int N, double rc2, int* count, uint64_t* keys, int* err,
+                  hipStream_t st);
+void launch_sort_rows(const int* row_ptr, int N, uint64_t* keys, int* src, int* shift, hipStream_t st);
+void launch_reverse(const int* row_ptr, const uint64_t* keys, int N, int* rev, int* err, hipStream_t st);
+void launch_unpack_shift(const int* shift_packed, int E, int* shift3, hipStream_t st);
+void launch_prune_count(const double* pos, const int* owner, const double* box, const int* row_ptr,
+                        const int* src, const int* shift, int N, double rc2, int* cnt, hipStream_t st);
+void launch_prune_compact(const double* pos, const int* owner, const double* box, const int* row_ptr,
+                          const int* src, const int* shift, const int* row_ptr_x, int N, double rc2,
+                          int* src_x, float4* dvec_x, int* old_idx, int* new_idx, hipStream_t st);
+void launch_prune_rev(const int* row_ptr_x, int N, const int* old_idx, const int* new_idx,
+                      const int* rev_skin, int* rev_x, hipStream_t st);
+
+// ---- tensor product (tp.hip) ---------------------------------------------------
+struct TpArgs {
+  int lmax, kind, cpt;
+  const int* row_ptr;
+  const int* src;
+  const float4* dvec;
+  const float* R;
+  int r_stride;
+  const float* h;
+  int h_nc;
+  float* A;
+  const float* dA;
+  float* dR;
+  float* dY;
+  float* dh;
+  int dh_nc;
+  int N, C;
+  float inv_nu;
+};
+// which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...)
+void launch_tp(int which, const TpArgs& a, hipStream_t st);
+
+// ---- per-atom stages (node.hip) -----------------------------------------------------
+// Rows of a matrix whose row r lives at base + (r / g) * s_atom + (r % g) * s_m
+// (an atom block of g = 2l + 1 rows); the row itself is contiguous.
+struct RowMap {
+  float* base;
+  long s_atom;
+  long s_m;
+  int g;
+};
+// C[M x Nc] (+)= A0[M x k0] B0[k0 x Nc] + A1[M x k1] B1[k1 x Nc]; B row-major.
+struct GemmArgs {
+  RowMap a0;
+  const float* b0;
+  int ldb0, k0;
+  RowMap a1;  // optional second product (k1 = 0: none)
+  const float* b1;
+  int ldb1, k1;
+  RowMap c;
+  int M, Nc, accumulate;
+};
+void launch_gemm(const GemmArgs& a, hipStream_t st);
+void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st);
+void launch_gate_bwd(const float* ht, const float* dh, float* dht, int N, int nc, int C, hipStream_t st);
+void launch_embed(const int* species, const float* emb, float* h0, int N, int C, hipStream_t st);
+void launch_readout(const float* h, int nc, const int* species, const float* Wr, const float* w2, const float* e0,
+                    int N, int C, double* e_atom, float* dh, hipStream_t st);
+void launch_energy(const double* e_atom, const int64_t* off, int S, double* energy, hipStream_t st);
+void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st);
+
+// ---- radial MLP (radial.hip) ---------------------------------------------------------
+void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
+                       const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, hipStream_t st);
+void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
+                       const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
+                       const float* dY, float4* g, int accumulate, float rc, int p, hipStream_t st);
+
+// ---- MD (md.hip) -----------------------------------------------------------------------
+void launch_kick(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa, int N,
+                 hipStream_t st);
+void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N, int* flag,
+                  hipStream_t st);
+void launch_wrap(double* x, const int* owner, const double* box, const uint8_t* pbc, int N, hipStream_t st);
+void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st);
+void launch_rekey(const int* src, const int* shift, int E, uint64_t* keys, hipStream_t st);
+
+}  // namespace e3mi

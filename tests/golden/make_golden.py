@@ -1,0 +1,42 @@
+"""Write the stored oracle results the GPU parity tests compare against.
+
+Calls only the seeded generators and the FP64 oracle; no value comes from the
+HIP library. Rerun after any change of the oracle's arithmetic or the inputs:
+
+    python tests/golden/make_golden.py [name ...]
+
+single_3000.npz  3,000-atom periodic box at 0.1 atoms/A^3 (jittered lattice,
+                 0.3 A noise), 4 species, r_c 5 A, l_max 3, 128 channels,
+                 2 layers: per-structure energy, per-atom energies, forces.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth  # noqa: E402
+from oracle import model as om  # noqa: E402
+
+
+def single_3000():
+    cfg, b = synth.single_config()
+    w = synth.model_weights(cfg, 2)
+    m = om.Model(cfg, w)
+    E, F, Ei = om.energy_forces(m, b, edge_chunk=8192)
+    np.savez_compressed(os.path.join(HERE, "single_3000.npz"), energy=E, forces=F, atom_energy=Ei,
+                        n_atoms=b.n_atoms)
+
+
+JOBS = {"single_3000": single_3000}
+
+if __name__ == "__main__":
+    torch.set_num_threads(os.cpu_count() or 1)
+    for name in sys.argv[1:] or list(JOBS):
+        t = time.time()
+        JOBS[name]()
+        print(f"{name}: {time.time() - t:.1f} s", flush=True)
