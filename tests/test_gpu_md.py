@@ -1,0 +1,87 @@
+"""GPU velocity-Verlet MD vs the oracle integrator, plus NVE conservation and
+packing invariance of trajectories."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import md as omd
+from oracle import model as om
+from tests.gpu_util import device, model, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_gpu(m, b, vel, n_steps, dt, rebuild_every=20, skin=1.0):
+    import torch
+    import paper_2605_22698_amd as e3
+    d = device()
+    cfg = synth.ModelConfig.from_json(m.config_json)
+    md = e3.MD(m, b.offsets, torch.tensor(b.pos, dtype=torch.float64, device=d),
+               torch.tensor(vel, dtype=torch.float64, device=d), torch.tensor(b.species, dtype=torch.int32, device=d),
+               synth.SPECIES_MASS[:cfg.n_species], b.cell, b.pbc, cfg.cutoff, skin, rebuild_every)
+    E = torch.empty(b.n_structures, dtype=torch.float64, device=d)
+    md.step(n_steps, dt, E)
+    x, v, F = md.state()
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), v.cpu().numpy(), E.cpu().numpy(), md
+
+
+def _min_image(d, b):
+    owner = np.repeat(np.arange(b.n_structures), np.diff(b.offsets))
+    L = b.cell[owner][:, [0, 1, 2], [0, 1, 2]]
+    per = b.pbc[owner].astype(bool)
+    return np.where(per, d - np.round(d / np.where(per, L, 1.0)) * L, d)
+
+
+@pytest.mark.parametrize("rebuild_every", [3, 20])
+def test_trajectory_matches_oracle(rebuild_every):
+    cfg = synth.ModelConfig(lmax=2, channels=32, layers=2, n_species=4, cutoff=5.0, avg_neighbors=10.0)
+    b = synth.jittered_lattice(40, 0.1, 0.3, 4, np.random.default_rng(51))
+    vel = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(52))
+    m = model(cfg, 7)
+    say(f"md parity rebuild_every={rebuild_every}")
+    x, v, E, _ = _run_gpu(m, b, vel, 12, 0.5, rebuild_every=rebuild_every)
+    om_m = om.Model(cfg, synth.model_weights(cfg, 7))
+
+    def force(xx):
+        Es, F, _ = om.energy_forces(om_m, synth.Batch(xx, b.species, b.cell, b.pbc, b.offsets))
+        return Es, F
+    xr, vr, Er = omd.velocity_verlet(force, b.pos, vel, synth.SPECIES_MASS[b.species], 0.5, 12)
+    assert np.abs(_min_image(x - xr, b)).max() < 1e-9
+    assert np.abs(v - vr).max() < 1e-9
+    assert abs(E[0] - Er[-1][0]) <= 1e-5 * abs(Er[-1][0])
+
+
+def test_nve_energy_conservation():
+    import torch
+    cfg, b = synth.single_config(n=600)
+    vel = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(53))
+    m = model(cfg, 2)
+    mass = synth.SPECIES_MASS[b.species]
+    x0, v0, E0, md = _run_gpu(m, b, vel, 0, 0.5)
+    tot0 = E0[0] + omd.kinetic_energy(v0, mass)
+    d = device()
+    E = torch.empty(1, dtype=torch.float64, device=d)
+    totals = []
+    for _ in range(10):
+        md.step(40, 0.5, E)
+        _, v, _ = md.state()
+        torch.cuda.synchronize()
+        totals.append(E.item() + omd.kinetic_energy(v.cpu().numpy(), mass))
+    ke = omd.kinetic_energy(v0, mass)
+    drift = max(abs(t - tot0) for t in totals)
+    say(f"NVE 400 steps: max |dE_total| {drift:.3e} eV (KE {ke:.3f} eV)")
+    assert drift < 1e-4 * ke
+    steps, rebuilds, violations = md.stats()
+    assert steps == 400 and rebuilds == 20 and violations == 0
+
+
+def test_packed_trajectories_equal_single():
+    cfg, b, _, _ = synth.differentiation_config(4, 30, 80)
+    vel = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(54))
+    m = model(cfg, 3)
+    x, v, E, _ = _run_gpu(m, b, vel, 25, 0.5, rebuild_every=10, skin=0.8)
+    for s in (1, 2):
+        a, z = b.offsets[s], b.offsets[s + 1]
+        xs, vs, Es, _ = _run_gpu(m, b.structure(s), vel[a:z], 25, 0.5, rebuild_every=10, skin=0.8)
+        assert np.array_equal(xs, x[a:z]) and np.array_equal(vs, v[a:z]) and Es[0] == E[s]
