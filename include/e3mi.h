@@ -69,7 +69,7 @@ typedef void* (*e3mi_alloc_fn)(size_t bytes, void* ctx);
 typedef void (*e3mi_free_fn)(void* ptr, void* ctx);
 
 /* Model configuration (JSON object, all keys required):
- *   lmax (2 or 3), channels (C, a multiple of 32), layers (T >= 1),
+ *   lmax (2 or 3), channels (C: 32, 64 or 128), layers (1 <= T <= 8),
  *   n_species, cutoff (r_c, angstrom), avg_neighbors (nu, the constant the
  *   neighbour sum is divided by), n_basis (8), envelope_p, radial_hidden (64),
  *   readout_hidden (16).
@@ -139,6 +139,24 @@ int e3mi_graph_copy_edges(const e3mi_graph* graph, int32_t* row_ptr, int32_t* sr
  * NULL. Asynchronous on `stream`. */
 int e3mi_energy_forces(e3mi_model* model, e3mi_graph* graph, const double* pos, double* energy,
                        float* forces, double* atom_energy, void* stream);
+
+/* Gradient of a loss L(E, F) with respect to the weights, given the upstream
+ * gradients grad_energy = dL/dE (device FP64 [S]) and grad_forces = dL/dF
+ * (device FP32 [N, 3]): writes dL/dtheta = sum_s dL/dE_s dE_s/dtheta +
+ * sum_i dL/dF_i . dF_i/dtheta to grad_weights (device FP64, n_weights, the
+ * layout of the weight vector; entries the energy does not depend on are 0).
+ * Training on energies and forces (Appendix F recipe; §5.2 differentiates
+ * forces for Hessian-row labels) needs this second-order term: it is formed
+ * as minus the weight gradient of the directional derivative of E along
+ * dL/dF, by a tangent pass and a reverse pass over primal and tangent values.
+ * Recomputes the forward pass; does not need a preceding energy_forces call.
+ * Asynchronous on `stream`. */
+int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, const double* grad_energy,
+                    const float* grad_forces, double* grad_weights, void* stream);
+
+/* Replace the weights (host FP64, same configuration and layout as at
+ * creation), e.g. after an optimiser step. Synchronises the device first. */
+int e3mi_model_set_weights(e3mi_model* model, const double* weights_host, size_t n_weights);
 
 /* Number of edges inside the model cutoff at the last energy_forces call on
  * this graph. Synchronises `stream`. */

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import BF16_MIX, FP32, E3miError, check, lib, ptr
 
-__all__ = ["Model", "Graph", "MD", "E3miError", "FP32", "BF16_MIX", "weight_count"]
+__all__ = ["Model", "Graph", "MD", "E3miError", "FP32", "BF16_MIX", "weight_count", "energy_forces"]
 
 
 def _stream(stream=None) -> int:
@@ -71,6 +71,24 @@ class Model:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         check(lib().e3mi_profile_query(self.handle, stage.encode(), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def set_weights(self, weights) -> None:
+        """Replace the weights (FP64 vector in the documented layout; any device)."""
+        w = weights.detach().to("cpu", dtype=__import__("torch").float64).contiguous().numpy() \
+            if hasattr(weights, "detach") else np.ascontiguousarray(weights, dtype=np.float64)
+        check(lib().e3mi_model_set_weights(self.handle, w.ctypes.data, w.size))
+
+    def param_grad(self, graph: "Graph", pos, grad_energy, grad_forces, stream=None):
+        """dL/dweights (FP64 device vector) for upstream dL/dE [S] and dL/dF [N,3]."""
+        import torch
+        n = weight_count(self.config_json)
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        gE = grad_energy.to(self.device, torch.float64).contiguous()
+        gF = grad_forces.to(self.device, torch.float32).contiguous()
+        pos = pos.contiguous()
+        check(lib().e3mi_param_grad(self.handle, graph.handle, ptr(pos), ptr(gE), ptr(gF), ptr(out),
+                                    _stream(stream)))
+        return out
 
     def footprint_bytes(self, n_atoms: int, n_edges: int) -> int:
         return int(lib().e3mi_footprint_bytes(self.handle, n_atoms, n_edges))
@@ -198,3 +216,49 @@ class MD:
             self.close()
         except Exception:
             pass
+
+
+def _energy_forces_function():
+    import torch
+
+    class EnergyForces(torch.autograd.Function):
+        """(E, F) of a packed batch as a differentiable function of the weights.
+
+        forward: the library's energy + forces; backward: its parameter-gradient
+        pass (second order through F). Positions are inputs, not differentiated.
+        """
+
+        @staticmethod
+        def forward(ctx, weights, pos, model, graph):
+            key = (weights.data_ptr(), weights._version, weights.device)
+            if getattr(model, "_weights_key", None) != key:
+                model.set_weights(weights)
+                model._weights_key = key
+            E, F, _ = model.energy_forces(graph, pos)
+            ctx.model, ctx.graph = model, graph
+            ctx.save_for_backward(pos)
+            return E, F
+
+        @staticmethod
+        def backward(ctx, gE, gF):
+            (pos,) = ctx.saved_tensors
+            m = ctx.model
+            if gE is None:
+                gE = torch.zeros(ctx.graph.n_structures, dtype=torch.float64, device=m.device)
+            if gF is None:
+                gF = torch.zeros((ctx.graph.n_atoms, 3), dtype=torch.float32, device=m.device)
+            g = m.param_grad(ctx.graph, pos, gE, gF)
+            return g, None, None, None
+
+    return EnergyForces
+
+
+_EF = None
+
+
+def energy_forces(weights, pos, model: Model, graph: Graph):
+    """Differentiable (E [S] FP64, F [N,3] FP32) with respect to `weights`."""
+    global _EF
+    if _EF is None:
+        _EF = _energy_forces_function()
+    return _EF.apply(weights, pos, model, graph)

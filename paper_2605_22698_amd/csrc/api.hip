@@ -10,6 +10,7 @@
 // The last layer keeps only its scalar outputs (the readout reads nothing
 // else), which removes its l3 > 0 paths without changing E or F.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -62,8 +63,8 @@ Config parse_config(const char* json) {
   c.radial_hidden = (int)json_number(s, "radial_hidden");
   c.readout_hidden = (int)json_number(s, "readout_hidden");
   E3MI_REQUIRE(c.lmax == 2 || c.lmax == 3, E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
-  E3MI_REQUIRE(c.channels >= 32 && c.channels % 32 == 0 && c.channels <= 256, E3MI_EUNSUPPORTED,
-               "channels must be a multiple of 32 in [32, 256]");
+  E3MI_REQUIRE(c.channels == 32 || c.channels == 64 || c.channels == 128, E3MI_EUNSUPPORTED,
+               "channels must be 32, 64 or 128");
   E3MI_REQUIRE(c.layers >= 1 && c.layers <= 8, E3MI_EINVAL, "layers must be in [1, 8]");
   E3MI_REQUIRE(c.n_species >= 1, E3MI_EINVAL, "n_species must be >= 1");
   E3MI_REQUIRE(c.cutoff > 0 && std::isfinite(c.cutoff), E3MI_EINVAL, "cutoff must be positive");
@@ -149,6 +150,10 @@ struct LayerWeights {
 struct Workspace {
   std::vector<std::unique_ptr<DevBuf>> h, ht, R;
   std::unique_ptr<DevBuf> A, dR, dY, g, dh_a, dh_b, dht, e_atom;
+  // second-order pass: per layer A, tangents and stored radial activations
+  std::vector<std::unique_ptr<DevBuf>> Al, Ad, hd, htd, Rd, P1d, H1d, P2d, H2d;
+  std::unique_ptr<DevBuf> dd, Bd, Prb, Prc, w2c, eb, xb, xc, Ab, Ac, hb_a, hb_b, hc_a, hc_b, Rb, Rc, P1g, P2g,
+      partial, vf;
 };
 
 }  // namespace e3mi
@@ -413,13 +418,77 @@ void prune(e3mi_graph* G, const double* pos, hipStream_t st) {
                    G->rev_x->as<int>(), st);
 }
 
+// Channels per thread of the tensor-product kernels (threads per receiver = C / cpt).
 int cpt_for(const LayerPlan& L, int C) {
-  if (L.kind == 1) return C <= 128 ? 1 : 2;
+  if (L.kind == 1) return 1;
   return C <= 64 ? 1 : C / 64;
 }
 
-void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* energy, float* forces,
-                   double* atom_energy, hipStream_t st) {
+// h~ = sum_p A_p W_l3[p] + h_in S_l3 for every computed output order l3 (rows
+// (atom, m), columns channels). `hin` may be NULL (no self connection term).
+void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* A, const float* hin, float* ht, int N,
+                hipStream_t st) {
+  const int C = M->cfg.channels;
+  long gbase = 0;
+  for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
+    const int P3 = L.p_used_l3[l3], g = 2 * l3 + 1;
+    GemmArgs ga{};
+    ga.a0 = RowMap{const_cast<float*>(A) + gbase, (long)g * P3 * C, (long)P3 * C, g};
+    ga.b0 = W.mix[l3].as<float>();
+    ga.ldb0 = C;
+    ga.k0 = P3 * C;
+    if (hin && l3 <= L.l1max) {
+      ga.a1 = RowMap{const_cast<float*>(hin) + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, g};
+      ga.b1 = W.self_[l3].as<float>();
+      ga.ldb1 = C;
+      ga.k1 = C;
+    }
+    ga.c = RowMap{ht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
+    ga.M = N * g;
+    ga.Nc = C;
+    launch_gemm(ga, st);
+    gbase += (long)N * g * P3 * C;
+  }
+}
+
+// Adjoint of the channel mix: dA = dht W^T per order, and (when dprev is not
+// NULL) dprev[l3] (+)= dht[l3] S^T for the orders present in the input.
+void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* dht, float* dA, float* dprev,
+                        int N, hipStream_t st) {
+  const int C = M->cfg.channels;
+  long gbase = 0;
+  for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
+    const int P3 = L.p_used_l3[l3], gg = 2 * l3 + 1;
+    GemmArgs ga{};
+    ga.a0 = RowMap{const_cast<float*>(dht) + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
+    ga.b0 = W.mixT[l3].as<float>();
+    ga.ldb0 = P3 * C;
+    ga.k0 = C;
+    ga.c = RowMap{dA + gbase, (long)gg * P3 * C, (long)P3 * C, gg};
+    ga.M = N * gg;
+    ga.Nc = P3 * C;
+    launch_gemm(ga, st);
+    gbase += (long)N * gg * P3 * C;
+  }
+  if (!dprev) return;
+  for (int l3 = 0; l3 <= std::min(L.l3max_used, L.l1max); ++l3) {
+    const int gg = 2 * l3 + 1;
+    GemmArgs ga{};
+    ga.a0 = RowMap{const_cast<float*>(dht) + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
+    ga.b0 = W.selfT[l3].as<float>();
+    ga.ldb0 = C;
+    ga.k0 = C;
+    ga.c = RowMap{dprev + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, gg};
+    ga.M = N * gg;
+    ga.Nc = C;
+    launch_gemm(ga, st);
+  }
+}
+
+// Primal forward pass: edge selection, embedding and every layer. Leaves
+// h^t, h~^t and R^t of every layer in the workspace; A in one shared buffer,
+// or per layer when keep_A (the parameter-gradient pass needs them).
+void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, hipStream_t st) {
   const Config& c = M->cfg;
   Allocator* a = &M->alloc;
   const int N = G->N, S = G->S, C = c.channels, T = c.layers;
@@ -429,10 +498,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
   const float rc = (float)c.cutoff;
   const int p_env = c.envelope_p;
   Workspace& w = M->ws;
-  if (N == 0) {
-    E3MI_HIP(hipMemsetAsync(energy, 0, sizeof(double) * S, st));
-    return;
-  }
+  (void)S;
   {
     ProfScope ps(&M->prof, stage_id(kPrune), st);
     prune(G, pos, st);
@@ -457,6 +523,10 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     pc_max = std::max(pc_max, (long)L.p_used * C);
   }
   ensure(w.A, a, sizeof(float) * (size_t)N * a_max);
+  if (keep_A) {
+    w.Al.resize(T + 1);
+    for (int t = 1; t <= T; ++t) ensure(w.Al[t], a, sizeof(float) * (size_t)N * M->plans[t - 1].a_per_atom);
+  }
   ensure(w.dR, a, sizeof(float) * (size_t)(Ecap + 1) * pc_max);
   ensure(w.dY, a, sizeof(float) * 16 * (size_t)(Ecap + 1));
   ensure(w.g, a, sizeof(float4) * (size_t)(Ecap + 1));
@@ -464,8 +534,6 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
   ensure(w.dh_b, a, sizeof(float) * (size_t)N * NC * C);
   ensure(w.dht, a, sizeof(float) * (size_t)N * NC * C);
   ensure(w.e_atom, a, sizeof(double) * (size_t)N);
-  float* A = w.A->as<float>();
-
   // ---- forward ----
   {
     ProfScope ps(&M->prof, stage_id(kEmbed), st);
@@ -477,6 +545,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     const float* hin = w.h[t - 1]->as<float>();
     float* R = w.R[t]->as<float>();
     const int PCu = L.p_used * C;
+    float* A = keep_A ? w.Al[t]->as<float>() : w.A->as<float>();
     {
       ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
       launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
@@ -502,30 +571,36 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       launch_tp(0, ta, st);
     }
     float* ht = w.ht[t]->as<float>();
-    long gbase = 0;
-    ProfScope ps_mix(&M->prof, stage_id(kMixFwd, t), st);
-    for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
-      const int P3 = L.p_used_l3[l3], g = 2 * l3 + 1;
-      GemmArgs ga{};
-      ga.a0 = RowMap{A + gbase, (long)g * P3 * C, (long)P3 * C, g};
-      ga.b0 = W.mix[l3].as<float>();
-      ga.ldb0 = C;
-      ga.k0 = P3 * C;
-      if (l3 <= L.l1max) {
-        ga.a1 = RowMap{const_cast<float*>(hin) + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, g};
-        ga.b1 = W.self_[l3].as<float>();
-        ga.ldb1 = C;
-        ga.k1 = C;
-      }
-      ga.c = RowMap{ht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
-      ga.M = N * g;
-      ga.Nc = C;
-      launch_gemm(ga, st);
-      gbase += (long)N * g * P3 * C;
+    {
+      ProfScope ps(&M->prof, stage_id(kMixFwd, t), st);
+      launch_mix(M, L, W, A, hin, ht, N, st);
     }
-    ProfScope ps_gate(&M->prof, stage_id(kGateFwd, t), st);
-    launch_gate_fwd(ht, w.h[t]->as<float>(), N, L.nc_out, C, st);
+    {
+      ProfScope ps(&M->prof, stage_id(kGateFwd, t), st);
+      launch_gate_fwd(ht, w.h[t]->as<float>(), N, L.nc_out, C, st);
+    }
   }
+}
+
+void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* energy, float* forces,
+                   double* atom_energy, hipStream_t st) {
+  const Config& c = M->cfg;
+  const int N = G->N, S = G->S, C = c.channels, T = c.layers;
+  const long Ecap = G->E;
+  const float inv_nu = (float)(1.0 / c.avg_neighbors);
+  const float rc = (float)c.cutoff;
+  const int p_env = c.envelope_p;
+  Workspace& w = M->ws;
+  if (N == 0) {
+    E3MI_HIP(hipMemsetAsync(energy, 0, sizeof(double) * S, st));
+    return;
+  }
+  forward_pass(M, G, pos, false, st);
+  const int* row_ptr = G->row_ptr_x->as<int>();
+  const int* src = G->src_x->as<int>();
+  const float4* dvec = G->dvec_x->as<float4>();
+  const int* species = G->species->as<int>();
+  float* A = w.A->as<float>();
   float* dcur = w.dh_a->as<float>();
   float* dother = w.dh_b->as<float>();
   {
@@ -550,35 +625,10 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       ProfScope ps(&M->prof, stage_id(kGateBwd, t), st);
       launch_gate_bwd(w.ht[t]->as<float>(), dcur, dht, N, L.nc_out, C, st);
     }
-    ProfScope ps_mixb(&M->prof, stage_id(kMixBwd, t), st);
-    long gbase = 0;
-    for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
-      const int P3 = L.p_used_l3[l3], gg = 2 * l3 + 1;
-      GemmArgs ga{};
-      ga.a0 = RowMap{dht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
-      ga.b0 = W.mixT[l3].as<float>();
-      ga.ldb0 = P3 * C;
-      ga.k0 = C;
-      ga.c = RowMap{A + gbase, (long)gg * P3 * C, (long)P3 * C, gg};
-      ga.M = N * gg;
-      ga.Nc = P3 * C;
-      launch_gemm(ga, st);
-      gbase += (long)N * gg * P3 * C;
-    }
-    if (t > 1) {
-      E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
-      for (int l3 = 0; l3 <= std::min(L.l3max_used, L.l1max); ++l3) {
-        const int gg = 2 * l3 + 1;
-        GemmArgs ga{};
-        ga.a0 = RowMap{dht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
-        ga.b0 = W.selfT[l3].as<float>();
-        ga.ldb0 = C;
-        ga.k0 = C;
-        ga.c = RowMap{dother + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, gg};
-        ga.M = N * gg;
-        ga.Nc = C;
-        launch_gemm(ga, st);
-      }
+    {
+      ProfScope ps(&M->prof, stage_id(kMixBwd, t), st);
+      if (t > 1) E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+      launch_mix_adjoint(M, L, W, dht, A, t > 1 ? dother : nullptr, N, st);
     }
     TpArgs ta{};
     ta.lmax = c.lmax;
@@ -640,22 +690,10 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
   return b;
 }
 
-e3mi_model* new_model(const char* json, const double* wts, size_t n, int precision, e3mi_alloc_fn al,
-                      e3mi_free_fn fr, void* ctx) {
-  auto M = std::make_unique<e3mi_model>();
-  M->cfg = parse_config(json);
+// Convert the FP64 weights to FP32 device tensors (and the transposed copies
+// the adjoint GEMMs read). Buffers are reused when they exist.
+void upload_weights(e3mi_model* M, const double* wts) {
   const Config& c = M->cfg;
-  E3MI_REQUIRE(precision == E3MI_FP32 || precision == E3MI_BF16_MIX, E3MI_EINVAL, "unknown precision");
-  E3MI_REQUIRE(precision == E3MI_FP32, E3MI_EUNSUPPORTED, "BF16 mode is not available in this build");
-  M->precision = precision;
-  E3MI_REQUIRE(wts, E3MI_EINVAL, "weights are NULL");
-  const size_t expect = weight_count(c);
-  E3MI_REQUIRE(n == expect, E3MI_EINVAL,
-               "weight count " + std::to_string(n) + " does not match the configuration (" + std::to_string(expect) + ")");
-  for (size_t i = 0; i < n; ++i) E3MI_REQUIRE(std::isfinite(wts[i]), E3MI_ENAN, "weights are not finite");
-  M->alloc.alloc = al;
-  M->alloc.free_fn = fr;
-  M->alloc.ctx = ctx;
   Allocator* a = &M->alloc;
   const int C = c.channels, H = c.radial_hidden;
   size_t cur = 0;
@@ -668,10 +706,14 @@ e3mi_model* new_model(const char* json, const double* wts, size_t n, int precisi
   M->emb = upload_f32(a, take((size_t)c.n_species * C));
   for (int t = 1; t <= c.layers; ++t) {
     const LayerPlan L = plan_layer(c, t);
-    M->plans.push_back(L);
-    auto W = std::make_unique<LayerWeights>();
-    for (DevBuf* b : {&W->rad1, &W->rad2, &W->rad2T, &W->rad3, &W->rad3T}) b->a = a;
-    for (int l = 0; l < 4; ++l) W->mix[l].a = W->mixT[l].a = W->self_[l].a = W->selfT[l].a = a;
+    if ((int)M->lw.size() < t) {
+      M->plans.push_back(L);
+      auto Wn = std::make_unique<LayerWeights>();
+      for (DevBuf* b : {&Wn->rad1, &Wn->rad2, &Wn->rad2T, &Wn->rad3, &Wn->rad3T}) b->a = a;
+      for (int l = 0; l < 4; ++l) Wn->mix[l].a = Wn->mixT[l].a = Wn->self_[l].a = Wn->selfT[l].a = a;
+      M->lw.push_back(std::move(Wn));
+    }
+    LayerWeights* W = M->lw[t - 1].get();
     auto up = [&](DevBuf& b, const std::vector<float>& v) {
       b.ensure(v.size() * sizeof(float));
       E3MI_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -701,13 +743,265 @@ e3mi_model* new_model(const char* json, const double* wts, size_t n, int precisi
       up(W->self_[l], s);
       up(W->selfT[l], transpose(s, C, C));
     }
-    M->lw.push_back(std::move(W));
   }
   M->read1 = upload_f32(a, take((size_t)C * c.readout_hidden));
   M->read2 = upload_f32(a, take((size_t)c.readout_hidden));
   M->e0 = upload_f32(a, take((size_t)c.n_species));
-  E3MI_REQUIRE(cur == n, E3MI_EINVAL, "internal: weight cursor mismatch");
+  E3MI_REQUIRE(cur == weight_count(c), E3MI_EINVAL, "internal: weight cursor mismatch");
+}
+
+e3mi_model* new_model(const char* json, const double* wts, size_t n, int precision, e3mi_alloc_fn al,
+                      e3mi_free_fn fr, void* ctx) {
+  auto M = std::make_unique<e3mi_model>();
+  M->cfg = parse_config(json);
+  const Config& c = M->cfg;
+  E3MI_REQUIRE(precision == E3MI_FP32 || precision == E3MI_BF16_MIX, E3MI_EINVAL, "unknown precision");
+  E3MI_REQUIRE(precision == E3MI_FP32, E3MI_EUNSUPPORTED, "BF16 mode is not available in this build");
+  M->precision = precision;
+  E3MI_REQUIRE(wts, E3MI_EINVAL, "weights are NULL");
+  const size_t expect = weight_count(c);
+  E3MI_REQUIRE(n == expect, E3MI_EINVAL,
+               "weight count " + std::to_string(n) + " does not match the configuration (" + std::to_string(expect) + ")");
+  for (size_t i = 0; i < n; ++i) E3MI_REQUIRE(std::isfinite(wts[i]), E3MI_ENAN, "weights are not finite");
+  M->alloc.alloc = al;
+  M->alloc.free_fn = fr;
+  M->alloc.ctx = ctx;
+  upload_weights(M.get(), wts);
   return M.release();
+}
+
+
+// Offsets of every weight tensor in the flat FP64 vector (file order).
+struct WeightOffsets {
+  size_t emb = 0, read1 = 0, read2 = 0, e0 = 0, total = 0;
+  std::vector<size_t> rad1, rad2, rad3;
+  std::vector<std::array<size_t, 4>> mix, self_;
+};
+
+WeightOffsets weight_offsets(const Config& c) {
+  WeightOffsets o;
+  const size_t C = c.channels, H = c.radial_hidden;
+  size_t cur = 0;
+  o.emb = cur;
+  cur += (size_t)c.n_species * C;
+  for (int t = 1; t <= c.layers; ++t) {
+    const LayerPlan L = plan_layer(c, t);
+    o.rad1.push_back(cur);
+    cur += (size_t)c.n_basis * H;
+    o.rad2.push_back(cur);
+    cur += H * H;
+    o.rad3.push_back(cur);
+    cur += H * (size_t)L.p_full * C;
+    std::array<size_t, 4> m{}, sf{};
+    for (int l3 = 0; l3 <= c.lmax; ++l3) {
+      m[l3] = cur;
+      cur += (size_t)L.p_full_l3[l3] * C * C;
+    }
+    for (int l = 0; l <= L.l1max; ++l) {
+      sf[l] = cur;
+      cur += C * C;
+    }
+    o.mix.push_back(m);
+    o.self_.push_back(sf);
+  }
+  o.read1 = cur;
+  cur += C * c.readout_hidden;
+  o.read2 = cur;
+  cur += c.readout_hidden;
+  o.e0 = cur;
+  cur += c.n_species;
+  o.total = cur;
+  return o;
+}
+
+// Gradient of sum_s gE_s E_s - D_v E (v = gF) with respect to every weight:
+// the vector-Jacobian product of (E, F) -> weights for upstream (gE, gF).
+// Forward (primal + tangent along v), then the reverse pass over both.
+void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* gE, const float* gF, double* out,
+                hipStream_t st) {
+  const Config& c = M->cfg;
+  Allocator* a = &M->alloc;
+  const int N = G->N, C = c.channels, T = c.layers, H = c.radial_hidden;
+  const long Ecap = G->E;
+  const int NC = (c.lmax + 1) * (c.lmax + 1);
+  const float inv_nu = (float)(1.0 / c.avg_neighbors);
+  const float rc = (float)c.cutoff;
+  const int p_env = c.envelope_p;
+  Workspace& w = M->ws;
+  const WeightOffsets off = weight_offsets(c);
+  E3MI_HIP(hipMemsetAsync(out, 0, sizeof(double) * off.total, st));
+  if (N == 0) return;
+  forward_pass(M, G, pos, true, st);
+  const int* row_ptr = G->row_ptr_x->as<int>();
+  const int* src = G->src_x->as<int>();
+  const float4* dvec = G->dvec_x->as<float4>();
+  const int* rows_dev = row_ptr + N;  // number of edges inside the cutoff
+  const size_t E1 = (size_t)Ecap + 1;
+
+  // ---- workspace ----
+  for (auto* v : {&w.Ad, &w.hd, &w.htd, &w.Rd, &w.P1d, &w.H1d, &w.P2d, &w.H2d}) v->resize(T + 1);
+  long a_max = 0, pc_max = 0;
+  for (int t = 1; t <= T; ++t) {
+    const LayerPlan& L = M->plans[t - 1];
+    ensure(w.Ad[t], a, sizeof(float) * (size_t)N * L.a_per_atom);
+    ensure(w.hd[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
+    ensure(w.htd[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
+    ensure(w.Rd[t], a, sizeof(float) * E1 * L.p_used * C);
+    for (auto* v : {&w.P1d, &w.H1d, &w.P2d, &w.H2d}) ensure((*v)[t], a, sizeof(float) * E1 * 2 * H);
+    a_max = std::max(a_max, L.a_per_atom);
+    pc_max = std::max(pc_max, (long)L.p_used * C);
+  }
+  ensure(w.dd, a, sizeof(float4) * E1);
+  ensure(w.Bd, a, sizeof(float) * E1 * 16);
+  for (auto* v : {&w.Prb, &w.Prc, &w.w2c}) ensure(*v, a, sizeof(float) * (size_t)N * 16);
+  ensure(w.eb, a, sizeof(float) * (size_t)N);
+  for (auto* v : {&w.xb, &w.xc, &w.hb_a, &w.hb_b, &w.hc_a, &w.hc_b}) ensure(*v, a, sizeof(float) * (size_t)N * NC * C);
+  for (auto* v : {&w.Ab, &w.Ac}) ensure(*v, a, sizeof(float) * (size_t)N * a_max);
+  for (auto* v : {&w.Rb, &w.Rc}) ensure(*v, a, sizeof(float) * E1 * pc_max);
+  for (auto* v : {&w.P1g, &w.P2g}) ensure(*v, a, sizeof(float) * E1 * 2 * H);
+  ensure(w.partial, a, sizeof(float) * std::max<size_t>(16u << 20, (size_t)H * pc_max));
+  float* partial = w.partial->as<float>();
+
+  // ---- tangent forward along v = gF ----
+  launch_edge_tangent(row_ptr, src, dvec, gF, N, w.dd->as<float4>(), st);
+  const float4* dd = w.dd->as<float4>();
+  for (int t = 1; t <= T; ++t) {
+    const LayerPlan& L = M->plans[t - 1];
+    LayerWeights& W = *M->lw[t - 1];
+    const int PCu = L.p_used * C;
+    launch_radial_dual_fwd(c.n_basis, dvec, dd, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
+                           W.rad3.as<float>(), L.p_full * C, PCu, w.Rd[t]->as<float>(), w.Bd->as<float>(),
+                           w.P1d[t]->as<float>(), w.H1d[t]->as<float>(), w.P2d[t]->as<float>(), w.H2d[t]->as<float>(),
+                           rc, p_env, st);
+    TpArgs ta{};
+    ta.lmax = c.lmax;
+    ta.kind = L.kind;
+    ta.cpt = cpt_for(L, C);
+    ta.row_ptr = row_ptr;
+    ta.src = src;
+    ta.dvec = dvec;
+    ta.dd = dd;
+    ta.R = w.R[t]->as<float>();
+    ta.Rd = w.Rd[t]->as<float>();
+    ta.r_stride = PCu;
+    ta.h = w.h[t - 1]->as<float>();
+    ta.hd = t > 1 ? w.hd[t - 1]->as<float>() : nullptr;
+    ta.h_nc = L.nc_in;
+    ta.Ad = w.Ad[t]->as<float>();
+    ta.N = N;
+    ta.C = C;
+    ta.inv_nu = inv_nu;
+    launch_tp(3, ta, st);
+    launch_mix(M, L, W, w.Ad[t]->as<float>(), t > 1 ? w.hd[t - 1]->as<float>() : nullptr, w.htd[t]->as<float>(), N,
+               st);
+    launch_gate_dual_fwd(w.ht[t]->as<float>(), w.htd[t]->as<float>(), w.hd[t]->as<float>(), N, L.nc_out, C, st);
+  }
+
+  // ---- reverse: readout ----
+  const int ncT = M->plans[T - 1].nc_out;
+  float* hb = w.hb_a->as<float>();
+  float* hc = w.hc_a->as<float>();
+  float* hb2 = w.hb_b->as<float>();
+  float* hc2 = w.hc_b->as<float>();
+  launch_readout_dual(w.h[T]->as<float>(), w.hd[T]->as<float>(), ncT, G->owner->as<int>(), gE, M->read1->as<float>(),
+                      M->read2->as<float>(), N, C, w.Prb->as<float>(), w.Prc->as<float>(), w.w2c->as<float>(), hb, hc,
+                      w.eb->as<float>(), st);
+  launch_gemm_tn(RowMap{w.h[T]->as<float>(), (long)ncT * C, 0, 1}, RowMap{w.Prb->as<float>(), 16, 0, 1},
+                 RowMap{w.hd[T]->as<float>(), (long)ncT * C, 0, 1}, RowMap{w.Prc->as<float>(), 16, 0, 1}, N, nullptr,
+                 C, 16, partial, out + off.read1, 16, st);
+  launch_group_sum(w.w2c->as<float>(), 16, nullptr, 1, N, 16, out + off.read2, 16, st);
+  launch_group_sum(w.eb->as<float>(), 1, G->species->as<int>(), c.n_species, N, 1, out + off.e0, 1, st);
+
+  // ---- reverse: layers ----
+  float* xb = w.xb->as<float>();
+  float* xc = w.xc->as<float>();
+  for (int t = T; t >= 1; --t) {
+    const LayerPlan& L = M->plans[t - 1];
+    LayerWeights& W = *M->lw[t - 1];
+    const int PCu = L.p_used * C;
+    const float* hin = w.h[t - 1]->as<float>();
+    const float* hdin = t > 1 ? w.hd[t - 1]->as<float>() : nullptr;
+    launch_gate_dual_bwd(w.ht[t]->as<float>(), w.htd[t]->as<float>(), hb, hc, xb, xc, N, L.nc_out, C, st);
+    // weight gradients of the channel mix and the self connection
+    long gbase = 0;
+    for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
+      const int P3 = L.p_used_l3[l3], g = 2 * l3 + 1;
+      const RowMap xbr{xb + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
+      const RowMap xcr{xc + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
+      launch_gemm_tn(RowMap{w.Al[t]->as<float>() + gbase, (long)g * P3 * C, (long)P3 * C, g}, xbr,
+                     RowMap{w.Ad[t]->as<float>() + gbase, (long)g * P3 * C, (long)P3 * C, g}, xcr, (long)N * g,
+                     nullptr, P3 * C, C, partial, out + off.mix[t - 1][l3], C, st);
+      if (l3 <= L.l1max)
+        launch_gemm_tn(RowMap{const_cast<float*>(hin) + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, g}, xbr,
+                       hdin ? RowMap{const_cast<float*>(hdin) + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, g}
+                            : RowMap{nullptr, 0, 0, 1},
+                       xcr, (long)N * g, nullptr, C, C, partial, out + off.self_[t - 1][l3], C, st);
+      gbase += (long)N * g * P3 * C;
+    }
+    // adjoints of A and A_dot; of h^{t-1} and h_dot^{t-1} through the self connection
+    E3MI_HIP(hipMemsetAsync(hb2, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+    if (t > 1) E3MI_HIP(hipMemsetAsync(hc2, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+    launch_mix_adjoint(M, L, W, xb, w.Ab->as<float>(), hb2, N, st);
+    launch_mix_adjoint(M, L, W, xc, w.Ac->as<float>(), t > 1 ? hc2 : nullptr, N, st);
+    // tensor product: adjoints of R and R_dot, then of h and h_dot
+    TpArgs ta{};
+    ta.lmax = c.lmax;
+    ta.kind = L.kind;
+    ta.cpt = cpt_for(L, C);
+    ta.row_ptr = row_ptr;
+    ta.src = src;
+    ta.dvec = dvec;
+    ta.dd = dd;
+    ta.R = w.R[t]->as<float>();
+    ta.Rd = w.Rd[t]->as<float>();
+    ta.r_stride = PCu;
+    ta.h = hin;
+    ta.hd = hdin;
+    ta.h_nc = L.nc_in;
+    ta.Ab = w.Ab->as<float>();
+    ta.Ac = w.Ac->as<float>();
+    ta.Rb = w.Rb->as<float>();
+    ta.Rc = w.Rc->as<float>();
+    ta.hb = hb2;
+    ta.hc = t > 1 ? hc2 : nullptr;
+    ta.dh_nc = L.nc_in;
+    ta.N = N;
+    ta.C = C;
+    ta.inv_nu = inv_nu;
+    launch_tp(4, ta, st);
+    launch_tp(5, ta, st);
+    // radial MLP: adjoints of the pre-activations, then the weight gradients
+    launch_radial_dual_bwd(row_ptr, N, Ecap, W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.Rb->as<float>(),
+                           w.Rc->as<float>(), w.P1d[t]->as<float>(), w.P2d[t]->as<float>(), w.P1g->as<float>(),
+                           w.P2g->as<float>(), st);
+    float* H2d = w.H2d[t]->as<float>();
+    float* H1d = w.H1d[t]->as<float>();
+    float* Bd = w.Bd->as<float>();
+    float* P1g = w.P1g->as<float>();
+    float* P2g = w.P2g->as<float>();
+    launch_gemm_tn(RowMap{H2d, 2L * H, 0, 1}, RowMap{w.Rb->as<float>(), PCu, 0, 1}, RowMap{H2d + H, 2L * H, 0, 1},
+                   RowMap{w.Rc->as<float>(), PCu, 0, 1}, Ecap, rows_dev, H, PCu, partial, out + off.rad3[t - 1],
+                   (long)L.p_full * C, st);
+    launch_gemm_tn(RowMap{H1d, 2L * H, 0, 1}, RowMap{P2g, 2L * H, 0, 1}, RowMap{H1d + H, 2L * H, 0, 1},
+                   RowMap{P2g + H, 2L * H, 0, 1}, Ecap, rows_dev, H, H, partial, out + off.rad2[t - 1], H, st);
+    launch_gemm_tn(RowMap{Bd, 16, 0, 1}, RowMap{P1g, 2L * H, 0, 1}, RowMap{Bd + 8, 16, 0, 1},
+                   RowMap{P1g + H, 2L * H, 0, 1}, Ecap, rows_dev, c.n_basis, H, partial, out + off.rad1[t - 1], H,
+                   st);
+    std::swap(hb, hb2);
+    std::swap(hc, hc2);
+  }
+  // embedding: h^0_i = W_emb[z_i]
+  launch_group_sum(hb, C, G->species->as<int>(), c.n_species, N, C, out + off.emb, C, st);
+}
+
+// Replace the weights of a model (same configuration), e.g. after an optimiser step.
+void set_weights(e3mi_model* M, const double* wts, size_t n) {
+  const Config& c = M->cfg;
+  E3MI_REQUIRE(wts, E3MI_EINVAL, "weights are NULL");
+  E3MI_REQUIRE(n == weight_count(c), E3MI_EINVAL, "weight count does not match the configuration");
+  for (size_t i = 0; i < n; ++i) E3MI_REQUIRE(std::isfinite(wts[i]), E3MI_ENAN, "weights are not finite");
+  E3MI_HIP(hipDeviceSynchronize());  // no kernel may still read the old weights
+  upload_weights(M, wts);
 }
 
 // ---- MD -----------------------------------------------------------------------------------
@@ -906,6 +1200,24 @@ int e3mi_energy_forces(e3mi_model* model, e3mi_graph* graph, const double* pos, 
   E3MI_REQUIRE(graph->N == 0 || pos, E3MI_EINVAL, "null positions");
   e3mi::energy_forces(model, graph, pos, energy, forces, atom_energy, e3mi::as_stream(stream));
   E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, const double* grad_energy,
+                    const float* grad_forces, double* grad_weights, void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model && graph && grad_energy && grad_forces && grad_weights, E3MI_EINVAL, "null argument");
+  E3MI_REQUIRE(graph->model == model, E3MI_EINVAL, "graph was built for another model");
+  E3MI_REQUIRE(graph->N == 0 || pos, E3MI_EINVAL, "null positions");
+  e3mi::param_grad(model, graph, pos, grad_energy, grad_forces, grad_weights, e3mi::as_stream(stream));
+  E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_model_set_weights(e3mi_model* model, const double* weights_host, size_t n_weights) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
+  e3mi::set_weights(model, weights_host, n_weights);
   E3MI_API_END
 }
 

@@ -88,6 +88,57 @@ __device__ __forceinline__ void real_sh_vjp(float x, float y, float z, const flo
   }
 }
 
+
+// Directional derivative of every harmonic polynomial along u:
+// Yd[c] = grad P_c(x, y, z) . u (the caller passes the tangential part of the
+// direction change, u = (I - n n^T) d_dot / r).
+template <int LMAX>
+__device__ __forceinline__ void real_sh_jvp(float x, float y, float z, float ux, float uy, float uz, float* Yd) {
+  Yd[0] = 0.0f;
+  if constexpr (LMAX >= 1) {
+    constexpr float s3 = 1.7320508075688772f;
+    Yd[1] = s3 * uy;
+    Yd[2] = s3 * uz;
+    Yd[3] = s3 * ux;
+  }
+  if constexpr (LMAX >= 2) {
+    constexpr float s15 = 3.872983346207417f, s5h = 1.118033988749895f;
+    Yd[4] = s15 * (y * ux + x * uy);
+    Yd[5] = s15 * (z * uy + y * uz);
+    Yd[6] = 6.0f * s5h * z * uz;
+    Yd[7] = s15 * (z * ux + x * uz);
+    Yd[8] = s15 * (x * ux - y * uy);
+  }
+  if constexpr (LMAX >= 3) {
+    constexpr float a358 = 2.091650066335189f, s105 = 10.246950765959598f;
+    constexpr float a218 = 1.620185174601965f, s7h = 1.3228756555322954f;
+    Yd[9] = a358 * (6.0f * x * y * ux + 3.0f * (x * x - y * y) * uy);
+    Yd[10] = s105 * (y * z * ux + x * z * uy + x * y * uz);
+    Yd[11] = a218 * ((5.0f * z * z - 1.0f) * uy + 10.0f * y * z * uz);
+    Yd[12] = s7h * (15.0f * z * z - 3.0f) * uz;
+    Yd[13] = a218 * ((5.0f * z * z - 1.0f) * ux + 10.0f * x * z * uz);
+    Yd[14] = s105 * (x * z * ux - y * z * uy) + 0.5f * s105 * (x * x - y * y) * uz;
+    Yd[15] = a358 * (3.0f * (x * x - y * y) * ux - 6.0f * x * y * uy);
+  }
+}
+
+// Harmonics and their directional derivatives for an edge vector d (length
+// r) moving with velocity dd: n = d / r, u = (I - n n^T) dd / r.
+template <int LMAX>
+__device__ __forceinline__ void real_sh_dual(float4 d, float4 dd, float* Y, float* Yd) {
+  const float ir = 1.0f / d.w;
+  const float x = d.x * ir, y = d.y * ir, z = d.z * ir;
+  real_sh<LMAX>(x, y, z, Y);
+  const float dot = x * dd.x + y * dd.y + z * dd.z;
+  real_sh_jvp<LMAX>(x, y, z, (dd.x - dot * x) * ir, (dd.y - dot * y) * ir, (dd.z - dot * z) * ir, Yd);
+}
+
+// silu'' = s (1 - s) (2 + x (1 - 2 s))
+__device__ __forceinline__ float silu_grad2(float x) {
+  const float s = sigmoidf(x);
+  return s * (1.0f - s) * (2.0f + x * (1.0f - 2.0f * s));
+}
+
 // Bessel x polynomial-envelope radial basis B_n(r), n = 1..NB, and optionally
 // its derivative dB_n/dr. Zero for r >= rc.
 template <int NB>

@@ -215,6 +215,182 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   }
 }
 
+
+// ---- second order (parameter gradients of a force-dependent loss) ----------------
+// Tangent pass along per-edge (d_dot, r_dot): B_dot = B'(r) r_dot,
+// P1_dot = B_dot W1, H1_dot = silu'(P1) P1_dot, P2_dot = H1_dot W2,
+// H2_dot = silu'(P2) P2_dot, R_dot = H2_dot W3. Stores, per edge, [B | B_dot],
+// [P1 | P1_dot], [H1 | H1_dot], [P2 | P2_dot], [H2 | H2_dot] for the reverse
+// pass and the weight-gradient reductions.
+template <int NB>
+__global__ void __launch_bounds__(256) k_radial_dual_fwd(const float4* __restrict__ dvec, const float4* __restrict__ dd,
+                                                         const int* __restrict__ row_ptr_x, int N,
+                                                         const float* __restrict__ W1, const float* __restrict__ W2,
+                                                         const float* __restrict__ W3, int ld3, int PC,
+                                                         float* __restrict__ Rd, float* __restrict__ Bd,
+                                                         float* __restrict__ P1d, float* __restrict__ H1d,
+                                                         float* __restrict__ P2d, float* __restrict__ H2d, float rc,
+                                                         int p) {
+  __shared__ float Bs[kTile][NB + 1];
+  __shared__ float Bts[kTile][NB + 1];
+  __shared__ float X[kTile][kLd];
+  __shared__ float Xt[kTile][kLd];
+  const int E = row_ptr_x[N];
+  const int e0 = blockIdx.x * kTile;
+  if (e0 >= E) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t < kTile) {
+    const int e = e0 + t;
+    const float r = e < E ? dvec[e].w : rc;
+    const float rdot = e < E ? dd[e].w : 0.0f;
+    float b[NB], db[NB];
+    radial_basis<NB>(r, rc, p, b, db);
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      Bs[t][n] = b[n];
+      Bts[t][n] = db[n] * rdot;
+      if (e < E) {
+        Bd[(long)e * 16 + n] = b[n];
+        Bd[(long)e * 16 + 8 + n] = db[n] * rdot;
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int row = t >> 2, cb = (t & 3) * 16;
+    const int e = e0 + row;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      float s = 0.0f, sd = 0.0f;
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        s += Bs[row][n] * W1[n * kH + cb + j];
+        sd += Bts[row][n] * W1[n * kH + cb + j];
+      }
+      const float h = siluf(s), hd = silu_grad(s) * sd;
+      X[row][cb + j] = h;
+      Xt[row][cb + j] = hd;
+      if (e < E) {
+        P1d[(long)e * 128 + cb + j] = s;
+        P1d[(long)e * 128 + 64 + cb + j] = sd;
+        H1d[(long)e * 128 + cb + j] = h;
+        H1d[(long)e * 128 + 64 + cb + j] = hd;
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+    const f32x16 a = block_64(X, rb, W2, kH, cb);
+    const f32x16 ad = block_64(Xt, rb, W2, kH, cb);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
+      const float h = siluf(a[r]), hd = silu_grad(a[r]) * ad[r];
+      X[row][col] = h;
+      Xt[row][col] = hd;
+      const int e = e0 + row;
+      if (e < E) {
+        P2d[(long)e * 128 + col] = a[r];
+        P2d[(long)e * 128 + 64 + col] = ad[r];
+        H2d[(long)e * 128 + col] = h;
+        H2d[(long)e * 128 + 64 + col] = hd;
+      }
+    }
+  }
+  __syncthreads();
+  for (int cc = w * 32; cc < PC; cc += 128) {
+    f32x16 a0 = {}, a1 = {};
+#pragma unroll 8
+    for (int kk = 0; kk < kH; kk += 2) {
+      const float b = W3[(kk + (lane >> 5)) * ld3 + cc + (lane & 31)];
+      a0 = mfma32(Xt[lane & 31][kk + (lane >> 5)], b, a0);
+      a1 = mfma32(Xt[32 + (lane & 31)][kk + (lane >> 5)], b, a1);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = acc_row(r, lane);
+      const int ea = e0 + row, eb = e0 + 32 + row;
+      if (ea < E) Rd[(long)ea * PC + cc + (lane & 31)] = a0[r];
+      if (eb < E) Rd[(long)eb * PC + cc + (lane & 31)] = a1[r];
+    }
+  }
+}
+
+// Reverse of the tangent pass: from the adjoints of R and R_dot (Rb, Rc) to
+// the adjoints of the pre-activations, [P2b | P2c] and [P1b | P1c]:
+//   H2b = Rb W3^T, H2c = Rc W3^T
+//   P2b = H2b silu'(P2) + H2c silu''(P2) P2_dot,  P2c = H2c silu'(P2)
+//   H1b = P2b W2^T, H1c = P2c W2^T
+//   P1b = H1b silu'(P1) + H1c silu''(P1) P1_dot,  P1c = H1c silu'(P1)
+__global__ void __launch_bounds__(256) k_radial_dual_bwd(const int* __restrict__ row_ptr_x, int N,
+                                                         const float* __restrict__ W2T, const float* __restrict__ W3T,
+                                                         int PC, const float* __restrict__ Rb,
+                                                         const float* __restrict__ Rc, const float* __restrict__ P1d,
+                                                         const float* __restrict__ P2d, float* __restrict__ P1g,
+                                                         float* __restrict__ P2g) {
+  __shared__ float Ds[kTile][33];
+  __shared__ float Dc[kTile][33];
+  __shared__ float X[kTile][kLd];
+  __shared__ float Xc[kTile][kLd];
+  const int E = row_ptr_x[N];
+  const int e0 = blockIdx.x * kTile;
+  if (e0 >= E) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+  f32x16 ab = {}, ac = {};
+  for (int kc = 0; kc < PC; kc += 32) {
+    __syncthreads();
+    {
+      const int row = t >> 2, c8 = (t & 3) * 8;
+      const int e = e0 + row;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        Ds[row][c8 + q] = e < E ? Rb[(long)e * PC + kc + c8 + q] : 0.0f;
+        Dc[row][c8 + q] = e < E ? Rc[(long)e * PC + kc + c8 + q] : 0.0f;
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 32; kk += 2) {
+      const float b = W3T[(kc + kk + (lane >> 5)) * kH + cb + (lane & 31)];
+      ab = mfma32(Ds[rb + (lane & 31)][kk + (lane >> 5)], b, ab);
+      ac = mfma32(Dc[rb + (lane & 31)][kk + (lane >> 5)], b, ac);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
+    const int e = e0 + row;
+    float pb = 0.0f, pc = 0.0f;
+    if (e < E) {
+      const float x = P2d[(long)e * 128 + col], xd = P2d[(long)e * 128 + 64 + col];
+      const float g1 = silu_grad(x);
+      pb = ab[r] * g1 + ac[r] * silu_grad2(x) * xd;
+      pc = ac[r] * g1;
+      P2g[(long)e * 128 + col] = pb;
+      P2g[(long)e * 128 + 64 + col] = pc;
+    }
+    X[row][col] = pb;
+    Xc[row][col] = pc;
+  }
+  __syncthreads();
+  const f32x16 hb = block_64(X, rb, W2T, kH, cb);
+  const f32x16 hc = block_64(Xc, rb, W2T, kH, cb);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
+    const int e = e0 + row;
+    if (e < E) {
+      const float x = P1d[(long)e * 128 + col], xd = P1d[(long)e * 128 + 64 + col];
+      const float g1 = silu_grad(x);
+      P1g[(long)e * 128 + col] = hb[r] * g1 + hc[r] * silu_grad2(x) * xd;
+      P1g[(long)e * 128 + 64 + col] = hc[r] * g1;
+    }
+  }
+}
+
 inline int tiles(long n) { return (int)((n + kTile - 1) / kTile); }
 
 }  // namespace
@@ -242,4 +418,21 @@ void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row
     throw Error(E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
 }
 
+}  // namespace e3mi
+
+namespace e3mi {
+void launch_radial_dual_fwd(int n_basis, const float4* dvec, const float4* dd, const int* row_ptr_x, int N, long e_cap,
+                            const float* W1, const float* W2, const float* W3, int ld3, int PC, float* Rd, float* Bd,
+                            float* P1d, float* H1d, float* P2d, float* H2d, float rc, int p, hipStream_t st) {
+  if (e_cap == 0) return;
+  if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
+  k_radial_dual_fwd<8><<<tiles(e_cap), 256, 0, st>>>(dvec, dd, row_ptr_x, N, W1, W2, W3, ld3, PC, Rd, Bd, P1d, H1d,
+                                                     P2d, H2d, rc, p);
+}
+void launch_radial_dual_bwd(const int* row_ptr_x, int N, long e_cap, const float* W2T, const float* W3T, int PC,
+                            const float* Rb, const float* Rc, const float* P1d, const float* P2d, float* P1g,
+                            float* P2g, hipStream_t st) {
+  if (e_cap == 0) return;
+  k_radial_dual_bwd<<<tiles(e_cap), 256, 0, st>>>(row_ptr_x, N, W2T, W3T, PC, Rb, Rc, P1d, P2d, P1g, P2g);
+}
 }  // namespace e3mi

@@ -208,8 +208,21 @@ struct TpArgs {
   int dh_nc;
   int N, C;
   float inv_nu;
+  // second-order (parameter-gradient) passes
+  const float4* dd;  // per-edge tangent (d_dot, r_dot)
+  const float* Rd;   // tangent of R, same layout as R
+  const float* hd;   // tangent of h (NULL: zero)
+  float* Ad;         // out: tangent of A
+  const float* Ab;   // adjoint of A
+  const float* Ac;   // adjoint of the tangent of A
+  float* Rb;         // out: adjoint of R
+  float* Rc;         // out: adjoint of the tangent of R
+  float* hb;         // in/out (+=): adjoint of h
+  float* hc;         // in/out (+=): adjoint of the tangent of h (NULL: not needed)
 };
-// which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...)
+// which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...),
+//        3 tangent forward (Ad), 4 second-order edge adjoint (Rb, Rc),
+//        5 second-order node adjoint (hb, hc += ...)
 void launch_tp(int which, const TpArgs& a, hipStream_t st);
 
 // ---- per-atom stages (node.hip) -----------------------------------------------------
@@ -247,6 +260,27 @@ void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, in
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
                        const float* dY, float4* g, int accumulate, float rc, int p, hipStream_t st);
+
+// ---- second-order passes (radial.hip, grad.hip) -------------------------------------
+void launch_radial_dual_fwd(int n_basis, const float4* dvec, const float4* dd, const int* row_ptr_x, int N, long e_cap,
+                            const float* W1, const float* W2, const float* W3, int ld3, int PC, float* Rd, float* Bd,
+                            float* P1d, float* H1d, float* P2d, float* H2d, float rc, int p, hipStream_t st);
+void launch_radial_dual_bwd(const int* row_ptr_x, int N, long e_cap, const float* W2T, const float* W3T, int PC,
+                            const float* Rb, const float* Rc, const float* P1d, const float* P2d, float* P1g,
+                            float* P2g, hipStream_t st);
+void launch_edge_tangent(const int* row_ptr, const int* src, const float4* dvec, const float* v, int N, float4* dd,
+                         hipStream_t st);
+void launch_gate_dual_fwd(const float* x, const float* xd, float* hd, int N, int nc, int C, hipStream_t st);
+void launch_gate_dual_bwd(const float* x, const float* xd, const float* hb, const float* hc, float* xb, float* xc,
+                          int N, int nc, int C, hipStream_t st);
+void launch_readout_dual(const float* h, const float* hd, int nc, const int* owner, const double* gE, const float* Wr,
+                         const float* w2, int N, int C, float* Pb, float* Pc, float* w2c, float* hb, float* hc,
+                         float* eb, hipStream_t st);
+void launch_group_sum(const float* X, long ld, const int* species, int n_groups, int N, int ncols, double* out,
+                      long ld_out, hipStream_t st);
+int tn_chunks(long rows);
+void launch_gemm_tn(RowMap x1, RowMap y1, RowMap x2, RowMap y2, long rows, const int* rows_dev, int mo, int no,
+                    float* partial, double* out, long ld_out, hipStream_t st);
 
 // ---- MD (md.hip) -----------------------------------------------------------------------
 void launch_kick(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa, int N,

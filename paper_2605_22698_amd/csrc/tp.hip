@@ -248,6 +248,222 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
   }
 }
 
+// ---- second order: reverse over the tangent along a position direction v ----
+//   A_dot = TP(h_dot, Y, R) + TP(h, Y_dot, R) + TP(h, Y, R_dot)
+// with Y_dot, R_dot the changes of the edge harmonics and radial weights when
+// every atom moves along v (d_dot = v_j - v_i). The reverse pass only needs the
+// adjoints of R, R_dot, h and h_dot (Y has no parameters).
+
+template <int LMAX, int KIND, int CPT>
+__global__ void __launch_bounds__(256) k_tp_dual_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
+                                                     const float4* __restrict__ dvec, const float4* __restrict__ dd,
+                                                     const float* __restrict__ R, const float* __restrict__ Rd,
+                                                     int r_stride, const float* __restrict__ h,
+                                                     const float* __restrict__ hd, int h_nc, float* __restrict__ Ad,
+                                                     int N, int C, float inv_nu) {
+  using PS = PathSet<LMAX, KIND>;
+  constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
+  const int i = blockIdx.x;
+  const int tpr = blockDim.x;
+  float acc[CPT][NOUT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) acc[c][o] = 0.0f;
+  const int e1 = row_ptr[i + 1];
+  for (int e = row_ptr[i]; e < e1; ++e) {
+    const int j = src[e];
+    float Y[NY], Yd[NY];
+    real_sh_dual<LMAX>(dvec[e], dd[e], Y, Yd);
+    const float* Re = R + (long)e * r_stride;
+    const float* Rde = Rd + (long)e * r_stride;
+    const float* hj = h + (long)j * h_nc * C;
+    const float* hdj = hd ? hd + (long)j * h_nc * C : nullptr;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int k = threadIdx.x + c * tpr;
+      float hv[NIN], hdv[NIN];
+#pragma unroll
+      for (int q = 0; q < NIN; ++q) {
+        hv[q] = hj[q * C + k];
+        hdv[q] = hdj ? hdj[q * C + k] : 0.0f;
+      }
+      static_for<NP>([&](auto pi) {
+        constexpr int g = PS::T.id[pi];
+        constexpr int l1 = kL1[g], l2 = kL2[g], l3 = kL3[g];
+        constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
+        constexpr int off = PS::T.off[pi];
+        const float rp = Re[pi * C + k], rdp = Rde[pi * C + k];
+        float tm[2 * l3 + 1], td[2 * l3 + 1];
+#pragma unroll
+        for (int m = 0; m < 2 * l3 + 1; ++m) tm[m] = td[m] = 0.0f;
+        static_for<nz>([&](auto z) {
+          constexpr int q = z0 + z;
+          const float a = hv[l1 * l1 + kM1[q]], ad = hdv[l1 * l1 + kM1[q]];
+          tm[kM3[q]] += a * (kC[q] * Y[l2 * l2 + kM2[q]]);
+          td[kM3[q]] += kC[q] * (ad * Y[l2 * l2 + kM2[q]] + a * Yd[l2 * l2 + kM2[q]]);
+        });
+#pragma unroll
+        for (int m = 0; m < 2 * l3 + 1; ++m) acc[c][off + m] += rdp * tm[m] + rp * td[m];
+      });
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int k = threadIdx.x + c * tpr;
+    static_for<NP>([&](auto pi) {
+      constexpr int g = PS::T.id[pi];
+      constexpr int l3 = kL3[g];
+      constexpr int off = PS::T.off[pi], rank = PS::T.rank[pi];
+      constexpr int P3 = PS::T.np_l3[l3];
+      float* base = Ad + a_group_base<PS>(l3, N, C);
+#pragma unroll
+      for (int m = 0; m < 2 * l3 + 1; ++m)
+        base[(((long)i * (2 * l3 + 1) + m) * P3 + rank) * C + k] = acc[c][off + m] * inv_nu;
+    });
+  }
+}
+
+template <int LMAX, int KIND, int CPT>
+__global__ void __launch_bounds__(256) k_tp_dual_bwd_edge(const int* __restrict__ row_ptr, const int* __restrict__ src,
+                                                          const float4* __restrict__ dvec, const float4* __restrict__ dd,
+                                                          int r_stride, const float* __restrict__ h,
+                                                          const float* __restrict__ hd, int h_nc,
+                                                          const float* __restrict__ Ab, const float* __restrict__ Ac,
+                                                          float* __restrict__ Rb, float* __restrict__ Rc, int N, int C,
+                                                          float inv_nu) {
+  using PS = PathSet<LMAX, KIND>;
+  constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
+  const int i = blockIdx.x;
+  const int tpr = blockDim.x;
+  float ab[CPT][NOUT], ac[CPT][NOUT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int k = threadIdx.x + c * tpr;
+    static_for<NP>([&](auto pi) {
+      constexpr int g = PS::T.id[pi];
+      constexpr int l3 = kL3[g];
+      constexpr int off = PS::T.off[pi], rank = PS::T.rank[pi];
+      constexpr int P3 = PS::T.np_l3[l3];
+      const long gb = a_group_base<PS>(l3, N, C);
+#pragma unroll
+      for (int m = 0; m < 2 * l3 + 1; ++m) {
+        const long idx = gb + (((long)i * (2 * l3 + 1) + m) * P3 + rank) * C + k;
+        ab[c][off + m] = Ab[idx] * inv_nu;
+        ac[c][off + m] = Ac[idx] * inv_nu;
+      }
+    });
+  }
+  const int e1 = row_ptr[i + 1];
+  for (int e = row_ptr[i]; e < e1; ++e) {
+    const int j = src[e];
+    float Y[NY], Yd[NY];
+    real_sh_dual<LMAX>(dvec[e], dd[e], Y, Yd);
+    const float* hj = h + (long)j * h_nc * C;
+    const float* hdj = hd ? hd + (long)j * h_nc * C : nullptr;
+    float* Rbe = Rb + (long)e * r_stride;
+    float* Rce = Rc + (long)e * r_stride;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int k = threadIdx.x + c * tpr;
+      float hv[NIN], hdv[NIN];
+#pragma unroll
+      for (int q = 0; q < NIN; ++q) {
+        hv[q] = hj[q * C + k];
+        hdv[q] = hdj ? hdj[q * C + k] : 0.0f;
+      }
+      static_for<NP>([&](auto pi) {
+        constexpr int g = PS::T.id[pi];
+        constexpr int l1 = kL1[g], l2 = kL2[g], l3 = kL3[g];
+        constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
+        constexpr int off = PS::T.off[pi];
+        float tm[2 * l3 + 1], td[2 * l3 + 1];
+#pragma unroll
+        for (int m = 0; m < 2 * l3 + 1; ++m) tm[m] = td[m] = 0.0f;
+        static_for<nz>([&](auto z) {
+          constexpr int q = z0 + z;
+          const float a = hv[l1 * l1 + kM1[q]], ad = hdv[l1 * l1 + kM1[q]];
+          tm[kM3[q]] += a * (kC[q] * Y[l2 * l2 + kM2[q]]);
+          td[kM3[q]] += kC[q] * (ad * Y[l2 * l2 + kM2[q]] + a * Yd[l2 * l2 + kM2[q]]);
+        });
+        float sb = 0.0f, sc = 0.0f;
+#pragma unroll
+        for (int m = 0; m < 2 * l3 + 1; ++m) {
+          sb += ab[c][off + m] * tm[m] + ac[c][off + m] * td[m];
+          sc += ac[c][off + m] * tm[m];
+        }
+        Rbe[pi * C + k] = sb;
+        Rce[pi * C + k] = sc;
+      });
+    }
+  }
+}
+
+template <int LMAX, int KIND, int CPT>
+__global__ void __launch_bounds__(256) k_tp_dual_bwd_node(const int* __restrict__ row_ptr, const int* __restrict__ src,
+                                                          const float4* __restrict__ dvec, const float4* __restrict__ dd,
+                                                          const float* __restrict__ R, const float* __restrict__ Rd,
+                                                          int r_stride, const float* __restrict__ Ab,
+                                                          const float* __restrict__ Ac, float* __restrict__ hb,
+                                                          float* __restrict__ hc, int dh_nc, int N, int C,
+                                                          float inv_nu) {
+  using PS = PathSet<LMAX, KIND>;
+  constexpr int NP = PS::NP, NIN = PS::NIN, NY = PS::NY;
+  const int j = blockIdx.x;
+  const int tpr = blockDim.x;
+  float accb[CPT][NIN], accc[CPT][NIN];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int q = 0; q < NIN; ++q) accb[c][q] = accc[c][q] = 0.0f;
+  const int e1 = row_ptr[j + 1];
+  for (int e = row_ptr[j]; e < e1; ++e) {
+    const int i2 = src[e];  // receiver of the reverse edge
+    const float4 d = dvec[e], v = dd[e];
+    float Y[NY], Yd[NY];
+    // the reverse edge has vector -d and tangent -d_dot
+    real_sh_dual<LMAX>(make_float4(-d.x, -d.y, -d.z, d.w), make_float4(-v.x, -v.y, -v.z, v.w), Y, Yd);
+    const float* Re = R + (long)e * r_stride;
+    const float* Rde = Rd + (long)e * r_stride;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int k = threadIdx.x + c * tpr;
+      static_for<NP>([&](auto pi) {
+        constexpr int g = PS::T.id[pi];
+        constexpr int l1 = kL1[g], l2 = kL2[g], l3 = kL3[g];
+        constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
+        constexpr int rank = PS::T.rank[pi];
+        constexpr int P3 = PS::T.np_l3[l3];
+        const float rp = Re[pi * C + k], rdp = Rde[pi * C + k];
+        const long gb = a_group_base<PS>(l3, N, C);
+        float u[2 * l3 + 1], w[2 * l3 + 1];
+#pragma unroll
+        for (int m = 0; m < 2 * l3 + 1; ++m) {
+          const long idx = gb + (((long)i2 * (2 * l3 + 1) + m) * P3 + rank) * C + k;
+          const float ab = Ab[idx], ac = Ac[idx];
+          u[m] = rp * ab + rdp * ac;  // multiplies Y
+          w[m] = rp * ac;             // multiplies Y_dot (h adjoint) and Y (h_dot adjoint)
+        }
+        static_for<nz>([&](auto z) {
+          constexpr int q = z0 + z;
+          const float y = kC[q] * Y[l2 * l2 + kM2[q]], yd = kC[q] * Yd[l2 * l2 + kM2[q]];
+          accb[c][l1 * l1 + kM1[q]] += y * u[kM3[q]] + yd * w[kM3[q]];
+          accc[c][l1 * l1 + kM1[q]] += y * w[kM3[q]];
+        });
+      });
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int k = threadIdx.x + c * tpr;
+#pragma unroll
+    for (int q = 0; q < NIN; ++q) {
+      hb[((long)j * dh_nc + q) * C + k] += accb[c][q] * inv_nu;
+      if (hc) hc[((long)j * dh_nc + q) * C + k] += accc[c][q] * inv_nu;
+    }
+  }
+}
+
 }  // namespace
 
 // ---- dispatch ---------------------------------------------------------------
@@ -262,21 +478,31 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
   else if (which == 1)
     k_tp_bwd_edge<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.dA,
                                                          a.dR, a.dY, a.N, a.C, a.inv_nu);
-  else
+  else if (which == 2)
     k_tp_bwd_node<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
                                                          a.dh_nc, a.N, a.C, a.inv_nu);
+  else if (which == 3)
+    k_tp_dual_fwd<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.R, a.Rd, a.r_stride, a.h,
+                                                         a.hd, a.h_nc, a.Ad, a.N, a.C, a.inv_nu);
+  else if (which == 4)
+    k_tp_dual_bwd_edge<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.r_stride, a.h, a.hd,
+                                                              a.h_nc, a.Ab, a.Ac, a.Rb, a.Rc, a.N, a.C, a.inv_nu);
+  else
+    k_tp_dual_bwd_node<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.R, a.Rd, a.r_stride,
+                                                              a.Ab, a.Ac, a.hb, a.hc, a.dh_nc, a.N, a.C, a.inv_nu);
 }
 
 template <int LMAX, int KIND>
 static void tp_cpt(int which, const TpArgs& a, hipStream_t st) {
-  switch (a.cpt) {
-    case 1: return tp_launch<LMAX, KIND, 1>(which, a, st);
-    case 2: return tp_launch<LMAX, KIND, 2>(which, a, st);
-    case 4:
-      if constexpr (KIND != kFull) return tp_launch<LMAX, KIND, 4>(which, a, st);
-      [[fallthrough]];
-    default: throw Error(E3MI_EUNSUPPORTED, "channels per thread not supported for this layer");
+  // Layers with every path keep one channel per thread (the accumulators of
+  // 99 outputs already fill the register file); the others take two.
+  if constexpr (KIND == kFull) {
+    if (a.cpt == 1) return tp_launch<LMAX, KIND, 1>(which, a, st);
+  } else {
+    if (a.cpt == 1) return tp_launch<LMAX, KIND, 1>(which, a, st);
+    if (a.cpt == 2) return tp_launch<LMAX, KIND, 2>(which, a, st);
   }
+  throw Error(E3MI_EUNSUPPORTED, "channels per thread not supported for this layer");
 }
 
 template <int LMAX>

@@ -51,7 +51,7 @@ def test_config_errors(lib):
     cfg = synth.tiny_config()[0]
     bad = cfg.to_json().replace('"lmax": 2', '"lmax": 5').encode()
     assert lib.e3mi_weight_count(bad, ctypes.byref(n)) == -6
-    bad = cfg.to_json().replace('"channels": 32', '"channels": 40').encode()
+    bad = cfg.to_json().replace('"channels": 32', '"channels": 96').encode()
     assert lib.e3mi_weight_count(bad, ctypes.byref(n)) == -6
     assert lib.e3mi_weight_count(cfg.to_json().encode(), None) == -1
 

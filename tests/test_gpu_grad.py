@@ -1,0 +1,77 @@
+"""Parameter gradients of an energy + force loss (second order through F):
+the library's pass behind torch.autograd vs the oracle's double backward."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import model as om
+from tests.gpu_util import device, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_loss_grads(cfg, seed_key, b, e_ref, f_ref, w_e=1.0, w_f=1.0, skin=0.5):
+    import torch
+    import paper_2605_22698_amd as e3
+    d = device()
+    wflat = synth.flatten_weights(cfg, synth.model_weights(cfg, seed_key))
+    m = e3.Model(cfg.to_json(), wflat, device=d)
+    pos = torch.tensor(b.pos, dtype=torch.float64, device=d)
+    sp = torch.tensor(b.species, dtype=torch.int32, device=d)
+    g = m.build_graph(b.offsets, pos, sp, b.cell, b.pbc, cfg.cutoff, skin)
+    w = torch.tensor(wflat, dtype=torch.float64, device=d, requires_grad=True)
+    E, F = e3.energy_forces(w, pos, m, g)
+    loss = (w_e * torch.mean((E - torch.tensor(e_ref, device=d)) ** 2)
+            + w_f * torch.sum((F.double() - torch.tensor(f_ref, device=d)) ** 2) / F.numel())
+    loss.backward()
+    torch.cuda.synchronize()
+    return loss.item(), w.grad.cpu().numpy()
+
+
+def _compare(cfg, seed_key, b, e_ref, f_ref, w_e=1.0, w_f=1.0, rel=2e-4):
+    loss_g, grad_g = _gpu_loss_grads(cfg, seed_key, b, e_ref, f_ref, w_e, w_f)
+    m = om.Model(cfg, synth.model_weights(cfg, seed_key))
+    loss_o, grads_o = om.loss_and_grads(m, b, e_ref, f_ref, w_e, w_f)
+    flat_o = synth.flatten_weights(cfg, grads_o)
+    assert abs(loss_g - loss_o) <= 1e-5 * abs(loss_o)
+    tot = np.linalg.norm(grad_g - flat_o) / np.linalg.norm(flat_o)
+    say(f"  loss {loss_o:.6e}; gradient rel L2 error {tot:.2e}")
+    assert tot <= rel
+    off = 0
+    for name, shape, _ in synth.weight_shapes(cfg):
+        n = int(np.prod(shape))
+        a, r = grad_g[off:off + n], flat_o[off:off + n]
+        off += n
+        nr = np.linalg.norm(r)
+        if nr > 1e-9 * np.linalg.norm(flat_o):
+            assert np.linalg.norm(a - r) <= 1e-3 * nr, (name, np.linalg.norm(a - r) / nr)
+        else:
+            assert np.linalg.norm(a) <= 1e-6 * np.linalg.norm(flat_o) + 1e-12, name
+
+
+def test_energy_and_force_loss_small_batch():
+    cfg, b, e_ref, f_ref = synth.differentiation_config(3, 20, 60)
+    say(f"grad: batch N={b.n_atoms}")
+    _compare(cfg, 3, b, e_ref, f_ref)
+
+
+def test_force_only_and_energy_only():
+    cfg, b, e_ref, f_ref = synth.differentiation_config(2, 25, 40)
+    _compare(cfg, 3, b, e_ref, f_ref, w_e=0.0, w_f=1.0)
+    _compare(cfg, 3, b, e_ref, f_ref, w_e=1.0, w_f=0.0)
+
+
+def test_three_layers_lmax2():
+    cfg = synth.ModelConfig(lmax=2, channels=32, layers=3, n_species=3, cutoff=5.0, avg_neighbors=20.0)
+    rng = np.random.default_rng(61)
+    b = synth.concat([synth.jittered_lattice(n, 0.1, 0.3, 3, rng) for n in (18, 33)])
+    e_ref = rng.standard_normal(2)
+    f_ref = rng.standard_normal((b.n_atoms, 3)) * 0.01
+    _compare(cfg, 8, b, e_ref, f_ref)
+
+
+def test_open_cluster_lmax3_three_layers():
+    cfg = synth.ModelConfig(lmax=3, channels=64, layers=3, n_species=3, cutoff=5.0, avg_neighbors=15.0)
+    rng = np.random.default_rng(62)
+    b = synth.uniform_cluster(20, 8.0, 1.0, 3, rng)
+    _compare(cfg, 9, b, rng.standard_normal(1), rng.standard_normal((20, 3)) * 0.01)
