@@ -167,7 +167,8 @@ int e3mi_graph_last_edge_count(const e3mi_graph* graph, int64_t* n_edges, void* 
  * FP64, forces, neighbour lists) stays on the device. Inputs as for
  * e3mi_build_graph plus: vel device FP64 [N, 3] (angstrom/fs), masses host
  * FP64 [n_species] (amu), rebuild_every >= 1 (steps between neighbour
- * rebuilds). Positions are wrapped into the cell at every rebuild. The device
+ * rebuilds). Positions are kept as integrated (never wrapped; image indices
+ * must stay within +-127 cells, else EOVERFLOW at the next rebuild). The device
  * tracks each atom's displacement since the last rebuild; when a scheduled
  * rebuild finds that some atom moved more than skin/2 in the interval, it is
  * counted as a skin violation and the interval is halved from then on.

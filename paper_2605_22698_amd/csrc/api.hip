@@ -427,7 +427,7 @@ int cpt_for(const LayerPlan& L, int C) {
 // h~ = sum_p A_p W_l3[p] + h_in S_l3 for every computed output order l3 (rows
 // (atom, m), columns channels). `hin` may be NULL (no self connection term).
 void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* A, const float* hin, float* ht, int N,
-                hipStream_t st) {
+                hipStream_t st, bool bf16 = false) {
   const int C = M->cfg.channels;
   long gbase = 0;
   for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
@@ -446,7 +446,7 @@ void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
     ga.c = RowMap{ht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
     ga.M = N * g;
     ga.Nc = C;
-    launch_gemm(ga, st);
+    launch_gemm(ga, st, bf16);
     gbase += (long)N * g * P3 * C;
   }
 }
@@ -454,7 +454,7 @@ void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
 // Adjoint of the channel mix: dA = dht W^T per order, and (when dprev is not
 // NULL) dprev[l3] (+)= dht[l3] S^T for the orders present in the input.
 void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* dht, float* dA, float* dprev,
-                        int N, hipStream_t st) {
+                        int N, hipStream_t st, bool bf16 = false) {
   const int C = M->cfg.channels;
   long gbase = 0;
   for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
@@ -467,7 +467,7 @@ void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
     ga.c = RowMap{dA + gbase, (long)gg * P3 * C, (long)P3 * C, gg};
     ga.M = N * gg;
     ga.Nc = P3 * C;
-    launch_gemm(ga, st);
+    launch_gemm(ga, st, bf16);
     gbase += (long)N * gg * P3 * C;
   }
   if (!dprev) return;
@@ -481,14 +481,14 @@ void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
     ga.c = RowMap{dprev + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, gg};
     ga.M = N * gg;
     ga.Nc = C;
-    launch_gemm(ga, st);
+    launch_gemm(ga, st, bf16);
   }
 }
 
 // Primal forward pass: edge selection, embedding and every layer. Leaves
 // h^t, h~^t and R^t of every layer in the workspace; A in one shared buffer,
 // or per layer when keep_A (the parameter-gradient pass needs them).
-void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, hipStream_t st) {
+void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, hipStream_t st, bool bf16) {
   const Config& c = M->cfg;
   Allocator* a = &M->alloc;
   const int N = G->N, S = G->S, C = c.channels, T = c.layers;
@@ -549,7 +549,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     {
       ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
       launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                        W.rad3.as<float>(), L.p_full * C, PCu, R, rc, p_env, st);
+                        W.rad3.as<float>(), L.p_full * C, PCu, R, rc, p_env, bf16, st);
     }
     TpArgs ta{};
     ta.lmax = c.lmax;
@@ -573,7 +573,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     float* ht = w.ht[t]->as<float>();
     {
       ProfScope ps(&M->prof, stage_id(kMixFwd, t), st);
-      launch_mix(M, L, W, A, hin, ht, N, st);
+      launch_mix(M, L, W, A, hin, ht, N, st, bf16);
     }
     {
       ProfScope ps(&M->prof, stage_id(kGateFwd, t), st);
@@ -595,7 +595,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     E3MI_HIP(hipMemsetAsync(energy, 0, sizeof(double) * S, st));
     return;
   }
-  forward_pass(M, G, pos, false, st);
+  forward_pass(M, G, pos, false, st, M->precision == E3MI_BF16_MIX);
   const int* row_ptr = G->row_ptr_x->as<int>();
   const int* src = G->src_x->as<int>();
   const float4* dvec = G->dvec_x->as<float4>();
@@ -628,7 +628,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     {
       ProfScope ps(&M->prof, stage_id(kMixBwd, t), st);
       if (t > 1) E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
-      launch_mix_adjoint(M, L, W, dht, A, t > 1 ? dother : nullptr, N, st);
+      launch_mix_adjoint(M, L, W, dht, A, t > 1 ? dother : nullptr, N, st, M->precision == E3MI_BF16_MIX);
     }
     TpArgs ta{};
     ta.lmax = c.lmax;
@@ -655,7 +655,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
       launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                         W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->as<float>(), w.dY->as<float>(), g,
-                        t != T ? 1 : 0, rc, p_env, st);
+                        t != T ? 1 : 0, rc, p_env, M->precision == E3MI_BF16_MIX, st);
     }
     if (t > 1) {
       ta.dh = dother;
@@ -756,7 +756,6 @@ e3mi_model* new_model(const char* json, const double* wts, size_t n, int precisi
   M->cfg = parse_config(json);
   const Config& c = M->cfg;
   E3MI_REQUIRE(precision == E3MI_FP32 || precision == E3MI_BF16_MIX, E3MI_EINVAL, "unknown precision");
-  E3MI_REQUIRE(precision == E3MI_FP32, E3MI_EUNSUPPORTED, "BF16 mode is not available in this build");
   M->precision = precision;
   E3MI_REQUIRE(wts, E3MI_EINVAL, "weights are NULL");
   const size_t expect = weight_count(c);
@@ -831,7 +830,7 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
   const WeightOffsets off = weight_offsets(c);
   E3MI_HIP(hipMemsetAsync(out, 0, sizeof(double) * off.total, st));
   if (N == 0) return;
-  forward_pass(M, G, pos, true, st);
+  forward_pass(M, G, pos, true, st, false);
   const int* row_ptr = G->row_ptr_x->as<int>();
   const int* src = G->src_x->as<int>();
   const float4* dvec = G->dvec_x->as<float4>();
@@ -1008,10 +1007,13 @@ void set_weights(e3mi_model* M, const double* wts, size_t n) {
 
 constexpr double kAccelUnit = 0.009648533;  // angstrom/fs^2 per (eV/angstrom)/amu
 
+// Positions are never wrapped: the cell list bins wrapped copies internally and
+// the image vectors refer to the raw positions, so a trajectory does not
+// depend on when its rebuilds happen (a request gives the same bits alone and
+// packed with others).
 void md_rebuild(e3mi_md* D, hipStream_t st) {
   e3mi_graph* G = D->graph;
   ProfScope ps(&D->model->prof, stage_id(kGraphBuild), st);
-  launch_wrap(D->x->as<double>(), G->owner->as<int>(), G->box_d->as<double>(), G->pbc_d->as<uint8_t>(), D->N, st);
   build_lists(G, D->x->as<double>(), st);
   D->since_build = 0;
   D->rebuilds++;
@@ -1057,8 +1059,6 @@ e3mi_md* new_md(e3mi_model* M, int S, const int64_t* off, const double* pos, con
   D->flag->ensure(sizeof(int));
   E3MI_HIP(hipMemsetAsync(D->flag->p, 0, sizeof(int), st));
   D->graph = new_graph(M, S, off, D->x->as<double>(), D->species->as<int>(), cell, pbc, cutoff, skin, st);
-  md_rebuild(D.get(), st);  // wrapped positions, lists relative to them
-  D->rebuilds = 0;
   energy_forces(M, D->graph, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
   E3MI_HIP(hipStreamSynchronize(st));
   return D.release();

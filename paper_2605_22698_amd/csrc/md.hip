@@ -4,7 +4,6 @@
 //   kick:  v += (dt/2) kappa F / m
 //   drift: x += dt v, and flag any atom that moved more than skin/2 since the
 //          neighbour lists were built (they must then be rebuilt)
-//   wrap:  move periodic coordinates back into [0, L) before a rebuild
 #include "common.h"
 #include "runtime.h"
 
@@ -36,19 +35,6 @@ __global__ void k_drift(double* __restrict__ x, const double* __restrict__ v, co
   if (d2 > limit2) atomicOr(flag, 1);
 }
 
-__global__ void k_wrap(double* __restrict__ x, const int* __restrict__ owner, const double* __restrict__ box,
-                       const uint8_t* __restrict__ pbc, int N) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int s = owner[i];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (pbc[3 * s + k]) {
-      const double L = box[3 * s + k];
-      x[3 * i + k] -= floor(x[3 * i + k] / L) * L;
-    }
-}
-
 __global__ void k_nonfinite(const double* __restrict__ x, int n, int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -68,10 +54,6 @@ void launch_drift(double* x, const double* v, const double* x_ref, double dt, do
                   hipStream_t st) {
   if (N == 0) return;
   k_drift<<<blocks(N, 256), 256, 0, st>>>(x, v, x_ref, dt, limit2, N, flag);
-}
-void launch_wrap(double* x, const int* owner, const double* box, const uint8_t* pbc, int N, hipStream_t st) {
-  if (N == 0) return;
-  k_wrap<<<blocks(N, 256), 256, 0, st>>>(x, owner, box, pbc, N);
 }
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st) {
   if (n == 0) return;

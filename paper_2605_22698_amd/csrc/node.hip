@@ -20,7 +20,9 @@ __device__ __forceinline__ long row_off(const RowMap& m, int r) {
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
 // 64x64 output tile per workgroup, K in steps of 16 staged through LDS, each
-// wave a 32x32 block on v_mfma_f32_32x32x2f32.
+// wave a 32x32 block on v_mfma_f32_32x32x2f32 (FP32), or with both operands
+// rounded to BF16 on v_mfma_f32_32x32x16_bf16 (BF), FP32 accumulation.
+template <bool BF>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs a) {
   __shared__ float As[64][17];
   __shared__ float Bs[16][65];
@@ -53,10 +55,21 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs a) {
         Bs[kr][c4 + 3] = v.w;
       }
       __syncthreads();
+      if constexpr (BF) {
+        const int k0 = 8 * (lane >> 5);
+        bf16x8 x, y;
 #pragma unroll
-      for (int kk = 0; kk < 16; kk += 2)
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[rb + (lane & 31)][kk + (lane >> 5)],
-                                                    Bs[kk + (lane >> 5)][cb + (lane & 31)], acc, 0, 0, 0);
+        for (int q = 0; q < 8; ++q) {
+          x[q] = (__bf16)As[rb + (lane & 31)][k0 + q];
+          y[q] = (__bf16)Bs[k0 + q][cb + (lane & 31)];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 2)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[rb + (lane & 31)][kk + (lane >> 5)],
+                                                      Bs[kk + (lane >> 5)][cb + (lane & 31)], acc, 0, 0, 0);
+      }
       __syncthreads();
     }
   }
@@ -188,12 +201,15 @@ inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_gemm(const GemmArgs& a, hipStream_t st) {
+void launch_gemm(const GemmArgs& a, hipStream_t st, bool bf16) {
   if (a.M == 0 || a.Nc == 0) return;
   if ((a.k0 % 4) || (a.k1 % 4) || (a.Nc % 4) || (a.ldb0 % 4) || (a.k1 && (a.ldb1 % 4)))
     throw Error(E3MI_EUNSUPPORTED, "GEMM dimensions must be multiples of 4");
   dim3 grid(blocks(a.M, 64), blocks(a.Nc, 64));
-  k_gemm<<<grid, 256, 0, st>>>(a);
+  if (bf16)
+    k_gemm<true><<<grid, 256, 0, st>>>(a);
+  else
+    k_gemm<false><<<grid, 256, 0, st>>>(a);
 }
 void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st) {
   if (N == 0) return;

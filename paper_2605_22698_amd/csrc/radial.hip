@@ -47,20 +47,69 @@ __device__ __forceinline__ void layer1(const float (*Bs)[NB + 1], const float* _
 }
 
 // acc (32x32 block of the wave) = X[rb:rb+32, :] * W[:, cb:cb+32], K = 64,
-// X from LDS, W row-major [64][ldw] from global memory.
+// X from LDS, W row-major [64][ldw] from global memory. BF: both operands
+// rounded to BF16 (nearest even) and multiplied on v_mfma_f32_32x32x16_bf16
+// (lane l supplies A[l%32][8 (l/32) .. +8] and B[8 (l/32) .. +8][l%32]),
+// FP32 accumulation either way.
+template <bool BF>
 __device__ __forceinline__ f32x16 block_64(const float (*X)[kLd], int rb, const float* __restrict__ W, int ldw, int cb) {
   const int lane = threadIdx.x & 63;
   f32x16 acc = {};
+  if constexpr (BF) {
+#pragma unroll
+    for (int kb = 0; kb < kH; kb += 16) {
+      const int k0 = kb + 8 * (lane >> 5);
+      bf16x8 a, b;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        a[q] = (__bf16)X[rb + (lane & 31)][k0 + q];
+        b[q] = (__bf16)W[(k0 + q) * ldw + cb + (lane & 31)];
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+  } else {
 #pragma unroll 8
-  for (int kk = 0; kk < kH; kk += 2) {
-    const float a = X[rb + (lane & 31)][kk + (lane >> 5)];
-    const float b = W[(kk + (lane >> 5)) * ldw + cb + (lane & 31)];
-    acc = mfma32(a, b, acc);
+    for (int kk = 0; kk < kH; kk += 2) {
+      const float a = X[rb + (lane & 31)][kk + (lane >> 5)];
+      const float b = W[(kk + (lane >> 5)) * ldw + cb + (lane & 31)];
+      acc = mfma32(a, b, acc);
+    }
   }
   return acc;
 }
 
-template <int NB>
+// Two 32x32 row blocks (rows 0-31 and 32-63 of X) times W[:, cc:cc+32], K = 64.
+template <bool BF>
+__device__ __forceinline__ void block_64x2(const float (*X)[kLd], const float* __restrict__ W, int ldw, int cc,
+                                           f32x16& a0, f32x16& a1) {
+  const int lane = threadIdx.x & 63;
+  a0 = f32x16{};
+  a1 = f32x16{};
+  if constexpr (BF) {
+#pragma unroll
+    for (int kb = 0; kb < kH; kb += 16) {
+      const int k0 = kb + 8 * (lane >> 5);
+      bf16x8 x0, x1, b;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        b[q] = (__bf16)W[(k0 + q) * ldw + cc + (lane & 31)];
+        x0[q] = (__bf16)X[lane & 31][k0 + q];
+        x1[q] = (__bf16)X[32 + (lane & 31)][k0 + q];
+      }
+      a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, b, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, b, a1, 0, 0, 0);
+    }
+  } else {
+#pragma unroll 8
+    for (int kk = 0; kk < kH; kk += 2) {
+      const float b = W[(kk + (lane >> 5)) * ldw + cc + (lane & 31)];
+      a0 = mfma32(X[lane & 31][kk + (lane >> 5)], b, a0);
+      a1 = mfma32(X[32 + (lane & 31)][kk + (lane >> 5)], b, a1);
+    }
+  }
+}
+
+template <int NB, bool BF>
 __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W3, int ld3, int PC,
@@ -84,20 +133,15 @@ __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ d
   __syncthreads();
   {
     const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-    const f32x16 acc = block_64(H, rb, W2, kH, cb);
+    const f32x16 acc = block_64<BF>(H, rb, W2, kH, cb);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 16; ++r) H[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(acc[r]);
   }
   __syncthreads();
   for (int cc = w * 32; cc < PC; cc += 128) {
-    f32x16 a0 = {}, a1 = {};
-#pragma unroll 8
-    for (int kk = 0; kk < kH; kk += 2) {
-      const float b = W3[(kk + (lane >> 5)) * ld3 + cc + (lane & 31)];
-      a0 = mfma32(H[lane & 31][kk + (lane >> 5)], b, a0);
-      a1 = mfma32(H[32 + (lane & 31)][kk + (lane >> 5)], b, a1);
-    }
+    f32x16 a0, a1;
+    block_64x2<BF>(H, W3, ld3, cc, a0, a1);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = acc_row(r, lane);
@@ -108,7 +152,7 @@ __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ d
   }
 }
 
-template <int NB, int LMAX>
+template <int NB, int LMAX, bool BF>
 __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W2T, const float* __restrict__ W3T,
@@ -140,7 +184,7 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   layer1<NB>(Bs, W1, P1, X);  // P1 = pre1, X = H1
   __syncthreads();
   {
-    const f32x16 acc = block_64(X, rb, W2, kH, cb);
+    const f32x16 acc = block_64<BF>(X, rb, W2, kH, cb);
 #pragma unroll
     for (int r = 0; r < 16; ++r) P2[rb + acc_row(r, lane)][cb + (lane & 31)] = acc[r];
   }
@@ -155,11 +199,25 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
       for (int q = 0; q < 8; ++q) Ds[row][c8 + q] = e < E ? dR[(long)e * PC + kc + c8 + q] : 0.0f;
     }
     __syncthreads();
+    if constexpr (BF) {
+#pragma unroll
+      for (int kb = 0; kb < 32; kb += 16) {
+        const int k0 = kb + 8 * (lane >> 5);
+        bf16x8 a, b;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a[q] = (__bf16)Ds[rb + (lane & 31)][k0 + q];
+          b[q] = (__bf16)W3T[(kc + k0 + q) * kH + cb + (lane & 31)];
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    } else {
 #pragma unroll 4
-    for (int kk = 0; kk < 32; kk += 2) {
-      const float a = Ds[rb + (lane & 31)][kk + (lane >> 5)];
-      const float b = W3T[(kc + kk + (lane >> 5)) * kH + cb + (lane & 31)];
-      acc = mfma32(a, b, acc);
+      for (int kk = 0; kk < 32; kk += 2) {
+        const float a = Ds[rb + (lane & 31)][kk + (lane >> 5)];
+        const float b = W3T[(kc + kk + (lane >> 5)) * kH + cb + (lane & 31)];
+        acc = mfma32(a, b, acc);
+      }
     }
   }
   __syncthreads();
@@ -172,7 +230,7 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   __syncthreads();
   {
     // dH1 = dpre2 W2^T ; dpre1 = dH1 * silu'(pre1) -> P2
-    const f32x16 a2 = block_64(X, rb, W2T, kH, cb);
+    const f32x16 a2 = block_64<BF>(X, rb, W2T, kH, cb);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
@@ -281,8 +339,8 @@ __global__ void __launch_bounds__(256) k_radial_dual_fwd(const float4* __restric
   __syncthreads();
   {
     const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-    const f32x16 a = block_64(X, rb, W2, kH, cb);
-    const f32x16 ad = block_64(Xt, rb, W2, kH, cb);
+    const f32x16 a = block_64<false>(X, rb, W2, kH, cb);
+    const f32x16 ad = block_64<false>(Xt, rb, W2, kH, cb);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -376,8 +434,8 @@ __global__ void __launch_bounds__(256) k_radial_dual_bwd(const int* __restrict__
     Xc[row][col] = pc;
   }
   __syncthreads();
-  const f32x16 hb = block_64(X, rb, W2T, kH, cb);
-  const f32x16 hc = block_64(Xc, rb, W2T, kH, cb);
+  const f32x16 hb = block_64<false>(X, rb, W2T, kH, cb);
+  const f32x16 hc = block_64<false>(Xc, rb, W2T, kH, cb);
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
@@ -396,24 +454,38 @@ inline int tiles(long n) { return (int)((n + kTile - 1) / kTile); }
 }  // namespace
 
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
-                       const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, hipStream_t st) {
+                       const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, bool bf16,
+                       hipStream_t st) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (PC % 32) throw Error(E3MI_EUNSUPPORTED, "paths x channels must be a multiple of 32");
-  k_radial_fwd<8><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p);
+  if (bf16)
+    k_radial_fwd<8, true><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p);
+  else
+    k_radial_fwd<8, false><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p);
+}
+
+template <int LMAX>
+static void radial_bwd_l(bool bf16, long e_cap, const float4* dvec, const int* row_ptr_x, int N, const float* W1,
+                         const float* W2, const float* W2T, const float* W3T, int PC, const float* dR, const float* dY,
+                         float4* g, int accumulate, float rc, int p, hipStream_t st) {
+  if (bf16)
+    k_radial_bwd<8, LMAX, true><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g,
+                                                              accumulate, rc, p);
+  else
+    k_radial_bwd<8, LMAX, false><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g,
+                                                               accumulate, rc, p);
 }
 
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
-                       const float* dY, float4* g, int accumulate, float rc, int p, hipStream_t st) {
+                       const float* dY, float4* g, int accumulate, float rc, int p, bool bf16, hipStream_t st) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (lmax == 3)
-    k_radial_bwd<8, 3><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate,
-                                                     rc, p);
+    radial_bwd_l<3>(bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st);
   else if (lmax == 2)
-    k_radial_bwd<8, 2><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate,
-                                                     rc, p);
+    radial_bwd_l<2>(bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st);
   else
     throw Error(E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
 }

@@ -245,7 +245,7 @@ struct GemmArgs {
   RowMap c;
   int M, Nc, accumulate;
 };
-void launch_gemm(const GemmArgs& a, hipStream_t st);
+void launch_gemm(const GemmArgs& a, hipStream_t st, bool bf16 = false);
 void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st);
 void launch_gate_bwd(const float* ht, const float* dh, float* dht, int N, int nc, int C, hipStream_t st);
 void launch_embed(const int* species, const float* emb, float* h0, int N, int C, hipStream_t st);
@@ -256,10 +256,11 @@ void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, f
 
 // ---- radial MLP (radial.hip) ---------------------------------------------------------
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
-                       const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, hipStream_t st);
+                       const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, bool bf16,
+                       hipStream_t st);
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
-                       const float* dY, float4* g, int accumulate, float rc, int p, hipStream_t st);
+                       const float* dY, float4* g, int accumulate, float rc, int p, bool bf16, hipStream_t st);
 
 // ---- second-order passes (radial.hip, grad.hip) -------------------------------------
 void launch_radial_dual_fwd(int n_basis, const float4* dvec, const float4* dd, const int* row_ptr_x, int N, long e_cap,
@@ -287,7 +288,6 @@ void launch_kick(double* v, const float* F, const int* species, const double* in
                  hipStream_t st);
 void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N, int* flag,
                   hipStream_t st);
-void launch_wrap(double* x, const int* owner, const double* box, const uint8_t* pbc, int N, hipStream_t st);
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st);
 void launch_rekey(const int* src, const int* shift, int E, uint64_t* keys, hipStream_t st);
 

@@ -124,3 +124,20 @@ def test_translation_and_image_shift_invariance():
     E1, F1, _, _ = gpu_energy_forces(m, moved, skin=0.5)
     np.testing.assert_allclose(E1, E0, rtol=1e-6)
     np.testing.assert_allclose(F1, F0, atol=1e-6 * np.abs(F0).max())
+
+
+def test_bf16_mode_errors_against_oracle():
+    # BF16 operands for the radial-MLP and channel-mix GEMMs (FP32 accumulation);
+    # the errors are reported and only bounded loosely.
+    ref = np.load(os.path.join(HERE, "golden", "single_3000.npz"))
+    cfg, b = synth.single_config()
+    E32, F32, _, _ = gpu_energy_forces(model(cfg, 2), b, skin=1.0)
+    E16, F16, _, _ = gpu_energy_forces(model(cfg, 2, precision=1), b, skin=1.0)
+    fmax = np.abs(ref["forces"]).max()
+    e16 = abs(E16[0] - ref["energy"][0]) / abs(ref["energy"][0])
+    f16 = np.abs(F16 - ref["forces"]).max() / fmax
+    e32 = abs(E32[0] - ref["energy"][0]) / abs(ref["energy"][0])
+    f32 = np.abs(F32 - ref["forces"]).max() / fmax
+    say(f"BF16: energy rel err {e16:.2e}, force err {f16:.2e} of max |F|; FP32: {e32:.2e}, {f32:.2e}")
+    assert e16 < 2e-2 and f16 < 5e-2
+    assert not np.array_equal(F16, F32)
