@@ -80,6 +80,41 @@ def work_model(cfg, t, E, N):
     return out
 
 
+def serving_run(e3, synth, torch, dev, n_requests, log):
+    """Continuous-batching MD: Poisson arrivals, atom counts log-uniform in
+    [50, 5000], 0.1 atoms/A^3, 4 species, l_max 3, 128 channels, FP32,
+    0.5 fs steps at 300 K, rebuild every 20 steps, 100 steps per request;
+    arrival rate set so the offered load is about 80% of a measured capacity."""
+    from paper_2605_22698_amd.serving import GpuExecutor, Request, Server
+    cfg = synth.serving_model()
+    m = e3.Model(cfg.to_json(), synth.flatten_weights(cfg, synth.model_weights(cfg, 4)), device=dev)
+    reqs = synth.serving_requests(n_requests, rate_per_s=1.0)
+    n_steps = 100
+    mean_atoms = float(np.mean([r[1].n_atoms for r in reqs]))
+    # capacity probe: one packed batch of the first requests
+    ex = GpuExecutor(m, synth.SPECIES_MASS[:4], cfg.cutoff)
+    probe = [ex.upload(Request(k, 0.0, b.pos, v, b.species, b.cell[0], b.pbc[0], 1))
+             for k, (_, b, v) in enumerate(reqs[:4])]
+    ex.launch(probe)
+    ex.step()
+    ms = np.median([ex.step() for _ in range(5)])
+    ex.close()
+    cap = sum(p["pos"].shape[0] for p in probe) / (ms / 1e3)          # atom-steps/s
+    rate = 0.8 * cap / (mean_atoms * n_steps)                          # requests/s
+    arr = np.cumsum(np.random.default_rng(synth.MASTER_SEED).exponential(1.0 / rate, size=len(reqs)))
+    srv = Server(GpuExecutor(m, synth.SPECIES_MASS[:4], cfg.cutoff), budget_bytes=int(200e9))
+    for k, ((_, b, v), t) in enumerate(zip(reqs, arr)):
+        srv.submit(Request(k, float(t), b.pos, v, b.species, b.cell[0], b.pbc[0], n_steps))
+    stats = srv.run(idle_wait=lambda dt: time.sleep(min(dt, 0.01)))
+    summ = stats.summary()
+    waits = [r.admitted_at - r.arrival for r in srv.done if r.admitted_at is not None]
+    log(f"serving: {summ}")
+    return {"requests": len(reqs), "steps_per_request": n_steps, "mean_atoms": mean_atoms,
+            "arrival_rate_per_s": rate, "p50_step_ms": summ["p50_ms"], "p99_step_ms": summ["p99_ms"],
+            "atom_steps_per_s": summ["atom_steps_per_s"], "atom_steps_per_busy_s": summ["atom_steps_per_busy_s"],
+            "repacks": summ["repacks"], "p50_queue_wait_s": float(np.percentile(waits, 50)) if waits else 0.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +123,8 @@ def main():
     ap.add_argument("--atoms", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-atoms", type=int, default=400)
+    ap.add_argument("--no-extras", action="store_true", help="skip the BF16 and serving side measurements")
+    ap.add_argument("--serving-requests", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -170,6 +207,24 @@ def main():
     roof["avg_launch_ms"] = tot / n
     roof["algorithmic_per_launch"] = {"flops": flops, "bytes": nbytes, "edges": n_edges}
 
+    md.close()
+
+    # ---- side measurements: BF16 mode and continuous-batching serving ----
+    extras = {}
+    if not args.no_extras:
+        m16 = e3.Model(cfg.to_json(), w, precision=e3.BF16_MIX, device=dev)
+        md16 = e3.MD(m16, b.offsets, pos_d, vel_d, sp_d, masses, b.cell, b.pbc, cfg.cutoff, skin, rebuild_every)
+        md16.step(args.warmup, dt, energy)
+        torch.cuda.synchronize()
+        k16 = max(20, args.steps // 2)
+        t1 = time.perf_counter()
+        md16.step(k16, dt, energy)
+        torch.cuda.synchronize()
+        t16 = time.perf_counter() - t1
+        extras["bf16"] = {"value": b.n_atoms * k16 / t16, "ms_per_step": 1e3 * t16 / k16, "steps": k16}
+        md16.close()
+        extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, log)
+
     # ---- oracle on the host cores (bounded sample) ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -215,6 +270,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 

@@ -154,6 +154,14 @@ int e3mi_energy_forces(e3mi_model* model, e3mi_graph* graph, const double* pos, 
 int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, const double* grad_energy,
                     const float* grad_forces, double* grad_weights, void* stream);
 
+/* Evaluation options of a model (bit mask, default 0):
+ *   E3MI_FLAG_UNFACTORISED_FIRST_LAYER (1): evaluate the first layer like
+ *     the others (per-edge radial weights R and tensor product) instead of
+ *     the exact species factorisation of its neighbour sum (its input is the
+ *     embedding of the sender's species); results agree to rounding. */
+#define E3MI_FLAG_UNFACTORISED_FIRST_LAYER 1
+int e3mi_model_set_flags(e3mi_model* model, int flags);
+
 /* Replace the weights (host FP64, same configuration and layout as at
  * creation), e.g. after an optimiser step. Synchronises the device first. */
 int e3mi_model_set_weights(e3mi_model* model, const double* weights_host, size_t n_weights);

@@ -72,6 +72,10 @@ class Model:
         check(lib().e3mi_profile_query(self.handle, stage.encode(), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def set_flags(self, unfactorised_first_layer: bool = False) -> None:
+        """Evaluation options; see e3mi_model_set_flags."""
+        check(lib().e3mi_model_set_flags(self.handle, 1 if unfactorised_first_layer else 0))
+
     def set_weights(self, weights) -> None:
         """Replace the weights (FP64 vector in the documented layout; any device)."""
         w = weights.detach().to("cpu", dtype=__import__("torch").float64).contiguous().numpy() \

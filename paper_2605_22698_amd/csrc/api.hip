@@ -132,11 +132,11 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Timed stages (per layer where it applies: index = stage * 8 + layer).
 enum Stage : int {
   kPrune = 0, kEmbed, kRadialFwd, kTpFwd, kMixFwd, kGateFwd, kReadout, kGateBwd, kMixBwd, kTpBwdEdge,
-  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kNumStages
+  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
     "prune", "embed", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd", "mix_bwd",
-    "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build"};
+    "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build", "first_fwd", "first_bwd"};
 inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
 
 }  // namespace
@@ -154,6 +154,7 @@ struct Workspace {
   std::vector<std::unique_ptr<DevBuf>> Al, Ad, hd, htd, Rd, P1d, H1d, P2d, H2d;
   std::unique_ptr<DevBuf> dd, Bd, Prb, Prc, w2c, eb, xb, xc, Ab, Ac, hb_a, hb_b, hc_a, hc_b, Rb, Rc, P1g, P2g,
       partial, vf;
+  std::unique_ptr<DevBuf> G1, dG1;  // first layer, [N, (l3+1)^2, S*64]
 };
 
 }  // namespace e3mi
@@ -165,6 +166,9 @@ struct e3mi_model {
   std::vector<e3mi::LayerPlan> plans;
   std::vector<std::unique_ptr<e3mi::LayerWeights>> lw;
   std::unique_ptr<e3mi::DevBuf> emb, read1, read2, e0;
+  // first layer factorised by species: U_l [S*64, C] and U_l^T [C, S*64] per output order
+  bool first_factorised = true;
+  std::unique_ptr<e3mi::DevBuf> U[4], UT[4];
   e3mi::Workspace ws;
   e3mi::Profiler prof;
 };
@@ -485,6 +489,13 @@ void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
   }
 }
 
+// Whether the energy/force path evaluates layer 1 through the species
+// factorisation (first.hip): always possible for layer 1 (its input is the
+// embedding) when the species x hidden width fits the kernel's LDS budget.
+bool factorised_first(const e3mi_model* M) {
+  return M->first_factorised && M->cfg.n_species * M->cfg.radial_hidden <= 512;
+}
+
 // Primal forward pass: edge selection, embedding and every layer. Leaves
 // h^t, h~^t and R^t of every layer in the workspace; A in one shared buffer,
 // or per layer when keep_A (the parameter-gradient pass needs them).
@@ -539,10 +550,51 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     ProfScope ps(&M->prof, stage_id(kEmbed), st);
     launch_embed(species, M->emb->as<float>(), w.h[0]->as<float>(), N, C, st);
   }
+  const bool fact = factorised_first(M) && !keep_A;
+  const int S64 = c.n_species * c.radial_hidden;
+  if (fact) {
+    ensure(w.G1, a, sizeof(float) * (size_t)N * M->plans[0].nc_out * S64);
+    ensure(w.dG1, a, sizeof(float) * (size_t)N * M->plans[0].nc_out * S64);
+  }
   for (int t = 1; t <= T; ++t) {
     const LayerPlan& L = M->plans[t - 1];
     LayerWeights& W = *M->lw[t - 1];
     const float* hin = w.h[t - 1]->as<float>();
+    if (t == 1 && fact) {
+      float* G1 = w.G1->as<float>();
+      {
+        ProfScope ps(&M->prof, stage_id(kFirstFwd, 1), st);
+        launch_first(true, c.lmax, L.l3max_used, row_ptr, src, dvec, species, N, S64, W.rad1.as<float>(),
+                     W.rad2.as<float>(), nullptr, G1, nullptr, nullptr, 0, rc, p_env, st);
+      }
+      float* ht = w.ht[1]->as<float>();
+      {
+        ProfScope ps(&M->prof, stage_id(kMixFwd, 1), st);
+        for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
+          const int g = 2 * l3 + 1;
+          GemmArgs ga{};
+          ga.a0 = RowMap{G1 + (long)l3 * l3 * S64, (long)L.nc_out * S64, (long)S64, g};
+          ga.b0 = M->U[l3]->as<float>();
+          ga.ldb0 = C;
+          ga.k0 = S64;
+          if (l3 == 0) {
+            ga.a1 = RowMap{const_cast<float*>(hin), (long)C, (long)C, 1};
+            ga.b1 = W.self_[0].as<float>();
+            ga.ldb1 = C;
+            ga.k1 = C;
+          }
+          ga.c = RowMap{ht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
+          ga.M = N * g;
+          ga.Nc = C;
+          launch_gemm(ga, st, bf16);
+        }
+      }
+      {
+        ProfScope ps(&M->prof, stage_id(kGateFwd, 1), st);
+        launch_gate_fwd(ht, w.h[1]->as<float>(), N, L.nc_out, C, st);
+      }
+      continue;
+    }
     float* R = w.R[t]->as<float>();
     const int PCu = L.p_used * C;
     float* A = keep_A ? w.Al[t]->as<float>() : w.A->as<float>();
@@ -615,6 +667,8 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
   // ---- adjoint: dE/dr ----
   float* dht = w.dht->as<float>();
   float4* g = w.g->as<float4>();
+  const bool fact = factorised_first(M);
+  const int S64 = c.n_species * c.radial_hidden;
   for (int t = T; t >= 1; --t) {
     const LayerPlan& L = M->plans[t - 1];
     LayerWeights& W = *M->lw[t - 1];
@@ -624,6 +678,30 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     {
       ProfScope ps(&M->prof, stage_id(kGateBwd, t), st);
       launch_gate_bwd(w.ht[t]->as<float>(), dcur, dht, N, L.nc_out, C, st);
+    }
+    if (t == 1 && fact) {
+      float* dG1 = w.dG1->as<float>();
+      {
+        ProfScope ps(&M->prof, stage_id(kMixBwd, 1), st);
+        for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
+          const int gg = 2 * l3 + 1;
+          GemmArgs ga{};
+          ga.a0 = RowMap{dht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
+          ga.b0 = M->UT[l3]->as<float>();
+          ga.ldb0 = S64;
+          ga.k0 = C;
+          ga.c = RowMap{dG1 + (long)l3 * l3 * S64, (long)L.nc_out * S64, (long)S64, gg};
+          ga.M = N * gg;
+          ga.Nc = S64;
+          launch_gemm(ga, st, M->precision == E3MI_BF16_MIX);
+        }
+      }
+      {
+        ProfScope ps(&M->prof, stage_id(kFirstBwd, 1), st);
+        launch_first(false, c.lmax, L.l3max_used, row_ptr, src, dvec, species, N, S64, W.rad1.as<float>(),
+                     W.rad2.as<float>(), W.rad2T.as<float>(), nullptr, dG1, g, T != 1 ? 1 : 0, rc, p_env, st);
+      }
+      continue;
     }
     {
       ProfScope ps(&M->prof, stage_id(kMixBwd, t), st);
@@ -690,6 +768,49 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
   return b;
 }
 
+// Offsets of every weight tensor in the flat FP64 vector (file order).
+struct WeightOffsets {
+  size_t emb = 0, read1 = 0, read2 = 0, e0 = 0, total = 0;
+  std::vector<size_t> rad1, rad2, rad3;
+  std::vector<std::array<size_t, 4>> mix, self_;
+};
+
+WeightOffsets weight_offsets(const Config& c) {
+  WeightOffsets o;
+  const size_t C = c.channels, H = c.radial_hidden;
+  size_t cur = 0;
+  o.emb = cur;
+  cur += (size_t)c.n_species * C;
+  for (int t = 1; t <= c.layers; ++t) {
+    const LayerPlan L = plan_layer(c, t);
+    o.rad1.push_back(cur);
+    cur += (size_t)c.n_basis * H;
+    o.rad2.push_back(cur);
+    cur += H * H;
+    o.rad3.push_back(cur);
+    cur += H * (size_t)L.p_full * C;
+    std::array<size_t, 4> m{}, sf{};
+    for (int l3 = 0; l3 <= c.lmax; ++l3) {
+      m[l3] = cur;
+      cur += (size_t)L.p_full_l3[l3] * C * C;
+    }
+    for (int l = 0; l <= L.l1max; ++l) {
+      sf[l] = cur;
+      cur += C * C;
+    }
+    o.mix.push_back(m);
+    o.self_.push_back(sf);
+  }
+  o.read1 = cur;
+  cur += C * c.readout_hidden;
+  o.read2 = cur;
+  cur += c.readout_hidden;
+  o.e0 = cur;
+  cur += c.n_species;
+  o.total = cur;
+  return o;
+}
+
 // Convert the FP64 weights to FP32 device tensors (and the transposed copies
 // the adjoint GEMMs read). Buffers are reused when they exist.
 void upload_weights(e3mi_model* M, const double* wts) {
@@ -748,6 +869,29 @@ void upload_weights(e3mi_model* M, const double* wts) {
   M->read2 = upload_f32(a, take((size_t)c.readout_hidden));
   M->e0 = upload_f32(a, take((size_t)c.n_species));
   E3MI_REQUIRE(cur == weight_count(c), E3MI_EINVAL, "internal: weight cursor mismatch");
+  // U_l = nu^-1 (W3[:, l C + k] W_emb[s, k]) W_mix_l, rows (s, q), in FP64.
+  const WeightOffsets off = weight_offsets(c);
+  const LayerPlan L1p = plan_layer(c, 1);
+  const int S64 = c.n_species * H;
+  for (int l = 0; l <= L1p.l3max_used; ++l) {
+    std::vector<double> U((size_t)S64 * C, 0.0);
+    const double* W3 = wts + off.rad3[0];
+    const double* Wm = wts + off.mix[0][l];   // [C, C]: one path (0,l,l) per order
+    const double* We = wts + off.emb;
+    std::vector<double> V(C);
+    for (int sp = 0; sp < c.n_species; ++sp)
+      for (int q = 0; q < H; ++q) {
+        for (int k = 0; k < C; ++k) V[k] = W3[(size_t)q * L1p.p_full * C + (size_t)l * C + k] * We[(size_t)sp * C + k];
+        double* Ur = &U[((size_t)sp * H + q) * C];
+        for (int k = 0; k < C; ++k) {
+          const double v = V[k] / c.avg_neighbors;
+          for (int kp = 0; kp < C; ++kp) Ur[kp] += v * Wm[(size_t)k * C + kp];
+        }
+      }
+    std::vector<float> Uf(U.begin(), U.end());
+    M->U[l] = upload_f32(a, Uf);
+    M->UT[l] = upload_f32(a, transpose(Uf, S64, C));
+  }
 }
 
 e3mi_model* new_model(const char* json, const double* wts, size_t n, int precision, e3mi_alloc_fn al,
@@ -769,49 +913,6 @@ e3mi_model* new_model(const char* json, const double* wts, size_t n, int precisi
   return M.release();
 }
 
-
-// Offsets of every weight tensor in the flat FP64 vector (file order).
-struct WeightOffsets {
-  size_t emb = 0, read1 = 0, read2 = 0, e0 = 0, total = 0;
-  std::vector<size_t> rad1, rad2, rad3;
-  std::vector<std::array<size_t, 4>> mix, self_;
-};
-
-WeightOffsets weight_offsets(const Config& c) {
-  WeightOffsets o;
-  const size_t C = c.channels, H = c.radial_hidden;
-  size_t cur = 0;
-  o.emb = cur;
-  cur += (size_t)c.n_species * C;
-  for (int t = 1; t <= c.layers; ++t) {
-    const LayerPlan L = plan_layer(c, t);
-    o.rad1.push_back(cur);
-    cur += (size_t)c.n_basis * H;
-    o.rad2.push_back(cur);
-    cur += H * H;
-    o.rad3.push_back(cur);
-    cur += H * (size_t)L.p_full * C;
-    std::array<size_t, 4> m{}, sf{};
-    for (int l3 = 0; l3 <= c.lmax; ++l3) {
-      m[l3] = cur;
-      cur += (size_t)L.p_full_l3[l3] * C * C;
-    }
-    for (int l = 0; l <= L.l1max; ++l) {
-      sf[l] = cur;
-      cur += C * C;
-    }
-    o.mix.push_back(m);
-    o.self_.push_back(sf);
-  }
-  o.read1 = cur;
-  cur += C * c.readout_hidden;
-  o.read2 = cur;
-  cur += c.readout_hidden;
-  o.e0 = cur;
-  cur += c.n_species;
-  o.total = cur;
-  return o;
-}
 
 // Gradient of sum_s gE_s E_s - D_v E (v = gF) with respect to every weight:
 // the vector-Jacobian product of (E, F) -> weights for upstream (gE, gF).
@@ -1211,6 +1312,14 @@ int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, con
   E3MI_REQUIRE(graph->N == 0 || pos, E3MI_EINVAL, "null positions");
   e3mi::param_grad(model, graph, pos, grad_energy, grad_forces, grad_weights, e3mi::as_stream(stream));
   E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_model_set_flags(e3mi_model* model, int flags) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
+  E3MI_REQUIRE((flags & ~1) == 0, E3MI_EINVAL, "unknown flag");
+  model->first_factorised = (flags & 1) == 0;
   E3MI_API_END
 }
 

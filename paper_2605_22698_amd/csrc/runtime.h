@@ -283,6 +283,11 @@ int tn_chunks(long rows);
 void launch_gemm_tn(RowMap x1, RowMap y1, RowMap x2, RowMap y2, long rows, const int* rows_dev, int mo, int no,
                     float* partial, double* out, long ld_out, hipStream_t st);
 
+// ---- species-factorised first layer (first.hip) ---------------------------------------
+void launch_first(bool fwd, int lmax, int l3max, const int* row_ptr, const int* src, const float4* dvec,
+                  const int* species, int N, int S64, const float* W1, const float* W2, const float* W2T, float* G,
+                  const float* dG, float4* g, int accumulate, float rc, int p, hipStream_t st);
+
 // ---- MD (md.hip) -----------------------------------------------------------------------
 void launch_kick(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa, int N,
                  hipStream_t st);

@@ -141,3 +141,15 @@ def test_bf16_mode_errors_against_oracle():
     say(f"BF16: energy rel err {e16:.2e}, force err {f16:.2e} of max |F|; FP32: {e32:.2e}, {f32:.2e}")
     assert e16 < 2e-2 and f16 < 5e-2
     assert not np.array_equal(F16, F32)
+
+
+def test_first_layer_factorisation_matches_per_edge_path():
+    import torch
+    cfg, b = synth.single_config(n=700)
+    m = model(cfg, 2)
+    E1, F1, Ei1, _ = gpu_energy_forces(m, b, skin=1.0)
+    m.set_flags(unfactorised_first_layer=True)
+    E2, F2, Ei2, _ = gpu_energy_forces(m, b, skin=1.0)
+    assert abs(E1[0] - E2[0]) <= 1e-6 * abs(E2[0])
+    assert np.abs(F1 - F2).max() <= 1e-4 * np.abs(F2).max()
+    assert not np.array_equal(F1, F2)  # two different evaluation orders
