@@ -493,7 +493,8 @@ void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
 // factorisation (first.hip): always possible for layer 1 (its input is the
 // embedding) when the species x hidden width fits the kernel's LDS budget.
 bool factorised_first(const e3mi_model* M) {
-  return M->first_factorised && M->cfg.n_species * M->cfg.radial_hidden <= 512;
+  const int S64 = M->cfg.n_species * M->cfg.radial_hidden;
+  return M->first_factorised && S64 <= 512 && first_lds_bytes(M->plans[0].l3max_used, S64) <= 65536;
 }
 
 // Primal forward pass: edge selection, embedding and every layer. Leaves

@@ -174,9 +174,10 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
                                                    float4* __restrict__ g, int accumulate, float rc, int p) {
   constexpr int NB = 8;
   constexpr int NC3 = (L3 + 1) * (L3 + 1);
+  // LDS kept under 64 KB (static + the receiver's dG): the first hidden
+  // layer's pre-activation is recomputed where its derivative is needed.
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float dBs[kTile][NB + 1];
-  __shared__ float P1[kTile][kLd];
   __shared__ float P2[kTile][kLd];
   __shared__ float X[kTile][kLd];
   __shared__ float Ys[kTile][NC3 + 1];
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
     __syncthreads();
     tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, dBs, Ys, sp);
     __syncthreads();
-    hidden1<NB>(Bs, W1, P1, X);
+    hidden1<NB>(Bs, W1, nullptr, X);
     __syncthreads();
     {
       const f32x16 acc = block_64(X, rb, W2, kH, cb);
@@ -225,12 +226,15 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
     }
     __syncthreads();
     {
-      // dH1 = dP2 W2^T, dP1 = dH1 silu'(P1) -> P2
+      // dH1 = dP2 W2^T, dP1 = dH1 silu'(P1) -> P2, with P1 = B W1 recomputed
       const f32x16 a2 = block_64(X, rb, W2T, kH, cb);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
-        P2[row][col] = a2[r] * silu_grad(P1[row][col]);
+        float p1 = 0.0f;
+#pragma unroll
+        for (int n = 0; n < NB; ++n) p1 += Bs[row][n] * W1[n * kH + col];
+        P2[row][col] = a2[r] * silu_grad(p1);
       }
     }
     __syncthreads();
@@ -282,11 +286,20 @@ static void first_launch(bool fwd, const int* row_ptr, const int* src, const flo
                                                p);
 }
 
+// LDS a first-layer workgroup needs (the larger, adjoint kernel): static
+// arrays plus the receiver's [(l3+1)^2, S*64] block. Kept within 64 KB.
+size_t first_lds_bytes(int l3max, int S64) {
+  const size_t nc3 = (size_t)(l3max + 1) * (l3max + 1);
+  const size_t fixed = 2 * kTile * 9 * 4 + 2 * kTile * kLd * 4 + 2 * kTile * (nc3 + 1) * 4 + kTile * 4;
+  return fixed + nc3 * S64 * 4;
+}
+
 void launch_first(bool fwd, int lmax, int l3max, const int* row_ptr, const int* src, const float4* dvec,
                   const int* species, int N, int S64, const float* W1, const float* W2, const float* W2T, float* G,
                   const float* dG, float4* g, int accumulate, float rc, int p, hipStream_t st) {
   if (N == 0) return;
-  if (S64 > kMaxS64) throw Error(E3MI_EUNSUPPORTED, "first-layer factorisation holds at most 8 species");
+  if (S64 > kMaxS64 || first_lds_bytes(l3max, S64) > 65536)
+    throw Error(E3MI_EUNSUPPORTED, "first-layer factorisation: too many species for the LDS budget");
   if (lmax == 3 && l3max == 3)
     first_launch<3, 3>(fwd, row_ptr, src, dvec, species, N, S64, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
   else if (lmax == 3 && l3max == 0)

@@ -284,6 +284,7 @@ void launch_gemm_tn(RowMap x1, RowMap y1, RowMap x2, RowMap y2, long rows, const
                     float* partial, double* out, long ld_out, hipStream_t st);
 
 // ---- species-factorised first layer (first.hip) ---------------------------------------
+size_t first_lds_bytes(int l3max, int S64);
 void launch_first(bool fwd, int lmax, int l3max, const int* row_ptr, const int* src, const float4* dvec,
                   const int* species, int N, int S64, const float* W1, const float* W2, const float* W2T, float* G,
                   const float* dG, float4* g, int accumulate, float rc, int p, hipStream_t st);
