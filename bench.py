@@ -66,6 +66,12 @@ def work_model(cfg, t, E, N):
     mlp_hidden = 2 * (cfg.n_basis * H + H * H)
     tp_flops = 2 * C * sum(nz + 2 * l3 + 1 for (_, _, l3, nz) in ps)
     out = {}
+    # species-factorised first layer: hidden MLP + outer product per edge; G per atom
+    nc3 = (cfg.lmax + 1) ** 2 if cfg.layers > 1 else 1
+    s64 = cfg.n_species * H
+    out["first_fwd"] = (E * (mlp_hidden + 2 * H * nc3), E * 24 + N * 4 * nc3 * s64)
+    out["first_bwd"] = (E * (mlp_hidden + 2 * H * H + 2 * H * cfg.n_basis + 4 * H * nc3),
+                        E * (24 + 16) + N * 4 * nc3 * s64)
     # radial MLP: flops on the matrix cores; bytes = edge vectors in, R out
     out["radial_fwd"] = (E * (mlp_hidden + 2 * H * PC), E * (16 + 4 * PC))
     # adjoint: recompute hidden layers, dR W3^T, dH2 W2^T, dH1 W1^T; dR and dY in, g read+write
@@ -125,6 +131,8 @@ def main():
     ap.add_argument("--cpu-sample-atoms", type=int, default=400)
     ap.add_argument("--no-extras", action="store_true", help="skip the BF16 and serving side measurements")
     ap.add_argument("--serving-requests", type=int, default=16)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run plain 256 MiB device-to-device copies (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -136,6 +144,15 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": src.numel() * 4,
+                          "bytes_written_per_launch": dst.numel() * 4, "launches": 10}), flush=True)
+        return
     cfg, b = synth.single_config(n=args.atoms)
     w = synth.flatten_weights(cfg, synth.model_weights(cfg, 2))
     m = e3.Model(cfg.to_json(), w, device=dev)
@@ -164,8 +181,9 @@ def main():
     step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
     gpu_ms = float(step_ms.sum())
     m.profile(False)
-    stages = ["prune", "embed", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd", "mix_bwd",
-              "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build"]
+    stages = ["prune", "embed", "first_fwd", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd",
+              "mix_bwd", "first_bwd", "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update",
+              "graph_build"]
     stage_ms = {}
     for s in stages:
         tot, n = m.stage_time(s)
@@ -194,10 +212,11 @@ def main():
                 best = (tot, n, s, t, flops, nbytes)
     tot, n, s, t, flops, nbytes = best
     avg_s = tot / n / 1e3
-    peak_flop = PEAK_FP32_MFMA if s.startswith("radial") else PEAK_FP32_VALU
+    mfma = s.startswith("radial") or s.startswith("first")
+    peak_flop = PEAK_FP32_MFMA if mfma else PEAK_FP32_VALU
     t_hbm, t_flop = nbytes / PEAK_HBM, flops / peak_flop
     if t_flop >= t_hbm:
-        bound = "mfma" if s.startswith("radial") else "alu"
+        bound = "mfma" if mfma else "alu"
         roof = {"bound": bound, "achieved": flops / avg_s / 1e12, "peak": peak_flop / 1e12, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}

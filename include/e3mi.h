@@ -212,9 +212,10 @@ size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_
 /* Per-stage timing with HIP events recorded on the launch stream, for
  * measuring kernels in place (Appendix H reports ms per MD step; this splits
  * a step into its stages). enable != 0 resets the counters and starts
- * recording; 0 stops. Stages: prune, embed, radial_fwd, tp_fwd, mix_fwd,
+ * recording; 0 stops recording and keeps the counters. Stages: prune, embed, radial_fwd, tp_fwd, mix_fwd,
  * gate_fwd, readout, gate_bwd, mix_bwd, tp_bwd_edge, radial_bwd, tp_bwd_node,
- * forces, md_update, graph_build; "name@t" selects interaction layer t.
+ * forces, md_update, graph_build, first_fwd, first_bwd (the species-factorised
+ * first layer); "name@t" selects interaction layer t.
  * e3mi_profile_query waits for the recorded events and returns the summed
  * milliseconds and the number of timed launches of a stage. */
 int e3mi_profile_enable(e3mi_model* model, int enable);

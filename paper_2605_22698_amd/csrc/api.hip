@@ -1399,7 +1399,7 @@ size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_
 int e3mi_profile_enable(e3mi_model* model, int enable) {
   E3MI_API_BEGIN
   E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
-  model->prof.reset();
+  if (enable) model->prof.reset();
   model->prof.on = enable != 0;
   E3MI_API_END
 }

@@ -138,8 +138,12 @@ def test_bf16_mode_errors_against_oracle():
     f16 = np.abs(F16 - ref["forces"]).max() / fmax
     e32 = abs(E32[0] - ref["energy"][0]) / abs(ref["energy"][0])
     f32 = np.abs(F32 - ref["forces"]).max() / fmax
-    say(f"BF16: energy rel err {e16:.2e}, force err {f16:.2e} of max |F|; FP32: {e32:.2e}, {f32:.2e}")
-    assert e16 < 2e-2 and f16 < 5e-2
+    per_atom = abs(E16[0] - ref["energy"][0]) / b.n_atoms
+    say(f"BF16: energy rel err {e16:.2e} ({per_atom:.2e} eV/atom), force err {f16:.2e} of max |F|; "
+        f"FP32: {e32:.2e}, {f32:.2e}")
+    # rounding the weights to BF16 shifts every atom's energy alike, so the
+    # total error grows with N: bound it per atom
+    assert per_atom < 1e-3 and f16 < 5e-2
     assert not np.array_equal(F16, F32)
 
 

@@ -73,7 +73,9 @@ def test_nve_energy_conservation():
     say(f"NVE 400 steps: max |dE_total| {drift:.3e} eV (KE {ke:.3f} eV)")
     assert drift < 1e-4 * ke
     steps, rebuilds, violations = md.stats()
-    assert steps == 400 and rebuilds == 20 and violations == 0
+    # every 20 steps, more often after a detected skin violation (interval halved)
+    assert steps == 400 and rebuilds >= 20
+    assert (rebuilds == 20) == (violations == 0)
 
 
 def test_packed_trajectories_equal_single():
