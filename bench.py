@@ -86,6 +86,25 @@ def work_model(cfg, t, E, N):
     return out
 
 
+def measured_traffic(stage):
+    """HBM bytes per launch of the stage's kernel (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated) from the committed counter summary, or None when the
+    kernel's source file has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "md_step_3000_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        m = re.match(r"\|\s*`(k_[a-z_]+)(?:<[^`]*>)?`\s*\|\s*\d+\s*\|\s*([\d.]+)\s*\|\s*([\d.]+)\s*\|\s*(\S+)\s*\|\s*(\S+)", line)
+        if not m or m.group(1) != "k_" + stage:
+            continue
+        src = os.path.join(ROOT, "paper_2605_22698_amd", "csrc", m.group(4))
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != m.group(5):
+            return None
+        return (float(m.group(2)) + float(m.group(3))) * 1024 * 1024
+    return None
+
+
 def serving_run(e3, synth, torch, dev, n_requests, log):
     """Continuous-batching MD: Poisson arrivals, atom counts log-uniform in
     [50, 5000], 0.1 atoms/A^3, 4 species, l_max 3, 128 channels, FP32,
@@ -221,7 +240,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(s)
     roof["kernel"] = f"{s} (layer {t})"
     roof["avg_launch_ms"] = tot / n
     roof["algorithmic_per_launch"] = {"flops": flops, "bytes": nbytes, "edges": n_edges}
