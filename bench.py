@@ -72,6 +72,16 @@ def work_model(cfg, t, E, N):
     out["first_fwd"] = (E * (mlp_hidden + 2 * H * nc3), E * 24 + N * 4 * nc3 * s64)
     out["first_bwd"] = (E * (mlp_hidden + 2 * H * H + 2 * H * cfg.n_basis + 4 * H * nc3),
                         E * (24 + 16) + N * 4 * nc3 * s64)
+    # fused last layer (scalar outputs): hidden MLP, T = sum_e H2 s^T and its
+    # W3 contraction forward; R recomputed, dH2 = W3 dR, MLP adjoint, and the
+    # contracted-feature terms backward. Bytes: edge vectors, h once per atom,
+    # A / dA once per atom, g read and written.
+    NL = cfg.lmax + 1
+    NY = (cfg.lmax + 1) ** 2
+    out["last_fwd"] = (E * (mlp_hidden + 2 * H * NL * C + 2 * C * NY) + N * 2 * H * NL * C,
+                       E * 20 + N * 4 * (NY * C + NL * C))
+    out["last_bwd"] = (E * (mlp_hidden + 4 * H * NL * C + 2 * H * H + 2 * H * cfg.n_basis + 6 * C * NY),
+                       E * (20 + 32) + N * 4 * (3 * NY * C + NL * C))
     # radial MLP: flops on the matrix cores; bytes = edge vectors in, R out
     out["radial_fwd"] = (E * (mlp_hidden + 2 * H * PC), E * (16 + 4 * PC))
     # adjoint: recompute hidden layers, dR W3^T, dH2 W2^T, dH1 W1^T; dR and dY in, g read+write
@@ -202,7 +212,7 @@ def main():
     m.profile(False)
     stages = ["prune", "embed", "first_fwd", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd",
               "mix_bwd", "first_bwd", "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update",
-              "graph_build"]
+              "graph_build", "last_fwd", "last_bwd"]
     stage_ms = {}
     for s in stages:
         tot, n = m.stage_time(s)
@@ -231,7 +241,7 @@ def main():
                 best = (tot, n, s, t, flops, nbytes)
     tot, n, s, t, flops, nbytes = best
     avg_s = tot / n / 1e3
-    mfma = s.startswith("radial") or s.startswith("first")
+    mfma = s.startswith("radial") or s.startswith("first") or s.startswith("last")
     peak_flop = PEAK_FP32_MFMA if mfma else PEAK_FP32_VALU
     t_hbm, t_flop = nbytes / PEAK_HBM, flops / peak_flop
     if t_flop >= t_hbm:

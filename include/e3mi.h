@@ -160,6 +160,15 @@ int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, con
  *     the exact species factorisation of its neighbour sum (its input is the
  *     embedding of the sender's species); results agree to rounding. */
 #define E3MI_FLAG_UNFACTORISED_FIRST_LAYER 1
+/*   E3MI_FLAG_UNFUSED_LAST_LAYER (2): evaluate the last layer (scalar outputs
+ *     only, Section 4's tensor product restricted to the paths that reach the
+ *     energy) with per-edge radial weights R in memory and separate radial /
+ *     tensor-product kernels, instead of the fused kernels that never store
+ *     R (the neighbour sum is taken as W3^T times a per-receiver product of
+ *     hidden activations and contracted features); results agree to
+ *     rounding. The fused path is only used in FP32 with two or more
+ *     layers; the parameter-gradient pass always uses the unfused one. */
+#define E3MI_FLAG_UNFUSED_LAST_LAYER 2
 int e3mi_model_set_flags(e3mi_model* model, int flags);
 
 /* Replace the weights (host FP64, same configuration and layout as at
@@ -215,7 +224,8 @@ size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_
  * recording; 0 stops recording and keeps the counters. Stages: prune, embed, radial_fwd, tp_fwd, mix_fwd,
  * gate_fwd, readout, gate_bwd, mix_bwd, tp_bwd_edge, radial_bwd, tp_bwd_node,
  * forces, md_update, graph_build, first_fwd, first_bwd (the species-factorised
- * first layer); "name@t" selects interaction layer t.
+ * first layer), last_fwd, last_bwd (the fused last layer); "name@t" selects
+ * interaction layer t.
  * e3mi_profile_query waits for the recorded events and returns the summed
  * milliseconds and the number of timed launches of a stage. */
 int e3mi_profile_enable(e3mi_model* model, int enable);

@@ -132,11 +132,12 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Timed stages (per layer where it applies: index = stage * 8 + layer).
 enum Stage : int {
   kPrune = 0, kEmbed, kRadialFwd, kTpFwd, kMixFwd, kGateFwd, kReadout, kGateBwd, kMixBwd, kTpBwdEdge,
-  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kNumStages
+  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kLastFwd, kLastBwd, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
     "prune", "embed", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd", "mix_bwd",
-    "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build", "first_fwd", "first_bwd"};
+    "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build", "first_fwd", "first_bwd",
+    "last_fwd", "last_bwd"};
 inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
 
 }  // namespace
@@ -168,6 +169,7 @@ struct e3mi_model {
   std::unique_ptr<e3mi::DevBuf> emb, read1, read2, e0;
   // first layer factorised by species: U_l [S*64, C] and U_l^T [C, S*64] per output order
   bool first_factorised = true;
+  bool last_fused = true;
   std::unique_ptr<e3mi::DevBuf> U[4], UT[4];
   e3mi::Workspace ws;
   e3mi::Profiler prof;
@@ -497,6 +499,35 @@ bool factorised_first(const e3mi_model* M) {
   return M->first_factorised && S64 <= 512 && first_lds_bytes(M->plans[0].l3max_used, S64) <= 65536;
 }
 
+// Whether layer t runs through the fused last-layer kernels (last.hip): the
+// scalar-output last layer of a stack of two or more, in FP32, when the
+// per-layer A and R are not kept for a second-order pass.
+bool fused_last(const e3mi_model* M, const LayerPlan& L, bool keep_A, bool bf16) {
+  return M->last_fused && L.kind == 2 && !keep_A && !bf16 && last_supported(M->cfg.lmax, M->cfg.channels);
+}
+
+LastArgs last_args(e3mi_model* M, e3mi_graph* G, const LayerPlan& L, LayerWeights& W, const float* hin) {
+  const Config& c = M->cfg;
+  LastArgs la{};
+  la.lmax = c.lmax;
+  la.C = c.channels;
+  la.N = G->N;
+  la.row_ptr = G->row_ptr_x->as<int>();
+  la.src = G->src_x->as<int>();
+  la.dvec = G->dvec_x->as<float4>();
+  la.h = hin;
+  la.W1 = W.rad1.as<float>();
+  la.W2 = W.rad2.as<float>();
+  la.W2T = W.rad2T.as<float>();
+  la.W3 = W.rad3.as<float>();
+  la.ldw3 = L.p_full * c.channels;
+  la.W3T = W.rad3T.as<float>();
+  la.rc = (float)c.cutoff;
+  la.inv_nu = (float)(1.0 / c.avg_neighbors);
+  la.p = c.envelope_p;
+  return la;
+}
+
 // Primal forward pass: edge selection, embedding and every layer. Leaves
 // h^t, h~^t and R^t of every layer in the workspace; A in one shared buffer,
 // or per layer when keep_A (the parameter-gradient pass needs them).
@@ -530,8 +561,10 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     const LayerPlan& L = M->plans[t - 1];
     ensure(w.h[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
     ensure(w.ht[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
-    ensure(w.R[t], a, sizeof(float) * (size_t)(Ecap + 1) * L.p_used * C);
     a_max = std::max(a_max, L.a_per_atom);
+    if (t == 1 && factorised_first(M) && !keep_A) continue;
+    if (fused_last(M, L, keep_A, bf16)) continue;
+    ensure(w.R[t], a, sizeof(float) * (size_t)(Ecap + 1) * L.p_used * C);
     pc_max = std::max(pc_max, (long)L.p_used * C);
   }
   ensure(w.A, a, sizeof(float) * (size_t)N * a_max);
@@ -539,7 +572,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     w.Al.resize(T + 1);
     for (int t = 1; t <= T; ++t) ensure(w.Al[t], a, sizeof(float) * (size_t)N * M->plans[t - 1].a_per_atom);
   }
-  ensure(w.dR, a, sizeof(float) * (size_t)(Ecap + 1) * pc_max);
+  if (pc_max) ensure(w.dR, a, sizeof(float) * (size_t)(Ecap + 1) * pc_max);
   ensure(w.dY, a, sizeof(float) * 16 * (size_t)(Ecap + 1));
   ensure(w.g, a, sizeof(float4) * (size_t)(Ecap + 1));
   ensure(w.dh_a, a, sizeof(float) * (size_t)N * NC * C);
@@ -596,9 +629,27 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
       }
       continue;
     }
+    float* A = keep_A ? w.Al[t]->as<float>() : w.A->as<float>();
+    if (fused_last(M, L, keep_A, bf16)) {
+      LastArgs la = last_args(M, G, L, W, hin);
+      la.A = A;
+      {
+        ProfScope ps(&M->prof, stage_id(kLastFwd, t), st);
+        launch_last(true, la, st);
+      }
+      float* ht = w.ht[t]->as<float>();
+      {
+        ProfScope ps(&M->prof, stage_id(kMixFwd, t), st);
+        launch_mix(M, L, W, A, hin, ht, N, st, bf16);
+      }
+      {
+        ProfScope ps(&M->prof, stage_id(kGateFwd, t), st);
+        launch_gate_fwd(ht, w.h[t]->as<float>(), N, L.nc_out, C, st);
+      }
+      continue;
+    }
     float* R = w.R[t]->as<float>();
     const int PCu = L.p_used * C;
-    float* A = keep_A ? w.Al[t]->as<float>() : w.A->as<float>();
     {
       ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
       launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
@@ -674,7 +725,6 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     const LayerPlan& L = M->plans[t - 1];
     LayerWeights& W = *M->lw[t - 1];
     const float* hin = w.h[t - 1]->as<float>();
-    const float* R = w.R[t]->as<float>();
     const int PCu = L.p_used * C;
     {
       ProfScope ps(&M->prof, stage_id(kGateBwd, t), st);
@@ -709,6 +759,20 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       if (t > 1) E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
       launch_mix_adjoint(M, L, W, dht, A, t > 1 ? dother : nullptr, N, st, M->precision == E3MI_BF16_MIX);
     }
+    if (fused_last(M, L, false, M->precision == E3MI_BF16_MIX)) {
+      LastArgs la = last_args(M, G, L, W, hin);
+      la.dA = A;
+      la.g = g;
+      la.accumulate = t != T ? 1 : 0;
+      la.dh = dother;
+      {
+        ProfScope ps(&M->prof, stage_id(kLastBwd, t), st);
+        launch_last(false, la, st);
+      }
+      std::swap(dcur, dother);
+      continue;
+    }
+    const float* R = w.R[t]->as<float>();
     TpArgs ta{};
     ta.lmax = c.lmax;
     ta.kind = L.kind;
@@ -759,10 +823,17 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
   b += N * (4 * 4 + 24 + 8) + 64 * 1024;             // per-atom graph data
   size_t a_max = 0, pc_max = 0;
   b += N * C * 4;                                    // embedding
+  const bool bf16 = M->precision == E3MI_BF16_MIX;
   for (int t = 1; t <= c.layers; ++t) {
     const LayerPlan& L = M->plans[t - 1];
-    b += 2 * N * L.nc_out * C * 4 + E * L.p_used * C * 4;
+    b += 2 * N * L.nc_out * C * 4;
     a_max = std::max(a_max, (size_t)L.a_per_atom);
+    if (t == 1 && factorised_first(M)) {
+      b += 2 * N * L.nc_out * (size_t)c.n_species * c.radial_hidden * 4;  // G and dG
+      continue;
+    }
+    if (fused_last(M, L, false, bf16)) continue;  // no per-edge R
+    b += E * L.p_used * C * 4;
     pc_max = std::max(pc_max, (size_t)L.p_used * C);
   }
   b += N * a_max * 4 + E * pc_max * 4 + E * (64 + 16) + 3 * N * NC * C * 4 + N * 8;
@@ -1319,8 +1390,9 @@ int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, con
 int e3mi_model_set_flags(e3mi_model* model, int flags) {
   E3MI_API_BEGIN
   E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
-  E3MI_REQUIRE((flags & ~1) == 0, E3MI_EINVAL, "unknown flag");
+  E3MI_REQUIRE((flags & ~3) == 0, E3MI_EINVAL, "unknown flag");
   model->first_factorised = (flags & 1) == 0;
+  model->last_fused = (flags & 2) == 0;
   E3MI_API_END
 }
 

@@ -20,6 +20,15 @@ __device__ __forceinline__ float silu_grad(float x) {
   return s * (1.0f + x * (1.0f - s));
 }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) in round-robin
+// order of the block index. For receiver-centric kernels, map block b so that
+// XCD b % 8 walks a contiguous range of receivers: neighbouring receivers
+// share senders, so their gathers hit the same L2. A bijection on [0, n).
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+  return x * q + min(x, r) + k;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

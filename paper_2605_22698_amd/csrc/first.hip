@@ -110,24 +110,36 @@ __device__ __forceinline__ void tile_geometry(const float4* __restrict__ dvec, c
 }
 
 template <int NB>
-__device__ __forceinline__ void hidden1(const float (*Bs)[NB + 1], const float* __restrict__ W1, float (*P1)[kLd],
-                                        float (*H1)[kLd]) {
-  const int t = threadIdx.x;
-  const int row = t >> 2, cb = (t & 3) * 16;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
+__device__ __forceinline__ void hidden1(const float (*Bs)[NB + 1], const float* __restrict__ W1, float (*H1)[kLd]) {
+  for (int o = threadIdx.x; o < kTile * kH; o += 256) {
+    const int row = o >> 6, col = o & 63;
     float s = 0.0f;
 #pragma unroll
-    for (int n = 0; n < NB; ++n) s += Bs[row][n] * W1[n * kH + cb + j];
-    if (P1) P1[row][cb + j] = s;
-    H1[row][cb + j] = siluf(s);
+    for (int n = 0; n < NB; ++n) s += Bs[row][n] * W1[n * kH + col];
+    H1[row][col] = siluf(s);
   }
 }
 
+// Column n of the (component, species) axis: n = c S + s.
+struct ColDecode {
+  int c, s;
+  bool ok;
+};
+__device__ __forceinline__ ColDecode decode(int n, int NN, int S) {
+  ColDecode d;
+  d.ok = n < NN;
+  d.c = d.ok ? n / S : 0;
+  d.s = d.ok ? n - d.c * S : -1;
+  return d;
+}
+
+// Forward: G_i[n = (c, s), q] = sum_e [z_j(e) = s] (CY)_e[c] H2_e[q], a product
+// over the receiver's edges on the matrix cores (A = species-masked CY^T,
+// B = H2), accumulated across tiles in registers.
 template <int LMAX, int L3>
 __global__ void __launch_bounds__(256) k_first_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                    const float4* __restrict__ dvec, const int* __restrict__ species,
-                                                   int S64, const float* __restrict__ W1, const float* __restrict__ W2,
+                                                   int S, const float* __restrict__ W1, const float* __restrict__ W2,
                                                    float rc, int p, float* __restrict__ G) {
   constexpr int NB = 8;
   constexpr int NC3 = (L3 + 1) * (L3 + 1);
@@ -135,98 +147,152 @@ __global__ void __launch_bounds__(256) k_first_fwd(const int* __restrict__ row_p
   __shared__ float X[kTile][kLd];
   __shared__ float Ys[kTile][NC3 + 1];
   __shared__ int sp[kTile];
-  extern __shared__ float Gs[];  // [NC3][S64]
   const int i = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int k = t; k < NC3 * S64; k += 256) Gs[k] = 0.0f;
+  const int NN = NC3 * S, NBLK = 2 * ((NN + 31) / 32);
+  f32x16 acc[2] = {f32x16{}, f32x16{}};
+  ColDecode cd[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) cd[k] = decode(((w + 4 * k) >> 1) * 32 + (lane & 31), NN, S);
   const int e1 = row_ptr[i + 1];
   for (int e0 = row_ptr[i]; e0 < e1; e0 += kTile) {
+    const int n_e = min(kTile, e1 - e0);
     __syncthreads();
     tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, nullptr, Ys, sp);
     __syncthreads();
-    hidden1<NB>(Bs, W1, nullptr, X);
+    hidden1<NB>(Bs, W1, X);
     __syncthreads();
     {
       const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-      const f32x16 acc = block_64(X, rb, W2, kH, cb);
+      const f32x16 a = block_64(X, rb, W2, kH, cb);
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) X[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(acc[r]);
+      for (int r = 0; r < 16; ++r) X[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(a[r]);
     }
     __syncthreads();
-    const int n_e = min(kTile, e1 - e0);
-    for (int e = 0; e < n_e; ++e) {
-      const float h = X[e][lane];
-      const int base = sp[e] * kH + lane;
-      for (int c = w; c < NC3; c += 4) Gs[c * S64 + base] += h * Ys[e][c];
+    for (int kk = 0; kk < n_e; kk += 2) {
+      const int e = kk + (lane >> 5);
+      const int se = sp[e];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int blk = w + 4 * k;
+        if (blk >= NBLK) break;
+        const float a = (cd[k].s == se) ? Ys[e][cd[k].c] : 0.0f;
+        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, X[e][(blk & 1) * 32 + (lane & 31)], acc[k], 0, 0, 0);
+      }
     }
   }
-  __syncthreads();
-  float* Gi = G + (long)i * NC3 * S64;
-  for (int k = t; k < NC3 * S64; k += 256) Gi[k] = Gs[k];
+  float* Gi = G + (long)i * NN * kH;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int blk = w + 4 * k;
+    if (blk >= NBLK) break;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int n = (blk >> 1) * 32 + acc_row(r, lane);
+      if (n < NN) Gi[n * kH + (blk & 1) * 32 + (lane & 31)] = acc[k][r];
+    }
+  }
 }
 
+// Adjoint, from dG (= dh~ U^T) of the receiver, held in LDS as U[n][q]:
+//   d(CY)_e[c] = D[e, (c, z_j)],  D = H2 U^T          (matrix cores, all species)
+//   dH2[e, q]  = sum_n [z_j = s_n] (CY)_e[c_n] U[n, q]  (matrix cores)
+//   dP2 = dH2 o silu'(P2), dH1 = dP2 W2^T, dP1 = dH1 o silu'(B W1),
+//   dr = sum_n (dP1 . W1[n, :]) dB_n/dr, and d(CY) -> dY -> direction,
+// giving g_e = dE/dd_e (added to the other layers' contributions).
 template <int LMAX, int L3>
 __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                    const float4* __restrict__ dvec, const int* __restrict__ species,
-                                                   int S64, const float* __restrict__ W1, const float* __restrict__ W2,
+                                                   int S, const float* __restrict__ W1, const float* __restrict__ W2,
                                                    const float* __restrict__ W2T, const float* __restrict__ dG,
                                                    float4* __restrict__ g, int accumulate, float rc, int p) {
   constexpr int NB = 8;
   constexpr int NC3 = (L3 + 1) * (L3 + 1);
-  // LDS kept under 64 KB (static + the receiver's dG): the first hidden
-  // layer's pre-activation is recomputed where its derivative is needed.
   __shared__ float Bs[kTile][NB + 1];
-  __shared__ float dBs[kTile][NB + 1];
-  __shared__ float P2[kTile][kLd];
-  __shared__ float X[kTile][kLd];
+  __shared__ float X[kTile][kLd];   // H1, H2, then dP2
+  __shared__ float G2[kTile][kLd];  // P2, then silu'(P2)
   __shared__ float Ys[kTile][NC3 + 1];
   __shared__ float dYs[kTile][NC3 + 1];
   __shared__ int sp[kTile];
-  extern __shared__ float Gs[];  // [NC3][S64], the receiver's dG
+  __shared__ float drs[4][kTile];
+  extern __shared__ float Ub[];     // [max(NN, 64)][kLd]: the receiver's dG, then dP1
+  float (*U)[kLd] = reinterpret_cast<float (*)[kLd]>(Ub);
   const int i = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-  const float* dGi = dG + (long)i * NC3 * S64;
-  for (int k = t; k < NC3 * S64; k += 256) Gs[k] = dGi[k];
+  const int NN = NC3 * S, NBLK = 2 * ((NN + 31) / 32);
+  const float* dGi = dG + (long)i * NN * kH;
+  ColDecode cd[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) cd[k] = decode(((w + 4 * k) >> 1) * 32 + (lane & 31), NN, S);
   const int e1 = row_ptr[i + 1];
   for (int e0 = row_ptr[i]; e0 < e1; e0 += kTile) {
+    const int n_e = min(kTile, e1 - e0);
     __syncthreads();
-    tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, dBs, Ys, sp);
+    for (int o = t; o < NN * kH; o += 256) U[o >> 6][o & 63] = dGi[o];
+    tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, nullptr, Ys, sp);
     __syncthreads();
-    hidden1<NB>(Bs, W1, nullptr, X);
+    hidden1<NB>(Bs, W1, X);
     __syncthreads();
     {
-      const f32x16 acc = block_64(X, rb, W2, kH, cb);
+      const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+      const f32x16 a = block_64(X, rb, W2, kH, cb);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) P2[rb + acc_row(r, lane)][cb + (lane & 31)] = acc[r];
+      for (int r = 0; r < 16; ++r) G2[rb + acc_row(r, lane)][cb + (lane & 31)] = a[r];
     }
     __syncthreads();
-    for (int e = w; e < kTile; e += 4) X[e][lane] = siluf(P2[e][lane]);  // H2
+    for (int o = t; o < kTile * kH; o += 256) {
+      const int row = o >> 6, col = o & 63;
+      const float p2 = G2[row][col];
+      X[row][col] = siluf(p2);
+      G2[row][col] = silu_grad(p2);
+    }
     __syncthreads();
-    // d(CY)_e[c] = sum_q dG[c, s_e, q] H2_e[q]
-    {
-      const int e = t >> 2;
-      const int base = sp[e] * kH;
-      for (int c = t & 3; c < NC3; c += 4) {
-        float s = 0.0f;
+    // d(CY): blocks (edge block eb, column block nb) of D = H2 U^T
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int blk = w + 4 * k;
+      if (blk >= NBLK) break;
+      const int eb = blk & 1, n = (blk >> 1) * 32 + (lane & 31);
+      f32x16 a = {};
 #pragma unroll 8
-        for (int q = 0; q < kH; ++q) s += Gs[c * S64 + base + q] * X[e][q];
-        dYs[e][c] = s;
+      for (int kk = 0; kk < kH; kk += 2) {
+        const int q = kk + (lane >> 5);
+        a = __builtin_amdgcn_mfma_f32_32x32x2f32(X[eb * 32 + (lane & 31)][q], cd[k].ok ? U[n][q] : 0.0f, a, 0, 0,
+                                                 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int e = eb * 32 + acc_row(r, lane);
+        if (cd[k].s == sp[e]) dYs[e][cd[k].c] = a[r];
+      }
+    }
+    // dH2: block (eb = w & 1, qb = w >> 1), K over the (component, species) axis
+    f32x16 d2 = {};
+    {
+      const int eb = w & 1, qb = w >> 1;
+      const int e = eb * 32 + (lane & 31);
+      const int se = sp[e];
+      for (int kk = 0; kk < NN; kk += 2) {
+        const ColDecode c = decode(kk + (lane >> 5), NN, S);
+        const float a = (c.s == se) ? Ys[e][c.c] : 0.0f;
+        const float b = c.ok ? U[kk + (lane >> 5)][qb * 32 + (lane & 31)] : 0.0f;
+        d2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d2, 0, 0, 0);
+      }
+    }
+    __syncthreads();  // X (H2) and U (dG) no longer read
+    {
+      const int eb = w & 1, qb = w >> 1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int e = eb * 32 + acc_row(r, lane), q = qb * 32 + (lane & 31);
+        X[e][q] = d2[r] * G2[e][q];
       }
     }
     __syncthreads();
-    // dH2[e, q] = sum_c dG[c, s_e, q] (CY)_e[c]  ->  dP2 = dH2 silu'(P2)  (into X)
-    for (int e = w; e < kTile; e += 4) {
-      const int base = sp[e] * kH + lane;
-      float s = 0.0f;
-#pragma unroll
-      for (int c = 0; c < NC3; ++c) s += Gs[c * S64 + base] * Ys[e][c];
-      X[e][lane] = s * silu_grad(P2[e][lane]);
-    }
-    __syncthreads();
     {
-      // dH1 = dP2 W2^T, dP1 = dH1 silu'(P1) -> P2, with P1 = B W1 recomputed
+      // dH1 = dP2 W2^T, dP1 = dH1 silu'(P1) -> U, with P1 = B W1 recomputed
+      const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
       const f32x16 a2 = block_64(X, rb, W2T, kH, cb);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -234,19 +300,31 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
         float p1 = 0.0f;
 #pragma unroll
         for (int n = 0; n < NB; ++n) p1 += Bs[row][n] * W1[n * kH + col];
-        P2[row][col] = a2[r] * silu_grad(p1);
+        U[row][col] = a2[r] * silu_grad(p1);
       }
     }
     __syncthreads();
-    if (t < kTile && e0 + t < e1) {
-      const int e = e0 + t;
-      float dr = 0.0f;
+    {
+      // dr partials: wave w takes basis functions 2w, 2w+1
+      const int e = lane;
+      const float r = lane < n_e ? dvec[e0 + lane].w : rc;
+      float b[NB], db[NB];
+      radial_basis<NB>(r, rc, p, b, db);
+      float part = 0.0f;
 #pragma unroll
       for (int n = 0; n < NB; ++n) {
+        if (n / (NB / 4) != w) continue;
         float s = 0.0f;
-        for (int q = 0; q < kH; ++q) s += P2[t][q] * W1[n * kH + q];
-        dr += s * dBs[t][n];
+#pragma unroll 8
+        for (int q = 0; q < kH; ++q) s += U[e][q] * W1[n * kH + q];
+        part += s * db[n];
       }
+      drs[w][e] = part;
+    }
+    __syncthreads();
+    if (t < n_e) {
+      const int e = e0 + t;
+      const float dr = drs[0][t] + drs[1][t] + drs[2][t] + drs[3][t];
       const float4 d = dvec[e];
       const float ir = 1.0f / d.w;
       const float nx = d.x * ir, ny = d.y * ir, nz = d.z * ir;
@@ -276,22 +354,25 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
 
 template <int LMAX, int L3>
 static void first_launch(bool fwd, const int* row_ptr, const int* src, const float4* dvec, const int* species, int N,
-                         int S64, const float* W1, const float* W2, const float* W2T, float* G, const float* dG,
+                         int S, const float* W1, const float* W2, const float* W2T, float* G, const float* dG,
                          float4* g, int accumulate, float rc, int p, hipStream_t st) {
-  const size_t lds = sizeof(float) * (size_t)(L3 + 1) * (L3 + 1) * S64;
-  if (fwd)
-    k_first_fwd<LMAX, L3><<<N, 256, lds, st>>>(row_ptr, src, dvec, species, S64, W1, W2, rc, p, G);
-  else
-    k_first_bwd<LMAX, L3><<<N, 256, lds, st>>>(row_ptr, src, dvec, species, S64, W1, W2, W2T, dG, g, accumulate, rc,
+  constexpr int NC3 = (L3 + 1) * (L3 + 1);
+  if (fwd) {
+    k_first_fwd<LMAX, L3><<<N, 256, 0, st>>>(row_ptr, src, dvec, species, S, W1, W2, rc, p, G);
+  } else {
+    const size_t lds = sizeof(float) * (size_t)std::max(NC3 * S, kTile) * kLd;
+    k_first_bwd<LMAX, L3><<<N, 256, lds, st>>>(row_ptr, src, dvec, species, S, W1, W2, W2T, dG, g, accumulate, rc,
                                                p);
+  }
 }
 
 // LDS a first-layer workgroup needs (the larger, adjoint kernel): static
-// arrays plus the receiver's [(l3+1)^2, S*64] block. Kept within 64 KB.
+// arrays plus the receiver's dG block [(l3+1)^2 S, 64] (padded rows, at least
+// 64 of them, later reused for dP1). Kept within 64 KB.
 size_t first_lds_bytes(int l3max, int S64) {
-  const size_t nc3 = (size_t)(l3max + 1) * (l3max + 1);
-  const size_t fixed = 2 * kTile * 9 * 4 + 2 * kTile * kLd * 4 + 2 * kTile * (nc3 + 1) * 4 + kTile * 4;
-  return fixed + nc3 * S64 * 4;
+  const size_t nc3 = (size_t)(l3max + 1) * (l3max + 1), S = (size_t)S64 / kH;
+  const size_t fixed = kTile * 9 * 4 + 2 * kTile * kLd * 4 + 2 * kTile * (nc3 + 1) * 4 + kTile * 4 + 4 * kTile * 4;
+  return fixed + std::max(nc3 * S, (size_t)kTile) * kLd * 4;
 }
 
 void launch_first(bool fwd, int lmax, int l3max, const int* row_ptr, const int* src, const float4* dvec,
@@ -301,13 +382,13 @@ void launch_first(bool fwd, int lmax, int l3max, const int* row_ptr, const int* 
   if (S64 > kMaxS64 || first_lds_bytes(l3max, S64) > 65536)
     throw Error(E3MI_EUNSUPPORTED, "first-layer factorisation: too many species for the LDS budget");
   if (lmax == 3 && l3max == 3)
-    first_launch<3, 3>(fwd, row_ptr, src, dvec, species, N, S64, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
+    first_launch<3, 3>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
   else if (lmax == 3 && l3max == 0)
-    first_launch<3, 0>(fwd, row_ptr, src, dvec, species, N, S64, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
+    first_launch<3, 0>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
   else if (lmax == 2 && l3max == 2)
-    first_launch<2, 2>(fwd, row_ptr, src, dvec, species, N, S64, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
+    first_launch<2, 2>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
   else if (lmax == 2 && l3max == 0)
-    first_launch<2, 0>(fwd, row_ptr, src, dvec, species, N, S64, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
+    first_launch<2, 0>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
   else
     throw Error(E3MI_EUNSUPPORTED, "first-layer factorisation: unsupported orders");
 }

@@ -289,6 +289,30 @@ void launch_first(bool fwd, int lmax, int l3max, const int* row_ptr, const int* 
                   const int* species, int N, int S64, const float* W1, const float* W2, const float* W2T, float* G,
                   const float* dG, float4* g, int accumulate, float rc, int p, hipStream_t st);
 
+// ---- fused last layer (last.hip) ----------------------------------------------------------
+struct LastArgs {
+  int lmax, C, N;
+  const int* row_ptr;
+  const int* src;
+  const float4* dvec;
+  const float* h;    // layer input [N, (lmax+1)^2, C]
+  const float* W1;   // [8, 64]
+  const float* W2;   // [64, 64]
+  const float* W2T;  // [64, 64]
+  const float* W3;   // [64, ldw3], scalar-output paths in the first (lmax+1) C columns
+  int ldw3;
+  const float* W3T;  // [(lmax+1) C, 64]
+  float* A;          // forward out: [N, lmax+1, C], nu^-1 applied
+  const float* dA;   // adjoint in: [N, lmax+1, C] (without nu^-1)
+  float4* g;         // adjoint out: per-edge dE/dd (+= when accumulate)
+  int accumulate;
+  float* dh;         // adjoint out (+=): [N, (lmax+1)^2, C]
+  float rc, inv_nu;
+  int p;
+};
+bool last_supported(int lmax, int C);
+void launch_last(bool fwd, const LastArgs& a, hipStream_t st);
+
 // ---- MD (md.hip) -----------------------------------------------------------------------
 void launch_kick(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa, int N,
                  hipStream_t st);

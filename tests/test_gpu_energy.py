@@ -157,3 +157,17 @@ def test_first_layer_factorisation_matches_per_edge_path():
     assert abs(E1[0] - E2[0]) <= 1e-6 * abs(E2[0])
     assert np.abs(F1 - F2).max() <= 1e-4 * np.abs(F2).max()
     assert not np.array_equal(F1, F2)  # two different evaluation orders
+
+
+@pytest.mark.parametrize("lmax,channels", [(3, 128), (3, 64), (2, 32)])
+def test_fused_last_layer_matches_unfused_path(lmax, channels):
+    cfg = synth.ModelConfig(lmax=lmax, channels=channels, layers=2, n_species=4, cutoff=5.0, avg_neighbors=52.36)
+    _, b = synth.single_config(n=500)
+    m = model(cfg, 5)
+    say(f"fused last layer l_max {lmax} C {channels}")
+    E1, F1, Ei1, _ = gpu_energy_forces(m, b, skin=1.0)
+    m.set_flags(unfused_last_layer=True)
+    E2, F2, Ei2, _ = gpu_energy_forces(m, b, skin=1.0)
+    assert np.abs(Ei1 - Ei2).max() <= 1e-5 * np.abs(Ei2).max()
+    assert abs(E1[0] - E2[0]) <= 1e-6 * abs(E2[0])
+    assert np.abs(F1 - F2).max() <= 1e-4 * np.abs(F2).max()
