@@ -144,7 +144,7 @@ inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
 
 // ---- model -----------------------------------------------------------------------
 struct LayerWeights {
-  DevBuf rad1, rad2, rad2T, rad3, rad3T;
+  DevBuf rad1, rad2, rad2T, rad3, rad3T, rad3u;
   DevBuf mix[4], mixT[4], self_[4], selfT[4];
 };
 
@@ -519,8 +519,8 @@ LastArgs last_args(e3mi_model* M, e3mi_graph* G, const LayerPlan& L, LayerWeight
   la.W1 = W.rad1.as<float>();
   la.W2 = W.rad2.as<float>();
   la.W2T = W.rad2T.as<float>();
-  la.W3 = W.rad3.as<float>();
-  la.ldw3 = L.p_full * c.channels;
+  la.W3 = W.rad3u.as<float>();
+  la.ldw3 = L.p_used * c.channels;
   la.W3T = W.rad3T.as<float>();
   la.rc = (float)c.cutoff;
   la.inv_nu = (float)(1.0 / c.avg_neighbors);
@@ -902,7 +902,7 @@ void upload_weights(e3mi_model* M, const double* wts) {
     if ((int)M->lw.size() < t) {
       M->plans.push_back(L);
       auto Wn = std::make_unique<LayerWeights>();
-      for (DevBuf* b : {&Wn->rad1, &Wn->rad2, &Wn->rad2T, &Wn->rad3, &Wn->rad3T}) b->a = a;
+      for (DevBuf* b : {&Wn->rad1, &Wn->rad2, &Wn->rad2T, &Wn->rad3, &Wn->rad3T, &Wn->rad3u}) b->a = a;
       for (int l = 0; l < 4; ++l) Wn->mix[l].a = Wn->mixT[l].a = Wn->self_[l].a = Wn->selfT[l].a = a;
       M->lw.push_back(std::move(Wn));
     }
@@ -923,6 +923,12 @@ void upload_weights(e3mi_model* M, const double* wts) {
     for (int k = 0; k < H; ++k)
       for (int col = 0; col < L.p_used * C; ++col) r3t[(size_t)col * H + k] = r3[(size_t)k * L.p_full * C + col];
     up(W->rad3T, r3t);
+    // the used columns alone, row-major [H, p_used C]
+    std::vector<float> r3u((size_t)H * L.p_used * C);
+    for (int k = 0; k < H; ++k)
+      for (int col = 0; col < L.p_used * C; ++col)
+        r3u[(size_t)k * L.p_used * C + col] = r3[(size_t)k * L.p_full * C + col];
+    up(W->rad3u, r3u);
     for (int l3 = 0; l3 <= c.lmax; ++l3) {
       const int P3 = L.p_full_l3[l3];
       const auto m = take((size_t)P3 * C * C);

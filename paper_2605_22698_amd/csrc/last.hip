@@ -38,6 +38,15 @@ constexpr int kNB = 8;   // radial basis size
 
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
+// Hides a per-lane pointer's value from the optimiser where it is formed, so
+// that loads through it with constant offsets are not turned into hoisted
+// 64-bit addresses (which would not fit in registers).
+template <class T>
+__device__ __forceinline__ const T* opaque_v(const T* p) {
+  asm volatile("" : "+v"(p));
+  return p;
+}
+
 // Orders the LDS accesses of one wave (lanes exchange data through LDS).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -237,7 +246,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_last_bwd(const int* __restrict__
                                                           const float4* __restrict__ dvec, const float* __restrict__ h,
                                                           const float* __restrict__ dA, const float* __restrict__ W1,
                                                           const float* __restrict__ W2, const float* __restrict__ W2T,
-                                                          const float* __restrict__ W3, int ldw3,
+                                                          const float* __restrict__ W3,
                                                           const float* __restrict__ W3T, float4* __restrict__ g,
                                                           int accumulate, float* __restrict__ dh, float rc, int p,
                                                           float inv_nu) {
@@ -289,14 +298,18 @@ __global__ void __launch_bounds__(64 * NW, 2) k_last_bwd(const int* __restrict__
       constexpr int lv = decltype(l)::value;
       constexpr float sgn = (lv & 1) ? -1.0f : 1.0f;
       {
-        // R^T_l[e, c] = sum_q H2[e, q] W3[q, l C + c]
+        // R^T_l[e, c] = sum_q H2[e, q] W3[q, l C + c]; the column of W3 is
+        // fetched in one batch
+        const float* w3l = opaque_v(W3 + (lane >> 5) * (NL * C) + lv * C + c);
+        float wB[kH / 2];
+#pragma unroll
+        for (int k = 0; k < kH / 2; ++k) wB[k] = w3l[2 * k * (NL * C)];
         f32x16 R[2] = {f32x16{}, f32x16{}};
-#pragma unroll 4
-        for (int kk = 0; kk < kH; kk += 2) {
-          const int q = kk + (lane >> 5);
-          const float bv = W3[(long)q * ldw3 + lv * C + c];
-          R[0] = mfma(X[lane & 31][q], bv, R[0]);
-          R[1] = mfma(X[32 + (lane & 31)][q], bv, R[1]);
+#pragma unroll
+        for (int k = 0; k < kH / 2; ++k) {
+          const int q = 2 * k + (lane >> 5);
+          R[0] = mfma(X[lane & 31][q], wB[k], R[0]);
+          R[1] = mfma(X[32 + (lane & 31)][q], wB[k], R[1]);
         }
         const float dai = inv_nu * dAi[lv * C + c];
         const float* dAl = dA + lv * C + c;
@@ -316,17 +329,31 @@ __global__ void __launch_bounds__(64 * NW, 2) k_last_bwd(const int* __restrict__
 #pragma unroll 1
       for (int g8 = 0; g8 < 4; ++g8) {
         const int c0 = 32 * w + 8 * g8 + 4 * (lane >> 5);
+        // every load of the group is issued before any of it is used
+        const float* wtp = opaque_v(W3T + (lv * C + c0) * kH + (lane & 31));
+        float wt[8];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          wt[2 * tt] = wtp[tt * kH];
+          wt[2 * tt + 1] = wtp[tt * kH + 32];
+        }
         const float4 da4 = *reinterpret_cast<const float4*>(dAi + lv * C + c0);
+        float4 hv4[2][2 * lv + 1];
+#pragma unroll
+        for (int eb = 0; eb < 2; ++eb) {
+          const float* hj = opaque_v(h + (long)js[eb * 32 + (lane & 31)] * NY * C + lv * lv * C + c0);
+#pragma unroll
+          for (int m = 0; m < 2 * lv + 1; ++m) hv4[eb][m] = *reinterpret_cast<const float4*>(hj + m * C);
+        }
         float dr[2][4];
 #pragma unroll
         for (int eb = 0; eb < 2; ++eb) {
           const int e = eb * 32 + (lane & 31);
-          const float* hj = h + (long)js[e] * NY * C + c0;
           const float d0 = DS[e][c0], d1 = DS[e][c0 + 1], d2 = DS[e][c0 + 2], d3 = DS[e][c0 + 3];
           float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
           for (int m = 0; m < 2 * lv + 1; ++m) {
-            const float4 hv = *reinterpret_cast<const float4*>(hj + (lv * lv + m) * C);
+            const float4 hv = hv4[eb][m];
             const float vv = Vs[e][lv * lv + m];
             s0 += hv.x * vv;
             s1 += hv.y * vv;
@@ -341,8 +368,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_last_bwd(const int* __restrict__
         }
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-          const float* wt = W3T + (long)(lv * C + c0 + tt) * kH + (lane & 31);
-          const float aq0 = wt[0], aq1 = wt[32];
+          const float aq0 = wt[2 * tt], aq1 = wt[2 * tt + 1];
           D[0][0] = mfma(aq0, dr[0][tt], D[0][0]);
           D[0][1] = mfma(aq0, dr[1][tt], D[0][1]);
           D[1][0] = mfma(aq1, dr[0][tt], D[1][0]);
@@ -458,7 +484,7 @@ void last_launch(bool fwd, const LastArgs& a, hipStream_t st) {
                                                    a.p, a.inv_nu);
   else
     k_last_bwd<LMAX, NW><<<a.N, 64 * NW, 0, st>>>(a.row_ptr, a.src, a.dvec, a.h, a.dA, a.W1, a.W2, a.W2T, a.W3,
-                                                   a.ldw3, a.W3T, a.g, a.accumulate, a.dh, a.rc, a.p, a.inv_nu);
+                                                   a.W3T, a.g, a.accumulate, a.dh, a.rc, a.p, a.inv_nu);
 }
 
 }  // namespace
@@ -468,6 +494,7 @@ bool last_supported(int lmax, int C) { return (lmax == 2 || lmax == 3) && (C == 
 void launch_last(bool fwd, const LastArgs& a, hipStream_t st) {
   if (a.N == 0) return;
   if (!last_supported(a.lmax, a.C)) throw Error(E3MI_EUNSUPPORTED, "fused last layer: unsupported order or width");
+  if (a.ldw3 != (a.lmax + 1) * a.C) throw Error(E3MI_EINVAL, "fused last layer: W3 must hold the used columns only");
   if (a.lmax == 3) {
     if (a.C == 128) last_launch<3, 4>(fwd, a, st);
     else if (a.C == 64) last_launch<3, 2>(fwd, a, st);
