@@ -156,14 +156,19 @@ __global__ void k_bin_fill(const int* __restrict__ atom_cell, const int* __restr
 // One thread per receiver: scan the cells whose unwrapped index range covers
 // [w_i - rc, w_i + rc] on every axis; each unwrapped cell u maps to the cell
 // u mod nb and the image floor(u / nb), so no (j, n) pair is visited twice.
+// One wave per receiver: the lanes scan the atoms of each stencil cell
+// together; hits are compacted with a ballot, so a row's edges are found in
+// the same order in the counting and the filling pass.
 template <bool FILL>
-__global__ void k_edges(const double* __restrict__ pos, const int* __restrict__ owner,
-                        const GridPlan* __restrict__ plan, const int* __restrict__ wrap,
-                        const int* __restrict__ cell_start, const int* __restrict__ cell_atoms,
-                        const int* __restrict__ row_ptr, int N, double rc2, int* __restrict__ count,
-                        uint64_t* __restrict__ keys, int* __restrict__ err) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+__global__ void __launch_bounds__(256) k_edges(const double* __restrict__ pos, const int* __restrict__ owner,
+                                               const GridPlan* __restrict__ plan, const int* __restrict__ wrap,
+                                               const int* __restrict__ cell_start, const int* __restrict__ cell_atoms,
+                                               const int* __restrict__ row_ptr, int N, double rc2,
+                                               int* __restrict__ count, uint64_t* __restrict__ keys,
+                                               int* __restrict__ err) {
+  const int i = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;  // the whole wave leaves together
   const GridPlan g = plan[owner[i]];
   const double rc = sqrt(rc2);
   const double xi[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
@@ -181,8 +186,9 @@ __global__ void k_edges(const double* __restrict__ pos, const int* __restrict__ 
       uhi[k] = uhi[k] > g.nb[k] - 1 ? g.nb[k] - 1 : uhi[k];
     }
   }
+  const uint64_t below = (1ull << lane) - 1ull;
   int n_found = 0;
-  int base = FILL ? row_ptr[i] : 0;
+  const int base = FILL ? row_ptr[i] : 0;
   for (int ux = ulo[0]; ux <= uhi[0]; ++ux) {
     const int cx = ux - floor_div(ux, g.nb[0]) * g.nb[0], nwx = g.periodic[0] ? floor_div(ux, g.nb[0]) : 0;
     for (int uy = ulo[1]; uy <= uhi[1]; ++uy) {
@@ -191,33 +197,35 @@ __global__ void k_edges(const double* __restrict__ pos, const int* __restrict__ 
         const int cz = uz - floor_div(uz, g.nb[2]) * g.nb[2], nwz = g.periodic[2] ? floor_div(uz, g.nb[2]) : 0;
         const int cell = g.cell_base + (cx * g.nb[1] + cy) * g.nb[2] + cz;
         const int b0 = cell_start[cell], b1 = cell_start[cell + 1];
-        for (int q = b0; q < b1; ++q) {
-          const int j = cell_atoms[q];
-          // image vector for the raw positions: r_j - r_i + n.L
-          const int n0 = nwx + ai[0] - wrap[3 * j];
-          const int n1 = nwy + ai[1] - wrap[3 * j + 1];
-          const int n2 = nwz + ai[2] - wrap[3 * j + 2];
-          if (j == i && n0 == 0 && n1 == 0 && n2 == 0) continue;
-          const double dx = (pos[3 * j] - xi[0]) + (double)n0 * g.len[0];
-          const double dy = (pos[3 * j + 1] - xi[1]) + (double)n1 * g.len[1];
-          const double dz = (pos[3 * j + 2] - xi[2]) + (double)n2 * g.len[2];
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < rc2) {
-            if (FILL) {
-              if (n0 < -127 || n0 > 127 || n1 < -127 || n1 > 127 || n2 < -127 || n2 > 127) {
-                atomicOr(err, 1);
-              }
-              const uint64_t key = ((uint64_t)(uint32_t)j << 24) | ((uint64_t)((n0 + 128) & 255) << 16) |
-                                   ((uint64_t)((n1 + 128) & 255) << 8) | (uint64_t)((n2 + 128) & 255);
-              keys[base + n_found] = key;
+        for (int q0 = b0; q0 < b1; q0 += 64) {
+          const int q = q0 + lane;
+          bool hit = false;
+          uint64_t key = 0;
+          if (q < b1) {
+            const int j = cell_atoms[q];
+            // image vector for the raw positions: r_j - r_i + n.L
+            const int n0 = nwx + ai[0] - wrap[3 * j];
+            const int n1 = nwy + ai[1] - wrap[3 * j + 1];
+            const int n2 = nwz + ai[2] - wrap[3 * j + 2];
+            const double dx = (pos[3 * j] - xi[0]) + (double)n0 * g.len[0];
+            const double dy = (pos[3 * j + 1] - xi[1]) + (double)n1 * g.len[1];
+            const double dz = (pos[3 * j + 2] - xi[2]) + (double)n2 * g.len[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            hit = r2 < rc2 && !(j == i && n0 == 0 && n1 == 0 && n2 == 0);
+            if (FILL && hit) {
+              if (n0 < -127 || n0 > 127 || n1 < -127 || n1 > 127 || n2 < -127 || n2 > 127) atomicOr(err, 1);
+              key = ((uint64_t)(uint32_t)j << 24) | ((uint64_t)((n0 + 128) & 255) << 16) |
+                    ((uint64_t)((n1 + 128) & 255) << 8) | (uint64_t)((n2 + 128) & 255);
             }
-            ++n_found;
           }
+          const uint64_t mask = __ballot(hit);
+          if (FILL && hit) keys[base + n_found + __popcll(mask & below)] = key;
+          n_found += __popcll(mask);
         }
       }
     }
   }
-  if (!FILL) count[i] = n_found;
+  if (!FILL && lane == 0) count[i] = n_found;
 }
 
 // One wave per row: rank sort of distinct 64-bit keys (rank = number of
@@ -391,11 +399,11 @@ void launch_edges(bool fill, const double* pos, const int* owner, const GridPlan
   (void)atom_cell;
   if (N == 0) return;
   if (fill)
-    k_edges<true><<<blocks(N, 128), 128, 0, st>>>(pos, owner, plan, wrap, cell_start, cell_atoms, row_ptr, N, rc2,
-                                                   count, keys, err);
+    k_edges<true><<<blocks((long)N * 64, 256), 256, 0, st>>>(pos, owner, plan, wrap, cell_start, cell_atoms, row_ptr,
+                                                              N, rc2, count, keys, err);
   else
-    k_edges<false><<<blocks(N, 128), 128, 0, st>>>(pos, owner, plan, wrap, cell_start, cell_atoms, row_ptr, N, rc2,
-                                                    count, keys, err);
+    k_edges<false><<<blocks((long)N * 64, 256), 256, 0, st>>>(pos, owner, plan, wrap, cell_start, cell_atoms, row_ptr,
+                                                               N, rc2, count, keys, err);
 }
 void launch_sort_rows(const int* row_ptr, int N, uint64_t* keys, int* src, int* shift, hipStream_t st) {
   if (N == 0) return;

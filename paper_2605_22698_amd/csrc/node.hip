@@ -19,44 +19,69 @@ __device__ __forceinline__ long row_off(const RowMap& m, int r) {
 }
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// 64x64 output tile per workgroup, K in steps of 16 staged through LDS, each
-// wave a 32x32 block on v_mfma_f32_32x32x2f32 (FP32), or with both operands
-// rounded to BF16 on v_mfma_f32_32x32x16_bf16 (BF), FP32 accumulation.
+// 64x64 output tile per workgroup, each wave a 32x32 block on
+// v_mfma_f32_32x32x2f32 (FP32), or with both operands rounded to BF16 on
+// v_mfma_f32_32x32x16_bf16 (BF), FP32 accumulation. K runs over the two
+// operand pairs in slabs of 32 staged through LDS; the next slab is fetched
+// into registers while the current one is multiplied.
+constexpr int kSlab = 32;
+
+struct Slab {
+  float4 a[2], b[2];
+};
+
+__device__ __forceinline__ void gemm_load_slab(const GemmArgs& a, int s, int s0, int bm, int bn, Slab& r) {
+  const int t = threadIdx.x;
+  const int op = s >= s0;
+  const RowMap am = op ? a.a1 : a.a0;
+  const float* __restrict__ B = op ? a.b1 : a.b0;
+  const int ldb = op ? a.ldb1 : a.ldb0;
+  const int K = op ? a.k1 : a.k0;
+  const int k0 = (op ? s - s0 : s) * kSlab;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int idx = t + 256 * i;
+    const int row = idx >> 3, kq = (idx & 7) * 4, gr = bm + row;
+    r.a[i] = (gr < a.M && k0 + kq < K) ? *reinterpret_cast<const float4*>(am.base + row_off(am, gr) + k0 + kq)
+                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int kr = idx >> 4, c4 = (idx & 15) * 4, gk = k0 + kr, gc = bn + c4;
+    r.b[i] = (gk < K && gc < a.Nc) ? *reinterpret_cast<const float4*>(B + (long)gk * ldb + gc)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
 template <bool BF>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs a) {
-  __shared__ float As[64][17];
-  __shared__ float Bs[16][65];
+  __shared__ float As[64][kSlab + 1];
+  __shared__ float Bs[kSlab][65];
   const int bm = blockIdx.x * 64, bn = blockIdx.y * 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+  const int s0 = (a.k0 + kSlab - 1) / kSlab, ns = s0 + (a.k1 + kSlab - 1) / kSlab;
   f32x16 acc = {};
-  for (int op = 0; op < 2; ++op) {
-    const RowMap am = op ? a.a1 : a.a0;
-    const float* __restrict__ B = op ? a.b1 : a.b0;
-    const int ldb = op ? a.ldb1 : a.ldb0;
-    const int K = op ? a.k1 : a.k0;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-      {
-        const int row = t >> 2, kq = (t & 3) * 4, gr = bm + row;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gr < a.M && k0 + kq < K) v = *reinterpret_cast<const float4*>(am.base + row_off(am, gr) + k0 + kq);
-        As[row][kq] = v.x;
-        As[row][kq + 1] = v.y;
-        As[row][kq + 2] = v.z;
-        As[row][kq + 3] = v.w;
-      }
-      {
-        const int kr = t >> 4, c4 = (t & 15) * 4, gk = k0 + kr, gc = bn + c4;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (gk < K && gc < a.Nc) v = *reinterpret_cast<const float4*>(B + (long)gk * ldb + gc);
-        Bs[kr][c4] = v.x;
-        Bs[kr][c4 + 1] = v.y;
-        Bs[kr][c4 + 2] = v.z;
-        Bs[kr][c4 + 3] = v.w;
-      }
-      __syncthreads();
-      if constexpr (BF) {
-        const int k0 = 8 * (lane >> 5);
+  Slab cur;
+  if (ns > 0) gemm_load_slab(a, 0, s0, bm, bn, cur);
+  for (int s = 0; s < ns; ++s) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = t + 256 * i;
+      const int row = idx >> 3, kq = (idx & 7) * 4;
+      As[row][kq] = cur.a[i].x;
+      As[row][kq + 1] = cur.a[i].y;
+      As[row][kq + 2] = cur.a[i].z;
+      As[row][kq + 3] = cur.a[i].w;
+      const int kr = idx >> 4, c4 = (idx & 15) * 4;
+      Bs[kr][c4] = cur.b[i].x;
+      Bs[kr][c4 + 1] = cur.b[i].y;
+      Bs[kr][c4 + 2] = cur.b[i].z;
+      Bs[kr][c4 + 3] = cur.b[i].w;
+    }
+    __syncthreads();
+    if (s + 1 < ns) gemm_load_slab(a, s + 1, s0, bm, bn, cur);
+    if constexpr (BF) {
+#pragma unroll
+      for (int kb = 0; kb < kSlab; kb += 16) {
+        const int k0 = kb + 8 * (lane >> 5);
         bf16x8 x, y;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -64,14 +89,14 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs a) {
           y[q] = (__bf16)Bs[k0 + q][cb + (lane & 31)];
         }
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, acc, 0, 0, 0);
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 2)
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[rb + (lane & 31)][kk + (lane >> 5)],
-                                                      Bs[kk + (lane >> 5)][cb + (lane & 31)], acc, 0, 0, 0);
       }
-      __syncthreads();
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < kSlab; kk += 2)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[rb + (lane & 31)][kk + (lane >> 5)],
+                                                    Bs[kk + (lane >> 5)][cb + (lane & 31)], acc, 0, 0, 0);
     }
+    __syncthreads();
   }
   const int col = bn + cb + (lane & 31);
   if (col < a.Nc) {
