@@ -203,13 +203,16 @@ __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ e_ato
   if (threadIdx.x == 0) energy[s] = red[0];
 }
 
-__global__ void k_forces(const int* __restrict__ row_ptr, const int* __restrict__ rev, const float4* __restrict__ g,
-                         int N, float* __restrict__ F) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per atom: the lanes take the row's edges in turn, then a fixed
+// reduction tree over the wave (bitwise repeatable).
+__global__ void __launch_bounds__(256) k_forces(const int* __restrict__ row_ptr, const int* __restrict__ rev,
+                                                const float4* __restrict__ g, int N, float* __restrict__ F) {
+  const int i = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= N) return;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   const int b = row_ptr[i + 1];
-  for (int e = row_ptr[i]; e < b; ++e) {
+  for (int e = row_ptr[i] + lane; e < b; e += 64) {
     const int re = rev[e];
     const float4 a = g[e];
     const float4 r = re >= 0 ? g[re] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -217,9 +220,14 @@ __global__ void k_forces(const int* __restrict__ row_ptr, const int* __restrict_
     fy += a.y - r.y;
     fz += a.z - r.z;
   }
-  F[3 * i] = fx;
-  F[3 * i + 1] = fy;
-  F[3 * i + 2] = fz;
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  fz = wave_sum(fz);
+  if (lane == 0) {
+    F[3 * i] = fx;
+    F[3 * i + 1] = fy;
+    F[3 * i + 2] = fz;
+  }
 }
 
 inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
@@ -258,7 +266,7 @@ void launch_energy(const double* e_atom, const int64_t* off, int S, double* ener
 }
 void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st) {
   if (N == 0) return;
-  k_forces<<<blocks(N, 256), 256, 0, st>>>(row_ptr, rev, g, N, F);
+  k_forces<<<blocks((long)N * 64, 256), 256, 0, st>>>(row_ptr, rev, g, N, F);
 }
 
 }  // namespace e3mi
