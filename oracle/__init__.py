@@ -18,7 +18,9 @@ hyperparameter tables fix the shapes):
                  connection, gate) -> readout; E = sum_i E_i (§5.3 readout
                  form with one head); forces F = -dE/dr by autograd (§5.2,
                  forces are derivatives of the energy); loss gradients
-  md.py          velocity-Verlet NVE integration (§1, batched MD)
+  md.py          velocity-Verlet NVE integration (§1, batched MD) and
+                 BAOAB Langevin NVT (§5.5)
+  rng.py         Philox4x64-10 counter-based random numbers (§5.5 seeds)
 
 The paper prints no equation for the interaction itself; every modelling
 choice is a reading anchored to the nearest printed hyperparameter. Each
@@ -27,4 +29,4 @@ function is pinned by tests against mathematics the paper's setting fixes
 energy values of the assembled model are pinned only through those
 properties: parity unpinned for the absolute value of `model.energy`.
 """
-from . import sh, cg, basis, neighbours, model, md  # noqa: F401
+from . import sh, cg, basis, neighbours, model, md, rng  # noqa: F401

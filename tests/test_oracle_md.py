@@ -1,10 +1,11 @@
-"""Pins of the oracle's velocity-Verlet integrator."""
+"""Pins of the oracle's velocity-Verlet and Langevin integrators."""
 import math
 
 import numpy as np
 
 import synth
 from oracle import md
+from oracle import md as omd
 from oracle import model as om
 
 
@@ -62,3 +63,41 @@ def test_maxwell_boltzmann_temperature():
     T = 2 * ke / (3 * b.n_atoms * synth.KB_EV)
     assert abs(T - 300.0) < 15.0
     np.testing.assert_allclose((synth.SPECIES_MASS[b.species][:, None] * v).sum(0), 0, atol=1e-12)
+
+
+def test_langevin_without_friction_is_velocity_verlet():
+    rng_np = np.random.default_rng(3)
+    x0 = rng_np.normal(size=(5, 3))
+    v0 = rng_np.normal(size=(5, 3)) * 0.01
+    m = np.array([1.0, 2.0, 3.0, 4.0, 5.0])
+    k = 2.5
+
+    def force(x):
+        return np.array([0.5 * k * np.sum(x * x)]), -k * x
+    xa, va, _ = omd.velocity_verlet(force, x0, v0, m, 0.7, 30)
+    xb, vb, _ = omd.langevin_baoab(force, x0, v0, m, 0.7, 30, 300.0, 0.0, [0, 5], [11], [0])
+    assert np.abs(xa - xb).max() < 1e-12 and np.abs(va - vb).max() < 1e-12
+
+
+def test_langevin_samples_boltzmann_temperature_in_harmonic_well():
+    # independent atoms in a harmonic well: <m v^2/kappa> = kB T per component and
+    # <k x^2> = kB T (BAOAB samples the configurational distribution of a
+    # harmonic well with an error of order (dt omega)^2 ~ 1e-3 here)
+    n, T, k, gamma, dt = 60, 300.0, 1.0, 0.05, 1.0
+    m = np.full(n, 12.0)
+    x0 = np.zeros((n, 3))
+    v0 = np.zeros((n, 3))
+
+    def force(x):
+        return np.array([0.5 * k * np.sum(x * x)]), -k * x
+    kT = omd.KB_EV * T
+    # warm up, then average over a second stretch
+    x, v, _ = omd.langevin_baoab(force, x0, v0, m, dt, 300, T, gamma, [0, n], [5], [0])
+    ke, pe, cnt = 0.0, 0.0, 0
+    for block in range(8):
+        x, v, _ = omd.langevin_baoab(force, x, v, m, dt, 100, T, gamma, [0, n], [5], [300 + 100 * block])
+        ke += np.mean(m[:, None] * v * v / omd.ACCEL_UNIT)
+        pe += np.mean(k * x * x)
+        cnt += 1
+    assert abs(ke / cnt / kT - 1.0) < 0.08
+    assert abs(pe / cnt / kT - 1.0) < 0.08
