@@ -204,6 +204,22 @@ int e3mi_md_create(e3mi_model* model, int n_structures, const int64_t* atom_offs
  * rebuild_every steps). */
 int e3mi_md_step(e3mi_md* md, int n_steps, double dt_fs, double* energy_out, void* stream);
 
+/* Switch the integrator to Langevin dynamics (Section 5.5: the NVT
+ * integrator; batched systems with independent random seeds), BAOAB
+ * splitting per step:
+ *   v += dt/2 kappa F/m;  x += dt/2 v;
+ *   v = c1 v + sqrt(1 - c1^2) sqrt(kB T kappa / m) z,  c1 = exp(-friction dt);
+ *   x += dt/2 v;  F = F(x);  v += dt/2 kappa F/m
+ * temperature_K >= 0, friction_per_fs >= 0 (0 returns to velocity Verlet).
+ * z: three standard normals per atom from Philox4x64-10 (Salmon et al.,
+ * SC'11) with key (seeds[s], 0) and counter (step, index of the atom in its
+ * structure s, 0, 0), Box-Muller on the uniforms ((x >> 11) + 1/2) 2^-53.
+ * seeds: host uint64 [S] (NULL: s); step0: host int64 [S], the counter of
+ * each structure's next step (NULL: 0), so a structure continued in another
+ * packing draws the same noise. Synchronises `stream`. */
+int e3mi_md_set_langevin(e3mi_md* md, double temperature_K, double friction_per_fs, const uint64_t* seeds,
+                         const int64_t* step0, void* stream);
+
 /* Copy the current state to caller device buffers (any may be NULL):
  * pos, vel FP64 [N, 3], forces FP32 [N, 3]. Asynchronous on `stream`. */
 int e3mi_md_state(const e3mi_md* md, double* pos, double* vel, float* forces, void* stream);

@@ -206,6 +206,17 @@ class MD:
         check(lib().e3mi_md_state(self.handle, ptr(x), ptr(v), ptr(F), _stream(stream)))
         return x, v, F
 
+    def set_langevin(self, temperature_K: float, friction_per_fs: float, seeds=None, step0=None, stream=None):
+        """Langevin (BAOAB) steps from now on; see e3mi_md_set_langevin.
+        seeds, step0: one per structure (host integers) or None."""
+        sd = None if seeds is None else np.ascontiguousarray(seeds, dtype=np.uint64)
+        s0 = None if step0 is None else np.ascontiguousarray(step0, dtype=np.int64)
+        for a in (sd, s0):
+            if a is not None and a.shape != (self.n_structures,):
+                raise ValueError("one seed and one step offset per structure")
+        check(lib().e3mi_md_set_langevin(self.handle, float(temperature_K), float(friction_per_fs), ptr(sd), ptr(s0),
+                                         _stream(stream)))
+
     def stats(self) -> Tuple[int, int, int]:
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         check(lib().e3mi_md_stats(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -198,6 +199,9 @@ struct e3mi_md {
   int rebuild_every = 1, since_build = 0;
   int64_t steps = 0, rebuilds = 0, skin_violations = 0;
   std::unique_ptr<e3mi::DevBuf> x, v, F, species, inv_mass, energy, flag;
+  // Langevin (BAOAB) when gamma > 0: per-structure seeds and step offsets
+  double temperature = 0, gamma = 0;
+  std::unique_ptr<e3mi::DevBuf> seeds, step0;
 };
 
 namespace e3mi {
@@ -1185,6 +1189,7 @@ void set_weights(e3mi_model* M, const double* wts, size_t n) {
 // ---- MD -----------------------------------------------------------------------------------
 
 constexpr double kAccelUnit = 0.009648533;  // angstrom/fs^2 per (eV/angstrom)/amu
+constexpr double kBoltzmannEv = 8.617333262e-5;  // eV/K
 
 // Positions are never wrapped: the cell list bins wrapped copies internally and
 // the image vectors refer to the raw positions, so a trajectory does not
@@ -1248,13 +1253,26 @@ void md_step(e3mi_md* D, int n_steps, double dt, double* energy_out, hipStream_t
   e3mi_graph* G = D->graph;
   const double hk = 0.5 * dt * kAccelUnit;
   const double lim = 0.5 * D->skin;
+  const bool langevin = D->gamma > 0;
+  const double c1 = std::exp(-D->gamma * dt), c2 = std::sqrt(std::max(0.0, 1.0 - c1 * c1));
   for (int s = 0; s < n_steps; ++s) {
     {
       ProfScope ps(&D->model->prof, stage_id(kMdUpdate), st);
       launch_kick(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(), hk,
                   D->N, st);
-      launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), dt, lim * lim, D->N,
-                   D->flag->as<int>(), st);
+      if (!langevin) {
+        launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), dt, lim * lim, D->N,
+                     D->flag->as<int>(), st);
+      } else {
+        // BAOAB: half drift, Ornstein-Uhlenbeck velocity update, half drift
+        launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), 0.5 * dt,
+                     std::numeric_limits<double>::infinity(), D->N, D->flag->as<int>(), st);
+        launch_ou(D->v->as<double>(), D->species->as<int>(), D->inv_mass->as<double>(), G->owner->as<int>(),
+                  G->off_d->as<int64_t>(), D->seeds->as<uint64_t>(), D->step0->as<int64_t>(), D->steps, c1, c2,
+                  kBoltzmannEv * D->temperature * kAccelUnit, D->N, st);
+        launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), 0.5 * dt, lim * lim, D->N,
+                     D->flag->as<int>(), st);
+      }
     }
     if (++D->since_build >= D->rebuild_every) {
       int fh = 0;
@@ -1278,6 +1296,27 @@ void md_step(e3mi_md* D, int n_steps, double dt, double* energy_out, hipStream_t
   }
   if (energy_out)
     E3MI_HIP(hipMemcpyAsync(energy_out, D->energy->p, sizeof(double) * D->S, hipMemcpyDeviceToDevice, st));
+}
+
+void md_set_langevin(e3mi_md* D, double temperature, double gamma, const uint64_t* seeds, const int64_t* step0,
+                     hipStream_t st) {
+  E3MI_REQUIRE(std::isfinite(temperature) && temperature >= 0, E3MI_EINVAL, "temperature must be >= 0");
+  E3MI_REQUIRE(std::isfinite(gamma) && gamma >= 0, E3MI_EINVAL, "friction must be >= 0");
+  Allocator* a = &D->model->alloc;
+  std::vector<uint64_t> sd((size_t)D->S);
+  std::vector<int64_t> s0((size_t)D->S);
+  for (int s = 0; s < D->S; ++s) {
+    sd[s] = seeds ? seeds[s] : (uint64_t)s;
+    s0[s] = step0 ? step0[s] : 0;
+    E3MI_REQUIRE(s0[s] >= 0, E3MI_EINVAL, "step offsets must be >= 0");
+  }
+  // the step offset is relative to this object's own step count
+  for (int s = 0; s < D->S; ++s) s0[s] -= D->steps;
+  E3MI_HIP(hipStreamSynchronize(st));
+  D->seeds = upload(a, sd.data(), sizeof(uint64_t) * sd.size());
+  D->step0 = upload(a, s0.data(), sizeof(int64_t) * s0.size());
+  D->temperature = temperature;
+  D->gamma = gamma;
 }
 
 void set_error(const std::string& m) { g_last_error = m; }
@@ -1459,6 +1498,14 @@ int e3mi_md_stats(const e3mi_md* md, int64_t* steps, int64_t* rebuilds, int64_t*
   if (steps) *steps = md->steps;
   if (rebuilds) *rebuilds = md->rebuilds;
   if (skin_violations) *skin_violations = md->skin_violations;
+  E3MI_API_END
+}
+
+int e3mi_md_set_langevin(e3mi_md* md, double temperature_K, double friction_per_fs, const uint64_t* seeds,
+                         const int64_t* step0, void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(md, E3MI_EINVAL, "null md");
+  e3mi::md_set_langevin(md, temperature_K, friction_per_fs, seeds, step0, e3mi::as_stream(stream));
   E3MI_API_END
 }
 

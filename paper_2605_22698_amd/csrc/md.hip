@@ -4,6 +4,15 @@
 //   kick:  v += (dt/2) kappa F / m
 //   drift: x += dt v, and flag any atom that moved more than skin/2 since the
 //          neighbour lists were built (they must then be rebuilt)
+// Langevin dynamics (Section 5.5: the NVT integrator, batched systems with
+// independent seeds) adds the Ornstein-Uhlenbeck velocity update of the BAOAB
+// splitting,
+//   ou:    v <- c1 v + c2 sqrt(kB T kappa / m) z,  c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2)
+// with z three standard normals per atom from the Philox4x64-10 counter-based
+// generator (Salmon et al., SC'11), key (seed of the atom's structure, 0) and
+// counter (step, index of the atom within its structure, 0, 0), turned into
+// normals by Box-Muller on the uniforms ((x >> 11) + 1/2) 2^-53. A structure's
+// noise is thus independent of what else is packed with it.
 #include "common.h"
 #include "runtime.h"
 
@@ -41,6 +50,46 @@ __global__ void k_nonfinite(const double* __restrict__ x, int n, int* __restrict
   if (!isfinite(x[i])) atomicOr(flag, 4);
 }
 
+// Philox4x64 block function, 10 rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+__global__ void k_ou(double* __restrict__ v, const int* __restrict__ species, const double* __restrict__ inv_mass,
+                     const int* __restrict__ owner, const int64_t* __restrict__ offsets,
+                     const uint64_t* __restrict__ seeds, const int64_t* __restrict__ step0, int64_t step, double c1,
+                     double c2, double kT_kappa, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int s = owner[i];
+  uint64_t c[4] = {(uint64_t)(step0[s] + step), (uint64_t)(i - offsets[s]), 0ull, 0ull};
+  philox4x64_10(c, seeds[s], 0ull);
+  constexpr double two53 = 1.0 / 9007199254740992.0;
+  double u[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) u[k] = ((double)(c[k] >> 11) + 0.5) * two53;
+  constexpr double two_pi = 6.283185307179586476925286766559;
+  const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+  const double z0 = r0 * cos(two_pi * u[1]), z1 = r0 * sin(two_pi * u[1]), z2 = r1 * cos(two_pi * u[3]);
+  const double sig = c2 * sqrt(kT_kappa * inv_mass[species[i]]);
+  v[3 * i] = c1 * v[3 * i] + sig * z0;
+  v[3 * i + 1] = c1 * v[3 * i + 1] + sig * z1;
+  v[3 * i + 2] = c1 * v[3 * i + 2] + sig * z2;
+}
+
 inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -54,6 +103,12 @@ void launch_drift(double* x, const double* v, const double* x_ref, double dt, do
                   hipStream_t st) {
   if (N == 0) return;
   k_drift<<<blocks(N, 256), 256, 0, st>>>(x, v, x_ref, dt, limit2, N, flag);
+}
+void launch_ou(double* v, const int* species, const double* inv_mass, const int* owner, const int64_t* offsets,
+               const uint64_t* seeds, const int64_t* step0, int64_t step, double c1, double c2, double kT_kappa, int N,
+               hipStream_t st) {
+  if (N == 0) return;
+  k_ou<<<blocks(N, 256), 256, 0, st>>>(v, species, inv_mass, owner, offsets, seeds, step0, step, c1, c2, kT_kappa, N);
 }
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st) {
   if (n == 0) return;

@@ -41,6 +41,7 @@ class Request:
     cell: np.ndarray
     pbc: np.ndarray
     n_steps: int
+    seed: int = 0                 # Langevin noise seed of this request (NVT only)
     # filled in by the server
     steps_done: int = 0
     admitted_at: Optional[float] = None
@@ -58,7 +59,8 @@ class GpuExecutor:
     """Packed MD state on the GPU through the library's MD entry points."""
 
     def __init__(self, model, masses, cutoff: float, skin: float = 1.0, rebuild_every: int = 20,
-                 dt_fs: float = 0.5, edges_per_atom: Optional[float] = None):
+                 dt_fs: float = 0.5, edges_per_atom: Optional[float] = None, temperature_K: float = 0.0,
+                 friction_per_fs: float = 0.0):
         import torch
         self.torch = torch
         self.model = model
@@ -68,6 +70,9 @@ class GpuExecutor:
         self.edges_per_atom = edges_per_atom if edges_per_atom is not None else 0.1 * 4.0 / 3.0 * math.pi * rc ** 3 * 1.3
         self.md = None
         self.slices: List[slice] = []
+        # Langevin NVT when friction > 0 (each request keeps its own seed and
+        # step counter across repacks, so its noise does not depend on the pack)
+        self.temperature, self.friction = temperature_K, friction_per_fs
         self._dev = model.device
 
     def footprint(self, n_atoms: int) -> int:
@@ -92,6 +97,9 @@ class GpuExecutor:
         self.md = e3.MD(self.model, off, pos, vel, sp, self.masses, cell, pbc, self.cutoff, self.skin,
                         self.rebuild_every)
         self.slices = [slice(int(off[k]), int(off[k + 1])) for k in range(len(parts))]
+        if self.friction > 0:
+            self.md.set_langevin(self.temperature, self.friction, [p.get("seed", 0) for p in parts],
+                                 [p.get("steps_done", 0) for p in parts])
         self._species = [p["species"] for p in parts]
 
     def step(self) -> float:
@@ -113,7 +121,8 @@ class GpuExecutor:
         return {"pos": torch.tensor(req.pos, dtype=torch.float64, device=self._dev),
                 "vel": torch.tensor(req.vel, dtype=torch.float64, device=self._dev),
                 "species": torch.tensor(req.species, dtype=torch.int32, device=self._dev),
-                "cell": np.asarray(req.cell, dtype=np.float64), "pbc": np.asarray(req.pbc, dtype=np.uint8)}
+                "cell": np.asarray(req.cell, dtype=np.float64), "pbc": np.asarray(req.pbc, dtype=np.uint8),
+                "seed": int(req.seed), "steps_done": int(req.steps_done)}
 
     def close(self):
         if self.md is not None:
@@ -201,6 +210,8 @@ class Server:
                     r.admitted_at = now
                     self.active.append(r)
                     self.state.append(self.ex.upload(r))
+                for r, st in zip(self.active, self.state):
+                    st["steps_done"] = r.steps_done
                 self.ex.launch(self.state)
                 self.stats.repacks += 1
             if not self.active:

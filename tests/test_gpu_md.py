@@ -87,3 +87,98 @@ def test_packed_trajectories_equal_single():
         a, z = b.offsets[s], b.offsets[s + 1]
         xs, vs, Es, _ = _run_gpu(m, b.structure(s), vel[a:z], 25, 0.5, rebuild_every=10, skin=0.8)
         assert np.array_equal(xs, x[a:z]) and np.array_equal(vs, v[a:z]) and Es[0] == E[s]
+
+
+def _two_structures():
+    b1 = synth.jittered_lattice(30, 0.1, 0.3, 4, np.random.default_rng(61))
+    b2 = synth.jittered_lattice(40, 0.1, 0.3, 4, np.random.default_rng(62))
+    return synth.concat([b1, b2])
+
+
+@pytest.mark.parametrize("rebuild_every", [4, 20])
+def test_langevin_trajectory_matches_oracle(rebuild_every):
+    import torch
+    import paper_2605_22698_amd as e3
+    cfg = synth.ModelConfig(lmax=2, channels=32, layers=2, n_species=4, cutoff=5.0, avg_neighbors=10.0)
+    b = _two_structures()
+    vel = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(63))
+    m = model(cfg, 7)
+    seeds, step0 = [7, 9], [3, 11]
+    T, gamma, dt, n = 300.0, 0.05, 0.5, 12
+    say(f"langevin parity rebuild_every={rebuild_every}")
+    d = device()
+    md = e3.MD(m, b.offsets, torch.tensor(b.pos, dtype=torch.float64, device=d),
+               torch.tensor(vel, dtype=torch.float64, device=d), torch.tensor(b.species, dtype=torch.int32, device=d),
+               synth.SPECIES_MASS[:cfg.n_species], b.cell, b.pbc, cfg.cutoff, 1.0, rebuild_every)
+    md.set_langevin(T, gamma, seeds, step0)
+    E = torch.empty(b.n_structures, dtype=torch.float64, device=d)
+    md.step(n, dt, E)
+    x, v, _ = md.state()
+    torch.cuda.synchronize()
+    x, v, E = x.cpu().numpy(), v.cpu().numpy(), E.cpu().numpy()
+    om_m = om.Model(cfg, synth.model_weights(cfg, 7))
+
+    def force(xx):
+        Es, F, _ = om.energy_forces(om_m, synth.Batch(xx, b.species, b.cell, b.pbc, b.offsets))
+        return Es, F
+    xr, vr, Er = omd.langevin_baoab(force, b.pos, vel, synth.SPECIES_MASS[b.species], dt, n, T, gamma, b.offsets,
+                                    seeds, step0)
+    assert np.abs(_min_image(x - xr, b)).max() < 1e-9
+    assert np.abs(v - vr).max() < 1e-9
+    assert np.all(np.abs(E - Er[-1]) <= 1e-5 * np.abs(Er[-1]))
+    # the thermostat acted: the trajectory is not the velocity-Verlet one
+    xv, _, _ = omd.velocity_verlet(force, b.pos, vel, synth.SPECIES_MASS[b.species], dt, n)
+    assert np.abs(_min_image(xv - xr, b)).max() > 1e-6
+
+
+def test_langevin_packed_equals_alone():
+    import torch
+    import paper_2605_22698_amd as e3
+    cfg, b, _, _ = synth.differentiation_config(3, 30, 80)
+    vel = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(64))
+    m = model(cfg, 3)
+    d = device()
+    seeds = [101, 202, 303]
+    step0 = [0, 5, 17]
+
+    def run(bb, vv, sd, s0):
+        md = e3.MD(m, bb.offsets, torch.tensor(bb.pos, dtype=torch.float64, device=d),
+                   torch.tensor(vv, dtype=torch.float64, device=d),
+                   torch.tensor(bb.species, dtype=torch.int32, device=d), synth.SPECIES_MASS[:cfg.n_species],
+                   bb.cell, bb.pbc, cfg.cutoff, 0.8, 10)
+        md.set_langevin(300.0, 0.02, sd, s0)
+        md.step(25, 0.5)
+        x, v, _ = md.state()
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), v.cpu().numpy()
+    x, v = run(b, vel, seeds, step0)
+    for s in range(3):
+        a, z = b.offsets[s], b.offsets[s + 1]
+        xs, vs = run(b.structure(s), vel[a:z], [seeds[s]], [step0[s]])
+        assert np.array_equal(xs, x[a:z]) and np.array_equal(vs, v[a:z])
+
+
+def test_langevin_equilibrates_to_target_temperature():
+    import torch
+    import paper_2605_22698_amd as e3
+    cfg, b = synth.single_config(n=300)
+    m = model(cfg, 2)
+    d = device()
+    mass = synth.SPECIES_MASS[b.species]
+    md = e3.MD(m, b.offsets, torch.tensor(b.pos, dtype=torch.float64, device=d),
+               torch.zeros((b.n_atoms, 3), dtype=torch.float64, device=d),
+               torch.tensor(b.species, dtype=torch.int32, device=d), synth.SPECIES_MASS[:cfg.n_species],
+               b.cell, b.pbc, cfg.cutoff, 1.0, 20)
+    T = 300.0
+    md.set_langevin(T, 0.1, [2026])
+    md.step(600, 0.5)
+    temps = []
+    for _ in range(100):
+        md.step(10, 0.5)
+        _, v, _ = md.state()
+        torch.cuda.synchronize()
+        ke = omd.kinetic_energy(v.cpu().numpy(), mass)
+        temps.append(2.0 * ke / (3.0 * b.n_atoms * omd.KB_EV))
+    t_mean = float(np.mean(temps))
+    say(f"Langevin NVT: mean T {t_mean:.1f} K (target {T} K)")
+    assert abs(t_mean / T - 1.0) < 0.05

@@ -33,9 +33,10 @@ def _requests(n):
     return out
 
 
-def _serve(m, reqs, budget, max_active=64):
+def _serve(m, reqs, budget, max_active=64, friction=0.0):
     clock = StepClock()
-    ex = GpuExecutor(m, synth.SPECIES_MASS[:4], 5.0, skin=1.0, rebuild_every=7)
+    ex = GpuExecutor(m, synth.SPECIES_MASS[:4], 5.0, skin=1.0, rebuild_every=7, temperature_K=300.0,
+                     friction_per_fs=friction)
     step = ex.step
 
     def timed_step():
@@ -74,3 +75,20 @@ def test_budget_forces_queueing_on_gpu():
     srv, stats = _serve(m, reqs, budget=int(one * 1.2))
     assert all(r.steps_done == r.n_steps for r in srv.done)
     assert any(r.admitted_at > r.arrival for r in srv.done)
+
+
+def test_langevin_requests_alone_equal_in_mix():
+    # NVT requests keep their own seed and step counter across repacks
+    m = model(synth.serving_model(), 4)
+    reqs = _requests(5)
+    for k, r in enumerate(reqs):
+        r.seed = 1000 + k
+    srv, stats = _serve(m, reqs, budget=1 << 40, friction=0.05)
+    assert stats.repacks >= 3
+    mixed = {r.rid: r for r in srv.done}
+    for k, r in enumerate(_requests(5)):
+        alone, _ = _serve(m, [Request(r.rid, 0.0, r.pos, r.vel, r.species, r.cell, r.pbc, r.n_steps, seed=1000 + k)],
+                          1 << 40, friction=0.05)
+        a = alone.done[0]
+        assert np.array_equal(a.final_pos, mixed[r.rid].final_pos), r.rid
+        assert np.array_equal(a.final_vel, mixed[r.rid].final_vel), r.rid
