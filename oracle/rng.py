@@ -45,6 +45,13 @@ def uniforms(seed: int, step: int, atom: int) -> Tuple[float, float, float, floa
     return tuple(((v >> 11) + 0.5) * 2.0 ** -53 for v in x)
 
 
+def barostat_uniforms(seed: int, move: int) -> Tuple[float, float]:
+    """Two uniforms for the move-th volume proposal of a structure: key
+    (seed, 1), counter (move, 0, 0, 0) (a stream apart from the thermostat's)."""
+    x = philox4x64_10((move, 0, 0, 0), (seed, 1))
+    return ((x[0] >> 11) + 0.5) * 2.0 ** -53, ((x[1] >> 11) + 0.5) * 2.0 ** -53
+
+
 def normals3(seed: int, step: int, atom: int) -> Tuple[float, float, float]:
     """Three standard normal draws for one atom at one step."""
     u0, u1, u2, u3 = uniforms(seed, step, atom)

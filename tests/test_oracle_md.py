@@ -101,3 +101,38 @@ def test_langevin_samples_boltzmann_temperature_in_harmonic_well():
         cnt += 1
     assert abs(ke / cnt / kT - 1.0) < 0.08
     assert abs(pe / cnt / kT - 1.0) < 0.08
+
+
+def test_mc_barostat_ideal_gas_volume():
+    # E = 0: the volume moves alone sample p(V) ~ V^N exp(-P V / kT),
+    # so <V> = (N + 1) kT / P (about 174 A^3 here; proposals up to +-60 A^3)
+    n, T, P_bar = 20, 300.0, 5000.0
+    kT = omd.KB_EV * T
+    P = P_bar * omd.BAR_EV_A3
+    x = np.random.default_rng(5).uniform(0, 10, size=(n, 3))
+    boxes = np.array([[10.0, 10.0, 10.0]])
+    E = np.zeros(1)
+    vols = []
+    for mv in range(6000):
+        x, boxes, E, _ = omd.barostat_move(lambda xx, bb: np.zeros(1), x, boxes, E, [0, n], T, P_bar, [60.0],
+                                           [17], [mv])
+        if mv >= 1000:
+            vols.append(np.prod(boxes[0]))
+    expect = (n + 1) * kT / P
+    assert abs(np.mean(vols) / expect - 1.0) < 0.05
+    # and the relative fluctuation of an ideal gas, 1 / sqrt(N + 1)
+    assert abs(np.std(vols) / np.mean(vols) * np.sqrt(n + 1) - 1.0) < 0.15
+
+
+def test_npt_without_moves_is_langevin():
+    rng_np = np.random.default_rng(8)
+    x0 = rng_np.normal(size=(6, 3))
+    v0 = rng_np.normal(size=(6, 3)) * 0.01
+    m = np.full(6, 4.0)
+
+    def force(x, boxes=None):
+        return np.array([0.5 * np.sum(x * x)]), -x
+    xa, va, _ = omd.langevin_baoab(force, x0, v0, m, 0.5, 10, 300.0, 0.1, [0, 6], [3], [0])
+    xb, vb, bb, _, dec = omd.langevin_npt(force, x0, v0, np.array([[9.0, 9.0, 9.0]]), m, 0.5, 10, 300.0, 0.1,
+                                          [0, 6], [3], [0], 1.0, 100, 0.01, [4], [0])
+    assert not dec and np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(bb, [[9.0, 9.0, 9.0]])
