@@ -220,6 +220,34 @@ int e3mi_md_step(e3mi_md* md, int n_steps, double dt_fs, double* energy_out, voi
 int e3mi_md_set_langevin(e3mi_md* md, double temperature_K, double friction_per_fs, const uint64_t* seeds,
                          const int64_t* step0, void* stream);
 
+/* Monte Carlo barostat on top of the Langevin integrator (Section 5.5: NPT
+ * with a Monte Carlo barostat combined with Langevin dynamics; batched
+ * systems with independent cells and seeds; Appendix D validates it). After
+ * a step that brings structure s's own step count (the step0 of
+ * e3mi_md_set_langevin plus the steps taken since) to a multiple of
+ * `interval`, s (periodic along every axis) proposes an isotropic volume
+ * change dV = (2 u0 - 1) dV_max_s, with dV_max_s = dv_max[s] (host FP64
+ * [S], A^3) or, when dv_max is NULL, volume_fraction x its volume when this
+ * call is made (fixed thereafter, so proposals are symmetric), scales its
+ * cell lengths and positions by (V'/V)^(1/3) (velocities kept), evaluates all
+ * proposals in one energy pass and accepts each with the Metropolis rule on
+ *   w = E' - E + P dV - N_s kB T ln(V'/V)      (P in bar, 1 bar = 6.241509074e-7 eV/A^3)
+ * i.e. accepts if w <= 0 or u1 < exp(-w / kB T); V' <= 0 is rejected.
+ * u0, u1: Philox4x64-10 with key (seeds[s], 1) and counter (move_s, 0, 0, 0),
+ * uniforms ((x >> 11) + 1/2) 2^-53 of the first two outputs; move_s starts at
+ * move0[s] (NULL: 0) and counts proposals. seeds NULL: s. interval 0 turns
+ * the barostat off. Requires e3mi_md_set_langevin with a positive friction
+ * and temperature (T of the acceptance rule). Each proposal costs two
+ * neighbour rebuilds and up to two energy evaluations and synchronises the
+ * stream. Errors: EINVAL for open axes or bad arguments. */
+int e3mi_md_set_barostat(e3mi_md* md, double pressure_bar, int interval, double volume_fraction,
+                         const double* dv_max, const uint64_t* seeds, const int64_t* move0);
+
+/* Current cells (host FP64 [S, 3, 3], rows = lattice vectors; changed by the
+ * barostat) and the barostat's proposal / acceptance counts (any output may
+ * be NULL). Reflects the last completed e3mi_md_step. */
+int e3mi_md_cells(const e3mi_md* md, double* cells, int64_t* proposed, int64_t* accepted);
+
 /* Copy the current state to caller device buffers (any may be NULL):
  * pos, vel FP64 [N, 3], forces FP32 [N, 3]. Asynchronous on `stream`. */
 int e3mi_md_state(const e3mi_md* md, double* pos, double* vel, float* forces, void* stream);
@@ -240,7 +268,8 @@ size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_
  * recording; 0 stops recording and keeps the counters. Stages: prune, embed, radial_fwd, tp_fwd, mix_fwd,
  * gate_fwd, readout, gate_bwd, mix_bwd, tp_bwd_edge, radial_bwd, tp_bwd_node,
  * forces, md_update, graph_build, first_fwd, first_bwd (the species-factorised
- * first layer), last_fwd, last_bwd (the fused last layer); "name@t" selects
+ * first layer), last_fwd, last_bwd (the fused last layer), barostat (volume
+ * moves, including their rebuilds and energy passes); "name@t" selects
  * interaction layer t.
  * e3mi_profile_query waits for the recorded events and returns the summed
  * milliseconds and the number of timed launches of a stage. */

@@ -32,8 +32,9 @@ well it samples the Boltzmann temperature.
 
 NPT (§5.5: a Monte Carlo barostat combined with the Langevin integrator,
 batched systems with independent cells and seeds; reading of the standard
-MC barostat): every `interval` steps, for each structure s with periodic
-box lengths L_s (volume V = L_x L_y L_z),
+MC barostat): after a step that brings a structure's own step count
+(step0_s + steps taken) to a multiple of `interval`, the structure s with
+periodic box lengths L_s (volume V = L_x L_y L_z) proposes a volume move,
   u_0, u_1 = rng.barostat_uniforms(seed_s, move_s)
   dV = (2 u_0 - 1) dV_max,  V' = V + dV,  lambda = (V'/V)^(1/3)
   (dV_max = f V_0, fixed from the volume V_0 when the barostat starts, so that
@@ -111,10 +112,10 @@ def langevin_baoab(force_fn: Callable[[np.ndarray], Tuple[np.ndarray, np.ndarray
 
 def barostat_move(energy_fn: Callable[[np.ndarray, np.ndarray], np.ndarray], x: np.ndarray, boxes: np.ndarray,
                   E_old: np.ndarray, offsets: Sequence[int], temperature: float, pressure_bar: float,
-                  dv_max: Sequence[float], seeds: Sequence[int], moves: Sequence[int]):
-    """One volume proposal per structure (all structures at once, each
-    decided alone). energy_fn(x, boxes) -> E_s. Returns x, boxes, E_s and the
-    accepted flags."""
+                  dv_max: Sequence[float], seeds: Sequence[int], moves: Sequence[int], active=None):
+    """One volume proposal per active structure (all at once, each decided
+    alone; inactive ones are left as they are). energy_fn(x, boxes) -> E_s.
+    Returns x, boxes, E_s and the accepted flags."""
     kT = KB_EV * temperature
     P = pressure_bar * BAR_EV_A3
     S = len(offsets) - 1
@@ -122,7 +123,10 @@ def barostat_move(energy_fn: Callable[[np.ndarray, np.ndarray], np.ndarray], x: 
     dV = np.zeros(S)
     ratio = np.ones(S)
     u1 = np.zeros(S)
+    active = np.ones(S, dtype=bool) if active is None else np.asarray(active, dtype=bool)
     for s in range(S):
+        if not active[s]:
+            continue
         a, b = rng.barostat_uniforms(int(seeds[s]), int(moves[s]))
         V = float(np.prod(boxes[s]))
         dV[s] = (2.0 * a - 1.0) * float(dv_max[s])
@@ -136,7 +140,7 @@ def barostat_move(energy_fn: Callable[[np.ndarray, np.ndarray], np.ndarray], x: 
     acc = np.zeros(S, dtype=bool)
     for s in range(S):
         n_s = int(offsets[s + 1] - offsets[s])
-        if float(np.prod(boxes[s])) + dV[s] > 0.0:
+        if active[s] and float(np.prod(boxes[s])) + dV[s] > 0.0:
             w = float(E_t[s] - E_old[s]) + P * dV[s] - n_s * kT * np.log(ratio[s])
             acc[s] = w <= 0.0 or u1[s] < np.exp(-w / kT)
     keep = acc[owner]
@@ -151,9 +155,9 @@ def langevin_npt(force_fn: Callable[[np.ndarray, np.ndarray], Tuple[np.ndarray, 
                  temperature: float, gamma: float, offsets: Sequence[int], seeds: Sequence[int],
                  step0: Sequence[int], pressure_bar: float, interval: int, fraction: float,
                  baro_seeds: Sequence[int], move0: Sequence[int]):
-    """BAOAB steps with a volume proposal after every `interval`-th step.
+    """BAOAB steps with volume proposals on each structure's own schedule.
     force_fn(x, boxes) -> (E_s, F). Returns x, v, boxes, E_s after every step and
-    the list of accepted flags per proposal."""
+    the (structure, accepted) pairs of every proposal, in order."""
     x = np.array(x, dtype=np.float64)
     boxes = np.array(boxes, dtype=np.float64)
     moves = np.array(move0, dtype=np.int64)
@@ -165,10 +169,12 @@ def langevin_npt(force_fn: Callable[[np.ndarray, np.ndarray], Tuple[np.ndarray, 
         x, v, Es = langevin_baoab(lambda xx: force_fn(xx, boxes), x, v, masses, dt, 1, temperature, gamma, offsets,
                                   seeds, [int(s0) + k for s0 in step0])
         E = Es[-1]
-        if (k + 1) % interval == 0:
+        active = np.array([(int(s0) + k + 1) % interval == 0 for s0 in step0])
+        if active.any():
             x, boxes, E, acc = barostat_move(lambda xx, bb: force_fn(xx, bb)[0], x, boxes, E, offsets, temperature,
-                                             pressure_bar, dv_max, baro_seeds, moves)
-            moves += 1
-            decisions.append(acc)
+                                             pressure_bar, dv_max, baro_seeds, moves, active)
+            for s in np.nonzero(active)[0]:
+                decisions.append((int(s), bool(acc[s])))
+            moves += active
         energies.append(np.asarray(E))
     return x, v, boxes, energies, decisions

@@ -217,6 +217,26 @@ class MD:
         check(lib().e3mi_md_set_langevin(self.handle, float(temperature_K), float(friction_per_fs), ptr(sd), ptr(s0),
                                          _stream(stream)))
 
+    def set_barostat(self, pressure_bar: float, interval: int, volume_fraction: float = 0.01, seeds=None,
+                     move0=None, dv_max=None):
+        """Monte Carlo volume moves on each structure's own schedule; see
+        e3mi_md_set_barostat. dv_max: per-structure volume step (A^3) or None."""
+        sd = None if seeds is None else np.ascontiguousarray(seeds, dtype=np.uint64)
+        m0 = None if move0 is None else np.ascontiguousarray(move0, dtype=np.int64)
+        dv = None if dv_max is None else np.ascontiguousarray(dv_max, dtype=np.float64)
+        for a in (sd, m0, dv):
+            if a is not None and a.shape != (self.n_structures,):
+                raise ValueError("one value per structure")
+        check(lib().e3mi_md_set_barostat(self.handle, float(pressure_bar), int(interval), float(volume_fraction),
+                                         ptr(dv), ptr(sd), ptr(m0)))
+
+    def cells(self):
+        """(cells [S, 3, 3] host FP64, proposals, accepted) after the last step."""
+        c = np.zeros((self.n_structures, 3, 3), dtype=np.float64)
+        p, a = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().e3mi_md_cells(self.handle, c.ctypes.data, ctypes.byref(p), ctypes.byref(a)))
+        return c, p.value, a.value
+
     def stats(self) -> Tuple[int, int, int]:
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         check(lib().e3mi_md_stats(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))

@@ -133,12 +133,13 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Timed stages (per layer where it applies: index = stage * 8 + layer).
 enum Stage : int {
   kPrune = 0, kEmbed, kRadialFwd, kTpFwd, kMixFwd, kGateFwd, kReadout, kGateBwd, kMixBwd, kTpBwdEdge,
-  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kLastFwd, kLastBwd, kNumStages
+  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kLastFwd, kLastBwd, kBarostat,
+  kNumStages
 };
 const char* const kStageNames[kNumStages] = {
     "prune", "embed", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd", "mix_bwd",
     "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build", "first_fwd", "first_bwd",
-    "last_fwd", "last_bwd"};
+    "last_fwd", "last_bwd", "barostat"};
 inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
 
 }  // namespace
@@ -202,6 +203,15 @@ struct e3mi_md {
   // Langevin (BAOAB) when gamma > 0: per-structure seeds and step offsets
   double temperature = 0, gamma = 0;
   std::unique_ptr<e3mi::DevBuf> seeds, step0;
+  std::vector<int64_t> step0_h;  // host copy: structure s has taken step0_h[s] + steps steps
+  // Monte Carlo barostat every baro_interval steps (0: off)
+  double pressure_bar = 0;
+  int baro_interval = 0;
+  std::vector<double> dv_max;
+  std::vector<uint64_t> baro_seed;
+  std::vector<int64_t> baro_move;
+  int64_t baro_proposed = 0, baro_accepted = 0;
+  std::unique_ptr<e3mi::DevBuf> x_save, lam, keep;
 };
 
 namespace e3mi {
@@ -1190,6 +1200,24 @@ void set_weights(e3mi_model* M, const double* wts, size_t n) {
 
 constexpr double kAccelUnit = 0.009648533;  // angstrom/fs^2 per (eV/angstrom)/amu
 constexpr double kBoltzmannEv = 8.617333262e-5;  // eV/K
+constexpr double kBarEvA3 = 6.241509074e-7;        // eV/A^3 per bar
+
+// Philox4x64-10 (Salmon et al., SC'11) on the host, for the barostat's two
+// uniforms per volume proposal: key (seed, 1), counter (move, 0, 0, 0).
+void philox4x64_10_host(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  for (int r = 0; r < 10; ++r) {
+    const unsigned __int128 p0 = (unsigned __int128)M0 * c[0], p1 = (unsigned __int128)M1 * c[2];
+    const uint64_t n0 = (uint64_t)(p1 >> 64) ^ c[1] ^ k0, n2 = (uint64_t)(p0 >> 64) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint64_t)p1;
+    c[2] = n2;
+    c[3] = (uint64_t)p0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
 
 // Positions are never wrapped: the cell list bins wrapped copies internally and
 // the image vectors refer to the raw positions, so a trajectory does not
@@ -1218,6 +1246,7 @@ e3mi_md* new_md(e3mi_model* M, int S, const int64_t* off, const double* pos, con
   D->skin = skin;
   Allocator* a = &M->alloc;
   E3MI_REQUIRE(off && S >= 1, E3MI_EINVAL, "bad atom_offsets");
+  E3MI_REQUIRE(cell && pbc, E3MI_EINVAL, "null cell or pbc");
   D->N = (int)off[S];
   E3MI_REQUIRE(D->N == 0 || (pos && vel && species), E3MI_EINVAL, "null state arrays");
   const size_t n3 = sizeof(double) * 3 * (D->N + 1);
@@ -1242,11 +1271,16 @@ e3mi_md* new_md(e3mi_model* M, int S, const int64_t* off, const double* pos, con
   D->flag = std::make_unique<DevBuf>(a);
   D->flag->ensure(sizeof(int));
   E3MI_HIP(hipMemsetAsync(D->flag->p, 0, sizeof(int), st));
+  D->off_h.assign(off, off + S + 1);
+  D->cell_h.assign(cell, cell + 9 * (size_t)S);
+  D->pbc_h.assign(pbc, pbc + 3 * (size_t)S);
   D->graph = new_graph(M, S, off, D->x->as<double>(), D->species->as<int>(), cell, pbc, cutoff, skin, st);
   energy_forces(M, D->graph, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
   E3MI_HIP(hipStreamSynchronize(st));
   return D.release();
 }
+
+void barostat_move(e3mi_md* D, const std::vector<int>& active, hipStream_t st);
 
 void md_step(e3mi_md* D, int n_steps, double dt, double* energy_out, hipStream_t st) {
   E3MI_REQUIRE(n_steps >= 0 && std::isfinite(dt), E3MI_EINVAL, "bad step arguments");
@@ -1293,9 +1327,121 @@ void md_step(e3mi_md* D, int n_steps, double dt, double* energy_out, hipStream_t
                   D->N, st);
     }
     D->steps++;
+    if (D->baro_interval > 0) {
+      // each structure proposes on its own schedule, so the moves do not
+      // depend on what else is packed with it
+      std::vector<int> active((size_t)D->S);
+      bool any = false;
+      for (int q = 0; q < D->S; ++q) {
+        active[q] = (D->step0_h[q] + D->steps) % D->baro_interval == 0;
+        any |= active[q] != 0;
+      }
+      if (any) barostat_move(D, active, st);
+    }
   }
   if (energy_out)
     E3MI_HIP(hipMemcpyAsync(energy_out, D->energy->p, sizeof(double) * D->S, hipMemcpyDeviceToDevice, st));
+}
+
+// One isotropic volume proposal per active structure, all evaluated in one
+// pass and each decided alone (Metropolis on dE + P dV - N kB T ln V'/V);
+// inactive structures are left as they are.
+void barostat_move(e3mi_md* D, const std::vector<int>& active, hipStream_t st) {
+  e3mi_graph* G = D->graph;
+  e3mi_model* M = D->model;
+  Allocator* a = &M->alloc;
+  const int S = D->S, N = D->N;
+  ProfScope ps(&M->prof, stage_id(kBarostat), st);
+  std::vector<double> E_old(S), E_t(S), lam(S, 1.0), dV(S, 0.0), u1(S, 0.0);
+  std::vector<int> ok(S, 1), keep(S, 1);
+  E3MI_HIP(hipMemcpyAsync(E_old.data(), D->energy->p, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  E3MI_HIP(hipStreamSynchronize(st));
+  const std::vector<double> box_old = G->box_h;
+  for (int s = 0; s < S; ++s) {
+    if (!active[s]) continue;
+    uint64_t c[4] = {(uint64_t)D->baro_move[s], 0ull, 0ull, 0ull};
+    philox4x64_10_host(c, D->baro_seed[s], 1ull);
+    const double ua = ((double)(c[0] >> 11) + 0.5) * 0x1.0p-53, ub = ((double)(c[1] >> 11) + 0.5) * 0x1.0p-53;
+    const double V = box_old[3 * s] * box_old[3 * s + 1] * box_old[3 * s + 2];
+    dV[s] = (2.0 * ua - 1.0) * D->dv_max[s];
+    u1[s] = ub;
+    if (V + dV[s] > 0.0) {
+      lam[s] = std::cbrt((V + dV[s]) / V);
+    } else {
+      ok[s] = 0;
+      dV[s] = 0.0;
+    }
+    for (int k = 0; k < 3; ++k) G->box_h[3 * s + k] = box_old[3 * s + k] * lam[s];
+  }
+  ensure(D->x_save, a, sizeof(double) * 3 * (size_t)(N + 1));
+  if (N) E3MI_HIP(hipMemcpyAsync(D->x_save->p, D->x->p, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
+  ensure(D->lam, a, sizeof(double) * S);
+  ensure(D->keep, a, sizeof(int) * S);
+  E3MI_HIP(hipMemcpyAsync(D->lam->p, lam.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+  launch_scale_positions(D->x->as<double>(), G->owner->as<int>(), D->lam->as<double>(), N, st);
+  E3MI_HIP(hipMemcpyAsync(G->box_d->p, G->box_h.data(), sizeof(double) * 3 * S, hipMemcpyHostToDevice, st));
+  build_lists(G, D->x->as<double>(), st);
+  energy_forces(M, G, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
+  E3MI_HIP(hipMemcpyAsync(E_t.data(), D->energy->p, sizeof(double) * S, hipMemcpyDeviceToHost, st));
+  E3MI_HIP(hipStreamSynchronize(st));
+  const double kT = kBoltzmannEv * D->temperature, P = D->pressure_bar * kBarEvA3;
+  bool all = true;
+  for (int s = 0; s < S; ++s) {
+    if (!active[s]) continue;
+    const double V = box_old[3 * s] * box_old[3 * s + 1] * box_old[3 * s + 2];
+    const double n_s = (double)(D->off_h[s + 1] - D->off_h[s]);
+    keep[s] = 0;
+    if (ok[s]) {
+      const double w = (E_t[s] - E_old[s]) + P * dV[s] - n_s * kT * std::log((V + dV[s]) / V);
+      keep[s] = (w <= 0.0 || u1[s] < std::exp(-w / kT)) ? 1 : 0;
+    }
+    D->baro_move[s]++;
+    D->baro_proposed++;
+    D->baro_accepted += keep[s];
+    if (!keep[s]) {
+      all = false;
+      for (int k = 0; k < 3; ++k) G->box_h[3 * s + k] = box_old[3 * s + k];
+    }
+    for (int k = 0; k < 3; ++k) D->cell_h[9 * s + 4 * k] = G->box_h[3 * s + k];
+  }
+  if (!all) {
+    // put the rejected structures back and evaluate the final state
+    E3MI_HIP(hipMemcpyAsync(D->keep->p, keep.data(), sizeof(int) * S, hipMemcpyHostToDevice, st));
+    launch_restore_rows(D->x->as<double>(), D->x_save->as<double>(), G->owner->as<int>(), D->keep->as<int>(), N, st);
+    E3MI_HIP(hipMemcpyAsync(G->box_d->p, G->box_h.data(), sizeof(double) * 3 * S, hipMemcpyHostToDevice, st));
+    build_lists(G, D->x->as<double>(), st);
+    energy_forces(M, G, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
+  }
+  E3MI_HIP(hipStreamSynchronize(st));  // the host vectors above must outlive the copies
+  D->since_build = 0;
+}
+
+void md_set_barostat(e3mi_md* D, double pressure_bar, int interval, double fraction, const double* dv_max,
+                     const uint64_t* seeds, const int64_t* move0) {
+  E3MI_REQUIRE(interval >= 0, E3MI_EINVAL, "interval must be >= 0");
+  if (interval == 0) {
+    D->baro_interval = 0;
+    return;
+  }
+  E3MI_REQUIRE(D->gamma > 0 && D->temperature > 0, E3MI_EINVAL,
+               "the barostat needs Langevin dynamics at a positive temperature (e3mi_md_set_langevin)");
+  E3MI_REQUIRE(std::isfinite(pressure_bar), E3MI_EINVAL, "pressure must be finite");
+  E3MI_REQUIRE(dv_max || (fraction > 0 && fraction < 1), E3MI_EINVAL, "volume fraction must be in (0, 1)");
+  e3mi_graph* G = D->graph;
+  D->dv_max.assign(D->S, 0.0);
+  D->baro_seed.assign(D->S, 0);
+  D->baro_move.assign(D->S, 0);
+  for (int s = 0; s < D->S; ++s) {
+    for (int k = 0; k < 3; ++k)
+      E3MI_REQUIRE(D->pbc_h[3 * s + k], E3MI_EINVAL, "the barostat needs structures periodic along every axis");
+    D->dv_max[s] = dv_max ? dv_max[s] : fraction * G->box_h[3 * s] * G->box_h[3 * s + 1] * G->box_h[3 * s + 2];
+    E3MI_REQUIRE(std::isfinite(D->dv_max[s]) && D->dv_max[s] > 0, E3MI_EINVAL, "volume steps must be positive");
+    D->baro_seed[s] = seeds ? seeds[s] : (uint64_t)s;
+    D->baro_move[s] = move0 ? move0[s] : 0;
+    E3MI_REQUIRE(D->baro_move[s] >= 0, E3MI_EINVAL, "move counters must be >= 0");
+  }
+  D->pressure_bar = pressure_bar;
+  D->baro_interval = interval;
 }
 
 void md_set_langevin(e3mi_md* D, double temperature, double gamma, const uint64_t* seeds, const int64_t* step0,
@@ -1312,6 +1458,7 @@ void md_set_langevin(e3mi_md* D, double temperature, double gamma, const uint64_
   }
   // the step offset is relative to this object's own step count
   for (int s = 0; s < D->S; ++s) s0[s] -= D->steps;
+  D->step0_h = s0;
   E3MI_HIP(hipStreamSynchronize(st));
   D->seeds = upload(a, sd.data(), sizeof(uint64_t) * sd.size());
   D->step0 = upload(a, s0.data(), sizeof(int64_t) * s0.size());
@@ -1506,6 +1653,23 @@ int e3mi_md_set_langevin(e3mi_md* md, double temperature_K, double friction_per_
   E3MI_API_BEGIN
   E3MI_REQUIRE(md, E3MI_EINVAL, "null md");
   e3mi::md_set_langevin(md, temperature_K, friction_per_fs, seeds, step0, e3mi::as_stream(stream));
+  E3MI_API_END
+}
+
+int e3mi_md_set_barostat(e3mi_md* md, double pressure_bar, int interval, double volume_fraction,
+                         const double* dv_max, const uint64_t* seeds, const int64_t* move0) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(md, E3MI_EINVAL, "null md");
+  e3mi::md_set_barostat(md, pressure_bar, interval, volume_fraction, dv_max, seeds, move0);
+  E3MI_API_END
+}
+
+int e3mi_md_cells(const e3mi_md* md, double* cells, int64_t* proposed, int64_t* accepted) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(md, E3MI_EINVAL, "null md");
+  if (cells) std::memcpy(cells, md->cell_h.data(), sizeof(double) * 9 * md->S);
+  if (proposed) *proposed = md->baro_proposed;
+  if (accepted) *accepted = md->baro_accepted;
   E3MI_API_END
 }
 

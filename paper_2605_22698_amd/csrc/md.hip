@@ -90,6 +90,27 @@ __global__ void k_ou(double* __restrict__ v, const int* __restrict__ species, co
   v[3 * i + 2] = c1 * v[3 * i + 2] + sig * z2;
 }
 
+// Monte Carlo barostat: scale a structure's positions by its factor, and
+// put back the rows of the structures whose volume move was rejected.
+__global__ void k_scale_positions(double* __restrict__ x, const int* __restrict__ owner, const double* __restrict__ lam,
+                                  int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double f = lam[owner[i]];
+  x[3 * i] *= f;
+  x[3 * i + 1] *= f;
+  x[3 * i + 2] *= f;
+}
+
+__global__ void k_restore_rows(double* __restrict__ x, const double* __restrict__ x_save, const int* __restrict__ owner,
+                               const int* __restrict__ keep, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N || keep[owner[i]]) return;
+  x[3 * i] = x_save[3 * i];
+  x[3 * i + 1] = x_save[3 * i + 1];
+  x[3 * i + 2] = x_save[3 * i + 2];
+}
+
 inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -109,6 +130,14 @@ void launch_ou(double* v, const int* species, const double* inv_mass, const int*
                hipStream_t st) {
   if (N == 0) return;
   k_ou<<<blocks(N, 256), 256, 0, st>>>(v, species, inv_mass, owner, offsets, seeds, step0, step, c1, c2, kT_kappa, N);
+}
+void launch_scale_positions(double* x, const int* owner, const double* lam, int N, hipStream_t st) {
+  if (N == 0) return;
+  k_scale_positions<<<blocks(N, 256), 256, 0, st>>>(x, owner, lam, N);
+}
+void launch_restore_rows(double* x, const double* x_save, const int* owner, const int* keep, int N, hipStream_t st) {
+  if (N == 0) return;
+  k_restore_rows<<<blocks(N, 256), 256, 0, st>>>(x, x_save, owner, keep, N);
 }
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st) {
   if (n == 0) return;

@@ -319,6 +319,8 @@ void launch_kick(double* v, const float* F, const int* species, const double* in
 void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N, int* flag,
                   hipStream_t st);
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st);
+void launch_scale_positions(double* x, const int* owner, const double* lam, int N, hipStream_t st);
+void launch_restore_rows(double* x, const double* x_save, const int* owner, const int* keep, int N, hipStream_t st);
 void launch_ou(double* v, const int* species, const double* inv_mass, const int* owner, const int64_t* offsets,
                const uint64_t* seeds, const int64_t* step0, int64_t step, double c1, double c2, double kT_kappa, int N,
                hipStream_t st);

@@ -48,6 +48,7 @@ class Request:
     finished_at: Optional[float] = None
     final_pos: Optional[np.ndarray] = None
     final_vel: Optional[np.ndarray] = None
+    final_cell: Optional[np.ndarray] = None
     rejected: bool = False
 
     @property
@@ -60,7 +61,8 @@ class GpuExecutor:
 
     def __init__(self, model, masses, cutoff: float, skin: float = 1.0, rebuild_every: int = 20,
                  dt_fs: float = 0.5, edges_per_atom: Optional[float] = None, temperature_K: float = 0.0,
-                 friction_per_fs: float = 0.0):
+                 friction_per_fs: float = 0.0, pressure_bar: Optional[float] = None, barostat_interval: int = 25,
+                 volume_fraction: float = 0.01):
         import torch
         self.torch = torch
         self.model = model
@@ -73,6 +75,10 @@ class GpuExecutor:
         # Langevin NVT when friction > 0 (each request keeps its own seed and
         # step counter across repacks, so its noise does not depend on the pack)
         self.temperature, self.friction = temperature_K, friction_per_fs
+        # NPT (Monte Carlo barostat) when a pressure is given: each request
+        # proposes on its own step schedule with a volume step fixed from its
+        # initial volume
+        self.pressure, self.baro_interval, self.volume_fraction = pressure_bar, barostat_interval, volume_fraction
         self._dev = model.device
 
     def footprint(self, n_atoms: int) -> int:
@@ -100,6 +106,10 @@ class GpuExecutor:
         if self.friction > 0:
             self.md.set_langevin(self.temperature, self.friction, [p.get("seed", 0) for p in parts],
                                  [p.get("steps_done", 0) for p in parts])
+            if self.pressure is not None:
+                self.md.set_barostat(self.pressure, self.baro_interval, seeds=[p.get("seed", 0) for p in parts],
+                                     move0=[p.get("steps_done", 0) // self.baro_interval for p in parts],
+                                     dv_max=[self.volume_fraction * p["volume0"] for p in parts])
         self._species = [p["species"] for p in parts]
 
     def step(self) -> float:
@@ -114,7 +124,8 @@ class GpuExecutor:
 
     def states(self) -> List[dict]:
         x, v, _ = self.md.state()
-        return [{"pos": x[s].clone(), "vel": v[s].clone()} for s in self.slices]
+        cells, _, _ = self.md.cells()
+        return [{"pos": x[s].clone(), "vel": v[s].clone(), "cell": cells[k].copy()} for k, s in enumerate(self.slices)]
 
     def upload(self, req: Request) -> dict:
         torch = self.torch
@@ -122,7 +133,8 @@ class GpuExecutor:
                 "vel": torch.tensor(req.vel, dtype=torch.float64, device=self._dev),
                 "species": torch.tensor(req.species, dtype=torch.int32, device=self._dev),
                 "cell": np.asarray(req.cell, dtype=np.float64), "pbc": np.asarray(req.pbc, dtype=np.uint8),
-                "seed": int(req.seed), "steps_done": int(req.steps_done)}
+                "seed": int(req.seed), "steps_done": int(req.steps_done),
+                "volume0": float(abs(np.linalg.det(np.asarray(req.cell, dtype=np.float64))))}
 
     def close(self):
         if self.md is not None:
@@ -199,6 +211,7 @@ class Server:
                     if r.steps_done >= r.n_steps:
                         r.final_pos = st["pos"].cpu().numpy()
                         r.final_vel = st["vel"].cpu().numpy()
+                        r.final_cell = np.asarray(st.get("cell", r.cell))
                         r.finished_at = now
                         self.done.append(r)
                     else:

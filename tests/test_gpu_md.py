@@ -182,3 +182,46 @@ def test_langevin_equilibrates_to_target_temperature():
     t_mean = float(np.mean(temps))
     say(f"Langevin NVT: mean T {t_mean:.1f} K (target {T} K)")
     assert abs(t_mean / T - 1.0) < 0.05
+
+
+def test_npt_trajectory_matches_oracle():
+    # Langevin + Monte Carlo barostat: positions, velocities, cells and the
+    # accept/reject decisions of 3 proposals per structure agree with the oracle
+    import torch
+    import paper_2605_22698_amd as e3
+    cfg = synth.ModelConfig(lmax=2, channels=32, layers=2, n_species=4, cutoff=5.0, avg_neighbors=10.0)
+    b = _two_structures()
+    vel = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(63))
+    m = model(cfg, 7)
+    T, gamma, dt, n, P, interval, frac = 300.0, 0.05, 0.5, 12, 1000.0, 4, 0.01
+    # the two structures are on different proposal schedules (step counts 3 and 10)
+    seeds, step0, bseeds, move0 = [7, 9], [3, 10], [21, 22], [0, 5]
+    say("npt parity")
+    d = device()
+    md = e3.MD(m, b.offsets, torch.tensor(b.pos, dtype=torch.float64, device=d),
+               torch.tensor(vel, dtype=torch.float64, device=d), torch.tensor(b.species, dtype=torch.int32, device=d),
+               synth.SPECIES_MASS[:cfg.n_species], b.cell, b.pbc, cfg.cutoff, 1.0, 20)
+    md.set_langevin(T, gamma, seeds, step0)
+    md.set_barostat(P, interval, frac, bseeds, move0)
+    E = torch.empty(b.n_structures, dtype=torch.float64, device=d)
+    md.step(n, dt, E)
+    x, v, _ = md.state()
+    torch.cuda.synchronize()
+    x, v, E = x.cpu().numpy(), v.cpu().numpy(), E.cpu().numpy()
+    cells, proposed, accepted = md.cells()
+    om_m = om.Model(cfg, synth.model_weights(cfg, 7))
+
+    def force(xx, boxes):
+        cell = np.array([np.diag(bb) for bb in boxes])
+        Es, F, _ = om.energy_forces(om_m, synth.Batch(xx, b.species, cell, b.pbc, b.offsets))
+        return Es, F
+    boxes0 = np.array([np.diag(c) for c in b.cell])
+    xr, vr, boxes, Er, dec = omd.langevin_npt(force, b.pos, vel, boxes0, synth.SPECIES_MASS[b.species], dt, n, T,
+                                              gamma, b.offsets, seeds, step0, P, interval, frac, bseeds, move0)
+    dec = np.array([a for _, a in dec])
+    assert proposed == dec.size and accepted == int(dec.sum())
+    assert 0 < accepted < proposed  # both outcomes exercised
+    assert np.abs(np.array([np.diag(c) for c in cells]) - boxes).max() < 1e-12
+    assert np.abs(x - xr).max() < 1e-9  # positions are unwrapped on both sides
+    assert np.abs(v - vr).max() < 1e-9
+    assert np.all(np.abs(E - Er[-1]) <= 1e-5 * np.abs(Er[-1]))

@@ -33,10 +33,10 @@ def _requests(n):
     return out
 
 
-def _serve(m, reqs, budget, max_active=64, friction=0.0):
+def _serve(m, reqs, budget, max_active=64, friction=0.0, pressure=None):
     clock = StepClock()
     ex = GpuExecutor(m, synth.SPECIES_MASS[:4], 5.0, skin=1.0, rebuild_every=7, temperature_K=300.0,
-                     friction_per_fs=friction)
+                     friction_per_fs=friction, pressure_bar=pressure, barostat_interval=3, volume_fraction=0.01)
     step = ex.step
 
     def timed_step():
@@ -92,3 +92,25 @@ def test_langevin_requests_alone_equal_in_mix():
         a = alone.done[0]
         assert np.array_equal(a.final_pos, mixed[r.rid].final_pos), r.rid
         assert np.array_equal(a.final_vel, mixed[r.rid].final_vel), r.rid
+
+
+def test_npt_requests_alone_equal_in_mix():
+    # NPT requests: own seeds, own proposal schedule, volume step fixed from
+    # their initial volume; cells change and continue across repacks
+    m = model(synth.serving_model(), 4)
+    reqs = _requests(5)
+    for k, r in enumerate(reqs):
+        r.seed = 2000 + k
+    srv, stats = _serve(m, reqs, budget=1 << 40, friction=0.05, pressure=1000.0)
+    assert stats.repacks >= 3
+    mixed = {r.rid: r for r in srv.done}
+    moved = 0
+    for k, r in enumerate(_requests(5)):
+        alone, _ = _serve(m, [Request(r.rid, 0.0, r.pos, r.vel, r.species, r.cell, r.pbc, r.n_steps, seed=2000 + k)],
+                          1 << 40, friction=0.05, pressure=1000.0)
+        a = alone.done[0]
+        assert np.array_equal(a.final_pos, mixed[r.rid].final_pos), r.rid
+        assert np.array_equal(a.final_vel, mixed[r.rid].final_vel), r.rid
+        assert np.array_equal(a.final_cell, mixed[r.rid].final_cell), r.rid
+        moved += int(not np.array_equal(a.final_cell, r.cell))
+    assert moved > 0  # some volume moves were accepted
