@@ -257,7 +257,7 @@ def main():
 
     md.close()
 
-    # ---- side measurements: BF16 mode and continuous-batching serving ----
+    # ---- side measurements: BF16 mode, NPT, continuous-batching serving ----
     extras = {}
     if not args.no_extras:
         m16 = e3.Model(cfg.to_json(), w, precision=e3.BF16_MIX, device=dev)
@@ -271,6 +271,22 @@ def main():
         t16 = time.perf_counter() - t1
         extras["bf16"] = {"value": b.n_atoms * k16 / t16, "ms_per_step": 1e3 * t16 / k16, "steps": k16}
         md16.close()
+        # NPT: Langevin (300 K, 0.01/fs) with a Monte Carlo volume move every 25 steps at 1 bar
+        mdp = e3.MD(m, b.offsets, pos_d, vel_d, sp_d, masses, b.cell, b.pbc, cfg.cutoff, skin, rebuild_every)
+        mdp.set_langevin(300.0, 0.01, [2026])
+        mdp.set_barostat(1.0, 25, 0.002, [2027])
+        mdp.step(args.warmup, dt, energy)
+        torch.cuda.synchronize()
+        kp = max(100, args.steps)
+        t1 = time.perf_counter()
+        mdp.step(kp, dt, energy)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t1
+        _, prop, acc = mdp.cells()
+        extras["npt"] = {"value": b.n_atoms * kp / tp, "ms_per_step": 1e3 * tp / kp, "steps": kp,
+                         "barostat": "Langevin 300 K, friction 0.01/fs, volume move every 25 steps at 1 bar",
+                         "proposals": prop, "accepted": acc}
+        mdp.close()
         extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, log)
 
     # ---- oracle on the host cores (bounded sample) ----
