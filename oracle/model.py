@@ -22,6 +22,18 @@ Appendix F hyperparameter tables:
   forces       F = -dE/dr (§5.2: the Hessian is minus the position
                    derivative of the forces, i.e. forces are -dE/dr)
 
+Electrostatics (§5.1, when the config enables `coulomb`; open structures):
+  charges      q_i = w_q . h_i[0] + b_q[z_i]  (a linear charge head on the
+                   final scalar features; reading)
+  correction   q~_i = q_i - (sum_{j in s} q_j - Q_s) / N_s  (the paper's
+                   charge-correction equation, Q_s the total charge)
+  E_LR         = 1/2 sum_{i != j in s} k_e q~_i q~_j / chi(r_ij),
+                   1/chi(r) = phi(r/r0) / sqrt(r^2 + 1) + (1 - phi(r/r0)) / r,
+                   phi(x) = 1 - 6x^5 + 15x^4 - 10x^3 for x < 1, else 0
+               (the PhysNet soft-core form the paper cites; chi(r) = r beyond
+               the soft-core radius r0; each atom carries half of each pair
+               term in its E_i), k_e = 14.399645 eV A / e^2.
+
 nu is a fixed constant of the model (the nominal neighbour count). Every
 layer outputs all orders l <= l_max. Computation is FP64 throughout.
 
@@ -37,6 +49,52 @@ from torch.utils.checkpoint import checkpoint
 
 from . import basis, cg
 from .sh import real_sh, sl
+
+K_E = 14.399645478425668  # e^2 / (4 pi eps0) in eV angstrom
+
+
+def soft_core_switch(x: torch.Tensor) -> torch.Tensor:
+    """phi(x) = 1 - 6x^5 + 15x^4 - 10x^3 for 0 <= x < 1, 0 beyond."""
+    p = 1.0 - 6.0 * x ** 5 + 15.0 * x ** 4 - 10.0 * x ** 3
+    return torch.where(x < 1.0, p, torch.zeros_like(x))
+
+
+def inv_chi(r: torch.Tensor, r0: float) -> torch.Tensor:
+    """1 / chi(r): the soft-core Coulomb kernel."""
+    phi = soft_core_switch(r / r0)
+    return phi / torch.sqrt(r * r + 1.0) + (1.0 - phi) / r
+
+
+def coulomb_atom_energies(pos: torch.Tensor, q: torch.Tensor, offsets: np.ndarray, r0: float) -> torch.Tensor:
+    """1/2 sum_{j != i, same structure} k_e q_i q_j / chi(r_ij) for every atom i
+    (all pairs of each structure, no cutoff)."""
+    out = []
+    for s in range(len(offsets) - 1):
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        x, qs = pos[a:b], q[a:b]
+        n = b - a
+        if n == 0:
+            continue
+        d = x[None, :, :] - x[:, None, :]
+        off = ~torch.eye(n, dtype=torch.bool)
+        r = torch.sqrt((d * d).sum(-1)[off])
+        pair = K_E * (qs[:, None] * qs[None, :])[off] * inv_chi(r, r0)
+        e = torch.zeros(n * n, dtype=pos.dtype).masked_scatter(off.reshape(-1), pair).reshape(n, n)
+        out.append(0.5 * e.sum(1))
+    return torch.cat(out) if out else torch.zeros(0, dtype=pos.dtype)
+
+
+def charges(model, h0: torch.Tensor, species: torch.Tensor, offsets: np.ndarray,
+            total_charge: np.ndarray) -> torch.Tensor:
+    """Corrected partial charges q~ from the final scalar features h0 [N, C]."""
+    w = model.w
+    q = h0 @ w["qhead"] + w["qbias"][species]
+    owner = torch.from_numpy(np.repeat(np.arange(len(offsets) - 1), np.diff(offsets)))
+    S = len(offsets) - 1
+    tot = torch.zeros(S, dtype=q.dtype).index_add(0, owner, q)
+    n = torch.from_numpy(np.diff(offsets).astype(np.float64))
+    shift = (tot - torch.from_numpy(np.asarray(total_charge, dtype=np.float64))) / torch.clamp(n, min=1.0)
+    return q - shift[owner]
 
 
 def silu(x):
@@ -79,9 +137,11 @@ class Model:
 
     def node_energies(self, pos: torch.Tensor, species: torch.Tensor, dst: torch.Tensor,
                       src: torch.Tensor, shift_vec: torch.Tensor, edge_chunk: Optional[int] = None,
-                      features: Optional[list] = None) -> torch.Tensor:
+                      features: Optional[list] = None, offsets: Optional[np.ndarray] = None,
+                      total_charge: Optional[np.ndarray] = None) -> torch.Tensor:
         """E_i for every atom. pos [N,3] FP64 (may require grad), shift_vec [E,3]
-        the Cartesian image displacement of each edge."""
+        the Cartesian image displacement of each edge. With the Coulomb term
+        the structure offsets (and total charges, default 0) are needed."""
         cfg, w = self.cfg, self.w
         N, C, L = pos.shape[0], cfg.channels, cfg.lmax
         nc = (L + 1) ** 2
@@ -125,13 +185,31 @@ class Model:
             if features is not None:
                 features.append(h)
         e = silu(h[:, :, 0] @ w["read1"]) @ w["read2"]
-        return e[:, 0] + w["e0"][species]
+        e = e[:, 0] + w["e0"][species]
+        if getattr(cfg, "coulomb", False):
+            if offsets is None:
+                offsets = np.array([0, N])
+            if total_charge is None:
+                total_charge = np.zeros(len(offsets) - 1)
+            q = charges(self, h[:, :, 0], species, offsets, total_charge)
+            e = e + coulomb_atom_energies(pos, q, offsets, cfg.soft_core_r0)
+        return e
 
 
 def structure_energies(e_atom: torch.Tensor, offsets: np.ndarray) -> torch.Tensor:
     """E_s = sum over the atoms of structure s."""
     owner = torch.from_numpy(np.repeat(np.arange(len(offsets) - 1), np.diff(offsets)))
     return torch.zeros(len(offsets) - 1, dtype=e_atom.dtype).index_add(0, owner, e_atom)
+
+
+def _total_charge(batch) -> np.ndarray:
+    c = getattr(batch, "charge", None)
+    return np.zeros(len(batch.offsets) - 1) if c is None else np.asarray(c, dtype=np.float64)
+
+
+def _check_open(model, batch):
+    if getattr(model.cfg, "coulomb", False) and np.any(np.asarray(batch.pbc)):
+        raise ValueError("the Coulomb term is defined for open structures only")
 
 
 def _edges(batch, cutoff):
@@ -147,7 +225,9 @@ def energy_forces(model: Model, batch, edge_chunk: Optional[int] = None, edges=N
     dst, src, shv = edges if edges is not None else _edges(batch, model.cfg.cutoff)
     pos = torch.tensor(batch.pos, dtype=torch.float64, requires_grad=True)
     species = torch.from_numpy(np.asarray(batch.species, dtype=np.int64))
-    e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk, features)
+    _check_open(model, batch)
+    e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk, features, batch.offsets,
+                                 _total_charge(batch))
     E = structure_energies(e_atom, batch.offsets)
     (g,) = torch.autograd.grad(E.sum(), pos)
     return E.detach().numpy(), (-g).numpy(), e_atom.detach().numpy()
@@ -157,8 +237,10 @@ def energy(model: Model, batch, edges=None, edge_chunk: Optional[int] = None) ->
     dst, src, shv = edges if edges is not None else _edges(batch, model.cfg.cutoff)
     pos = torch.tensor(batch.pos, dtype=torch.float64)
     species = torch.from_numpy(np.asarray(batch.species, dtype=np.int64))
+    _check_open(model, batch)
     with torch.no_grad():
-        e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk)
+        e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk, None, batch.offsets,
+                                     _total_charge(batch))
     return structure_energies(e_atom, batch.offsets).numpy()
 
 
@@ -175,7 +257,9 @@ def loss_and_grads(model: Model, batch, e_ref: np.ndarray, f_ref: np.ndarray,
     try:
         pos = torch.tensor(batch.pos, dtype=torch.float64, requires_grad=True)
         species = torch.from_numpy(np.asarray(batch.species, dtype=np.int64))
-        e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk)
+        _check_open(model, batch)
+        e_atom = model.node_energies(pos, species, dst, src, shv, edge_chunk, None, batch.offsets,
+                                     _total_charge(batch))
         E = structure_energies(e_atom, batch.offsets)
         (g,) = torch.autograd.grad(E.sum(), pos, create_graph=True)
         F = -g

@@ -13,7 +13,7 @@ from __future__ import annotations
 import dataclasses
 import json
 import math
-from typing import Dict, List, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -51,6 +51,9 @@ class ModelConfig:
     n_species     number of chemical species
     readout_hidden width of the hidden layer of the energy readout
     avg_neighbors normalisation constant nu of the neighbour sum
+    coulomb       add the charge head and the soft-core Coulomb energy (open
+                  structures only)
+    soft_core_r0  radius below which the Coulomb distance is regularised (angstrom)
     """
     lmax: int
     channels: int
@@ -62,6 +65,8 @@ class ModelConfig:
     envelope_p: int = 6
     radial_hidden: int = 64
     readout_hidden: int = 16
+    coulomb: bool = False
+    soft_core_r0: float = 2.0
 
     def to_json(self) -> str:
         return json.dumps(dataclasses.asdict(self), sort_keys=True)
@@ -112,6 +117,8 @@ def weight_shapes(cfg: ModelConfig) -> List[Tuple[str, Tuple[int, ...], int]]:
       read1               [C, readout_hidden]
       read2               [readout_hidden, 1]
       e0                  [S]             per-species reference energy (zeros)
+      qhead               [C]             charge head (only with coulomb)
+      qbias               [S]             per-species charge offset (only with coulomb)
     """
     C, H = cfg.channels, cfg.radial_hidden
     out: List[Tuple[str, Tuple[int, ...], int]] = [("emb", (cfg.n_species, C), cfg.n_species)]
@@ -127,6 +134,9 @@ def weight_shapes(cfg: ModelConfig) -> List[Tuple[str, Tuple[int, ...], int]]:
     out.append(("read1", (C, cfg.readout_hidden), C))
     out.append(("read2", (cfg.readout_hidden, 1), cfg.readout_hidden))
     out.append(("e0", (cfg.n_species,), 0))
+    if cfg.coulomb:
+        out.append(("qhead", (C,), C))
+        out.append(("qbias", (cfg.n_species,), cfg.n_species))
     return out
 
 
@@ -165,12 +175,17 @@ class Batch:
     cell     [S, 3, 3] FP64  rows are the lattice vectors (orthorhombic here)
     pbc      [S, 3] uint8    periodic flags per axis
     offsets  [S+1]  int64    structure s owns atoms offsets[s]:offsets[s+1]
+    charge   [S]    FP64     total charge of each structure (None: 0)
     """
     pos: np.ndarray
     species: np.ndarray
     cell: np.ndarray
     pbc: np.ndarray
     offsets: np.ndarray
+    charge: Optional[np.ndarray] = None
+
+    def total_charge(self) -> np.ndarray:
+        return np.zeros(self.n_structures) if self.charge is None else np.asarray(self.charge, dtype=np.float64)
 
     @property
     def n_atoms(self) -> int:
@@ -183,7 +198,8 @@ class Batch:
     def structure(self, s: int) -> "Batch":
         a, b = int(self.offsets[s]), int(self.offsets[s + 1])
         return Batch(self.pos[a:b].copy(), self.species[a:b].copy(), self.cell[s:s + 1].copy(),
-                     self.pbc[s:s + 1].copy(), np.array([0, b - a], dtype=np.int64))
+                     self.pbc[s:s + 1].copy(), np.array([0, b - a], dtype=np.int64),
+                     None if self.charge is None else np.asarray(self.charge)[s:s + 1].copy())
 
 
 def concat(batches: Sequence[Batch]) -> Batch:
@@ -192,7 +208,9 @@ def concat(batches: Sequence[Batch]) -> Batch:
                  np.concatenate([b.species for b in batches]).astype(np.int32),
                  np.concatenate([b.cell for b in batches]).astype(np.float64),
                  np.concatenate([b.pbc for b in batches]).astype(np.uint8),
-                 np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64))
+                 np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64),
+                 None if all(b.charge is None for b in batches)
+                 else np.concatenate([b.total_charge() for b in batches]))
 
 
 def uniform_cluster(n: int, box: float, d_min: float, n_species: int,
