@@ -68,11 +68,24 @@ typedef enum e3mi_precision {
 typedef void* (*e3mi_alloc_fn)(size_t bytes, void* ctx);
 typedef void (*e3mi_free_fn)(void* ptr, void* ctx);
 
-/* Model configuration (JSON object, all keys required):
+/* Model configuration (JSON object; all keys required unless marked optional):
  *   lmax (2 or 3), channels (C: 32, 64 or 128), layers (1 <= T <= 8),
  *   n_species, cutoff (r_c, angstrom), avg_neighbors (nu, the constant the
  *   neighbour sum is divided by), n_basis (8), envelope_p, radial_hidden (64),
- *   readout_hidden (16).
+ *   readout_hidden (16);
+ *   coulomb (optional JSON boolean, default false) and, when true,
+ *   soft_core_r0 (r0 > 0, angstrom): Section 5.1 electrostatics. A linear
+ *   charge head on the last layer's scalar features gives q_i = w_q . h_i +
+ *   b_q[z_i]; the charge-correction equation shifts the charges of each
+ *   structure uniformly so that they sum to its total charge Q_s (0 unless
+ *   set by e3mi_graph_set_total_charge); the long-range-interaction equation
+ *   adds 1/2 sum_{i != j in s} k_e q~_i q~_j / chi(r_ij) over ALL pairs of a
+ *   structure (no cutoff), with PhysNet's soft core 1/chi(r) = f(r/r0) /
+ *   sqrt(r^2 + 1) + (1 - f(r/r0)) / r, f(x) = 1 - 6x^5 + 15x^4 - 10x^3 on
+ *   [0, 1) and 0 beyond, k_e = 14.3996 eV A. Each atom's energy carries half
+ *   of each of its pair terms. Open structures only: building a graph with a
+ *   periodic axis for such a model fails with E3MI_EUNSUPPORTED, and so does
+ *   e3mi_param_grad.
  * Readings of the paper behind each key: Appendix F tables (l_max, channels,
  * layers, num_rbf 8, radial net of 2 hidden layers of 64 with swish,
  * polynomial envelope, gate nonlinearity, readout 16x0e -> 0e, cutoff 5 A).
@@ -86,6 +99,7 @@ typedef void (*e3mi_free_fn)(void* ptr, void* ctx);
  *                 mix_l3 [P_{t,l3}*C, C] for l3 = 0..lmax (row q*C + k),
  *                 self_l3 [C, C] for each l3 among the layer's input orders
  *   read1 [C, readout_hidden], read2 [readout_hidden, 1], e0 [n_species]
+ *   with coulomb: qhead [C], qbias [n_species]
  */
 
 /* Number of FP64 weights the configuration expects. */
@@ -179,6 +193,11 @@ int e3mi_model_set_weights(e3mi_model* model, const double* weights_host, size_t
  * this graph. Synchronises `stream`. */
 int e3mi_graph_last_edge_count(const e3mi_graph* graph, int64_t* n_edges, void* stream);
 
+/* Total charge Q_s of every structure (host FP64 [S], elementary charges) for
+ * the charge correction of Section 5.1; used by models with the Coulomb term,
+ * ignored by others. A new graph starts neutral. Synchronous. */
+int e3mi_graph_set_total_charge(e3mi_graph* graph, const double* total_charge);
+
 /* Velocity-Verlet NVE molecular dynamics on a packed batch (Section 1: batched
  * MD; Appendix H: ms per MD step). The state (positions and velocities in
  * FP64, forces, neighbour lists) stays on the device. Inputs as for
@@ -248,6 +267,11 @@ int e3mi_md_set_barostat(e3mi_md* md, double pressure_bar, int interval, double 
  * be NULL). Reflects the last completed e3mi_md_step. */
 int e3mi_md_cells(const e3mi_md* md, double* cells, int64_t* proposed, int64_t* accepted);
 
+/* Total charges (host FP64 [S]) of an MD state's structures, as
+ * e3mi_graph_set_total_charge; the forces of the current positions are
+ * recomputed. Synchronises `stream`. */
+int e3mi_md_set_total_charge(e3mi_md* md, const double* total_charge, void* stream);
+
 /* Copy the current state to caller device buffers (any may be NULL):
  * pos, vel FP64 [N, 3], forces FP32 [N, 3]. Asynchronous on `stream`. */
 int e3mi_md_state(const e3mi_md* md, double* pos, double* vel, float* forces, void* stream);
@@ -269,7 +293,8 @@ size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_
  * gate_fwd, readout, gate_bwd, mix_bwd, tp_bwd_edge, radial_bwd, tp_bwd_node,
  * forces, md_update, graph_build, first_fwd, first_bwd (the species-factorised
  * first layer), last_fwd, last_bwd (the fused last layer), barostat (volume
- * moves, including their rebuilds and energy passes); "name@t" selects
+ * moves, including their rebuilds and energy passes), coulomb (charge
+ * correction, pair sum and its charge adjoint); "name@t" selects
  * interaction layer t.
  * e3mi_profile_query waits for the recorded events and returns the summed
  * milliseconds and the number of timed launches of a stage. */

@@ -159,6 +159,14 @@ class Graph:
         check(lib().e3mi_graph_last_edge_count(self.handle, ctypes.byref(e), _stream(stream)))
         return e.value
 
+    def set_total_charge(self, total_charge):
+        """Total charge of each structure (elementary charges) for the
+        charge correction of the Coulomb term; see e3mi_graph_set_total_charge."""
+        q = np.ascontiguousarray(total_charge, dtype=np.float64)
+        if q.shape != (self.n_structures,):
+            raise ValueError("one total charge per structure")
+        check(lib().e3mi_graph_set_total_charge(self.handle, q.ctypes.data))
+
     def edges(self, stream=None):
         """Skin list as device tensors (row_ptr [N+1], src [E], shift [E,3], rev [E])."""
         import torch
@@ -229,6 +237,13 @@ class MD:
                 raise ValueError("one value per structure")
         check(lib().e3mi_md_set_barostat(self.handle, float(pressure_bar), int(interval), float(volume_fraction),
                                          ptr(dv), ptr(sd), ptr(m0)))
+
+    def set_total_charge(self, total_charge, stream=None):
+        """Total charge of each structure; recomputes the current forces."""
+        q = np.ascontiguousarray(total_charge, dtype=np.float64)
+        if q.shape != (self.n_structures,):
+            raise ValueError("one total charge per structure")
+        check(lib().e3mi_md_set_total_charge(self.handle, q.ctypes.data, _stream(stream)))
 
     def cells(self):
         """(cells [S, 3, 3] host FP64, proposals, accepted) after the last step."""

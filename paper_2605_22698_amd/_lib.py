@@ -53,6 +53,8 @@ SIGNATURES = {
     "e3mi_md_set_langevin": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_double, _p, _p, _p]),
     "e3mi_md_set_barostat": (ctypes.c_int, [_p, ctypes.c_double, ctypes.c_int, ctypes.c_double, _p, _p, _p]),
     "e3mi_md_cells": (ctypes.c_int, [_p, _p, _i64p, _i64p]),
+    "e3mi_graph_set_total_charge": (ctypes.c_int, [_p, _p]),
+    "e3mi_md_set_total_charge": (ctypes.c_int, [_p, _p, _p]),
     "e3mi_md_destroy": (ctypes.c_int, [_p]),
     "e3mi_footprint_bytes": (ctypes.c_size_t, [_p, ctypes.c_int64, ctypes.c_int64]),
     "e3mi_profile_enable": (ctypes.c_int, [_p, ctypes.c_int]),

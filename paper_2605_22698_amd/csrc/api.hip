@@ -34,7 +34,30 @@ struct Config {
   int lmax = 0, channels = 0, layers = 0, n_species = 0, n_basis = 0, envelope_p = 0, radial_hidden = 0,
       readout_hidden = 0;
   double cutoff = 0, avg_neighbors = 0;
+  // Section 5.1 electrostatics: charge head + soft-core Coulomb (open structures)
+  bool coulomb = false;
+  double soft_core_r0 = 0;
 };
+
+size_t json_find(const std::string& s, const char* key) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = s.find(k);
+  if (p == std::string::npos) return p;
+  p = s.find(':', p + k.size());
+  if (p == std::string::npos) throw Error(E3MI_EINVAL, std::string("config: malformed value of ") + key);
+  p = s.find_first_not_of(" \t\r\n", p + 1);
+  if (p == std::string::npos) throw Error(E3MI_EINVAL, std::string("config: malformed value of ") + key);
+  return p;
+}
+
+// An optional JSON boolean (absent: false).
+bool json_bool(const std::string& s, const char* key) {
+  const size_t p = json_find(s, key);
+  if (p == std::string::npos) return false;
+  if (s.compare(p, 4, "true") == 0) return true;
+  if (s.compare(p, 5, "false") == 0) return false;
+  throw Error(E3MI_EINVAL, std::string("config: value of ") + key + " is not true or false");
+}
 
 double json_number(const std::string& s, const char* key) {
   const std::string k = std::string("\"") + key + "\"";
@@ -63,6 +86,11 @@ Config parse_config(const char* json) {
   c.envelope_p = (int)json_number(s, "envelope_p");
   c.radial_hidden = (int)json_number(s, "radial_hidden");
   c.readout_hidden = (int)json_number(s, "readout_hidden");
+  c.coulomb = json_bool(s, "coulomb");
+  if (c.coulomb) {
+    c.soft_core_r0 = json_number(s, "soft_core_r0");
+    E3MI_REQUIRE(c.soft_core_r0 > 0 && std::isfinite(c.soft_core_r0), E3MI_EINVAL, "soft_core_r0 must be positive");
+  }
   E3MI_REQUIRE(c.lmax == 2 || c.lmax == 3, E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
   E3MI_REQUIRE(c.channels == 32 || c.channels == 64 || c.channels == 128, E3MI_EUNSUPPORTED,
                "channels must be 32, 64 or 128");
@@ -125,6 +153,7 @@ size_t weight_count(const Config& c) {
     n += (size_t)(L.l1max + 1) * C * C;  // self connection per input order
   }
   n += C * c.readout_hidden + c.readout_hidden + c.n_species;
+  if (c.coulomb) n += C + c.n_species;  // charge head and per-species charge offset
   return n;
 }
 
@@ -133,13 +162,13 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Timed stages (per layer where it applies: index = stage * 8 + layer).
 enum Stage : int {
   kPrune = 0, kEmbed, kRadialFwd, kTpFwd, kMixFwd, kGateFwd, kReadout, kGateBwd, kMixBwd, kTpBwdEdge,
-  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kLastFwd, kLastBwd, kBarostat,
+  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kLastFwd, kLastBwd, kBarostat, kCoulomb,
   kNumStages
 };
 const char* const kStageNames[kNumStages] = {
     "prune", "embed", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd", "mix_bwd",
     "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build", "first_fwd", "first_bwd",
-    "last_fwd", "last_bwd", "barostat"};
+    "last_fwd", "last_bwd", "barostat", "coulomb"};
 inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
 
 }  // namespace
@@ -158,6 +187,7 @@ struct Workspace {
   std::unique_ptr<DevBuf> dd, Bd, Prb, Prc, w2c, eb, xb, xc, Ab, Ac, hb_a, hb_b, hc_a, hc_b, Rb, Rc, P1g, P2g,
       partial, vf;
   std::unique_ptr<DevBuf> G1, dG1;  // first layer, [N, (l3+1)^2, S*64]
+  std::unique_ptr<DevBuf> q_raw, q, pot, fc;  // electrostatics: charges, potential, forces
 };
 
 }  // namespace e3mi
@@ -168,7 +198,7 @@ struct e3mi_model {
   e3mi::Allocator alloc;
   std::vector<e3mi::LayerPlan> plans;
   std::vector<std::unique_ptr<e3mi::LayerWeights>> lw;
-  std::unique_ptr<e3mi::DevBuf> emb, read1, read2, e0;
+  std::unique_ptr<e3mi::DevBuf> emb, read1, read2, e0, qhead, qbias;
   // first layer factorised by species: U_l [S*64, C] and U_l^T [C, S*64] per output order
   bool first_factorised = true;
   bool last_fused = true;
@@ -187,6 +217,9 @@ struct e3mi_graph {
   std::vector<uint8_t> pbc_h;
   std::unique_ptr<e3mi::DevBuf> off_d, owner, box_d, pbc_d, species, row_ptr, src, shift, rev, keys;
   std::unique_ptr<e3mi::DevBuf> cnt, row_ptr_x, src_x, dvec_x, old_idx, new_idx, rev_x, x_ref;
+  // electrostatics: total charge per structure, and (structure, first atom) per 64-atom tile
+  std::unique_ptr<e3mi::DevBuf> charge, ctiles;
+  int n_ctiles = 0;
 };
 
 struct e3mi_md {
@@ -403,6 +436,19 @@ e3mi_graph* new_graph(e3mi_model* M, int S, const int64_t* off, const double* po
   G->off_d = upload(a, G->off_h.data(), sizeof(int64_t) * (S + 1));
   G->box_d = upload(a, G->box_h.data(), sizeof(double) * 3 * S);
   G->pbc_d = upload(a, G->pbc_h.data(), 3 * S);
+  {
+    const std::vector<double> zero((size_t)S, 0.0);
+    G->charge = upload(a, zero.data(), sizeof(double) * S);
+  }
+  if (M->cfg.coulomb) {
+    for (int s = 0; s < S * 3; ++s)
+      E3MI_REQUIRE(!pbc[s], E3MI_EUNSUPPORTED, "the Coulomb term is defined for open structures only (pbc all 0)");
+    std::vector<int2> tiles;
+    for (int s = 0; s < S; ++s)
+      for (int64_t i0 = off[s]; i0 < off[s + 1]; i0 += 64) tiles.push_back(make_int2(s, (int)i0));
+    G->n_ctiles = (int)tiles.size();
+    G->ctiles = upload(a, tiles.data(), sizeof(int2) * tiles.size());
+  }
   G->owner = std::make_unique<DevBuf>(a);
   G->owner->ensure(sizeof(int) * (G->N + 1));
   G->species = std::make_unique<DevBuf>(a);
@@ -721,11 +767,28 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
   float* A = w.A->as<float>();
   float* dcur = w.dh_a->as<float>();
   float* dother = w.dh_b->as<float>();
+  const bool coulomb = c.coulomb;
+  if (coulomb) {
+    E3MI_REQUIRE(G->ctiles, E3MI_EINVAL, "graph was built for a model without the Coulomb term");
+    for (auto* b : {&w.q_raw, &w.q, &w.pot}) ensure(*b, &M->alloc, sizeof(float) * (size_t)N);
+    ensure(w.fc, &M->alloc, sizeof(float) * 3 * (size_t)N);
+  }
   {
     ProfScope ps(&M->prof, stage_id(kReadout), st);
     launch_readout(w.h[T]->as<float>(), M->plans[T - 1].nc_out, species, M->read1->as<float>(),
-                   M->read2->as<float>(), M->e0->as<float>(), N, C, w.e_atom->as<double>(), dcur, st);
-    launch_energy(w.e_atom->as<double>(), G->off_d->as<int64_t>(), S, energy, st);
+                   M->read2->as<float>(), M->e0->as<float>(), N, C, w.e_atom->as<double>(), dcur, st,
+                   coulomb ? M->qhead->as<float>() : nullptr, coulomb ? M->qbias->as<float>() : nullptr,
+                   coulomb ? w.q_raw->as<float>() : nullptr);
+    if (!coulomb) launch_energy(w.e_atom->as<double>(), G->off_d->as<int64_t>(), S, energy, st);
+  }
+  if (coulomb) {
+    ProfScope ps(&M->prof, stage_id(kCoulomb), st);
+    const int64_t* offd = G->off_d->as<int64_t>();
+    launch_charge_fix(w.q_raw->as<float>(), offd, G->charge->as<double>(), S, w.q->as<float>(), st);
+    launch_coulomb(G->ctiles->as<int2>(), G->n_ctiles, offd, pos, w.q->as<float>(), (float)c.soft_core_r0,
+                   w.e_atom->as<double>(), w.pot->as<float>(), w.fc->as<float>(), st);
+    launch_coulomb_dq(offd, S, w.pot->as<float>(), M->qhead->as<float>(), C, dcur, st);
+    launch_energy(w.e_atom->as<double>(), offd, S, energy, st);
   }
   if (atom_energy)
     E3MI_HIP(hipMemcpyAsync(atom_energy, w.e_atom->p, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
@@ -824,7 +887,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
   }
   {
     ProfScope ps(&M->prof, stage_id(kForces), st);
-    launch_forces(row_ptr, G->rev_x->as<int>(), g, N, forces, st);
+    launch_forces(row_ptr, G->rev_x->as<int>(), g, N, forces, st, coulomb ? w.fc->as<float>() : nullptr);
   }
 }
 
@@ -856,7 +919,7 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
 
 // Offsets of every weight tensor in the flat FP64 vector (file order).
 struct WeightOffsets {
-  size_t emb = 0, read1 = 0, read2 = 0, e0 = 0, total = 0;
+  size_t emb = 0, read1 = 0, read2 = 0, e0 = 0, qhead = 0, qbias = 0, total = 0;
   std::vector<size_t> rad1, rad2, rad3;
   std::vector<std::array<size_t, 4>> mix, self_;
 };
@@ -893,6 +956,12 @@ WeightOffsets weight_offsets(const Config& c) {
   cur += c.readout_hidden;
   o.e0 = cur;
   cur += c.n_species;
+  if (c.coulomb) {
+    o.qhead = cur;
+    cur += C;
+    o.qbias = cur;
+    cur += c.n_species;
+  }
   o.total = cur;
   return o;
 }
@@ -960,6 +1029,10 @@ void upload_weights(e3mi_model* M, const double* wts) {
   M->read1 = upload_f32(a, take((size_t)C * c.readout_hidden));
   M->read2 = upload_f32(a, take((size_t)c.readout_hidden));
   M->e0 = upload_f32(a, take((size_t)c.n_species));
+  if (c.coulomb) {
+    M->qhead = upload_f32(a, take((size_t)C));
+    M->qbias = upload_f32(a, take((size_t)c.n_species));
+  }
   E3MI_REQUIRE(cur == weight_count(c), E3MI_EINVAL, "internal: weight cursor mismatch");
   // U_l = nu^-1 (W3[:, l C + k] W_emb[s, k]) W_mix_l, rows (s, q), in FP64.
   const WeightOffsets off = weight_offsets(c);
@@ -1020,6 +1093,7 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
   const float rc = (float)c.cutoff;
   const int p_env = c.envelope_p;
   Workspace& w = M->ws;
+  E3MI_REQUIRE(!c.coulomb, E3MI_EUNSUPPORTED, "parameter gradients of the Coulomb term are not implemented");
   const WeightOffsets off = weight_offsets(c);
   E3MI_HIP(hipMemsetAsync(out, 0, sizeof(double) * off.total, st));
   if (N == 0) return;
@@ -1670,6 +1744,27 @@ int e3mi_md_cells(const e3mi_md* md, double* cells, int64_t* proposed, int64_t* 
   if (cells) std::memcpy(cells, md->cell_h.data(), sizeof(double) * 9 * md->S);
   if (proposed) *proposed = md->baro_proposed;
   if (accepted) *accepted = md->baro_accepted;
+  E3MI_API_END
+}
+
+int e3mi_graph_set_total_charge(e3mi_graph* graph, const double* total_charge) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(graph && total_charge, E3MI_EINVAL, "null argument");
+  for (int s = 0; s < graph->S; ++s)
+    E3MI_REQUIRE(std::isfinite(total_charge[s]), E3MI_EINVAL, "total charges must be finite");
+  E3MI_HIP(hipMemcpy(graph->charge->p, total_charge, sizeof(double) * graph->S, hipMemcpyHostToDevice));
+  E3MI_API_END
+}
+
+int e3mi_md_set_total_charge(e3mi_md* md, const double* total_charge, void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(md, E3MI_EINVAL, "null md");
+  const int rc = e3mi_graph_set_total_charge(md->graph, total_charge);
+  if (rc != E3MI_OK) return rc;
+  hipStream_t st = e3mi::as_stream(stream);
+  e3mi::energy_forces(md->model, md->graph, md->x->as<double>(), md->energy->as<double>(), md->F->as<float>(),
+                      nullptr, st);
+  E3MI_HIP(hipStreamSynchronize(st));
   E3MI_API_END
 }
 

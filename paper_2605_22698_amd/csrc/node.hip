@@ -156,7 +156,9 @@ __global__ void k_embed(const int* __restrict__ species, const float* __restrict
 __global__ void __launch_bounds__(256) k_readout(const float* __restrict__ h, int nc, const int* __restrict__ species,
                                                  const float* __restrict__ Wr, const float* __restrict__ w2,
                                                  const float* __restrict__ e0, int N, int C,
-                                                 double* __restrict__ e_atom, float* __restrict__ dh) {
+                                                 double* __restrict__ e_atom, float* __restrict__ dh,
+                                                 const float* __restrict__ wq, const float* __restrict__ bq,
+                                                 float* __restrict__ q_raw) {
   const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= N) return;
@@ -164,10 +166,16 @@ __global__ void __launch_bounds__(256) k_readout(const float* __restrict__ h, in
   float pre[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) pre[q] = 0.0f;
+  float qa = 0.0f;
   for (int k = lane; k < C; k += 64) {
     const float x = hi[k];
 #pragma unroll
     for (int q = 0; q < 16; ++q) pre[q] += x * Wr[k * 16 + q];
+    if (wq) qa += x * wq[k];
+  }
+  if (wq) {
+    qa = wave_sum(qa);
+    if (lane == 0) q_raw[i] = qa + bq[species[i]];
   }
   float e = 0.0f;
 #pragma unroll
@@ -206,7 +214,8 @@ __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ e_ato
 // One wave per atom: the lanes take the row's edges in turn, then a fixed
 // reduction tree over the wave (bitwise repeatable).
 __global__ void __launch_bounds__(256) k_forces(const int* __restrict__ row_ptr, const int* __restrict__ rev,
-                                                const float4* __restrict__ g, int N, float* __restrict__ F) {
+                                                const float4* __restrict__ g, int N, const float* __restrict__ extra,
+                                                float* __restrict__ F) {
   const int i = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= N) return;
@@ -223,6 +232,11 @@ __global__ void __launch_bounds__(256) k_forces(const int* __restrict__ row_ptr,
   fx = wave_sum(fx);
   fy = wave_sum(fy);
   fz = wave_sum(fz);
+  if (extra) {
+    fx += extra[3 * i];
+    fy += extra[3 * i + 1];
+    fz += extra[3 * i + 2];
+  }
   if (lane == 0) {
     F[3 * i] = fx;
     F[3 * i + 1] = fy;
@@ -257,16 +271,18 @@ void launch_embed(const int* species, const float* emb, float* h0, int N, int C,
   k_embed<<<blocks((long)N * C, 256), 256, 0, st>>>(species, emb, h0, N, C);
 }
 void launch_readout(const float* h, int nc, const int* species, const float* Wr, const float* w2, const float* e0,
-                    int N, int C, double* e_atom, float* dh, hipStream_t st) {
+                    int N, int C, double* e_atom, float* dh, hipStream_t st, const float* wq, const float* bq,
+                    float* q_raw) {
   if (N == 0) return;
-  k_readout<<<blocks((long)N * 64, 256), 256, 0, st>>>(h, nc, species, Wr, w2, e0, N, C, e_atom, dh);
+  k_readout<<<blocks((long)N * 64, 256), 256, 0, st>>>(h, nc, species, Wr, w2, e0, N, C, e_atom, dh, wq, bq, q_raw);
 }
 void launch_energy(const double* e_atom, const int64_t* off, int S, double* energy, hipStream_t st) {
   k_energy<<<S, 256, 0, st>>>(e_atom, off, energy);
 }
-void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st) {
+void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st,
+                   const float* extra) {
   if (N == 0) return;
-  k_forces<<<blocks((long)N * 64, 256), 256, 0, st>>>(row_ptr, rev, g, N, F);
+  k_forces<<<blocks((long)N * 64, 256), 256, 0, st>>>(row_ptr, rev, g, N, extra, F);
 }
 
 }  // namespace e3mi

@@ -250,9 +250,22 @@ void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_
 void launch_gate_bwd(const float* ht, const float* dh, float* dht, int N, int nc, int C, hipStream_t st);
 void launch_embed(const int* species, const float* emb, float* h0, int N, int C, hipStream_t st);
 void launch_readout(const float* h, int nc, const int* species, const float* Wr, const float* w2, const float* e0,
-                    int N, int C, double* e_atom, float* dh, hipStream_t st);
+                    int N, int C, double* e_atom, float* dh, hipStream_t st, const float* wq = nullptr,
+                    const float* bq = nullptr, float* q_raw = nullptr);
 void launch_energy(const double* e_atom, const int64_t* off, int S, double* energy, hipStream_t st);
-void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st);
+void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st,
+                   const float* extra = nullptr);
+
+// ---- electrostatics of open structures (coulomb.hip) ---------------------------------
+// q~ = q - (sum_s q - Q_s) / N_s per structure
+void launch_charge_fix(const float* q_raw, const int64_t* off, const double* Q, int S, float* q, hipStream_t st);
+// soft-core Coulomb over all pairs of each structure: e_atom += 1/2 k q~_i phi_i,
+// pot = k phi, fc = Coulomb forces [N, 3]; tiles = (structure, first receiver) per 64 receivers
+void launch_coulomb(const int2* tiles, int n_tiles, const int64_t* off, const double* pos, const float* q, float r0,
+                    double* e_atom, float* pot, float* fc, hipStream_t st);
+// dh[i, k] += (pot_i - mean_s pot) wq[k]
+void launch_coulomb_dq(const int64_t* off, int S, const float* pot, const float* wq, int C, float* dh,
+                       hipStream_t st);
 
 // ---- radial MLP (radial.hip) ---------------------------------------------------------
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,

@@ -135,8 +135,9 @@ def weight_shapes(cfg: ModelConfig) -> List[Tuple[str, Tuple[int, ...], int]]:
     out.append(("read2", (cfg.readout_hidden, 1), cfg.readout_hidden))
     out.append(("e0", (cfg.n_species,), 0))
     if cfg.coulomb:
-        out.append(("qhead", (C,), C))
-        out.append(("qbias", (cfg.n_species,), cfg.n_species))
+        # fan-in scaled by 10: partial charges of a few tenths of e
+        out.append(("qhead", (C,), 10 * C))
+        out.append(("qbias", (cfg.n_species,), 10 * cfg.n_species))
     return out
 
 
@@ -330,6 +331,28 @@ def serving_requests(n_requests: int, rate_per_s: float, lo: int = 50, hi: int =
         v = maxwell_boltzmann(b, 300.0, rr)
         out.append((t, b, v))
     return out
+
+
+def open_box(n: int, n_species: int, rng: np.random.Generator) -> Batch:
+    """A liquid-density (0.1 atoms/A^3) jittered lattice with every axis open:
+    a compact cluster cut from the liquid."""
+    b = jittered_lattice(n, DENSITY, 0.3, n_species, rng)
+    b.pbc[:] = 0
+    return b
+
+
+def electrostatics_config(n_structures: int = 64, lo: int = 20, hi: int = 200, seed_key: int = 6
+                          ) -> Tuple[ModelConfig, Batch]:
+    """Batch of open clusters at 0.1 atoms/A^3, atom counts uniform in
+    [lo, hi], 4 species, total charges uniform in {-1, 0, +1}; l_max 3, 128
+    channels, 2 layers, r_c 5 A, Coulomb term with a 2 A soft core."""
+    rng = seed_for(seed_key)
+    sizes = rng.integers(lo, hi + 1, size=n_structures)
+    batch = concat([open_box(int(n), 4, rng) for n in sizes])
+    batch.charge = rng.integers(-1, 2, size=n_structures).astype(np.float64)
+    cfg = ModelConfig(lmax=3, channels=128, layers=2, n_species=4, cutoff=5.0,
+                      avg_neighbors=nominal_neighbors(DENSITY, 5.0), coulomb=True, soft_core_r0=2.0)
+    return cfg, batch
 
 
 def scale_config(n: int = 100000) -> Tuple[ModelConfig, Batch]:

@@ -1,0 +1,164 @@
+"""GPU charge head, charge correction and soft-core Coulomb term (§5.1) vs the
+FP64 oracle: energies <= 1e-5 relative, forces <= 1e-4 eV/A max-abs (and
+<= 1e-3 of the largest force)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import model as om
+from tests.gpu_util import check_energy, check_forces, device, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_model(cfg, w):
+    import paper_2605_22698_amd as e3
+    return e3.Model(cfg.to_json(), synth.flatten_weights(cfg, w), device=device())
+
+
+def _gpu(m, b, skin=0.0):
+    import torch
+    d = device()
+    pos = torch.tensor(b.pos, dtype=torch.float64, device=d)
+    sp = torch.tensor(b.species, dtype=torch.int32, device=d)
+    cfg = synth.ModelConfig.from_json(m.config_json)
+    g = m.build_graph(b.offsets, pos, sp, b.cell, b.pbc, cfg.cutoff, skin)
+    g.set_total_charge(b.total_charge())
+    E, F, Ei = m.energy_forces(g, pos, atom_energy=True)
+    torch.cuda.synchronize()
+    return E.cpu().numpy(), F.cpu().numpy().astype(np.float64), Ei.cpu().numpy()
+
+
+def _cfg(lmax=2, C=32, r0=2.0, n_species=3):
+    return synth.ModelConfig(lmax=lmax, channels=C, layers=2, n_species=n_species, cutoff=5.0,
+                             avg_neighbors=synth.nominal_neighbors(0.1, 5.0), coulomb=True, soft_core_r0=r0)
+
+
+def test_tiny_cluster_with_coulomb():
+    _, b = synth.tiny_config()
+    cfg = _cfg()
+    w = synth.model_weights(cfg, 61)
+    b.charge = np.array([1.0])
+    say("coulomb tiny cluster")
+    E, F, Ei = _gpu(_gpu_model(cfg, w), b)
+    Er, Fr, Eir = om.energy_forces(om.Model(cfg, w), b)
+    e = check_energy(E, Er, Eir)
+    f = check_forces(F, Fr)
+    np.testing.assert_allclose(Ei, Eir, atol=1e-6 * np.abs(Eir).max())
+    say(f"  energy rel err {e:.2e}; force err {f[0]:.2e} eV/A ({f[1]:.2e} of max)")
+
+
+def test_packed_clusters_span_tiles_and_ragged_tails():
+    # sizes straddle the 64-receiver tile (63, 64, 65, 130) and include a
+    # one-atom structure (no pairs: its charge is its total charge)
+    rng = np.random.default_rng(62)
+    sizes = [63, 1, 64, 130, 65, 7]
+    b = synth.concat([synth.open_box(n, 4, rng) for n in sizes])
+    b.charge = np.array([0.0, 1.0, -1.0, 2.0, 0.5, 0.0])
+    cfg = _cfg(lmax=3, C=64, n_species=4)
+    w = synth.model_weights(cfg, 63)
+    say(f"coulomb packed N={b.n_atoms}")
+    E, F, Ei = _gpu(_gpu_model(cfg, w), b, skin=0.5)
+    Er, Fr, Eir = om.energy_forces(om.Model(cfg, w), b)
+    for s in range(b.n_structures):
+        a, z = b.offsets[s], b.offsets[s + 1]
+        check_energy(E[s:s + 1], Er[s:s + 1], Eir[a:z])
+    f = check_forces(F, Fr)
+    say(f"  force err {f[0]:.2e} eV/A ({f[1]:.2e} of max)")
+
+
+def test_alone_equals_packed_bitwise():
+    rng = np.random.default_rng(64)
+    parts = [synth.open_box(n, 4, rng) for n in (40, 90, 17)]
+    for p, q in zip(parts, (1.0, 0.0, -1.0)):
+        p.charge = np.array([q])
+    b = synth.concat(parts)
+    cfg = _cfg(lmax=3, C=64, n_species=4)
+    m = _gpu_model(cfg, synth.model_weights(cfg, 65))
+    E, F, _ = _gpu(m, b)
+    for s, p in enumerate(parts):
+        Es, Fs, _ = _gpu(m, p)
+        a, z = b.offsets[s], b.offsets[s + 1]
+        assert Es[0] == E[s]
+        assert np.array_equal(Fs, F[a:z])
+
+
+def test_large_cluster_coulomb_part_against_oracle_pair_sum():
+    # With a zero feature head the charges are the corrected species offsets,
+    # and the Coulomb part of (E, F) is the GPU result with the term on minus
+    # the same model with it off: the short-range kernels see identical inputs.
+    import torch
+    rng = np.random.default_rng(66)
+    b = synth.open_box(2000, 4, rng)
+    b.charge = np.array([-1.0])
+    cfg = _cfg(lmax=3, C=64, n_species=4)
+    w = synth.model_weights(cfg, 67)
+    w["qhead"] = np.zeros_like(w["qhead"])
+    w["qbias"] = np.array([0.35, -0.4, 0.2, -0.1])
+    cfg0 = synth.ModelConfig(**{**cfg.__dict__, "coulomb": False})
+    w0 = {k: v for k, v in w.items() if k not in ("qhead", "qbias")}
+    say("coulomb 2000-atom cluster")
+    E1, F1, _ = _gpu(_gpu_model(cfg, w), b, skin=1.0)
+    E0, F0, _ = _gpu(_gpu_model(cfg0, w0), b, skin=1.0)
+    q = w["qbias"][b.species]
+    q = torch.from_numpy(q - (q.sum() - b.charge[0]) / b.n_atoms)
+    x = torch.tensor(b.pos, dtype=torch.float64, requires_grad=True)
+    Ec = om.coulomb_atom_energies(x, q, b.offsets, cfg.soft_core_r0).sum()
+    (gx,) = torch.autograd.grad(Ec, x)
+    Ec, Fc = float(Ec.detach()), -gx.numpy()
+    assert abs((E1[0] - E0[0]) - Ec) <= 1e-5 * abs(Ec), (E1[0] - E0[0], Ec)
+    err = np.abs((F1 - F0) - Fc).max()
+    assert err <= 1e-4 and err <= 1e-3 * np.abs(Fc).max(), (err, np.abs(Fc).max())
+    say(f"  E_LR {Ec:.6f} eV, force err {err:.2e} eV/A")
+
+
+def test_md_with_total_charge_matches_oracle():
+    import torch
+    import paper_2605_22698_amd as e3
+    from oracle import md as omd
+    d = device()
+    rng = np.random.default_rng(68)
+    parts = [synth.open_box(n, 3, rng) for n in (30, 45)]
+    b = synth.concat(parts)
+    b.charge = np.array([1.0, -1.0])
+    cfg = _cfg()
+    w = synth.model_weights(cfg, 69)
+    m = _gpu_model(cfg, w)
+    vel = synth.maxwell_boltzmann(b, 300.0, np.random.default_rng(70))
+    md = e3.MD(m, b.offsets, torch.tensor(b.pos, dtype=torch.float64, device=d),
+               torch.tensor(vel, dtype=torch.float64, device=d), torch.tensor(b.species, dtype=torch.int32, device=d),
+               synth.SPECIES_MASS[:3], b.cell, b.pbc, cfg.cutoff, 1.0, 5)
+    md.set_total_charge(b.charge)
+    E = torch.empty(2, dtype=torch.float64, device=d)
+    md.step(10, 0.5, E)
+    x, v, _ = md.state()
+    torch.cuda.synchronize()
+    om_m = om.Model(cfg, w)
+
+    def force(xx):
+        Es, F, _ = om.energy_forces(om_m, synth.Batch(xx, b.species, b.cell, b.pbc, b.offsets, b.charge))
+        return Es, F
+    xr, vr, Er = omd.velocity_verlet(force, b.pos, vel, synth.SPECIES_MASS[b.species], 0.5, 10)
+    assert np.abs(x.cpu().numpy() - xr).max() < 1e-8
+    assert np.abs(v.cpu().numpy() - vr).max() < 1e-8
+    np.testing.assert_allclose(E.cpu().numpy(), Er[-1], rtol=1e-5)
+
+
+def test_periodic_graph_and_parameter_gradient_are_rejected():
+    import torch
+    import paper_2605_22698_amd as e3
+    cfg = _cfg()
+    m = _gpu_model(cfg, synth.model_weights(cfg, 71))
+    b = synth.jittered_lattice(40, 0.1, 0.3, 3, np.random.default_rng(72))
+    pos = torch.tensor(b.pos, dtype=torch.float64, device=device())
+    sp = torch.tensor(b.species, dtype=torch.int32, device=device())
+    with pytest.raises(e3.E3miError):
+        m.build_graph(b.offsets, pos, sp, b.cell, b.pbc, cfg.cutoff, 0.0)
+    bo = synth.open_box(20, 3, np.random.default_rng(73))
+    pos = torch.tensor(bo.pos, dtype=torch.float64, device=device())
+    sp = torch.tensor(bo.species, dtype=torch.int32, device=device())
+    g = m.build_graph(bo.offsets, pos, sp, bo.cell, bo.pbc, cfg.cutoff, 0.0)
+    gE = torch.ones(1, dtype=torch.float64, device=device())
+    gF = torch.zeros((20, 3), dtype=torch.float32, device=device())
+    with pytest.raises(e3.E3miError):
+        m.param_grad(g, pos, gE, gF)
