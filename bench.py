@@ -96,17 +96,18 @@ def work_model(cfg, t, E, N):
     return out
 
 
-def measured_traffic(stage):
-    """HBM bytes per launch of the stage's kernel (FETCH_SIZE + WRITE_SIZE,
-    copy-calibrated) from the committed counter summary, or None when the
-    kernel's source file has changed since the counters were taken."""
+def measured_traffic(kernel, summary="md_step_3000_hbm_traffic.md"):
+    """HBM bytes per launch of a kernel (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated) from a committed counter summary, or None when the
+    kernel's source file has changed since the counters were taken. kernel:
+    the name as listed, with its template arguments or without (any)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "md_step_3000_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     for line in open(path):
-        m = re.match(r"\|\s*`(k_[a-z_]+)(?:<[^`]*>)?`\s*\|\s*\d+\s*\|\s*([\d.]+)\s*\|\s*([\d.]+)\s*\|\s*(\S+)\s*\|\s*(\S+)", line)
-        if not m or m.group(1) != "k_" + stage:
+        m = re.match(r"\|\s*`([^`]+)`\s*\|\s*\d+\s*\|\s*([\d.]+)\s*\|\s*([\d.]+)\s*\|\s*(\S+)\s*\|\s*(\S+)", line)
+        if not m or kernel not in (m.group(1), m.group(1).split("<")[0]):
             continue
         src = os.path.join(ROOT, "paper_2605_22698_amd", "csrc", m.group(4))
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != m.group(5):
@@ -150,6 +151,73 @@ def serving_run(e3, synth, torch, dev, n_requests, log):
             "repacks": summ["repacks"], "p50_queue_wait_s": float(np.percentile(waits, 50)) if waits else 0.0}
 
 
+COULOMB_FLOPS_PER_PAIR = 20  # distance 8, rsqrt 1, potential 2, force factor 3, force 6
+
+
+def coulomb_run(e3, synth, torch, dev, steps, warmup, log):
+    """Electrostatics (charge head + soft-core Coulomb over all pairs of each
+    open structure): MD atom-steps/s of a batch of charged open clusters with
+    and without the term, and the pair kernel against the FP32 vector peak on
+    one large cluster."""
+    cfg, b = synth.electrostatics_config()
+    wd = synth.model_weights(cfg, 8)
+    cfg0 = synth.ModelConfig(**{**cfg.__dict__, "coulomb": False})
+    out = {"workload": f"{b.n_structures} open clusters, {b.n_atoms} atoms (20-200 each), 0.1 atoms/A^3, "
+                       f"total charges in {{-1, 0, 1}}, l_max 3, 128 channels, 2 layers, r_c 5 A, r0 2 A"}
+    vel = synth.maxwell_boltzmann(b, 300.0, synth.seed_for(6, 9))
+    pos_d = torch.tensor(b.pos, dtype=torch.float64, device=dev)
+    vel_d = torch.tensor(vel, dtype=torch.float64, device=dev)
+    sp_d = torch.tensor(b.species, dtype=torch.int32, device=dev)
+    energy = torch.empty(b.n_structures, dtype=torch.float64, device=dev)
+    for key, c, w in (("with", cfg, wd), ("without", cfg0, {k: v for k, v in wd.items() if k not in ("qhead", "qbias")})):
+        m = e3.Model(c.to_json(), synth.flatten_weights(c, w), device=dev)
+        md = e3.MD(m, b.offsets, pos_d, vel_d, sp_d, synth.SPECIES_MASS[:4], b.cell, b.pbc, c.cutoff, 1.0, 20)
+        if c.coulomb:
+            md.set_total_charge(b.charge)
+        md.step(warmup, 0.5, energy)
+        torch.cuda.synchronize()
+        m.profile(True)
+        t1 = time.perf_counter()
+        md.step(steps, 0.5, energy)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        m.profile(False)
+        out[f"value_{key}"] = b.n_atoms * steps / dt
+        out[f"ms_per_step_{key}"] = 1e3 * dt / steps
+        if c.coulomb:
+            tot, n = m.stage_time("coulomb")
+            out["coulomb_kernel_ms_per_step"] = tot / steps
+        md.close()
+        log(f"coulomb batch ({key} the term): {out[f'value_{key}']:.3e} atom-steps/s")
+    out["steps"] = steps
+    # pair kernel on one large open cluster
+    n_big = 20000
+    bb = synth.open_box(n_big, 4, synth.seed_for(6, 11))
+    m = e3.Model(cfg.to_json(), synth.flatten_weights(cfg, wd), device=dev)
+    pb = torch.tensor(bb.pos, dtype=torch.float64, device=dev)
+    g = m.build_graph(bb.offsets, pb, torch.tensor(bb.species, dtype=torch.int32, device=dev), bb.cell, bb.pbc,
+                      cfg.cutoff, 0.0)
+    g.set_total_charge([0.0])
+    m.energy_forces(g, pb)
+    torch.cuda.synchronize()
+    m.profile(True)
+    for _ in range(5):
+        m.energy_forces(g, pb)
+    torch.cuda.synchronize()
+    m.profile(False)
+    tot, n = m.stage_time("coulomb")
+    avg_s = tot / n / 1e3
+    flops = float(n_big) * (n_big - 1) * COULOMB_FLOPS_PER_PAIR
+    out["roofline"] = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                       "unit": "TFLOP/s", "frac": flops / avg_s / PEAK_FP32_VALU,
+                       "traffic": measured_traffic("k_coulomb<16>", "coulomb_hbm_traffic.md"),
+                       "kernel": f"k_coulomb, one open cluster of {n_big} atoms", "avg_launch_ms": tot / n,
+                       "algorithmic_per_launch": {"flops": flops, "pairs": n_big * (n_big - 1)}}
+    log(f"coulomb pair kernel: {tot / n:.3f} ms for {n_big} atoms, "
+        f"{out['roofline']['achieved']:.1f} TFLOP/s ({out['roofline']['frac']:.1%})")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +228,8 @@ def main():
     ap.add_argument("--cpu-sample-atoms", type=int, default=400)
     ap.add_argument("--no-extras", action="store_true", help="skip the BF16 and serving side measurements")
     ap.add_argument("--serving-requests", type=int, default=16)
+    ap.add_argument("--coulomb-only", action="store_true",
+                    help="only run the electrostatics measurement (for profiling its kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 256 MiB device-to-device copies (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -181,6 +251,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read_per_launch": src.numel() * 4,
                           "bytes_written_per_launch": dst.numel() * 4, "launches": 10}), flush=True)
+        return
+    if args.coulomb_only:
+        print(json.dumps({"coulomb": coulomb_run(e3, synth, torch, dev, args.steps, args.warmup, log)}), flush=True)
         return
     cfg, b = synth.single_config(n=args.atoms)
     w = synth.flatten_weights(cfg, synth.model_weights(cfg, 2))
@@ -250,7 +323,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(s)
+    roof["traffic"] = measured_traffic("k_" + s)
     roof["kernel"] = f"{s} (layer {t})"
     roof["avg_launch_ms"] = tot / n
     roof["algorithmic_per_launch"] = {"flops": flops, "bytes": nbytes, "edges": n_edges}
@@ -288,6 +361,7 @@ def main():
                          "proposals": prop, "accepted": acc}
         mdp.close()
         extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, log)
+        extras["coulomb"] = coulomb_run(e3, synth, torch, dev, max(20, args.steps // 2), args.warmup, log)
 
     # ---- oracle on the host cores (bounded sample) ----
     cpu = None

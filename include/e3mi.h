@@ -293,8 +293,8 @@ size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_
  * gate_fwd, readout, gate_bwd, mix_bwd, tp_bwd_edge, radial_bwd, tp_bwd_node,
  * forces, md_update, graph_build, first_fwd, first_bwd (the species-factorised
  * first layer), last_fwd, last_bwd (the fused last layer), barostat (volume
- * moves, including their rebuilds and energy passes), coulomb (charge
- * correction, pair sum and its charge adjoint); "name@t" selects
+ * moves, including their rebuilds and energy passes), coulomb (the
+ * all-pairs electrostatics kernel); "name@t" selects
  * interaction layer t.
  * e3mi_profile_query waits for the recorded events and returns the summed
  * milliseconds and the number of timed launches of a stage. */

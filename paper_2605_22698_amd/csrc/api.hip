@@ -187,7 +187,7 @@ struct Workspace {
   std::unique_ptr<DevBuf> dd, Bd, Prb, Prc, w2c, eb, xb, xc, Ab, Ac, hb_a, hb_b, hc_a, hc_b, Rb, Rc, P1g, P2g,
       partial, vf;
   std::unique_ptr<DevBuf> G1, dG1;  // first layer, [N, (l3+1)^2, S*64]
-  std::unique_ptr<DevBuf> q_raw, q, pot, fc;  // electrostatics: charges, potential, forces
+  std::unique_ptr<DevBuf> q_raw, q, pot, fc, pot_mean;  // electrostatics: charges, potential, forces
 };
 
 }  // namespace e3mi
@@ -219,7 +219,7 @@ struct e3mi_graph {
   std::unique_ptr<e3mi::DevBuf> cnt, row_ptr_x, src_x, dvec_x, old_idx, new_idx, rev_x, x_ref;
   // electrostatics: total charge per structure, and (structure, first atom) per 64-atom tile
   std::unique_ptr<e3mi::DevBuf> charge, ctiles;
-  int n_ctiles = 0;
+  int n_ctiles = 0, c_waves = 1;
 };
 
 struct e3mi_md {
@@ -444,9 +444,14 @@ e3mi_graph* new_graph(e3mi_model* M, int S, const int64_t* off, const double* po
     for (int s = 0; s < S * 3; ++s)
       E3MI_REQUIRE(!pbc[s], E3MI_EUNSUPPORTED, "the Coulomb term is defined for open structures only (pbc all 0)");
     std::vector<int2> tiles;
-    for (int s = 0; s < S; ++s)
+    int64_t n_max = 0;
+    for (int s = 0; s < S; ++s) {
+      n_max = std::max<int64_t>(n_max, off[s + 1] - off[s]);
       for (int64_t i0 = off[s]; i0 < off[s + 1]; i0 += 64) tiles.push_back(make_int2(s, (int)i0));
+    }
     G->n_ctiles = (int)tiles.size();
+    // enough waves per tile to cover the largest structure's senders in one round, at most 16
+    while (G->c_waves < 16 && 64 * G->c_waves < n_max) G->c_waves *= 2;
     G->ctiles = upload(a, tiles.data(), sizeof(int2) * tiles.size());
   }
   G->owner = std::make_unique<DevBuf>(a);
@@ -772,6 +777,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     E3MI_REQUIRE(G->ctiles, E3MI_EINVAL, "graph was built for a model without the Coulomb term");
     for (auto* b : {&w.q_raw, &w.q, &w.pot}) ensure(*b, &M->alloc, sizeof(float) * (size_t)N);
     ensure(w.fc, &M->alloc, sizeof(float) * 3 * (size_t)N);
+    ensure(w.pot_mean, &M->alloc, sizeof(float) * (size_t)S);
   }
   {
     ProfScope ps(&M->prof, stage_id(kReadout), st);
@@ -782,12 +788,15 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     if (!coulomb) launch_energy(w.e_atom->as<double>(), G->off_d->as<int64_t>(), S, energy, st);
   }
   if (coulomb) {
-    ProfScope ps(&M->prof, stage_id(kCoulomb), st);
     const int64_t* offd = G->off_d->as<int64_t>();
     launch_charge_fix(w.q_raw->as<float>(), offd, G->charge->as<double>(), S, w.q->as<float>(), st);
-    launch_coulomb(G->ctiles->as<int2>(), G->n_ctiles, offd, pos, w.q->as<float>(), (float)c.soft_core_r0,
-                   w.e_atom->as<double>(), w.pot->as<float>(), w.fc->as<float>(), st);
-    launch_coulomb_dq(offd, S, w.pot->as<float>(), M->qhead->as<float>(), C, dcur, st);
+    {
+      ProfScope ps(&M->prof, stage_id(kCoulomb), st);
+      launch_coulomb(G->ctiles->as<int2>(), G->n_ctiles, G->c_waves, offd, pos, w.q->as<float>(), (float)c.soft_core_r0,
+                     w.e_atom->as<double>(), w.pot->as<float>(), w.fc->as<float>(), st);
+    }
+    launch_coulomb_dq(offd, G->owner->as<int>(), S, N, w.pot->as<float>(), w.pot_mean->as<float>(),
+                      M->qhead->as<float>(), C, dcur, st);
     launch_energy(w.e_atom->as<double>(), offd, S, energy, st);
   }
   if (atom_energy)

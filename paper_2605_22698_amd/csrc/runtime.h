@@ -260,12 +260,13 @@ void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, f
 // q~ = q - (sum_s q - Q_s) / N_s per structure
 void launch_charge_fix(const float* q_raw, const int64_t* off, const double* Q, int S, float* q, hipStream_t st);
 // soft-core Coulomb over all pairs of each structure: e_atom += 1/2 k q~_i phi_i,
-// pot = k phi, fc = Coulomb forces [N, 3]; tiles = (structure, first receiver) per 64 receivers
-void launch_coulomb(const int2* tiles, int n_tiles, const int64_t* off, const double* pos, const float* q, float r0,
-                    double* e_atom, float* pot, float* fc, hipStream_t st);
-// dh[i, k] += (pot_i - mean_s pot) wq[k]
-void launch_coulomb_dq(const int64_t* off, int S, const float* pot, const float* wq, int C, float* dh,
-                       hipStream_t st);
+// pot = k phi, fc = Coulomb forces [N, 3]; tiles = (structure, first receiver) per 64 receivers;
+// waves (1, 2, 4, 8, 16) split each tile's senders
+void launch_coulomb(const int2* tiles, int n_tiles, int waves, const int64_t* off, const double* pos, const float* q,
+                    float r0, double* e_atom, float* pot, float* fc, hipStream_t st);
+// dh[i, k] += (pot_i - mean_s pot) wq[k]; mean: scratch [S]; owner: structure of each atom
+void launch_coulomb_dq(const int64_t* off, const int* owner, int S, int N, const float* pot, float* mean,
+                       const float* wq, int C, float* dh, hipStream_t st);
 
 // ---- radial MLP (radial.hip) ---------------------------------------------------------
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,

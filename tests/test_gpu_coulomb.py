@@ -69,8 +69,9 @@ def test_packed_clusters_span_tiles_and_ragged_tails():
 
 def test_alone_equals_packed_bitwise():
     rng = np.random.default_rng(64)
-    parts = [synth.open_box(n, 4, rng) for n in (40, 90, 17)]
-    for p, q in zip(parts, (1.0, 0.0, -1.0)):
+    # the 700-atom cluster makes the packed launch wider than any other alone
+    parts = [synth.open_box(n, 4, rng) for n in (40, 90, 17, 700)]
+    for p, q in zip(parts, (1.0, 0.0, -1.0, 2.0)):
         p.charge = np.array([q])
     b = synth.concat(parts)
     cfg = _cfg(lmax=3, C=64, n_species=4)
