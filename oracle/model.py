@@ -22,6 +22,16 @@ Appendix F hyperparameter tables:
   forces       F = -dE/dr (§5.2: the Hessian is minus the position
                    derivative of the forces, i.e. forces are -dE/dr)
 
+Product block (MACE's symmetric contraction of body order 2; the paper's
+MACE models use correlation 2, Appendix F; the block follows Batatia et al.,
+NeurIPS 2022, written per channel k with species-dependent weights; reading):
+  A~^L      the channel mix of the layer's neighbour sum, without the self
+            connection, for every order L <= lmax
+  B^L_k     = w1[z_i, L, k] A~^L_k + sum_{(l1 <= l2, L)} w2[z_i, p, k] (A~^{l1}_k (x) A~^{l2}_k)_L
+            where (x)_L is the CG coupling of the two orders into L
+  h~^L      = B^L W_lin,L + h^{t-1,L} W_self,L,  then the gate; output orders
+            L <= lmax, only L = 0 in the last layer
+
 Electrostatics (§5.1, when the config enables `coulomb`; open structures):
   charges      q_i = w_q . h_i[0] + b_q[z_i]  (a linear charge head on the
                    final scalar features; reading)
@@ -135,6 +145,40 @@ class Model:
             out.append(torch.zeros(n_atoms, C, 2 * l3 + 1, dtype=msg.dtype).index_add(0, dst, msg))
         return torch.cat(out, dim=2) / cfg.avg_neighbors
 
+    def coupling(self, l1: int, l2: int, L: int) -> torch.Tensor:
+        if (l1, l2, L) not in self.cg:
+            self.cg[(l1, l2, L)] = torch.tensor(cg.real_cg(l1, l2, L))
+        return self.cg[(l1, l2, L)]
+
+    def product_basis(self, t: int, At: List[torch.Tensor], species: torch.Tensor) -> List[torch.Tensor]:
+        """B^L for L <= the layer's output order, from A~ (list over l of [N, C, 2l+1])."""
+        cfg, w = self.cfg, self.w
+        lo = 0 if t == cfg.layers else cfg.lmax
+        w1 = w[f"sym1_{t}"][species]                      # [N, lo+1, C]
+        w2 = w[f"sym2_{t}"][species]                      # [N, pairs, C]
+        out = [w1[:, L, :, None] * At[L] for L in range(lo + 1)]
+        p = 0
+        for L in range(lo + 1):
+            for l1 in range(cfg.lmax + 1):
+                for l2 in range(l1, cfg.lmax + 1):
+                    if not (abs(l1 - l2) <= L <= l1 + l2 and (l1 + l2 + L) % 2 == 0):
+                        continue
+                    prod = torch.einsum("abc,nka,nkb->nkc", self.coupling(l1, l2, L), At[l1], At[l2])
+                    out[L] = out[L] + w2[:, p, :, None] * prod
+                    p += 1
+        return out
+
+    def _product_block(self, t, At, h, species, l_in):
+        w = self.w
+        Bs = self.product_basis(t, At, species)
+        ht = []
+        for L, B in enumerate(Bs):
+            acc = torch.einsum("nkm,kq->nqm", B, w[f"lin_{t}_{L}"])
+            if L in l_in:
+                acc = acc + torch.einsum("nkm,kq->nqm", h[:, :, sl(L)], w[f"self_{t}_{L}"])
+            ht.append(acc)
+        return ht
+
     def node_energies(self, pos: torch.Tensor, species: torch.Tensor, dst: torch.Tensor,
                       src: torch.Tensor, shift_vec: torch.Tensor, edge_chunk: Optional[int] = None,
                       features: Optional[list] = None, offsets: Optional[np.ndarray] = None,
@@ -167,6 +211,7 @@ class Model:
                 Ap.append(A[:, :, off:off + 2 * l3 + 1])
                 off += 2 * l3 + 1
             l_in = [0] if t == 1 else list(range(L + 1))
+            mace = getattr(cfg, "correlation", 1) == 2
             ht = []
             for l3 in range(L + 1):
                 acc = torch.zeros(N, C, 2 * l3 + 1, dtype=torch.float64)
@@ -177,11 +222,15 @@ class Model:
                         continue
                     acc = acc + torch.einsum("nkm,kq->nqm", Ap[pi], Wm[q * C:(q + 1) * C])
                     q += 1
-                if l3 in l_in:
+                if l3 in l_in and not mace:
                     acc = acc + torch.einsum("nkm,kq->nqm", h[:, :, sl(l3)], w[f"self_{t}_{l3}"])
                 ht.append(acc)
+            if mace:
+                ht = self._product_block(t, ht, h, species, l_in)
             g = torch.sigmoid(ht[0])                       # [N, C, 1]
-            h = torch.cat([silu(ht[0])] + [ht[l] * g for l in range(1, L + 1)], dim=2)
+            h = torch.cat([silu(ht[0])] + [ht[l] * g for l in range(1, len(ht))], dim=2)
+            if h.shape[2] < nc:
+                h = torch.cat([h, torch.zeros(N, C, nc - h.shape[2], dtype=h.dtype)], dim=2)
             if features is not None:
                 features.append(h)
         e = silu(h[:, :, 0] @ w["read1"]) @ w["read2"]

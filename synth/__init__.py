@@ -54,6 +54,9 @@ class ModelConfig:
     coulomb       add the charge head and the soft-core Coulomb energy (open
                   structures only)
     soft_core_r0  radius below which the Coulomb distance is regularised (angstrom)
+    correlation   1: the channel mix feeds the gate directly; 2: a MACE-style
+                  product block (symmetric contraction of body order 2) sits
+                  between the channel mix and the gate in every layer
     """
     lmax: int
     channels: int
@@ -67,6 +70,7 @@ class ModelConfig:
     readout_hidden: int = 16
     coulomb: bool = False
     soft_core_r0: float = 2.0
+    correlation: int = 1
 
     def to_json(self) -> str:
         return json.dumps(dataclasses.asdict(self), sort_keys=True)
@@ -103,6 +107,25 @@ def path_counts(cfg: ModelConfig, t: int) -> List[int]:
     return counts
 
 
+def product_out_order(cfg: ModelConfig, t: int) -> int:
+    """Highest output order of layer t's product block (the last layer only
+    needs scalars)."""
+    return 0 if t == cfg.layers else cfg.lmax
+
+
+def product_pairs(cfg: ModelConfig, lout: int) -> List[Tuple[int, int, int]]:
+    """(l1, l2, L) couplings of two features of orders l1 <= l2 <= lmax into
+    order L <= lout (triangle rule, even l1 + l2 + L), ordered by (L, l1, l2).
+    Only fixes weight shapes and their order."""
+    out = []
+    for L in range(lout + 1):
+        for l1 in range(cfg.lmax + 1):
+            for l2 in range(l1, cfg.lmax + 1):
+                if abs(l1 - l2) <= L <= l1 + l2 and (l1 + l2 + L) % 2 == 0:
+                    out.append((l1, l2, L))
+    return out
+
+
 def weight_shapes(cfg: ModelConfig) -> List[Tuple[str, Tuple[int, ...], int]]:
     """(name, shape, fan_in) of every weight tensor, in file order.
 
@@ -114,6 +137,10 @@ def weight_shapes(cfg: ModelConfig) -> List[Tuple[str, Tuple[int, ...], int]]:
         rad3_t            [H, P_t*C]      column = p*C + k, paths ordered by (l3, l1, l2)
         mix_t_l3          [P_{t,l3}*C, C] row = q*C + k, q = rank of the path among those with this l3
         self_t_l3         [C, C]          only for l3 present in the layer's input
+        with correlation 2 (Lo = product_out_order, pairs = product_pairs(Lo)):
+        sym1_t            [S, Lo+1, C]    per-species, per-channel weight of the linear term
+        sym2_t            [S, len(pairs), C]  ... of each product coupling
+        lin_t_L           [C, C]          L = 0..Lo, linear after the product block
       read1               [C, readout_hidden]
       read2               [readout_hidden, 1]
       e0                  [S]             per-species reference energy (zeros)
@@ -131,6 +158,13 @@ def weight_shapes(cfg: ModelConfig) -> List[Tuple[str, Tuple[int, ...], int]]:
             out.append((f"mix_{t}_{l3}", (pc[l3] * C, C), pc[l3] * C))
         for l3 in layer_input_orders(cfg, t):
             out.append((f"self_{t}_{l3}", (C, C), C))
+        if cfg.correlation == 2:
+            lo = product_out_order(cfg, t)
+            npair = len(product_pairs(cfg, lo))
+            out.append((f"sym1_{t}", (cfg.n_species, lo + 1, C), 2))
+            out.append((f"sym2_{t}", (cfg.n_species, npair, C), npair))
+            for L in range(lo + 1):
+                out.append((f"lin_{t}_{L}", (C, C), C))
     out.append(("read1", (C, cfg.readout_hidden), C))
     out.append(("read2", (cfg.readout_hidden, 1), cfg.readout_hidden))
     out.append(("e0", (cfg.n_species,), 0))
