@@ -37,6 +37,8 @@ struct Config {
   // Section 5.1 electrostatics: charge head + soft-core Coulomb (open structures)
   bool coulomb = false;
   double soft_core_r0 = 0;
+  // 2: a product block of body order 2 (MACE's symmetric contraction) in every layer
+  int correlation = 1;
 };
 
 size_t json_find(const std::string& s, const char* key) {
@@ -87,6 +89,8 @@ Config parse_config(const char* json) {
   c.radial_hidden = (int)json_number(s, "radial_hidden");
   c.readout_hidden = (int)json_number(s, "readout_hidden");
   c.coulomb = json_bool(s, "coulomb");
+  c.correlation = json_find(s, "correlation") == std::string::npos ? 1 : (int)json_number(s, "correlation");
+  E3MI_REQUIRE(c.correlation == 1 || c.correlation == 2, E3MI_EUNSUPPORTED, "correlation must be 1 or 2");
   if (c.coulomb) {
     c.soft_core_r0 = json_number(s, "soft_core_r0");
     E3MI_REQUIRE(c.soft_core_r0 > 0 && std::isfinite(c.soft_core_r0), E3MI_EINVAL, "soft_core_r0 must be positive");
@@ -109,8 +113,11 @@ Config parse_config(const char* json) {
 struct LayerPlan {
   int kind;
   int l1max;           // highest input order
-  int l3max_used;      // highest output order computed (0 for the last layer)
+  int l3max_used;      // highest order of the neighbour sum A (and its mix A~) computed
+  int lout;            // highest order of h~^t (0 for the last layer)
   int nc_in, nc_out;   // components of h^{t-1} and of h~^t as stored
+  int nc_a;            // components of A~ = (l3max_used + 1)^2
+  int n_prod;          // couplings of the product block (0 without it)
   int p_full;          // paths in the weight tensors of this layer
   int p_full_l3[4];    // per output order
   int p_used;          // paths evaluated
@@ -121,11 +128,17 @@ struct LayerPlan {
 LayerPlan plan_layer(const Config& c, int t) {
   LayerPlan L{};
   const int T = c.layers;
-  L.kind = T == 1 ? 3 : (t == 1 ? 0 : (t == T ? 2 : 1));
+  // with the product block every order of A~ feeds the products, so even the
+  // last layer computes all orders of A (its outputs stay scalar)
+  const bool prod = c.correlation == 2;
+  L.kind = prod ? (t == 1 ? 0 : 1) : (T == 1 ? 3 : (t == 1 ? 0 : (t == T ? 2 : 1)));
   L.l1max = t == 1 ? 0 : c.lmax;
-  L.l3max_used = t == T ? 0 : c.lmax;
+  L.l3max_used = (prod || t < T) ? c.lmax : 0;
+  L.lout = t == T ? 0 : c.lmax;
   L.nc_in = (L.l1max + 1) * (L.l1max + 1);
-  L.nc_out = (L.l3max_used + 1) * (L.l3max_used + 1);
+  L.nc_out = (L.lout + 1) * (L.lout + 1);
+  L.nc_a = (L.l3max_used + 1) * (L.l3max_used + 1);
+  L.n_prod = prod ? product_pair_count(c.lmax, L.lout) : 0;
   for (int l = 0; l < 4; ++l) L.p_full_l3[l] = L.p_used_l3[l] = 0;
   for (int g = 0; g < e3mi_cg::kNumPaths; ++g) {
     const int l1 = e3mi_cg::kL1[g], l2 = e3mi_cg::kL2[g], l3 = e3mi_cg::kL3[g];
@@ -151,6 +164,8 @@ size_t weight_count(const Config& c) {
     n += (size_t)c.n_basis * H + H * H + H * (size_t)L.p_full * C;
     for (int l = 0; l <= c.lmax; ++l) n += (size_t)L.p_full_l3[l] * C * C;
     n += (size_t)(L.l1max + 1) * C * C;  // self connection per input order
+    if (L.n_prod)  // product block: w1, w2 and the linear after it
+      n += (size_t)c.n_species * (L.lout + 1) * C + (size_t)c.n_species * L.n_prod * C + (L.lout + 1) * C * C;
   }
   n += C * c.readout_hidden + c.readout_hidden + c.n_species;
   if (c.coulomb) n += C + c.n_species;  // charge head and per-species charge offset
@@ -162,13 +177,13 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Timed stages (per layer where it applies: index = stage * 8 + layer).
 enum Stage : int {
   kPrune = 0, kEmbed, kRadialFwd, kTpFwd, kMixFwd, kGateFwd, kReadout, kGateBwd, kMixBwd, kTpBwdEdge,
-  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kLastFwd, kLastBwd, kBarostat, kCoulomb,
+  kRadialBwd, kTpBwdNode, kForces, kMdUpdate, kGraphBuild, kFirstFwd, kFirstBwd, kLastFwd, kLastBwd, kBarostat, kCoulomb, kProductFwd, kProductBwd,
   kNumStages
 };
 const char* const kStageNames[kNumStages] = {
     "prune", "embed", "radial_fwd", "tp_fwd", "mix_fwd", "gate_fwd", "readout", "gate_bwd", "mix_bwd",
     "tp_bwd_edge", "radial_bwd", "tp_bwd_node", "forces", "md_update", "graph_build", "first_fwd", "first_bwd",
-    "last_fwd", "last_bwd", "barostat", "coulomb"};
+    "last_fwd", "last_bwd", "barostat", "coulomb", "product_fwd", "product_bwd"};
 inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
 
 }  // namespace
@@ -177,6 +192,7 @@ inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
 struct LayerWeights {
   DevBuf rad1, rad2, rad2T, rad3, rad3T, rad3u;
   DevBuf mix[4], mixT[4], self_[4], selfT[4];
+  DevBuf sym1, sym2, lin[4], linT[4];  // product block
 };
 
 struct Workspace {
@@ -188,6 +204,8 @@ struct Workspace {
       partial, vf;
   std::unique_ptr<DevBuf> G1, dG1;  // first layer, [N, (l3+1)^2, S*64]
   std::unique_ptr<DevBuf> q_raw, q, pot, fc, pot_mean;  // electrostatics: charges, potential, forces
+  std::vector<std::unique_ptr<DevBuf>> at;             // product block: A~ per layer
+  std::unique_ptr<DevBuf> Bp, dat;                     // product block: B (or dB), dA~
 };
 
 }  // namespace e3mi
@@ -495,10 +513,11 @@ int cpt_for(const LayerPlan& L, int C) {
   return C <= 64 ? 1 : C / 64;
 }
 
-// h~ = sum_p A_p W_l3[p] + h_in S_l3 for every computed output order l3 (rows
-// (atom, m), columns channels). `hin` may be NULL (no self connection term).
-void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* A, const float* hin, float* ht, int N,
-                hipStream_t st, bool bf16 = false) {
+// h~ = sum_p A_p W_l3[p] + h_in S_l3 for every computed order l3 (rows
+// (atom, m), columns channels); out has out_nc components per atom. `hin` may
+// be NULL (no self connection term).
+void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* A, const float* hin, float* ht,
+                int out_nc, int N, hipStream_t st, bool bf16 = false) {
   const int C = M->cfg.channels;
   long gbase = 0;
   for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
@@ -514,7 +533,7 @@ void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
       ga.ldb1 = C;
       ga.k1 = C;
     }
-    ga.c = RowMap{ht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
+    ga.c = RowMap{ht + (long)l3 * l3 * C, (long)out_nc * C, (long)C, g};
     ga.M = N * g;
     ga.Nc = C;
     launch_gemm(ga, st, bf16);
@@ -522,16 +541,75 @@ void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
   }
 }
 
+// After the product block: h~^L = B^L W_lin,L + h_in^L S_L for L <= lout.
+void launch_lin(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* B, const float* hin, float* ht,
+                int N, hipStream_t st, bool bf16) {
+  const int C = M->cfg.channels;
+  for (int l = 0; l <= L.lout; ++l) {
+    const int g = 2 * l + 1;
+    GemmArgs ga{};
+    ga.a0 = RowMap{const_cast<float*>(B) + (long)l * l * C, (long)L.nc_out * C, (long)C, g};
+    ga.b0 = W.lin[l].as<float>();
+    ga.ldb0 = C;
+    ga.k0 = C;
+    if (hin && l <= L.l1max) {
+      ga.a1 = RowMap{const_cast<float*>(hin) + (long)l * l * C, (long)L.nc_in * C, (long)C, g};
+      ga.b1 = W.self_[l].as<float>();
+      ga.ldb1 = C;
+      ga.k1 = C;
+    }
+    ga.c = RowMap{ht + (long)l * l * C, (long)L.nc_out * C, (long)C, g};
+    ga.M = N * g;
+    ga.Nc = C;
+    launch_gemm(ga, st, bf16);
+  }
+}
+
+// Adjoint of launch_lin: dB^L = dh~^L W_lin,L^T and (dprev not NULL) dprev^L = dh~^L S_L^T.
+void launch_lin_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* dht, float* dB, float* dprev,
+                        int N, hipStream_t st, bool bf16) {
+  const int C = M->cfg.channels;
+  for (int l = 0; l <= L.lout; ++l) {
+    const int g = 2 * l + 1;
+    for (int which = 0; which < 2; ++which) {
+      if (which == 1 && (!dprev || l > L.l1max)) continue;
+      GemmArgs ga{};
+      ga.a0 = RowMap{const_cast<float*>(dht) + (long)l * l * C, (long)L.nc_out * C, (long)C, g};
+      ga.b0 = which == 0 ? W.linT[l].as<float>() : W.selfT[l].as<float>();
+      ga.ldb0 = C;
+      ga.k0 = C;
+      ga.c = which == 0 ? RowMap{dB + (long)l * l * C, (long)L.nc_out * C, (long)C, g}
+                        : RowMap{dprev + (long)l * l * C, (long)L.nc_in * C, (long)C, g};
+      ga.M = N * g;
+      ga.Nc = C;
+      launch_gemm(ga, st, bf16);
+    }
+  }
+}
+
+ProductArgs product_args(e3mi_model* M, e3mi_graph* G, const LayerPlan& L, LayerWeights& W, const float* at) {
+  ProductArgs p;
+  p.lmax = M->cfg.lmax;
+  p.lout = L.lout;
+  p.N = G->N;
+  p.C = M->cfg.channels;
+  p.at = at;
+  p.species = G->species->as<int>();
+  p.w1 = W.sym1.as<float>();
+  p.w2 = W.sym2.as<float>();
+  return p;
+}
+
 // Adjoint of the channel mix: dA = dht W^T per order, and (when dprev is not
 // NULL) dprev[l3] (+)= dht[l3] S^T for the orders present in the input.
-void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* dht, float* dA, float* dprev,
-                        int N, hipStream_t st, bool bf16 = false) {
+void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* dht, int dht_nc, float* dA,
+                        float* dprev, int N, hipStream_t st, bool bf16 = false) {
   const int C = M->cfg.channels;
   long gbase = 0;
   for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
     const int P3 = L.p_used_l3[l3], gg = 2 * l3 + 1;
     GemmArgs ga{};
-    ga.a0 = RowMap{const_cast<float*>(dht) + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
+    ga.a0 = RowMap{const_cast<float*>(dht) + (long)l3 * l3 * C, (long)dht_nc * C, (long)C, gg};
     ga.b0 = W.mixT[l3].as<float>();
     ga.ldb0 = P3 * C;
     ga.k0 = C;
@@ -545,7 +623,7 @@ void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
   for (int l3 = 0; l3 <= std::min(L.l3max_used, L.l1max); ++l3) {
     const int gg = 2 * l3 + 1;
     GemmArgs ga{};
-    ga.a0 = RowMap{const_cast<float*>(dht) + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
+    ga.a0 = RowMap{const_cast<float*>(dht) + (long)l3 * l3 * C, (long)dht_nc * C, (long)C, gg};
     ga.b0 = W.selfT[l3].as<float>();
     ga.ldb0 = C;
     ga.k0 = C;
@@ -652,9 +730,28 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
   const bool fact = factorised_first(M) && !keep_A;
   const int S64 = c.n_species * c.radial_hidden;
   if (fact) {
-    ensure(w.G1, a, sizeof(float) * (size_t)N * M->plans[0].nc_out * S64);
-    ensure(w.dG1, a, sizeof(float) * (size_t)N * M->plans[0].nc_out * S64);
+    ensure(w.G1, a, sizeof(float) * (size_t)N * M->plans[0].nc_a * S64);
+    ensure(w.dG1, a, sizeof(float) * (size_t)N * M->plans[0].nc_a * S64);
   }
+  // product block: the mix writes A~ (no self connection); B follows, then
+  // h~ = B W_lin + h_in S
+  const bool prod = c.correlation == 2;
+  if (prod) {
+    w.at.resize(T + 1);
+    for (int t = 1; t <= T; ++t) ensure(w.at[t], a, sizeof(float) * (size_t)N * M->plans[t - 1].nc_a * C);
+    ensure(w.Bp, a, sizeof(float) * (size_t)N * NC * C);
+    ensure(w.dat, a, sizeof(float) * (size_t)N * NC * C);
+  }
+  auto product_tail = [&](int t, const LayerPlan& L, LayerWeights& W, const float* hin, float* ht) {
+    ProductArgs pa = product_args(M, G, L, W, w.at[t]->as<float>());
+    pa.B = w.Bp->as<float>();
+    {
+      ProfScope ps(&M->prof, stage_id(kProductFwd, t), st);
+      launch_product(true, pa, st);
+    }
+    ProfScope ps(&M->prof, stage_id(kMixFwd, t), st);
+    launch_lin(M, L, W, w.Bp->as<float>(), hin, ht, N, st, bf16);
+  };
   for (int t = 1; t <= T; ++t) {
     const LayerPlan& L = M->plans[t - 1];
     LayerWeights& W = *M->lw[t - 1];
@@ -667,27 +764,30 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
                      W.rad2.as<float>(), nullptr, G1, nullptr, nullptr, 0, rc, p_env, st);
       }
       float* ht = w.ht[1]->as<float>();
+      float* mix_out = prod ? w.at[1]->as<float>() : ht;
+      const int mix_nc = prod ? L.nc_a : L.nc_out;
       {
         ProfScope ps(&M->prof, stage_id(kMixFwd, 1), st);
         for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
           const int g = 2 * l3 + 1;
           GemmArgs ga{};
-          ga.a0 = RowMap{G1 + (long)l3 * l3 * S64, (long)L.nc_out * S64, (long)S64, g};
+          ga.a0 = RowMap{G1 + (long)l3 * l3 * S64, (long)L.nc_a * S64, (long)S64, g};
           ga.b0 = M->U[l3]->as<float>();
           ga.ldb0 = C;
           ga.k0 = S64;
-          if (l3 == 0) {
+          if (l3 == 0 && !prod) {
             ga.a1 = RowMap{const_cast<float*>(hin), (long)C, (long)C, 1};
             ga.b1 = W.self_[0].as<float>();
             ga.ldb1 = C;
             ga.k1 = C;
           }
-          ga.c = RowMap{ht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
+          ga.c = RowMap{mix_out + (long)l3 * l3 * C, (long)mix_nc * C, (long)C, g};
           ga.M = N * g;
           ga.Nc = C;
           launch_gemm(ga, st, bf16);
         }
       }
+      if (prod) product_tail(1, L, W, hin, ht);
       {
         ProfScope ps(&M->prof, stage_id(kGateFwd, 1), st);
         launch_gate_fwd(ht, w.h[1]->as<float>(), N, L.nc_out, C, st);
@@ -705,7 +805,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
       float* ht = w.ht[t]->as<float>();
       {
         ProfScope ps(&M->prof, stage_id(kMixFwd, t), st);
-        launch_mix(M, L, W, A, hin, ht, N, st, bf16);
+        launch_mix(M, L, W, A, hin, ht, L.nc_out, N, st, bf16);
       }
       {
         ProfScope ps(&M->prof, stage_id(kGateFwd, t), st);
@@ -742,8 +842,12 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     float* ht = w.ht[t]->as<float>();
     {
       ProfScope ps(&M->prof, stage_id(kMixFwd, t), st);
-      launch_mix(M, L, W, A, hin, ht, N, st, bf16);
+      if (prod)
+        launch_mix(M, L, W, A, nullptr, w.at[t]->as<float>(), L.nc_a, N, st, bf16);
+      else
+        launch_mix(M, L, W, A, hin, ht, L.nc_out, N, st, bf16);
     }
+    if (prod) product_tail(t, L, W, hin, ht);
     {
       ProfScope ps(&M->prof, stage_id(kGateFwd, t), st);
       launch_gate_fwd(ht, w.h[t]->as<float>(), N, L.nc_out, C, st);
@@ -807,6 +911,8 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
   float4* g = w.g->as<float4>();
   const bool fact = factorised_first(M);
   const int S64 = c.n_species * c.radial_hidden;
+  const bool prod = c.correlation == 2;
+  const bool bf16 = M->precision == E3MI_BF16_MIX;
   for (int t = T; t >= 1; --t) {
     const LayerPlan& L = M->plans[t - 1];
     LayerWeights& W = *M->lw[t - 1];
@@ -816,6 +922,26 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       ProfScope ps(&M->prof, stage_id(kGateBwd, t), st);
       launch_gate_bwd(w.ht[t]->as<float>(), dcur, dht, N, L.nc_out, C, st);
     }
+    // product block: dB = dh~ W_lin^T (the self-connection part goes to the
+    // previous layer's gradient), then dA~; the mix adjoint starts from dA~
+    const float* dmix = dht;
+    int dmix_nc = L.nc_out;
+    if (prod) {
+      {
+        ProfScope ps(&M->prof, stage_id(kMixBwd, t), st);
+        if (t > 1) E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+        launch_lin_adjoint(M, L, W, dht, w.Bp->as<float>(), t > 1 ? dother : nullptr, N, st, bf16);
+      }
+      ProductArgs pa = product_args(M, G, L, W, w.at[t]->as<float>());
+      pa.dB = w.Bp->as<float>();
+      pa.dat = w.dat->as<float>();
+      {
+        ProfScope ps(&M->prof, stage_id(kProductBwd, t), st);
+        launch_product(false, pa, st);
+      }
+      dmix = w.dat->as<float>();
+      dmix_nc = L.nc_a;
+    }
     if (t == 1 && fact) {
       float* dG1 = w.dG1->as<float>();
       {
@@ -823,11 +949,11 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
         for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
           const int gg = 2 * l3 + 1;
           GemmArgs ga{};
-          ga.a0 = RowMap{dht + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, gg};
+          ga.a0 = RowMap{const_cast<float*>(dmix) + (long)l3 * l3 * C, (long)dmix_nc * C, (long)C, gg};
           ga.b0 = M->UT[l3]->as<float>();
           ga.ldb0 = S64;
           ga.k0 = C;
-          ga.c = RowMap{dG1 + (long)l3 * l3 * S64, (long)L.nc_out * S64, (long)S64, gg};
+          ga.c = RowMap{dG1 + (long)l3 * l3 * S64, (long)L.nc_a * S64, (long)S64, gg};
           ga.M = N * gg;
           ga.Nc = S64;
           launch_gemm(ga, st, M->precision == E3MI_BF16_MIX);
@@ -842,8 +968,8 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     }
     {
       ProfScope ps(&M->prof, stage_id(kMixBwd, t), st);
-      if (t > 1) E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
-      launch_mix_adjoint(M, L, W, dht, A, t > 1 ? dother : nullptr, N, st, M->precision == E3MI_BF16_MIX);
+      if (t > 1 && !prod) E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+      launch_mix_adjoint(M, L, W, dmix, dmix_nc, A, (t > 1 && !prod) ? dother : nullptr, N, st, bf16);
     }
     if (fused_last(M, L, false, M->precision == E3MI_BF16_MIX)) {
       LastArgs la = last_args(M, G, L, W, hin);
@@ -913,6 +1039,7 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
   for (int t = 1; t <= c.layers; ++t) {
     const LayerPlan& L = M->plans[t - 1];
     b += 2 * N * L.nc_out * C * 4;
+    if (L.n_prod) b += N * L.nc_a * C * 4;  // A~ kept for the product block's adjoint
     a_max = std::max(a_max, (size_t)L.a_per_atom);
     if (t == 1 && factorised_first(M)) {
       b += 2 * N * L.nc_out * (size_t)c.n_species * c.radial_hidden * 4;  // G and dG
@@ -923,12 +1050,15 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
     pc_max = std::max(pc_max, (size_t)L.p_used * C);
   }
   b += N * a_max * 4 + E * pc_max * 4 + E * (64 + 16) + 3 * N * NC * C * 4 + N * 8;
+  if (c.correlation == 2) b += 2 * N * NC * C * 4;  // B / dB and dA~
   return b;
 }
 
 // Offsets of every weight tensor in the flat FP64 vector (file order).
 struct WeightOffsets {
   size_t emb = 0, read1 = 0, read2 = 0, e0 = 0, qhead = 0, qbias = 0, total = 0;
+  std::vector<size_t> sym1, sym2;
+  std::vector<std::array<size_t, 4>> lin;
   std::vector<size_t> rad1, rad2, rad3;
   std::vector<std::array<size_t, 4>> mix, self_;
 };
@@ -958,6 +1088,19 @@ WeightOffsets weight_offsets(const Config& c) {
     }
     o.mix.push_back(m);
     o.self_.push_back(sf);
+    std::array<size_t, 4> ln{};
+    o.sym1.push_back(cur);
+    o.sym2.push_back(cur);
+    if (L.n_prod) {
+      cur += (size_t)c.n_species * (L.lout + 1) * C;
+      o.sym2.back() = cur;
+      cur += (size_t)c.n_species * L.n_prod * C;
+      for (int l = 0; l <= L.lout; ++l) {
+        ln[l] = cur;
+        cur += C * C;
+      }
+    }
+    o.lin.push_back(ln);
   }
   o.read1 = cur;
   cur += C * c.readout_hidden;
@@ -994,8 +1137,10 @@ void upload_weights(e3mi_model* M, const double* wts) {
     if ((int)M->lw.size() < t) {
       M->plans.push_back(L);
       auto Wn = std::make_unique<LayerWeights>();
-      for (DevBuf* b : {&Wn->rad1, &Wn->rad2, &Wn->rad2T, &Wn->rad3, &Wn->rad3T, &Wn->rad3u}) b->a = a;
-      for (int l = 0; l < 4; ++l) Wn->mix[l].a = Wn->mixT[l].a = Wn->self_[l].a = Wn->selfT[l].a = a;
+      for (DevBuf* b : {&Wn->rad1, &Wn->rad2, &Wn->rad2T, &Wn->rad3, &Wn->rad3T, &Wn->rad3u, &Wn->sym1, &Wn->sym2})
+        b->a = a;
+      for (int l = 0; l < 4; ++l)
+        Wn->mix[l].a = Wn->mixT[l].a = Wn->self_[l].a = Wn->selfT[l].a = Wn->lin[l].a = Wn->linT[l].a = a;
       M->lw.push_back(std::move(Wn));
     }
     LayerWeights* W = M->lw[t - 1].get();
@@ -1033,6 +1178,15 @@ void upload_weights(e3mi_model* M, const double* wts) {
       const auto s = take((size_t)C * C);
       up(W->self_[l], s);
       up(W->selfT[l], transpose(s, C, C));
+    }
+    if (L.n_prod) {
+      up(W->sym1, take((size_t)c.n_species * (L.lout + 1) * C));
+      up(W->sym2, take((size_t)c.n_species * L.n_prod * C));
+      for (int l = 0; l <= L.lout; ++l) {
+        const auto m = take((size_t)C * C);
+        up(W->lin[l], m);
+        up(W->linT[l], transpose(m, C, C));
+      }
     }
   }
   M->read1 = upload_f32(a, take((size_t)C * c.readout_hidden));
@@ -1103,6 +1257,7 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
   const int p_env = c.envelope_p;
   Workspace& w = M->ws;
   E3MI_REQUIRE(!c.coulomb, E3MI_EUNSUPPORTED, "parameter gradients of the Coulomb term are not implemented");
+  E3MI_REQUIRE(c.correlation == 1, E3MI_EUNSUPPORTED, "parameter gradients of the product block are not implemented");
   const WeightOffsets off = weight_offsets(c);
   E3MI_HIP(hipMemsetAsync(out, 0, sizeof(double) * off.total, st));
   if (N == 0) return;
@@ -1167,7 +1322,8 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
     ta.C = C;
     ta.inv_nu = inv_nu;
     launch_tp(3, ta, st);
-    launch_mix(M, L, W, w.Ad[t]->as<float>(), t > 1 ? w.hd[t - 1]->as<float>() : nullptr, w.htd[t]->as<float>(), N,
+    launch_mix(M, L, W, w.Ad[t]->as<float>(), t > 1 ? w.hd[t - 1]->as<float>() : nullptr, w.htd[t]->as<float>(),
+               L.nc_out, N,
                st);
     launch_gate_dual_fwd(w.ht[t]->as<float>(), w.htd[t]->as<float>(), w.hd[t]->as<float>(), N, L.nc_out, C, st);
   }
@@ -1216,8 +1372,8 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
     // adjoints of A and A_dot; of h^{t-1} and h_dot^{t-1} through the self connection
     E3MI_HIP(hipMemsetAsync(hb2, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
     if (t > 1) E3MI_HIP(hipMemsetAsync(hc2, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
-    launch_mix_adjoint(M, L, W, xb, w.Ab->as<float>(), hb2, N, st);
-    launch_mix_adjoint(M, L, W, xc, w.Ac->as<float>(), t > 1 ? hc2 : nullptr, N, st);
+    launch_mix_adjoint(M, L, W, xb, L.nc_out, w.Ab->as<float>(), hb2, N, st);
+    launch_mix_adjoint(M, L, W, xc, L.nc_out, w.Ac->as<float>(), t > 1 ? hc2 : nullptr, N, st);
     // tensor product: adjoints of R and R_dot, then of h and h_dot
     TpArgs ta{};
     ta.lmax = c.lmax;

@@ -1,0 +1,169 @@
+// MACE-style product block between the channel mix and the gate (the
+// symmetric contraction of body order 2; the paper's MACE models use
+// correlation 2, Appendix F). For atom i of species z and channel k:
+//   B^L_k = w1[z, L, k] A~^L_k + sum_p w2[z, p, k] sum C^{l1 l2 L}_{m1 m2 M} A~^{l1}_{m1,k} A~^{l2}_{m2,k}
+// over the couplings p = (l1 <= l2, L) of the Clebsch-Gordan table with
+// L <= LOUT, in table order (by L, then l1, then l2). The block is
+// per-channel and per-atom (no dense contraction), so it runs on the vector
+// ALU with one thread per (atom, channel): loads and stores are coalesced
+// over channels and the coefficients are immediates. Its adjoint:
+//   dA~^L += w1 dB^L,  dA~^{l1} += w2 C dB^L A~^{l2},  dA~^{l2} += w2 C dB^L A~^{l1}.
+#include "common.h"
+#include "paths.h"
+#include "runtime.h"
+
+namespace e3mi {
+namespace {
+
+template <int LMAX, int LOUT>
+struct ProductSet {
+  static constexpr int NA = (LMAX + 1) * (LMAX + 1);  // components of A~
+  static constexpr int NB = (LOUT + 1) * (LOUT + 1);  // components of B
+  static constexpr bool keep(int g) { return kL1[g] <= kL2[g] && kL2[g] <= LMAX && kL3[g] <= LOUT; }
+  static constexpr int count() {
+    int c = 0;
+    for (int g = 0; g < kNumPaths; ++g) c += keep(g) ? 1 : 0;
+    return c;
+  }
+  static constexpr int NP = count();
+  struct Table {
+    int id[NP];
+  };
+  static constexpr Table make() {
+    Table t{};
+    int c = 0;
+    for (int g = 0; g < kNumPaths; ++g)
+      if (keep(g)) t.id[c++] = g;
+    return t;
+  }
+  static constexpr Table T = make();
+};
+
+template <int LMAX, int LOUT>
+__global__ void __launch_bounds__(256) k_product_fwd(const float* __restrict__ at, const int* __restrict__ species,
+                                                     const float* __restrict__ w1, const float* __restrict__ w2,
+                                                     int N, int lg_c, float* __restrict__ B) {
+  using PS = ProductSet<LMAX, LOUT>;
+  const int C = 1 << lg_c;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ((long)N << lg_c)) return;
+  const int i = (int)(e >> lg_c), k = (int)(e & (C - 1));
+  const int z = species[i];
+  float a[PS::NA];
+#pragma unroll
+  for (int q = 0; q < PS::NA; ++q) a[q] = at[((long)i * PS::NA + q) * C + k];
+  const float* w1z = w1 + (long)z * (LOUT + 1) * C + k;
+  const float* w2z = w2 + (long)z * PS::NP * C + k;
+  float b[PS::NB];
+#pragma unroll
+  for (int L = 0; L <= LOUT; ++L) {
+    const float wl = w1z[L * C];
+#pragma unroll
+    for (int m = 0; m < 2 * L + 1; ++m) b[L * L + m] = wl * a[L * L + m];
+  }
+  static_for<PS::NP>([&](auto p) {
+    constexpr int g = PS::T.id[p];
+    constexpr int l1 = kL1[g], l2 = kL2[g], l3 = kL3[g];
+    constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
+    float t[2 * l3 + 1];
+#pragma unroll
+    for (int m = 0; m < 2 * l3 + 1; ++m) t[m] = 0.0f;
+    static_for<nz>([&](auto zz) {
+      constexpr int q = z0 + zz;
+      t[kM3[q]] += kC[q] * (a[l1 * l1 + kM1[q]] * a[l2 * l2 + kM2[q]]);
+    });
+    const float wp = w2z[(int)p * C];
+#pragma unroll
+    for (int m = 0; m < 2 * l3 + 1; ++m) b[l3 * l3 + m] += wp * t[m];
+  });
+#pragma unroll
+  for (int q = 0; q < PS::NB; ++q) B[((long)i * PS::NB + q) * C + k] = b[q];
+}
+
+template <int LMAX, int LOUT>
+__global__ void __launch_bounds__(256) k_product_bwd(const float* __restrict__ at, const int* __restrict__ species,
+                                                     const float* __restrict__ w1, const float* __restrict__ w2,
+                                                     const float* __restrict__ dB, int N, int lg_c,
+                                                     float* __restrict__ dat) {
+  using PS = ProductSet<LMAX, LOUT>;
+  const int C = 1 << lg_c;
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ((long)N << lg_c)) return;
+  const int i = (int)(e >> lg_c), k = (int)(e & (C - 1));
+  const int z = species[i];
+  float a[PS::NA], da[PS::NA], db[PS::NB];
+#pragma unroll
+  for (int q = 0; q < PS::NA; ++q) {
+    a[q] = at[((long)i * PS::NA + q) * C + k];
+    da[q] = 0.0f;
+  }
+#pragma unroll
+  for (int q = 0; q < PS::NB; ++q) db[q] = dB[((long)i * PS::NB + q) * C + k];
+  const float* w1z = w1 + (long)z * (LOUT + 1) * C + k;
+  const float* w2z = w2 + (long)z * PS::NP * C + k;
+#pragma unroll
+  for (int L = 0; L <= LOUT; ++L) {
+    const float wl = w1z[L * C];
+#pragma unroll
+    for (int m = 0; m < 2 * L + 1; ++m) da[L * L + m] = wl * db[L * L + m];
+  }
+  static_for<PS::NP>([&](auto p) {
+    constexpr int g = PS::T.id[p];
+    constexpr int l1 = kL1[g], l2 = kL2[g], l3 = kL3[g];
+    constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
+    const float wp = w2z[(int)p * C];
+    float s[2 * l3 + 1];
+#pragma unroll
+    for (int m = 0; m < 2 * l3 + 1; ++m) s[m] = wp * db[l3 * l3 + m];
+    static_for<nz>([&](auto zz) {
+      constexpr int q = z0 + zz;
+      const float c = kC[q] * s[kM3[q]];
+      da[l1 * l1 + kM1[q]] += c * a[l2 * l2 + kM2[q]];
+      da[l2 * l2 + kM2[q]] += c * a[l1 * l1 + kM1[q]];
+    });
+  });
+#pragma unroll
+  for (int q = 0; q < PS::NA; ++q) dat[((long)i * PS::NA + q) * C + k] = da[q];
+}
+
+int log2_channels(int C) {
+  int lg = 0;
+  while ((1 << lg) < C) ++lg;
+  if ((1 << lg) != C) throw Error(E3MI_EUNSUPPORTED, "product block: channels must be a power of two");
+  return lg;
+}
+
+template <int LMAX, int LOUT>
+void product_l(bool fwd, const ProductArgs& p, int lg, int grid, hipStream_t st) {
+  if (fwd)
+    k_product_fwd<LMAX, LOUT><<<grid, 256, 0, st>>>(p.at, p.species, p.w1, p.w2, p.N, lg, p.B);
+  else
+    k_product_bwd<LMAX, LOUT><<<grid, 256, 0, st>>>(p.at, p.species, p.w1, p.w2, p.dB, p.N, lg, p.dat);
+}
+
+}  // namespace
+
+int product_pair_count(int lmax, int lout) {
+  int c = 0;
+  for (int g = 0; g < kNumPaths; ++g) c += (kL1[g] <= kL2[g] && kL2[g] <= lmax && kL3[g] <= lout) ? 1 : 0;
+  return c;
+}
+
+void launch_product(bool fwd, const ProductArgs& p, hipStream_t st) {
+  if (p.N == 0) return;
+  const int lg = log2_channels(p.C);
+  const long n = (long)p.N * p.C;
+  const int grid = (int)((n + 255) / 256);
+  if (p.lmax == 3 && p.lout == 3)
+    product_l<3, 3>(fwd, p, lg, grid, st);
+  else if (p.lmax == 3 && p.lout == 0)
+    product_l<3, 0>(fwd, p, lg, grid, st);
+  else if (p.lmax == 2 && p.lout == 2)
+    product_l<2, 2>(fwd, p, lg, grid, st);
+  else if (p.lmax == 2 && p.lout == 0)
+    product_l<2, 0>(fwd, p, lg, grid, st);
+  else
+    throw Error(E3MI_EUNSUPPORTED, "product block: unsupported (lmax, output order)");
+}
+
+}  // namespace e3mi

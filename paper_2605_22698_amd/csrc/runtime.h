@@ -256,6 +256,20 @@ void launch_energy(const double* e_atom, const int64_t* off, int S, double* ener
 void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st,
                    const float* extra = nullptr);
 
+// ---- product block of body order 2 (product.hip) -------------------------------------
+struct ProductArgs {
+  int lmax = 0, lout = 0, N = 0, C = 0;
+  const float* at = nullptr;       // A~ [N, (lmax+1)^2, C]
+  const int* species = nullptr;    // [N]
+  const float* w1 = nullptr;       // [S, lout+1, C]
+  const float* w2 = nullptr;       // [S, pairs, C]
+  float* B = nullptr;              // forward output [N, (lout+1)^2, C]
+  const float* dB = nullptr;       // adjoint input  [N, (lout+1)^2, C]
+  float* dat = nullptr;            // adjoint output [N, (lmax+1)^2, C] (overwritten)
+};
+int product_pair_count(int lmax, int lout);
+void launch_product(bool fwd, const ProductArgs& p, hipStream_t st);
+
 // ---- electrostatics of open structures (coulomb.hip) ---------------------------------
 // q~ = q - (sum_s q - Q_s) / N_s per structure
 void launch_charge_fix(const float* q_raw, const int64_t* off, const double* Q, int S, float* q, hipStream_t st);
