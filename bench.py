@@ -151,6 +151,72 @@ def serving_run(e3, synth, torch, dev, n_requests, log):
             "repacks": summ["repacks"], "p50_queue_wait_s": float(np.percentile(waits, 50)) if waits else 0.0}
 
 
+def product_work(cfg, t, N):
+    """Algorithmic (flops, HBM bytes) of one launch of the product block of
+    layer t, forward and adjoint, per (atom, channel): forward 3 flops per CG
+    nonzero of each coupling (l1 <= l2, L <= Lo), 2 per output component of
+    each coupling for its weight, 1 per component of B for the linear term;
+    adjoint 5 per nonzero (both factors), 1 per output component of each
+    coupling, 1 per component of B. Bytes = A~ in and B out (forward), A~ and
+    dB in and dA~ out (adjoint)."""
+    L1, L2, L3, NZ = cg_nnz()
+    lo = 0 if t == cfg.layers else cfg.lmax
+    na, nb = (cfg.lmax + 1) ** 2, (lo + 1) ** 2
+    sel = [g for g in range(len(L1)) if L1[g] <= L2[g] <= cfg.lmax and L3[g] <= lo]
+    nz = sum(NZ[g] for g in sel)
+    nout = sum(2 * L3[g] + 1 for g in sel)
+    per_fwd = 3 * nz + 2 * nout + nb
+    per_bwd = 5 * nz + nout + nb
+    NCn = N * cfg.channels
+    return {"product_fwd": (per_fwd * NCn, 4 * NCn * (na + nb)),
+            "product_bwd": (per_bwd * NCn, 4 * NCn * (2 * na + nb))}
+
+
+def product_run(e3, synth, torch, dev, n_atoms, steps, warmup, log):
+    """MD of the single-structure box with the product block of body order 2
+    (MACE's symmetric contraction, correlation 2) in both layers, against the
+    same box without it; the dominant product kernel against HBM."""
+    cfg1, b = synth.single_config(n=n_atoms)
+    cfg = synth.ModelConfig(**{**cfg1.__dict__, "correlation": 2})
+    vel = synth.maxwell_boltzmann(b, 300.0, synth.seed_for(2, 9))
+    pos_d = torch.tensor(b.pos, dtype=torch.float64, device=dev)
+    vel_d = torch.tensor(vel, dtype=torch.float64, device=dev)
+    sp_d = torch.tensor(b.species, dtype=torch.int32, device=dev)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    m = e3.Model(cfg.to_json(), synth.flatten_weights(cfg, synth.model_weights(cfg, 2)), device=dev)
+    md = e3.MD(m, b.offsets, pos_d, vel_d, sp_d, synth.SPECIES_MASS[:4], b.cell, b.pbc, cfg.cutoff, 1.0, 20)
+    md.step(warmup, 0.5, energy)
+    torch.cuda.synchronize()
+    m.profile(True)
+    t1 = time.perf_counter()
+    md.step(steps, 0.5, energy)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    m.profile(False)
+    out = {"workload": f"MD step, {b.n_atoms}-atom periodic box, l_max 3, 128 channels, 2 layers, "
+                       f"product block of body order 2 in both layers (every layer keeps all orders of A~)",
+           "value": b.n_atoms * steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps}
+    best = None
+    stage = {}
+    for t in range(1, cfg.layers + 1):
+        for s, (flops, nbytes) in product_work(cfg, t, b.n_atoms).items():
+            tot, n = m.stage_time(f"{s}@{t}")
+            stage[f"{s}@{t}"] = tot / steps
+            if n and (best is None or tot / n > best[0]):
+                best = (tot / n, s, t, flops, nbytes)
+    out["stage_ms_per_step"] = stage
+    ms, s, t, flops, nbytes = best
+    out["roofline"] = {"bound": "hbm", "achieved": nbytes / (ms / 1e3) / 1e9, "peak": PEAK_HBM / 1e9,
+                       "unit": "GB/s", "frac": nbytes / (ms / 1e3) / PEAK_HBM,
+                       "traffic": measured_traffic(f"k_{s}", "product_hbm_traffic.md"),
+                       "kernel": f"{s} (layer {t})", "avg_launch_ms": ms,
+                       "algorithmic_per_launch": {"flops": flops, "bytes": nbytes}}
+    md.close()
+    log(f"product block: {out['value']:.3e} atom-steps/s; {s}@{t} {ms:.4f} ms, "
+        f"{out['roofline']['achieved']:.0f} GB/s ({out['roofline']['frac']:.1%})")
+    return out
+
+
 COULOMB_FLOPS_PER_PAIR = 20  # distance 8, rsqrt 1, potential 2, force factor 3, force 6
 
 
@@ -230,6 +296,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=16)
     ap.add_argument("--coulomb-only", action="store_true",
                     help="only run the electrostatics measurement (for profiling its kernels)")
+    ap.add_argument("--product-only", action="store_true",
+                    help="only run the product-block measurement (for profiling its kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run plain 256 MiB device-to-device copies (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -251,6 +319,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read_per_launch": src.numel() * 4,
                           "bytes_written_per_launch": dst.numel() * 4, "launches": 10}), flush=True)
+        return
+    if args.product_only:
+        print(json.dumps({"product": product_run(e3, synth, torch, dev, args.atoms, args.steps, args.warmup, log)}),
+              flush=True)
         return
     if args.coulomb_only:
         print(json.dumps({"coulomb": coulomb_run(e3, synth, torch, dev, args.steps, args.warmup, log)}), flush=True)
@@ -362,6 +434,7 @@ def main():
         mdp.close()
         extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, log)
         extras["coulomb"] = coulomb_run(e3, synth, torch, dev, max(20, args.steps // 2), args.warmup, log)
+        extras["product"] = product_run(e3, synth, torch, dev, args.atoms, max(20, args.steps // 4), args.warmup, log)
 
     # ---- oracle on the host cores (bounded sample) ----
     cpu = None

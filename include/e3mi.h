@@ -85,7 +85,17 @@ typedef void (*e3mi_free_fn)(void* ptr, void* ctx);
  *   [0, 1) and 0 beyond, k_e = 14.3996 eV A. Each atom's energy carries half
  *   of each of its pair terms. Open structures only: building a graph with a
  *   periodic axis for such a model fails with E3MI_EUNSUPPORTED, and so does
- *   e3mi_param_grad.
+ *   e3mi_param_grad;
+ *   correlation (optional, 1 or 2, default 1): 2 inserts MACE's product block
+ *   of body order 2 (Appendix F: the MACE models use correlation 2) in every
+ *   layer. With A~^l the layer's channel mix (no self connection) for every
+ *   order l <= lmax, per atom of species z and channel k:
+ *     B^L = w1[z, L] A~^L + sum_p w2[z, p] (A~^{l1} (x) A~^{l2})_L
+ *   over the couplings p = (l1 <= l2, L) of the CG table (natural parity,
+ *   ordered by L, then l1, then l2; L <= lmax, only L = 0 in the last layer),
+ *   then h~^L = B^L W_lin,L + h_in^L W_self,L and the gate. Every layer then
+ *   computes every order of A (no fused scalar-only last layer), and
+ *   e3mi_param_grad fails with E3MI_EUNSUPPORTED.
  * Readings of the paper behind each key: Appendix F tables (l_max, channels,
  * layers, num_rbf 8, radial net of 2 hidden layers of 64 with swish,
  * polynomial envelope, gate nonlinearity, readout 16x0e -> 0e, cutoff 5 A).
@@ -97,7 +107,9 @@ typedef void (*e3mi_free_fn)(void* ptr, void* ctx);
  *   emb [n_species, C]
  *   for t = 1..T: rad1 [n_basis, H], rad2 [H, H], rad3 [H, P_t*C] (column p*C + k),
  *                 mix_l3 [P_{t,l3}*C, C] for l3 = 0..lmax (row q*C + k),
- *                 self_l3 [C, C] for each l3 among the layer's input orders
+ *                 self_l3 [C, C] for each l3 among the layer's input orders,
+ *                 with correlation 2 (Lo = 0 for t = T, else lmax; n_p couplings):
+ *                 sym1 [n_species, Lo+1, C], sym2 [n_species, n_p, C], lin_L [C, C] for L = 0..Lo
  *   read1 [C, readout_hidden], read2 [readout_hidden, 1], e0 [n_species]
  *   with coulomb: qhead [C], qbias [n_species]
  */
@@ -294,7 +306,8 @@ size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_
  * forces, md_update, graph_build, first_fwd, first_bwd (the species-factorised
  * first layer), last_fwd, last_bwd (the fused last layer), barostat (volume
  * moves, including their rebuilds and energy passes), coulomb (the
- * all-pairs electrostatics kernel); "name@t" selects
+ * all-pairs electrostatics kernel), product_fwd, product_bwd (the product
+ * block of correlation 2); "name@t" selects
  * interaction layer t.
  * e3mi_profile_query waits for the recorded events and returns the summed
  * milliseconds and the number of timed launches of a stage. */
