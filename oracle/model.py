@@ -21,6 +21,10 @@ Appendix F hyperparameter tables:
   energy       E_s = sum_{i in s} E_i
   forces       F = -dE/dr (§5.2: the Hessian is minus the position
                    derivative of the forces, i.e. forces are -dE/dr)
+  Hessian      (H v)_j = sum_i v_i . d^2 E / dr_i dr_j = d(grad E . v)/dr_j,
+                   the Hessian-vector product of §5.2's full-Hessian equation
+                   (sampled Hessian rows are H v for v = one unit vector per
+                   structure; the full Hessian is 3n such products)
 
 Product block (MACE's symmetric contraction of body order 2; the paper's
 MACE models use correlation 2, Appendix F; the block follows Batatia et al.,
@@ -280,6 +284,18 @@ def energy_forces(model: Model, batch, edge_chunk: Optional[int] = None, edges=N
     E = structure_energies(e_atom, batch.offsets)
     (g,) = torch.autograd.grad(E.sum(), pos)
     return E.detach().numpy(), (-g).numpy(), e_atom.detach().numpy()
+
+
+def hessian_vector(model: Model, batch, v: np.ndarray, edges=None) -> np.ndarray:
+    """H v [N, 3] in FP64 by differentiating grad E . v once more."""
+    dst, src, shv = edges if edges is not None else _edges(batch, model.cfg.cutoff)
+    pos = torch.tensor(batch.pos, dtype=torch.float64, requires_grad=True)
+    species = torch.from_numpy(np.asarray(batch.species, dtype=np.int64))
+    _check_open(model, batch)
+    e_atom = model.node_energies(pos, species, dst, src, shv, None, None, batch.offsets, _total_charge(batch))
+    (g,) = torch.autograd.grad(e_atom.sum(), pos, create_graph=True)
+    (hv,) = torch.autograd.grad((g * torch.as_tensor(v, dtype=torch.float64)).sum(), pos)
+    return hv.numpy()
 
 
 def energy(model: Model, batch, edges=None, edge_chunk: Optional[int] = None) -> np.ndarray:
