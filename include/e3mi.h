@@ -180,6 +180,21 @@ int e3mi_energy_forces(e3mi_model* model, e3mi_graph* graph, const double* pos, 
 int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, const double* grad_energy,
                     const float* grad_forces, double* grad_weights, void* stream);
 
+/* Hessian-vector product of the energy with respect to the positions
+ * (Section 5.2, the full-Hessian equation): hv_j = sum_i H_ji v_i with
+ * H_ij = d^2 E / dr_i dr_j = -dF_i/dr_j, summed over the structures of the
+ * graph (structures do not interact, so H is block diagonal). v and hv:
+ * device FP32 [N, 3] (hv is overwritten). A sampled Hessian row of the
+ * paper's training scheme is hv for v = one unit vector per structure (atom
+ * i_s, Cartesian axis a); the full Hessian of a batch takes 3 max_s N_s
+ * products. Computed like e3mi_param_grad (tangent pass along v, reverse
+ * pass over primal and tangent values) with the reverse pass continued
+ * through every layer's harmonics and radial basis to the positions; no
+ * weight gradients are formed. Errors: E3MI_EUNSUPPORTED for models with the
+ * Coulomb term or the product block. Asynchronous on `stream`. */
+int e3mi_hessian_vector(e3mi_model* model, e3mi_graph* graph, const double* pos, const float* v, float* hv,
+                        void* stream);
+
 /* Evaluation options of a model (bit mask, default 0):
  *   E3MI_FLAG_UNFACTORISED_FIRST_LAYER (1): evaluate the first layer like
  *     the others (per-edge radial weights R and tensor product) instead of

@@ -95,6 +95,50 @@ class Model:
                                     _stream(stream)))
         return out
 
+    def hessian_vector(self, graph: "Graph", pos, v, stream=None):
+        """H v (FP32 device [N, 3]) for a direction v [N, 3]; see e3mi_hessian_vector."""
+        import torch
+        v = v.to(self.device, torch.float32).contiguous()
+        hv = torch.empty_like(v)
+        check(lib().e3mi_hessian_vector(self.handle, graph.handle, ptr(pos.contiguous()), ptr(v), ptr(hv),
+                                        _stream(stream)))
+        return hv
+
+    def hessian_rows(self, graph: "Graph", pos, rows, stream=None):
+        """Sampled Hessian rows (Section 5.2): rows[r, s] is an atom index
+        within structure s; returns [R, 3, N, 3] with out[r, a] = H v for v
+        the sum over structures of the unit vectors (atom rows[r, s], axis a),
+        i.e. every structure's Hessian row of that atom and axis."""
+        import torch
+        rows = np.asarray(rows, dtype=np.int64).reshape(-1, graph.n_structures)
+        off = graph.offsets
+        if np.any(rows < 0) or np.any(rows >= np.diff(off)[None, :]):
+            raise ValueError("row atom index outside its structure")
+        out = torch.empty((rows.shape[0], 3, graph.n_atoms, 3), dtype=torch.float32, device=self.device)
+        for r in range(rows.shape[0]):
+            for a in range(3):
+                v = torch.zeros((graph.n_atoms, 3), dtype=torch.float32, device=self.device)
+                v[torch.as_tensor(off[:-1] + rows[r], device=self.device), a] = 1.0
+                out[r, a] = self.hessian_vector(graph, pos, v, stream)
+        return out
+
+    def hessian(self, graph: "Graph", pos, stream=None):
+        """Full Hessian of every structure (list of FP32 [3 N_s, 3 N_s]) from
+        3 max_s N_s Hessian-vector products, each probing one coordinate of
+        every structure at once."""
+        import torch
+        off = graph.offsets
+        sizes = np.diff(off)
+        out = [torch.empty((3 * n, 3 * n), dtype=torch.float32, device=self.device) for n in sizes]
+        for k in range(3 * int(sizes.max(initial=0))):
+            have = np.nonzero(sizes > k // 3)[0]
+            v = torch.zeros((graph.n_atoms, 3), dtype=torch.float32, device=self.device)
+            v[torch.as_tensor(off[have] + k // 3, device=self.device), k % 3] = 1.0
+            hv = self.hessian_vector(graph, pos, v, stream)
+            for s in have:
+                out[s][:, k] = hv[off[s]:off[s + 1]].reshape(-1)
+        return out
+
     def footprint_bytes(self, n_atoms: int, n_edges: int) -> int:
         return int(lib().e3mi_footprint_bytes(self.handle, n_atoms, n_edges))
 
@@ -127,6 +171,7 @@ class Graph:
         pbc = np.ascontiguousarray(pbc, dtype=np.uint8).reshape(-1, 3)
         self.n_structures = len(off) - 1
         self.n_atoms = int(off[-1])
+        self.offsets = off
         assert cell.shape[0] == self.n_structures and pbc.shape[0] == self.n_structures
         pos = pos.contiguous()
         self._species = species.to(torch.int32).contiguous()

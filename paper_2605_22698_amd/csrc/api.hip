@@ -205,6 +205,7 @@ struct Workspace {
   std::unique_ptr<DevBuf> G1, dG1;  // first layer, [N, (l3+1)^2, S*64]
   std::unique_ptr<DevBuf> q_raw, q, pot, fc, pot_mean;  // electrostatics: charges, potential, forces
   std::vector<std::unique_ptr<DevBuf>> at;             // product block: A~ per layer
+  std::unique_ptr<DevBuf> Ygb, Ygc, ghv, zeroE;        // Hessian-vector products
   std::unique_ptr<DevBuf> Bp, dat;                     // product block: B (or dB), dA~
 };
 
@@ -1242,11 +1243,14 @@ e3mi_model* new_model(const char* json, const double* wts, size_t n, int precisi
 }
 
 
-// Gradient of sum_s gE_s E_s - D_v E (v = gF) with respect to every weight:
-// the vector-Jacobian product of (E, F) -> weights for upstream (gE, gF).
-// Forward (primal + tangent along v), then the reverse pass over both.
-void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* gE, const float* gF, double* out,
-                hipStream_t st) {
+// Second-order pass for s = sum_s gE_s E_s - D_v E (v = gF): forward (primal
+// + tangent along v), then the reverse pass over both. out (may be NULL): the
+// gradient of s with respect to every weight, i.e. the vector-Jacobian
+// product of (E, F) -> weights for upstream (gE, gF). hv (may be NULL):
+// -ds/dr, which for gE = 0 is the Hessian-vector product H v (the reverse pass
+// is continued through each layer's edge geometry).
+void second_order(e3mi_model* M, e3mi_graph* G, const double* pos, const double* gE, const float* gF, double* out,
+                  float* hv, hipStream_t st) {
   const Config& c = M->cfg;
   Allocator* a = &M->alloc;
   const int N = G->N, C = c.channels, T = c.layers, H = c.radial_hidden;
@@ -1256,10 +1260,12 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
   const float rc = (float)c.cutoff;
   const int p_env = c.envelope_p;
   Workspace& w = M->ws;
-  E3MI_REQUIRE(!c.coulomb, E3MI_EUNSUPPORTED, "parameter gradients of the Coulomb term are not implemented");
-  E3MI_REQUIRE(c.correlation == 1, E3MI_EUNSUPPORTED, "parameter gradients of the product block are not implemented");
+  E3MI_REQUIRE(!c.coulomb, E3MI_EUNSUPPORTED,
+               "second-order passes (parameter gradients, Hessian-vector products) of the Coulomb term are not implemented");
+  E3MI_REQUIRE(c.correlation == 1, E3MI_EUNSUPPORTED,
+               "second-order passes (parameter gradients, Hessian-vector products) of the product block are not implemented");
   const WeightOffsets off = weight_offsets(c);
-  E3MI_HIP(hipMemsetAsync(out, 0, sizeof(double) * off.total, st));
+  if (out) E3MI_HIP(hipMemsetAsync(out, 0, sizeof(double) * off.total, st));
   if (N == 0) return;
   forward_pass(M, G, pos, true, st, false);
   const int* row_ptr = G->row_ptr_x->as<int>();
@@ -1291,6 +1297,10 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
   for (auto* v : {&w.P1g, &w.P2g}) ensure(*v, a, sizeof(float) * E1 * 2 * H);
   ensure(w.partial, a, sizeof(float) * std::max<size_t>(16u << 20, (size_t)H * pc_max));
   float* partial = w.partial->as<float>();
+  if (hv) {
+    for (auto* v : {&w.Ygb, &w.Ygc}) ensure(*v, a, sizeof(float) * E1 * 16);
+    ensure(w.ghv, a, sizeof(float4) * E1);
+  }
 
   // ---- tangent forward along v = gF ----
   launch_edge_tangent(row_ptr, src, dvec, gF, N, w.dd->as<float4>(), st);
@@ -1337,11 +1347,13 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
   launch_readout_dual(w.h[T]->as<float>(), w.hd[T]->as<float>(), ncT, G->owner->as<int>(), gE, M->read1->as<float>(),
                       M->read2->as<float>(), N, C, w.Prb->as<float>(), w.Prc->as<float>(), w.w2c->as<float>(), hb, hc,
                       w.eb->as<float>(), st);
-  launch_gemm_tn(RowMap{w.h[T]->as<float>(), (long)ncT * C, 0, 1}, RowMap{w.Prb->as<float>(), 16, 0, 1},
-                 RowMap{w.hd[T]->as<float>(), (long)ncT * C, 0, 1}, RowMap{w.Prc->as<float>(), 16, 0, 1}, N, nullptr,
-                 C, 16, partial, out + off.read1, 16, st);
-  launch_group_sum(w.w2c->as<float>(), 16, nullptr, 1, N, 16, out + off.read2, 16, st);
-  launch_group_sum(w.eb->as<float>(), 1, G->species->as<int>(), c.n_species, N, 1, out + off.e0, 1, st);
+  if (out) {
+    launch_gemm_tn(RowMap{w.h[T]->as<float>(), (long)ncT * C, 0, 1}, RowMap{w.Prb->as<float>(), 16, 0, 1},
+                   RowMap{w.hd[T]->as<float>(), (long)ncT * C, 0, 1}, RowMap{w.Prc->as<float>(), 16, 0, 1}, N,
+                   nullptr, C, 16, partial, out + off.read1, 16, st);
+    launch_group_sum(w.w2c->as<float>(), 16, nullptr, 1, N, 16, out + off.read2, 16, st);
+    launch_group_sum(w.eb->as<float>(), 1, G->species->as<int>(), c.n_species, N, 1, out + off.e0, 1, st);
+  }
 
   // ---- reverse: layers ----
   float* xb = w.xb->as<float>();
@@ -1355,7 +1367,7 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
     launch_gate_dual_bwd(w.ht[t]->as<float>(), w.htd[t]->as<float>(), hb, hc, xb, xc, N, L.nc_out, C, st);
     // weight gradients of the channel mix and the self connection
     long gbase = 0;
-    for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
+    for (int l3 = 0; l3 <= (out ? L.l3max_used : -1); ++l3) {
       const int P3 = L.p_used_l3[l3], g = 2 * l3 + 1;
       const RowMap xbr{xb + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
       const RowMap xcr{xc + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
@@ -1405,6 +1417,19 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
     launch_radial_dual_bwd(row_ptr, N, Ecap, W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.Rb->as<float>(),
                            w.Rc->as<float>(), w.P1d[t]->as<float>(), w.P2d[t]->as<float>(), w.P1g->as<float>(),
                            w.P2g->as<float>(), st);
+    if (hv) {
+      // continue to the positions through the harmonics and the radial basis
+      ta.Yb = w.Ygb->as<float>();
+      ta.Yc = w.Ygc->as<float>();
+      launch_tp(6, ta, st);
+      launch_hvp_geo(c.lmax, row_ptr, N, Ecap, dvec, dd, w.Ygb->as<float>(), w.Ygc->as<float>(), w.P1g->as<float>(),
+                     W.rad1.as<float>(), rc, p_env, t != T ? 1 : 0, w.ghv->as<float4>(), st);
+    }
+    if (!out) {
+      std::swap(hb, hb2);
+      std::swap(hc, hc2);
+      continue;
+    }
     float* H2d = w.H2d[t]->as<float>();
     float* H1d = w.H1d[t]->as<float>();
     float* Bd = w.Bd->as<float>();
@@ -1422,7 +1447,24 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
     std::swap(hc, hc2);
   }
   // embedding: h^0_i = W_emb[z_i]
-  launch_group_sum(hb, C, G->species->as<int>(), c.n_species, N, C, out + off.emb, C, st);
+  if (out) launch_group_sum(hb, C, G->species->as<int>(), c.n_species, N, C, out + off.emb, C, st);
+  if (hv) launch_forces(row_ptr, G->rev_x->as<int>(), w.ghv->as<float4>(), N, hv, st);
+}
+
+void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* gE, const float* gF, double* out,
+                hipStream_t st) {
+  E3MI_REQUIRE(out, E3MI_EINVAL, "null output");
+  second_order(M, G, pos, gE, gF, out, nullptr, st);
+}
+
+// H v = d(grad E . v)/dr: the second-order pass with no energy seed, continued
+// to the positions.
+void hessian_vector(e3mi_model* M, e3mi_graph* G, const double* pos, const float* v, float* hv, hipStream_t st) {
+  E3MI_REQUIRE(v && hv, E3MI_EINVAL, "null argument");
+  Workspace& w = M->ws;
+  ensure(w.zeroE, &M->alloc, sizeof(double) * (size_t)std::max(G->S, 1));
+  E3MI_HIP(hipMemsetAsync(w.zeroE->p, 0, sizeof(double) * (size_t)std::max(G->S, 1), st));
+  second_order(M, G, pos, w.zeroE->as<double>(), v, nullptr, hv, st);
 }
 
 // Replace the weights of a model (same configuration), e.g. after an optimiser step.
@@ -1814,6 +1856,17 @@ int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, con
   E3MI_REQUIRE(graph->model == model, E3MI_EINVAL, "graph was built for another model");
   E3MI_REQUIRE(graph->N == 0 || pos, E3MI_EINVAL, "null positions");
   e3mi::param_grad(model, graph, pos, grad_energy, grad_forces, grad_weights, e3mi::as_stream(stream));
+  E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_hessian_vector(e3mi_model* model, e3mi_graph* graph, const double* pos, const float* v, float* hv,
+                        void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model && graph, E3MI_EINVAL, "null argument");
+  E3MI_REQUIRE(graph->model == model, E3MI_EINVAL, "graph was built for another model");
+  E3MI_REQUIRE(graph->N == 0 || (pos && v && hv), E3MI_EINVAL, "null positions, vector or output");
+  if (graph->N) e3mi::hessian_vector(model, graph, pos, v, hv, e3mi::as_stream(stream));
   E3MI_HIP(hipGetLastError());
   E3MI_API_END
 }

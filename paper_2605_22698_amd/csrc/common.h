@@ -98,6 +98,31 @@ __device__ __forceinline__ void real_sh_vjp(float x, float y, float z, const flo
 }
 
 
+// Directional derivative of real_sh_vjp along u: H u with H = sum_c dY[c]
+// times the Hessian of the polynomial P_c at (x, y, z).
+template <int LMAX>
+__device__ __forceinline__ void real_sh_vjp_jvp(float x, float y, float z, float ux, float uy, float uz,
+                                                const float* dY, float& hx, float& hy, float& hz) {
+  hx = hy = hz = 0.0f;
+  if constexpr (LMAX >= 2) {
+    constexpr float s15 = 3.872983346207417f, s5h = 1.118033988749895f;
+    hx += s15 * (uy * dY[4] + uz * dY[7] + ux * dY[8]);
+    hy += s15 * (ux * dY[4] + uz * dY[5] - uy * dY[8]);
+    hz += s15 * (uy * dY[5] + ux * dY[7]) + 6.0f * s5h * uz * dY[6];
+  }
+  if constexpr (LMAX >= 3) {
+    constexpr float a358 = 2.091650066335189f, s105 = 10.246950765959598f;
+    constexpr float a218 = 1.620185174601965f, s7h = 1.3228756555322954f;
+    const float xy_d = ux * y + x * uy, xx_yy_d = 2.0f * (x * ux - y * uy);
+    hx += a358 * (6.0f * xy_d * dY[9] + 3.0f * xx_yy_d * dY[15]) +
+          s105 * ((uy * z + y * uz) * dY[10] + (ux * z + x * uz) * dY[14]) + a218 * 10.0f * z * uz * dY[13];
+    hy += a358 * (3.0f * xx_yy_d * dY[9] - 6.0f * xy_d * dY[15]) +
+          s105 * ((ux * z + x * uz) * dY[10] - (uy * z + y * uz) * dY[14]) + a218 * 10.0f * z * uz * dY[11];
+    hz += s105 * xy_d * dY[10] + 10.0f * a218 * (uz * (y * dY[11] + x * dY[13]) + z * (uy * dY[11] + ux * dY[13])) +
+          s7h * 30.0f * z * uz * dY[12] + 0.5f * s105 * xx_yy_d * dY[14];
+  }
+}
+
 // Directional derivative of every harmonic polynomial along u:
 // Yd[c] = grad P_c(x, y, z) . u (the caller passes the tangential part of the
 // direction change, u = (I - n n^T) d_dot / r).

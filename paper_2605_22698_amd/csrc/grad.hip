@@ -209,6 +209,111 @@ __global__ void k_reduce_partials(const float* __restrict__ partial, int chunks,
   out[(idx / no) * ld_out + idx % no] = s;
 }
 
+// Bessel x envelope basis with its first and second radial derivatives
+// (r inside the cutoff).
+template <int NB>
+__device__ __forceinline__ void radial_basis_d2(float r, float rc, int p, float* B, float* dB, float* d2B) {
+  const float x = r / rc;
+  float xp2 = 1.0f;  // x^(p-2)
+  for (int k = 0; k < p - 2; ++k) xp2 *= x;
+  const float xp1 = xp2 * x, xp = xp1 * x;
+  const float fp = (float)p, c3 = 0.5f * fp * (fp + 1.0f) * (fp + 2.0f);
+  const float u = 1.0f - 0.5f * (fp + 1.0f) * (fp + 2.0f) * xp + fp * (fp + 2.0f) * xp * x -
+                  0.5f * fp * (fp + 1.0f) * xp * x * x;
+  const float om = 1.0f - x;
+  const float du = -c3 * xp1 * om * om / rc;
+  const float d2u = -c3 * ((fp - 1.0f) * xp2 * om * om - 2.0f * xp1 * om) / (rc * rc);
+  const float pref = sqrtf(2.0f / rc);
+  const float ir = 1.0f / r;
+  const float w = 3.14159265358979f / rc;
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    const float kk = (n + 1) * w;
+    float s, c;
+    sincosf(kk * r, &s, &c);
+    const float b = pref * s * ir;
+    const float b1 = pref * (kk * c * ir - s * ir * ir);
+    const float b2 = pref * (-kk * kk * s * ir - 2.0f * kk * c * ir * ir + 2.0f * s * ir * ir * ir);
+    B[n] = b * u;
+    dB[n] = b1 * u + b * du;
+    d2B[n] = b2 * u + 2.0f * b1 * du + b * d2u;
+  }
+}
+
+// Per-edge position adjoint of the second-order scalar s (the Hessian-vector
+// pass: s = -D_v E) through the edge geometry of one layer. With n = d/r,
+// the tangent d_dot, r_dot = n . d_dot, P = I - n n^T and u = P d_dot / r:
+//   harmonics  Y = P_c(n), Y_dot = grad P_c(n) . u, adjoints Yb, Yc:
+//     g += P G1 / r + P (H u) / r - r_dot/r^2 P G2 - (G2 . n)/r^2 P d_dot - (G2 . P d_dot)/r^2 n
+//     G1 = sum Yb grad P, G2 = sum Yc grad P, H = sum Yc hess P
+//   basis      B(r), B_dot = B'(r) r_dot, adjoints Bb = W1 P1b, Bc = W1 P1c:
+//     g += (Bb . B' + r_dot Bc . B'') n + (Bc . B') P d_dot / r
+// One thread per edge; g accumulates over the layers.
+template <int LMAX>
+__global__ void __launch_bounds__(256) k_hvp_geo(const int* __restrict__ row_ptr_x, int N,
+                                                 const float4* __restrict__ dvec, const float4* __restrict__ dd,
+                                                 const float* __restrict__ Yb, const float* __restrict__ Yc,
+                                                 const float* __restrict__ P1g, const float* __restrict__ W1,
+                                                 float rc, int p, int accumulate, float4* __restrict__ g) {
+  __shared__ float w1s[8 * 64];
+  for (int q = threadIdx.x; q < 8 * 64; q += blockDim.x) w1s[q] = W1[q];
+  __syncthreads();
+  const int E = row_ptr_x[N];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  constexpr int NY = (LMAX + 1) * (LMAX + 1);
+  const float4 d = dvec[e], t = dd[e];
+  const float r = d.w, ir = 1.0f / r;
+  const float nx = d.x * ir, ny = d.y * ir, nz = d.z * ir;
+  const float rd = t.w;
+  const float px = t.x - nx * rd, py = t.y - ny * rd, pz = t.z - nz * rd;  // P d_dot
+  float yb[NY], yc[NY];
+#pragma unroll
+  for (int q = 0; q < NY; ++q) {
+    yb[q] = Yb[(long)e * 16 + q];
+    yc[q] = Yc[(long)e * 16 + q];
+  }
+  float g1x, g1y, g1z, g2x, g2y, g2z, hx, hy, hz;
+  real_sh_vjp<LMAX>(nx, ny, nz, yb, g1x, g1y, g1z);
+  real_sh_vjp<LMAX>(nx, ny, nz, yc, g2x, g2y, g2z);
+  real_sh_vjp_jvp<LMAX>(nx, ny, nz, px * ir, py * ir, pz * ir, yc, hx, hy, hz);
+  // P applied to (G1 + H u) / r - r_dot / r^2 G2
+  const float ax = (g1x + hx) * ir - rd * ir * ir * g2x;
+  const float ay = (g1y + hy) * ir - rd * ir * ir * g2y;
+  const float az = (g1z + hz) * ir - rd * ir * ir * g2z;
+  const float an = ax * nx + ay * ny + az * nz;
+  const float g2n = g2x * nx + g2y * ny + g2z * nz;
+  const float g2p = g2x * px + g2y * py + g2z * pz;
+  float gx = ax - an * nx - g2n * ir * ir * px - g2p * ir * ir * nx;
+  float gy = ay - an * ny - g2n * ir * ir * py - g2p * ir * ir * ny;
+  float gz = az - an * nz - g2n * ir * ir * pz - g2p * ir * ir * nz;
+  // radial basis
+  float B[8], dB[8], d2B[8];
+  radial_basis_d2<8>(r, rc, p, B, dB, d2B);
+  const float* pb = P1g + (long)e * 128;
+  float sr = 0.0f, sd = 0.0f;  // coefficients of n and of P d_dot / r
+  for (int n = 0; n < 8; ++n) {
+    float bb = 0.0f, bc = 0.0f;
+#pragma unroll 8
+    for (int q = 0; q < 64; ++q) {
+      bb += w1s[n * 64 + q] * pb[q];
+      bc += w1s[n * 64 + q] * pb[64 + q];
+    }
+    sr += bb * dB[n] + rd * bc * d2B[n];
+    sd += bc * dB[n];
+  }
+  gx += sr * nx + sd * px * ir;
+  gy += sr * ny + sd * py * ir;
+  gz += sr * nz + sd * pz * ir;
+  if (accumulate) {
+    const float4 o = g[e];
+    gx += o.x;
+    gy += o.y;
+    gz += o.z;
+  }
+  g[e] = make_float4(gx, gy, gz, 0.0f);
+}
+
 }  // namespace
 
 void launch_edge_tangent(const int* row_ptr, const int* src, const float4* dvec, const float* v, int N, float4* dd,
@@ -257,6 +362,19 @@ void launch_gemm_tn(RowMap x1, RowMap y1, RowMap x2, RowMap y2, long rows, const
     k_gemm_tn<<<grid, 256, 0, st>>>(x1, y1, x2, y2, (int)rows, rows_dev, mo, no, chunk_rows, partial);
     k_reduce_partials<<<blocks((long)mo * no, 256), 256, 0, st>>>(partial, chunks, mo, no, out, ld_out);
   }
+}
+
+void launch_hvp_geo(int lmax, const int* row_ptr_x, int N, long e_cap, const float4* dvec, const float4* dd,
+                    const float* Yb, const float* Yc, const float* P1g, const float* W1, float rc, int p,
+                    int accumulate, float4* g, hipStream_t st) {
+  if (e_cap == 0) return;
+  const int grid = blocks(e_cap, 256);
+  if (lmax == 3)
+    k_hvp_geo<3><<<grid, 256, 0, st>>>(row_ptr_x, N, dvec, dd, Yb, Yc, P1g, W1, rc, p, accumulate, g);
+  else if (lmax == 2)
+    k_hvp_geo<2><<<grid, 256, 0, st>>>(row_ptr_x, N, dvec, dd, Yb, Yc, P1g, W1, rc, p, accumulate, g);
+  else
+    throw Error(E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
 }
 
 }  // namespace e3mi

@@ -219,10 +219,13 @@ struct TpArgs {
   float* Rc;         // out: adjoint of the tangent of R
   float* hb;         // in/out (+=): adjoint of h
   float* hc;         // in/out (+=): adjoint of the tangent of h (NULL: not needed)
+  float* Yb;         // out: adjoint of the harmonics per edge [E, 16]
+  float* Yc;         // out: adjoint of the harmonics' tangent per edge [E, 16]
 };
 // which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...),
 //        3 tangent forward (Ad), 4 second-order edge adjoint (Rb, Rc),
-//        5 second-order node adjoint (hb, hc += ...)
+//        5 second-order node adjoint (hb, hc += ...),
+//        6 adjoints of the harmonics and their tangent (Yb, Yc) for Hessian-vector products
 void launch_tp(int which, const TpArgs& a, hipStream_t st);
 
 // ---- per-atom stages (node.hip) -----------------------------------------------------
@@ -255,6 +258,12 @@ void launch_readout(const float* h, int nc, const int* species, const float* Wr,
 void launch_energy(const double* e_atom, const int64_t* off, int S, double* energy, hipStream_t st);
 void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st,
                    const float* extra = nullptr);
+
+// Hessian-vector products (grad.hip): per-edge position adjoint of the
+// second-order scalar through one layer's edge geometry, g (+)= ...
+void launch_hvp_geo(int lmax, const int* row_ptr_x, int N, long e_cap, const float4* dvec, const float4* dd,
+                    const float* Yb, const float* Yc, const float* P1g, const float* W1, float rc, int p,
+                    int accumulate, float4* g, hipStream_t st);
 
 // ---- product block of body order 2 (product.hip) -------------------------------------
 struct ProductArgs {

@@ -464,6 +464,117 @@ __global__ void __launch_bounds__(256) k_tp_dual_bwd_node(const int* __restrict_
   }
 }
 
+// Adjoints of the harmonics and of their tangent for the Hessian-vector
+// product: with eb = ab R + ac R_dot and ec = ac R per (path, output, channel),
+//   Yb[l2 m2] = sum C (eb h[l1 m1] + ec h_dot[l1 m1]),  Yc[l2 m2] = sum C ec h[l1 m1]
+// summed over paths, CG entries and the channels of the workgroup; one row
+// [16] of each per edge.
+template <int LMAX, int KIND, int CPT>
+__global__ void __launch_bounds__(256) k_tp_dual_geo(const int* __restrict__ row_ptr, const int* __restrict__ src,
+                                                     const float* __restrict__ R, const float* __restrict__ Rd,
+                                                     int r_stride, const float* __restrict__ h,
+                                                     const float* __restrict__ hd, int h_nc,
+                                                     const float* __restrict__ Ab, const float* __restrict__ Ac,
+                                                     float* __restrict__ Yb, float* __restrict__ Yc, int N, int C,
+                                                     float inv_nu) {
+  using PS = PathSet<LMAX, KIND>;
+  constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
+  __shared__ float red[4][2 * 16];
+  const int i = blockIdx.x;
+  const int tpr = blockDim.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float ab[CPT][NOUT], ac[CPT][NOUT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int k = threadIdx.x + c * tpr;
+    static_for<NP>([&](auto pi) {
+      constexpr int g = PS::T.id[pi];
+      constexpr int l3 = kL3[g];
+      constexpr int off = PS::T.off[pi], rank = PS::T.rank[pi];
+      constexpr int P3 = PS::T.np_l3[l3];
+      const long gb = a_group_base<PS>(l3, N, C);
+#pragma unroll
+      for (int m = 0; m < 2 * l3 + 1; ++m) {
+        const long idx = gb + (((long)i * (2 * l3 + 1) + m) * P3 + rank) * C + k;
+        ab[c][off + m] = Ab[idx] * inv_nu;
+        ac[c][off + m] = Ac[idx] * inv_nu;
+      }
+    });
+  }
+  const int e1 = row_ptr[i + 1];
+  for (int e = row_ptr[i]; e < e1; ++e) {
+    const int j = src[e];
+    const float* Re = R + (long)e * r_stride;
+    const float* Rde = Rd + (long)e * r_stride;
+    const float* hj = h + (long)j * h_nc * C;
+    const float* hdj = hd ? hd + (long)j * h_nc * C : nullptr;
+    float yb[NY], yc[NY];
+#pragma unroll
+    for (int q = 0; q < NY; ++q) yb[q] = yc[q] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const int k = threadIdx.x + c * tpr;
+      float hv[NIN], hdv[NIN];
+#pragma unroll
+      for (int q = 0; q < NIN; ++q) {
+        hv[q] = hj[q * C + k];
+        hdv[q] = hdj ? hdj[q * C + k] : 0.0f;
+      }
+      static_for<NP>([&](auto pi) {
+        constexpr int g = PS::T.id[pi];
+        constexpr int l1 = kL1[g], l2 = kL2[g];
+        constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
+        constexpr int off = PS::T.off[pi];
+        const float rp = Re[pi * C + k], rdp = Rde[pi * C + k];
+        static_for<nz>([&](auto z) {
+          constexpr int q = z0 + z;
+          const float eb = kC[q] * (ab[c][off + kM3[q]] * rp + ac[c][off + kM3[q]] * rdp);
+          const float ec = kC[q] * (ac[c][off + kM3[q]] * rp);
+          yb[l2 * l2 + kM2[q]] += eb * hv[l1 * l1 + kM1[q]] + ec * hdv[l1 * l1 + kM1[q]];
+          yc[l2 * l2 + kM2[q]] += ec * hv[l1 * l1 + kM1[q]];
+        });
+      });
+    }
+    // reduce over the channels of the workgroup
+    if (tpr >= 64) {
+#pragma unroll
+      for (int q = 0; q < NY; ++q) {
+        yb[q] = group_sum<64>(yb[q]);
+        yc[q] = group_sum<64>(yc[q]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NY; ++q) {
+          red[wave][q] = yb[q];
+          red[wave][16 + q] = yc[q];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NY; ++q) {
+        yb[q] = group_sum<32>(yb[q]);
+        yc[q] = group_sum<32>(yc[q]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NY; ++q) {
+          red[0][q] = yb[q];
+          red[0][16 + q] = yc[q];
+        }
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * 16) {
+      const int q = threadIdx.x & 15;
+      float v = 0.0f;
+      if (q < NY)
+        for (int w = 0; w < (tpr + 63) / 64; ++w) v += red[w][threadIdx.x];
+      (threadIdx.x < 16 ? Yb : Yc)[(long)e * 16 + q] = v;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 // ---- dispatch ---------------------------------------------------------------
@@ -487,9 +598,12 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
   else if (which == 4)
     k_tp_dual_bwd_edge<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.r_stride, a.h, a.hd,
                                                               a.h_nc, a.Ab, a.Ac, a.Rb, a.Rc, a.N, a.C, a.inv_nu);
-  else
+  else if (which == 5)
     k_tp_dual_bwd_node<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.R, a.Rd, a.r_stride,
                                                               a.Ab, a.Ac, a.hb, a.hc, a.dh_nc, a.N, a.C, a.inv_nu);
+  else
+    k_tp_dual_geo<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.R, a.Rd, a.r_stride, a.h, a.hd, a.h_nc,
+                                                         a.Ab, a.Ac, a.Yb, a.Yc, a.N, a.C, a.inv_nu);
 }
 
 template <int LMAX, int KIND>
