@@ -217,6 +217,48 @@ def product_run(e3, synth, torch, dev, n_atoms, steps, warmup, log):
     return out
 
 
+def hessian_run(e3, synth, torch, dev, n_atoms, reps, log):
+    """Hessian-vector products: full Hessians of a batch of small open
+    molecules (at most 31 atoms, the sizes of the paper's Hessian study) from
+    3 max N_s products, against energy+forces of the same batch; and one
+    product on the single-structure box."""
+    rng = synth.seed_for(7)
+    sizes = rng.integers(10, 32, size=64)
+    b = synth.concat([synth.open_box(int(n), 4, rng) for n in sizes])
+    cfg1, box = synth.single_config(n=n_atoms)
+    cfg = cfg1
+    m = e3.Model(cfg.to_json(), synth.flatten_weights(cfg, synth.model_weights(cfg, 2)), device=dev)
+    pos = torch.tensor(b.pos, dtype=torch.float64, device=dev)
+    g = m.build_graph(b.offsets, pos, torch.tensor(b.species, dtype=torch.int32, device=dev), b.cell, b.pbc,
+                      cfg.cutoff, 0.0)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / k
+    t_ef = timed(lambda: m.energy_forces(g, pos), reps)
+    t_h = timed(lambda: m.hessian(g, pos), max(1, reps // 10))
+    out = {"workload": f"full Hessians of {b.n_structures} open molecules of 10-31 atoms ({b.n_atoms} atoms), "
+                       f"l_max 3, 128 channels, 2 layers, r_c 5 A; {3 * int(sizes.max())} products per batch",
+           "structures_per_s": b.n_structures / t_h, "ms_per_batch": 1e3 * t_h,
+           "ms_energy_forces_per_batch": 1e3 * t_ef, "hessian_over_energy_forces": t_h / t_ef,
+           "ms_per_product": 1e3 * t_h / (3 * int(sizes.max()))}
+    posb = torch.tensor(box.pos, dtype=torch.float64, device=dev)
+    gb = m.build_graph(box.offsets, posb, torch.tensor(box.species, dtype=torch.int32, device=dev), box.cell,
+                       box.pbc, cfg.cutoff, 0.0)
+    v = torch.tensor(np.random.default_rng(5).normal(size=box.pos.shape), dtype=torch.float32, device=dev)
+    out["ms_per_product_box"] = 1e3 * timed(lambda: m.hessian_vector(gb, posb, v), reps)
+    out["ms_energy_forces_box"] = 1e3 * timed(lambda: m.energy_forces(gb, posb), reps)
+    out["box"] = f"{box.n_atoms}-atom periodic box of the main workload"
+    log(f"hessian: {out['structures_per_s']:.1f} full Hessians/s ({out['hessian_over_energy_forces']:.1f}x E+F); "
+        f"H v on the box {out['ms_per_product_box']:.2f} ms vs E+F {out['ms_energy_forces_box']:.2f} ms")
+    return out
+
+
 COULOMB_FLOPS_PER_PAIR = 20  # distance 8, rsqrt 1, potential 2, force factor 3, force 6
 
 
@@ -296,6 +338,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=16)
     ap.add_argument("--coulomb-only", action="store_true",
                     help="only run the electrostatics measurement (for profiling its kernels)")
+    ap.add_argument("--hessian-only", action="store_true",
+                    help="only run the Hessian-vector-product measurement (for profiling its kernels)")
     ap.add_argument("--product-only", action="store_true",
                     help="only run the product-block measurement (for profiling its kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -319,6 +363,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read_per_launch": src.numel() * 4,
                           "bytes_written_per_launch": dst.numel() * 4, "launches": 10}), flush=True)
+        return
+    if args.hessian_only:
+        print(json.dumps({"hessian": hessian_run(e3, synth, torch, dev, args.atoms, args.steps, log)}), flush=True)
         return
     if args.product_only:
         print(json.dumps({"product": product_run(e3, synth, torch, dev, args.atoms, args.steps, args.warmup, log)}),
@@ -435,6 +482,7 @@ def main():
         extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, log)
         extras["coulomb"] = coulomb_run(e3, synth, torch, dev, max(20, args.steps // 2), args.warmup, log)
         extras["product"] = product_run(e3, synth, torch, dev, args.atoms, max(20, args.steps // 4), args.warmup, log)
+        extras["hessian"] = hessian_run(e3, synth, torch, dev, args.atoms, 20, log)
 
     # ---- oracle on the host cores (bounded sample) ----
     cpu = None

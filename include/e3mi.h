@@ -195,6 +195,13 @@ int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, con
 int e3mi_hessian_vector(e3mi_model* model, e3mi_graph* graph, const double* pos, const float* v, float* hv,
                         void* stream);
 
+/* n_vec Hessian-vector products at the same positions: v and hv are device
+ * FP32 [n_vec, N, 3]; hv[k] = H v[k]. The primal forward pass runs once and
+ * each direction costs one tangent and one reverse pass. Same errors as
+ * e3mi_hessian_vector. */
+int e3mi_hessian_vectors(e3mi_model* model, e3mi_graph* graph, const double* pos, int n_vec, const float* v,
+                         float* hv, void* stream);
+
 /* Evaluation options of a model (bit mask, default 0):
  *   E3MI_FLAG_UNFACTORISED_FIRST_LAYER (1): evaluate the first layer like
  *     the others (per-edge radial weights R and tensor product) instead of

@@ -104,40 +104,50 @@ class Model:
                                         _stream(stream)))
         return hv
 
+    def hessian_vectors(self, graph: "Graph", pos, V, stream=None):
+        """H V[k] for every direction (V: [K, N, 3]; FP32 device result of the
+        same shape); see e3mi_hessian_vectors."""
+        import torch
+        V = V.to(self.device, torch.float32).contiguous()
+        HV = torch.empty_like(V)
+        check(lib().e3mi_hessian_vectors(self.handle, graph.handle, ptr(pos.contiguous()), V.shape[0], ptr(V),
+                                         ptr(HV), _stream(stream)))
+        return HV
+
+    def _unit_directions(self, graph: "Graph", atoms):
+        """[K, N, 3] directions: direction k has, for every structure s with
+        atoms[k, s] >= 0, a unit entry at (that atom of s, axis k % 3)."""
+        import torch
+        K, S = atoms.shape
+        kk, ss = np.nonzero(atoms >= 0)
+        V = torch.zeros((K, graph.n_atoms, 3), dtype=torch.float32, device=self.device)
+        if len(kk):
+            idx = torch.as_tensor(np.stack([kk, graph.offsets[ss] + atoms[kk, ss], kk % 3]), device=self.device)
+            V[idx[0], idx[1], idx[2]] = 1.0
+        return V
+
     def hessian_rows(self, graph: "Graph", pos, rows, stream=None):
         """Sampled Hessian rows (Section 5.2): rows[r, s] is an atom index
         within structure s; returns [R, 3, N, 3] with out[r, a] = H v for v
         the sum over structures of the unit vectors (atom rows[r, s], axis a),
         i.e. every structure's Hessian row of that atom and axis."""
-        import torch
         rows = np.asarray(rows, dtype=np.int64).reshape(-1, graph.n_structures)
-        off = graph.offsets
-        if np.any(rows < 0) or np.any(rows >= np.diff(off)[None, :]):
+        if np.any(rows < 0) or np.any(rows >= np.diff(graph.offsets)[None, :]):
             raise ValueError("row atom index outside its structure")
-        out = torch.empty((rows.shape[0], 3, graph.n_atoms, 3), dtype=torch.float32, device=self.device)
-        for r in range(rows.shape[0]):
-            for a in range(3):
-                v = torch.zeros((graph.n_atoms, 3), dtype=torch.float32, device=self.device)
-                v[torch.as_tensor(off[:-1] + rows[r], device=self.device), a] = 1.0
-                out[r, a] = self.hessian_vector(graph, pos, v, stream)
-        return out
+        V = self._unit_directions(graph, np.repeat(rows, 3, axis=0))
+        return self.hessian_vectors(graph, pos, V, stream).view(rows.shape[0], 3, graph.n_atoms, 3)
 
     def hessian(self, graph: "Graph", pos, stream=None):
         """Full Hessian of every structure (list of FP32 [3 N_s, 3 N_s]) from
         3 max_s N_s Hessian-vector products, each probing one coordinate of
         every structure at once."""
-        import torch
         off = graph.offsets
         sizes = np.diff(off)
-        out = [torch.empty((3 * n, 3 * n), dtype=torch.float32, device=self.device) for n in sizes]
-        for k in range(3 * int(sizes.max(initial=0))):
-            have = np.nonzero(sizes > k // 3)[0]
-            v = torch.zeros((graph.n_atoms, 3), dtype=torch.float32, device=self.device)
-            v[torch.as_tensor(off[have] + k // 3, device=self.device), k % 3] = 1.0
-            hv = self.hessian_vector(graph, pos, v, stream)
-            for s in have:
-                out[s][:, k] = hv[off[s]:off[s + 1]].reshape(-1)
-        return out
+        K = 3 * int(sizes.max(initial=0))
+        atom = np.arange(K)[:, None] // 3
+        V = self._unit_directions(graph, np.where(atom < sizes[None, :], atom, -1))
+        HV = self.hessian_vectors(graph, pos, V, stream)  # [K, N, 3]; column k of every Hessian
+        return [HV[:3 * n, off[s]:off[s + 1]].reshape(3 * n, 3 * n).t().contiguous() for s, n in enumerate(sizes)]
 
     def footprint_bytes(self, n_atoms: int, n_edges: int) -> int:
         return int(lib().e3mi_footprint_bytes(self.handle, n_atoms, n_edges))

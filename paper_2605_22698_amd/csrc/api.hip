@@ -1250,7 +1250,7 @@ e3mi_model* new_model(const char* json, const double* wts, size_t n, int precisi
 // -ds/dr, which for gE = 0 is the Hessian-vector product H v (the reverse pass
 // is continued through each layer's edge geometry).
 void second_order(e3mi_model* M, e3mi_graph* G, const double* pos, const double* gE, const float* gF, double* out,
-                  float* hv, hipStream_t st) {
+                  float* hv, hipStream_t st, bool primal_ready = false) {
   const Config& c = M->cfg;
   Allocator* a = &M->alloc;
   const int N = G->N, C = c.channels, T = c.layers, H = c.radial_hidden;
@@ -1267,7 +1267,9 @@ void second_order(e3mi_model* M, e3mi_graph* G, const double* pos, const double*
   const WeightOffsets off = weight_offsets(c);
   if (out) E3MI_HIP(hipMemsetAsync(out, 0, sizeof(double) * off.total, st));
   if (N == 0) return;
-  forward_pass(M, G, pos, true, st, false);
+  // primal_ready: the previous call on this graph and positions left the
+  // primal values (h, h~, R, A per layer) in the workspace
+  if (!primal_ready) forward_pass(M, G, pos, true, st, false);
   const int* row_ptr = G->row_ptr_x->as<int>();
   const int* src = G->src_x->as<int>();
   const float4* dvec = G->dvec_x->as<float4>();
@@ -1457,14 +1459,19 @@ void param_grad(e3mi_model* M, e3mi_graph* G, const double* pos, const double* g
   second_order(M, G, pos, gE, gF, out, nullptr, st);
 }
 
-// H v = d(grad E . v)/dr: the second-order pass with no energy seed, continued
-// to the positions.
-void hessian_vector(e3mi_model* M, e3mi_graph* G, const double* pos, const float* v, float* hv, hipStream_t st) {
+// H v_k = d(grad E . v_k)/dr for k < n_vec (v, hv: [n_vec, N, 3]): the
+// second-order pass with no energy seed, continued to the positions; the
+// primal forward pass runs once for all directions.
+void hessian_vectors(e3mi_model* M, e3mi_graph* G, const double* pos, int n_vec, const float* v, float* hv,
+                     hipStream_t st) {
   E3MI_REQUIRE(v && hv, E3MI_EINVAL, "null argument");
+  E3MI_REQUIRE(n_vec >= 0, E3MI_EINVAL, "n_vec must be >= 0");
   Workspace& w = M->ws;
   ensure(w.zeroE, &M->alloc, sizeof(double) * (size_t)std::max(G->S, 1));
   E3MI_HIP(hipMemsetAsync(w.zeroE->p, 0, sizeof(double) * (size_t)std::max(G->S, 1), st));
-  second_order(M, G, pos, w.zeroE->as<double>(), v, nullptr, hv, st);
+  const size_t stride = 3 * (size_t)G->N;
+  for (int k = 0; k < n_vec; ++k)
+    second_order(M, G, pos, w.zeroE->as<double>(), v + k * stride, nullptr, hv + k * stride, st, k > 0);
 }
 
 // Replace the weights of a model (same configuration), e.g. after an optimiser step.
@@ -1862,11 +1869,16 @@ int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, con
 
 int e3mi_hessian_vector(e3mi_model* model, e3mi_graph* graph, const double* pos, const float* v, float* hv,
                         void* stream) {
+  return e3mi_hessian_vectors(model, graph, pos, 1, v, hv, stream);
+}
+
+int e3mi_hessian_vectors(e3mi_model* model, e3mi_graph* graph, const double* pos, int n_vec, const float* v,
+                         float* hv, void* stream) {
   E3MI_API_BEGIN
   E3MI_REQUIRE(model && graph, E3MI_EINVAL, "null argument");
   E3MI_REQUIRE(graph->model == model, E3MI_EINVAL, "graph was built for another model");
-  E3MI_REQUIRE(graph->N == 0 || (pos && v && hv), E3MI_EINVAL, "null positions, vector or output");
-  if (graph->N) e3mi::hessian_vector(model, graph, pos, v, hv, e3mi::as_stream(stream));
+  E3MI_REQUIRE(graph->N == 0 || n_vec == 0 || (pos && v && hv), E3MI_EINVAL, "null positions, vectors or output");
+  if (graph->N) e3mi::hessian_vectors(model, graph, pos, n_vec, v, hv, e3mi::as_stream(stream));
   E3MI_HIP(hipGetLastError());
   E3MI_API_END
 }
