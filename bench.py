@@ -259,6 +259,39 @@ def hessian_run(e3, synth, torch, dev, n_atoms, reps, log):
     return out
 
 
+def scale_run(e3, synth, torch, dev, steps, warmup, log):
+    """The 100,000-atom, 3-layer box (r_c 6 A): MD atom-steps/s in FP32 and in
+    BF16 mode. Its middle layer keeps per-edge R, about 106 GB in FP32 for
+    the 9 million edges, so it runs in receiver chunks of at most 8 GiB."""
+    cfg, b = synth.scale_config()
+    w = synth.flatten_weights(cfg, synth.model_weights(cfg, 5))
+    vel = synth.maxwell_boltzmann(b, 300.0, synth.seed_for(5, 9))
+    pos_d = torch.tensor(b.pos, dtype=torch.float64, device=dev)
+    vel_d = torch.tensor(vel, dtype=torch.float64, device=dev)
+    sp_d = torch.tensor(b.species, dtype=torch.int32, device=dev)
+    energy = torch.empty(1, dtype=torch.float64, device=dev)
+    out = {"workload": f"MD step, {b.n_atoms}-atom periodic box, 0.1 atoms/A^3, 4 species, r_c 6 A, l_max 3, "
+                       f"128 channels, 3 layers, skin 1 A, rebuild every 20 steps", "steps": steps}
+    for name, prec in (("fp32", e3.FP32), ("bf16", e3.BF16_MIX)):
+        m = e3.Model(cfg.to_json(), w, precision=prec, device=dev)
+        md = e3.MD(m, b.offsets, pos_d, vel_d, sp_d, synth.SPECIES_MASS[:4], b.cell, b.pbc, cfg.cutoff, 1.0, 20)
+        md.step(warmup, 0.5, energy)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        md.step(steps, 0.5, energy)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        out[f"value_{name}"] = b.n_atoms * steps / dt
+        out[f"ms_per_step_{name}"] = 1e3 * dt / steps
+        out[f"energy_eV_{name}"] = energy.item()
+        md.close()
+        m.close()
+        torch.cuda.empty_cache()
+        log(f"100k box {name}: {out[f'value_{name}']:.3e} atom-steps/s ({out[f'ms_per_step_{name}']:.0f} ms/step)")
+    out["bf16_over_fp32"] = out["value_bf16"] / out["value_fp32"]
+    return out
+
+
 COULOMB_FLOPS_PER_PAIR = 20  # distance 8, rsqrt 1, potential 2, force factor 3, force 6
 
 
@@ -338,6 +371,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=16)
     ap.add_argument("--coulomb-only", action="store_true",
                     help="only run the electrostatics measurement (for profiling its kernels)")
+    ap.add_argument("--scale-only", action="store_true",
+                    help="only run the 100,000-atom FP32 / BF16 measurement")
     ap.add_argument("--hessian-only", action="store_true",
                     help="only run the Hessian-vector-product measurement (for profiling its kernels)")
     ap.add_argument("--product-only", action="store_true",
@@ -363,6 +398,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read_per_launch": src.numel() * 4,
                           "bytes_written_per_launch": dst.numel() * 4, "launches": 10}), flush=True)
+        return
+    if args.scale_only:
+        print(json.dumps({"scale": scale_run(e3, synth, torch, dev, args.steps, args.warmup, log)}), flush=True)
         return
     if args.hessian_only:
         print(json.dumps({"hessian": hessian_run(e3, synth, torch, dev, args.atoms, args.steps, log)}), flush=True)
@@ -483,6 +521,7 @@ def main():
         extras["coulomb"] = coulomb_run(e3, synth, torch, dev, max(20, args.steps // 2), args.warmup, log)
         extras["product"] = product_run(e3, synth, torch, dev, args.atoms, max(20, args.steps // 4), args.warmup, log)
         extras["hessian"] = hessian_run(e3, synth, torch, dev, args.atoms, 20, log)
+        extras["scale"] = scale_run(e3, synth, torch, dev, 5, 2, log)
 
     # ---- oracle on the host cores (bounded sample) ----
     cpu = None

@@ -219,6 +219,17 @@ int e3mi_hessian_vectors(e3mi_model* model, e3mi_graph* graph, const double* pos
 #define E3MI_FLAG_UNFUSED_LAST_LAYER 2
 int e3mi_model_set_flags(e3mi_model* model, int flags);
 
+/* Most bytes of per-edge radial weights R (and of their adjoint) that an
+ * energy_forces call holds at once for the layers evaluated with R in memory
+ * (middle layers, and every layer of a model with the product block); default
+ * 8 GiB, at least 1 MiB. Larger edge sets are processed in chunks of whole
+ * receivers (the adjoint then recomputes R per chunk), so a 100,000-atom,
+ * 9-million-edge, 3-layer model (about 106 GB of R per layer in FP32, Section
+ * 4's tensor product at scale) runs in bounded memory. The chunking reads the
+ * pruned row pointer back to the host once per call. Results agree with the
+ * unchunked evaluation to rounding (bitwise when there is one chunk). */
+int e3mi_model_set_r_chunk_bytes(e3mi_model* model, size_t bytes);
+
 /* Replace the weights (host FP64, same configuration and layout as at
  * creation), e.g. after an optimiser step. Synchronises the device first. */
 int e3mi_model_set_weights(e3mi_model* model, const double* weights_host, size_t n_weights);

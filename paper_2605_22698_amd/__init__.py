@@ -77,6 +77,10 @@ class Model:
         flags = (1 if unfactorised_first_layer else 0) | (2 if unfused_last_layer else 0)
         check(lib().e3mi_model_set_flags(self.handle, flags))
 
+    def set_r_chunk_bytes(self, n_bytes: int) -> None:
+        """Most bytes of per-edge radial weights held at once; see e3mi_model_set_r_chunk_bytes."""
+        check(lib().e3mi_model_set_r_chunk_bytes(self.handle, int(n_bytes)))
+
     def set_weights(self, weights) -> None:
         """Replace the weights (FP64 vector in the documented layout; any device)."""
         w = weights.detach().to("cpu", dtype=__import__("torch").float64).contiguous().numpy() \

@@ -206,6 +206,8 @@ struct Workspace {
   std::unique_ptr<DevBuf> q_raw, q, pot, fc, pot_mean;  // electrostatics: charges, potential, forces
   std::vector<std::unique_ptr<DevBuf>> at;             // product block: A~ per layer
   std::unique_ptr<DevBuf> Ygb, Ygc, ghv, zeroE;        // Hessian-vector products
+  std::vector<int> rp_host;                            // pruned row pointer on the host (receiver chunks)
+  bool rp_valid = false;
   std::unique_ptr<DevBuf> Bp, dat;                     // product block: B (or dB), dA~
 };
 
@@ -221,6 +223,7 @@ struct e3mi_model {
   // first layer factorised by species: U_l [S*64, C] and U_l^T [C, S*64] per output order
   bool first_factorised = true;
   bool last_fused = true;
+  size_t r_chunk_bytes = size_t(8) << 30;  // most bytes of per-edge R (and dR) held at once
   std::unique_ptr<e3mi::DevBuf> U[4], UT[4];
   e3mi::Workspace ws;
   e3mi::Profiler prof;
@@ -672,6 +675,51 @@ LastArgs last_args(e3mi_model* M, e3mi_graph* G, const LayerPlan& L, LayerWeight
   return la;
 }
 
+// Receiver chunks of a layer evaluated with per-edge R in memory: each chunk's
+// edges hold at most the model's r_chunk_bytes of R (and of dR in the
+// adjoint), so R never needs the whole edge set at once. One chunk
+// {0, N, 0, -1} (every edge, no host synchronisation) when the whole edge
+// capacity fits; otherwise the pruned row pointer is read back once per
+// evaluation.
+struct RChunk {
+  int i0, i1;  // receivers [i0, i1)
+  int e0, e1;  // edges [e0, e1); e1 = -1: all edges of all receivers
+};
+
+size_t r_chunk_edges(const e3mi_model* M, long Ecap, int PCu) {
+  return std::min<size_t>((size_t)(Ecap + 1), M->r_chunk_bytes / ((size_t)PCu * sizeof(float)));
+}
+
+std::vector<RChunk> r_chunks(e3mi_model* M, e3mi_graph* G, int PCu, hipStream_t st) {
+  const int N = G->N;
+  const size_t cap = r_chunk_edges(M, G->E, PCu);
+  if (cap >= (size_t)(G->E + 1)) return {RChunk{0, N, 0, -1}};
+  Workspace& w = M->ws;
+  if (!w.rp_valid) {
+    w.rp_host.resize((size_t)N + 1);
+    E3MI_HIP(hipMemcpyAsync(w.rp_host.data(), G->row_ptr_x->p, sizeof(int) * ((size_t)N + 1), hipMemcpyDeviceToHost,
+                            st));
+    E3MI_HIP(hipStreamSynchronize(st));
+    w.rp_valid = true;
+  }
+  const std::vector<int>& rp = w.rp_host;
+  std::vector<RChunk> out;
+  for (int i0 = 0; i0 < N;) {
+    int i1 = i0 + 1;  // a receiver's row always fits (its edges are few)
+    while (i1 < N && (size_t)(rp[i1 + 1] - rp[i0]) <= cap) ++i1;
+    E3MI_REQUIRE((size_t)(rp[i1] - rp[i0]) <= cap, E3MI_EOVERFLOW, "one receiver's edges exceed the R chunk");
+    out.push_back(RChunk{i0, i1, rp[i0], rp[i1]});
+    i0 = i1;
+  }
+  return out;
+}
+
+void set_chunk(TpArgs& ta, const RChunk& ch) {
+  ta.i0 = ch.e1 < 0 ? 0 : ch.i0;
+  ta.n_recv = ch.e1 < 0 ? 0 : ch.i1 - ch.i0;
+  ta.e_first = ch.e1 < 0 ? 0 : ch.e0;
+}
+
 // Primal forward pass: edge selection, embedding and every layer. Leaves
 // h^t, h~^t and R^t of every layer in the workspace; A in one shared buffer,
 // or per layer when keep_A (the parameter-gradient pass needs them).
@@ -690,6 +738,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     ProfScope ps(&M->prof, stage_id(kPrune), st);
     prune(G, pos, st);
   }
+  w.rp_valid = false;
   const int* row_ptr = G->row_ptr_x->as<int>();
   const int* src = G->src_x->as<int>();
   const float4* dvec = G->dvec_x->as<float4>();
@@ -708,7 +757,9 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     a_max = std::max(a_max, L.a_per_atom);
     if (t == 1 && factorised_first(M) && !keep_A) continue;
     if (fused_last(M, L, keep_A, bf16)) continue;
-    ensure(w.R[t], a, sizeof(float) * (size_t)(Ecap + 1) * L.p_used * C);
+    // the second-order pass keeps R of every edge; otherwise at most one chunk
+    const size_t r_edges = keep_A ? (size_t)(Ecap + 1) : r_chunk_edges(M, Ecap, L.p_used * C);
+    ensure(w.R[t], a, sizeof(float) * r_edges * L.p_used * C);
     pc_max = std::max(pc_max, (long)L.p_used * C);
   }
   ensure(w.A, a, sizeof(float) * (size_t)N * a_max);
@@ -716,7 +767,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     w.Al.resize(T + 1);
     for (int t = 1; t <= T; ++t) ensure(w.Al[t], a, sizeof(float) * (size_t)N * M->plans[t - 1].a_per_atom);
   }
-  if (pc_max) ensure(w.dR, a, sizeof(float) * (size_t)(Ecap + 1) * pc_max);
+  if (pc_max) ensure(w.dR, a, sizeof(float) * r_chunk_edges(M, Ecap, (int)pc_max) * pc_max);
   ensure(w.dY, a, sizeof(float) * 16 * (size_t)(Ecap + 1));
   ensure(w.g, a, sizeof(float4) * (size_t)(Ecap + 1));
   ensure(w.dh_a, a, sizeof(float) * (size_t)N * NC * C);
@@ -816,11 +867,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     }
     float* R = w.R[t]->as<float>();
     const int PCu = L.p_used * C;
-    {
-      ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
-      launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                        W.rad3.as<float>(), L.p_full * C, PCu, R, rc, p_env, bf16, st);
-    }
+    const std::vector<RChunk> chunks = keep_A ? std::vector<RChunk>{RChunk{0, N, 0, -1}} : r_chunks(M, G, PCu, st);
     TpArgs ta{};
     ta.lmax = c.lmax;
     ta.kind = L.kind;
@@ -836,7 +883,13 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     ta.N = N;
     ta.C = C;
     ta.inv_nu = inv_nu;
-    {
+    for (const RChunk& ch : chunks) {
+      {
+        ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
+        launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
+                          W.rad3.as<float>(), L.p_full * C, PCu, R, rc, p_env, bf16, st, ch.e0, ch.e1);
+      }
+      set_chunk(ta, ch);
       ProfScope ps(&M->prof, stage_id(kTpFwd, t), st);
       launch_tp(0, ta, st);
     }
@@ -1003,23 +1056,35 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     ta.N = N;
     ta.C = C;
     ta.inv_nu = inv_nu;
-    {
-      ProfScope ps(&M->prof, stage_id(kTpBwdEdge, t), st);
-      launch_tp(1, ta, st);
+    ta.dh = dother;
+    ta.dh_nc = L.nc_in;
+    // with more than one chunk R is recomputed chunk by chunk (the forward
+    // pass kept only the last chunk)
+    const std::vector<RChunk> chunks = r_chunks(M, G, PCu, st);
+    for (const RChunk& ch : chunks) {
+      if (chunks.size() > 1) {
+        ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
+        launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
+                          W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->as<float>(), rc, p_env, bf16, st, ch.e0,
+                          ch.e1);
+      }
+      set_chunk(ta, ch);
+      {
+        ProfScope ps(&M->prof, stage_id(kTpBwdEdge, t), st);
+        launch_tp(1, ta, st);
+      }
+      {
+        ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
+        launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
+                          W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->as<float>(), w.dY->as<float>(), g,
+                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1);
+      }
+      if (t > 1) {
+        ProfScope ps(&M->prof, stage_id(kTpBwdNode, t), st);
+        launch_tp(2, ta, st);
+      }
     }
-    {
-      ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
-      launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                        W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->as<float>(), w.dY->as<float>(), g,
-                        t != T ? 1 : 0, rc, p_env, M->precision == E3MI_BF16_MIX, st);
-    }
-    if (t > 1) {
-      ta.dh = dother;
-      ta.dh_nc = L.nc_in;
-      ProfScope ps(&M->prof, stage_id(kTpBwdNode, t), st);
-      launch_tp(2, ta, st);
-      std::swap(dcur, dother);
-    }
+    if (t > 1) std::swap(dcur, dother);
   }
   {
     ProfScope ps(&M->prof, stage_id(kForces), st);
@@ -1880,6 +1945,14 @@ int e3mi_hessian_vectors(e3mi_model* model, e3mi_graph* graph, const double* pos
   E3MI_REQUIRE(graph->N == 0 || n_vec == 0 || (pos && v && hv), E3MI_EINVAL, "null positions, vectors or output");
   if (graph->N) e3mi::hessian_vectors(model, graph, pos, n_vec, v, hv, e3mi::as_stream(stream));
   E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_model_set_r_chunk_bytes(e3mi_model* model, size_t bytes) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
+  E3MI_REQUIRE(bytes >= (size_t)1 << 20, E3MI_EINVAL, "the R chunk must be at least 1 MiB");
+  model->r_chunk_bytes = bytes;
   E3MI_API_END
 }
 

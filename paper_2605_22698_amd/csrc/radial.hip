@@ -113,11 +113,13 @@ template <int NB, bool BF>
 __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W3, int ld3, int PC,
-                                                    float* __restrict__ R, float rc, int p) {
+                                                    float* __restrict__ R, float rc, int p, int e_first, int e_end) {
+  // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); R is
+  // indexed from e_first
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float H[kTile][kLd];
-  const int E = row_ptr_x[N];
-  const int e0 = blockIdx.x * kTile;
+  const int E = e_end >= 0 ? e_end : row_ptr_x[N];
+  const int e0 = e_first + blockIdx.x * kTile;
   if (e0 >= E) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (t < kTile) {
@@ -146,8 +148,8 @@ __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ d
     for (int r = 0; r < 16; ++r) {
       const int row = acc_row(r, lane);
       const int ea = e0 + row, eb = e0 + 32 + row;
-      if (ea < E) R[(long)ea * PC + cc + (lane & 31)] = a0[r];
-      if (eb < E) R[(long)eb * PC + cc + (lane & 31)] = a1[r];
+      if (ea < E) R[(long)(ea - e_first) * PC + cc + (lane & 31)] = a0[r];
+      if (eb < E) R[(long)(eb - e_first) * PC + cc + (lane & 31)] = a1[r];
     }
   }
 }
@@ -157,15 +159,18 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W2T, const float* __restrict__ W3T,
                                                     int PC, const float* __restrict__ dR, const float* __restrict__ dY,
-                                                    float4* __restrict__ g, int accumulate, float rc, int p) {
+                                                    float4* __restrict__ g, int accumulate, float rc, int p,
+                                                    int e_first, int e_end) {
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float dBs[kTile][NB + 1];
   __shared__ float P1[kTile][kLd];
   __shared__ float P2[kTile][kLd];
   __shared__ float X[kTile][kLd];
   __shared__ float Ds[kTile][33];
-  const int E = row_ptr_x[N];
-  const int e0 = blockIdx.x * kTile;
+  // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); dR is
+  // indexed from e_first, dY and g by edge
+  const int E = e_end >= 0 ? e_end : row_ptr_x[N];
+  const int e0 = e_first + blockIdx.x * kTile;
   if (e0 >= E) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
@@ -196,7 +201,7 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
       const int row = t >> 2, c8 = (t & 3) * 8;
       const int e = e0 + row;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) Ds[row][c8 + q] = e < E ? dR[(long)e * PC + kc + c8 + q] : 0.0f;
+      for (int q = 0; q < 8; ++q) Ds[row][c8 + q] = e < E ? dR[(long)(e - e_first) * PC + kc + c8 + q] : 0.0f;
     }
     __syncthreads();
     if constexpr (BF) {
@@ -455,37 +460,44 @@ inline int tiles(long n) { return (int)((n + kTile - 1) / kTile); }
 
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
                        const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, bool bf16,
-                       hipStream_t st) {
+                       hipStream_t st, int e_first, int e_end) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (PC % 32) throw Error(E3MI_EUNSUPPORTED, "paths x channels must be a multiple of 32");
+  const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
+  if (grid == 0) return;
   if (bf16)
-    k_radial_fwd<8, true><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p);
+    k_radial_fwd<8, true><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p, e_first, e_end);
   else
-    k_radial_fwd<8, false><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p);
+    k_radial_fwd<8, false><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p, e_first, e_end);
 }
 
 template <int LMAX>
 static void radial_bwd_l(bool bf16, long e_cap, const float4* dvec, const int* row_ptr_x, int N, const float* W1,
                          const float* W2, const float* W2T, const float* W3T, int PC, const float* dR, const float* dY,
-                         float4* g, int accumulate, float rc, int p, hipStream_t st) {
+                         float4* g, int accumulate, float rc, int p, hipStream_t st, int e_first, int e_end) {
+  const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
+  if (grid == 0) return;
   if (bf16)
-    k_radial_bwd<8, LMAX, true><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g,
-                                                              accumulate, rc, p);
+    k_radial_bwd<8, LMAX, true><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g,
+                                                      accumulate, rc, p, e_first, e_end);
   else
-    k_radial_bwd<8, LMAX, false><<<tiles(e_cap), 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g,
-                                                               accumulate, rc, p);
+    k_radial_bwd<8, LMAX, false><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g,
+                                                               accumulate, rc, p, e_first, e_end);
 }
 
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
-                       const float* dY, float4* g, int accumulate, float rc, int p, bool bf16, hipStream_t st) {
+                       const float* dY, float4* g, int accumulate, float rc, int p, bool bf16, hipStream_t st,
+                       int e_first, int e_end) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (lmax == 3)
-    radial_bwd_l<3>(bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st);
+    radial_bwd_l<3>(bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st, e_first,
+                    e_end);
   else if (lmax == 2)
-    radial_bwd_l<2>(bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st);
+    radial_bwd_l<2>(bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st, e_first,
+                    e_end);
   else
     throw Error(E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
 }

@@ -221,6 +221,9 @@ struct TpArgs {
   float* hc;         // in/out (+=): adjoint of the tangent of h (NULL: not needed)
   float* Yb;         // out: adjoint of the harmonics per edge [E, 16]
   float* Yc;         // out: adjoint of the harmonics' tangent per edge [E, 16]
+  // receiver chunk (first-order kernels 0-2): receivers i0 .. i0 + n_recv - 1
+  // (n_recv 0: all N from i0 = 0), R and dR indexed from edge e_first
+  int i0, n_recv, e_first;
 };
 // which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...),
 //        3 tangent forward (Ad), 4 second-order edge adjoint (Rb, Rc),
@@ -294,10 +297,11 @@ void launch_coulomb_dq(const int64_t* off, const int* owner, int S, int N, const
 // ---- radial MLP (radial.hip) ---------------------------------------------------------
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
                        const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, bool bf16,
-                       hipStream_t st);
+                       hipStream_t st, int e_first = 0, int e_end = -1);
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
-                       const float* dY, float4* g, int accumulate, float rc, int p, bool bf16, hipStream_t st);
+                       const float* dY, float4* g, int accumulate, float rc, int p, bool bf16, hipStream_t st,
+                       int e_first = 0, int e_end = -1);
 
 // ---- second-order passes (radial.hip, grad.hip) -------------------------------------
 void launch_radial_dual_fwd(int n_basis, const float4* dvec, const float4* dd, const int* row_ptr_x, int N, long e_cap,

@@ -34,10 +34,11 @@ template <int LMAX, int KIND, int CPT>
 __global__ void __launch_bounds__(256) k_tp_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                 const float4* __restrict__ dvec, const float* __restrict__ R,
                                                 int r_stride, const float* __restrict__ h, int h_nc,
-                                                float* __restrict__ A, int N, int C, float inv_nu) {
+                                                float* __restrict__ A, int N, int C, float inv_nu, int i0,
+                                                int e_first) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
-  const int i = blockIdx.x;
+  const int i = i0 + blockIdx.x;
   const int tpr = blockDim.x;
   float acc[CPT][NOUT];
 #pragma unroll
@@ -51,7 +52,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(const int* __restrict__ row_ptr,
     const float ir = 1.0f / d.w;
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const float* Re = R + (long)e * r_stride;
+    const float* Re = R + (long)(e - e_first) * r_stride;
     const float* hj = h + (long)j * h_nc * C;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -98,11 +99,12 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
                                                      const float4* __restrict__ dvec, const float* __restrict__ R,
                                                      int r_stride, const float* __restrict__ h, int h_nc,
                                                      const float* __restrict__ dA, float* __restrict__ dR,
-                                                     float* __restrict__ dY, int N, int C, float inv_nu) {
+                                                     float* __restrict__ dY, int N, int C, float inv_nu, int i0,
+                                                     int e_first) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
   __shared__ float red[4][16];
-  const int i = blockIdx.x;
+  const int i = i0 + blockIdx.x;
   const int tpr = blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float dai[CPT][NOUT];
@@ -127,8 +129,8 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
     const float ir = 1.0f / d.w;
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const float* Re = R + (long)e * r_stride;
-    float* dRe = dR + (long)e * r_stride;
+    const float* Re = R + (long)(e - e_first) * r_stride;
+    float* dRe = dR + (long)(e - e_first) * r_stride;
     const float* hj = h + (long)j * h_nc * C;
     float dyp[NY];
 #pragma unroll
@@ -200,10 +202,11 @@ template <int LMAX, int KIND, int CPT>
 __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                      const float4* __restrict__ dvec, const float* __restrict__ R,
                                                      int r_stride, const float* __restrict__ dA,
-                                                     float* __restrict__ dh, int dh_nc, int N, int C, float inv_nu) {
+                                                     float* __restrict__ dh, int dh_nc, int N, int C, float inv_nu,
+                                                     int i0, int e_first) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NIN = PS::NIN, NY = PS::NY;
-  const int j = blockIdx.x;
+  const int j = i0 + blockIdx.x;
   const int tpr = blockDim.x;
   float acc[CPT][NIN];
 #pragma unroll
@@ -217,7 +220,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
     const float ir = -1.0f / d.w;  // direction of the reverse edge
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const float* Re = R + (long)e * r_stride;
+    const float* Re = R + (long)(e - e_first) * r_stride;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int k = threadIdx.x + c * tpr;
@@ -583,15 +586,18 @@ template <int LMAX, int KIND, int CPT>
 static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
   const int tpr = a.C / CPT;
   if (a.N == 0) return;
+  const int nr = a.n_recv > 0 ? a.n_recv : a.N;  // receivers of this launch
+  if (which <= 2 && a.n_recv == 0 && (a.i0 != 0 || a.e_first != 0))
+    throw Error(E3MI_EINVAL, "tensor product: receiver offset without a receiver count");
   if (which == 0)
-    k_tp_fwd<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.A, a.N,
-                                                    a.C, a.inv_nu);
+    k_tp_fwd<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.A, a.N,
+                                                   a.C, a.inv_nu, a.i0, a.e_first);
   else if (which == 1)
-    k_tp_bwd_edge<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.dA,
-                                                         a.dR, a.dY, a.N, a.C, a.inv_nu);
+    k_tp_bwd_edge<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.dA,
+                                                        a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first);
   else if (which == 2)
-    k_tp_bwd_node<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
-                                                         a.dh_nc, a.N, a.C, a.inv_nu);
+    k_tp_bwd_node<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
+                                                        a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first);
   else if (which == 3)
     k_tp_dual_fwd<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.R, a.Rd, a.r_stride, a.h,
                                                          a.hd, a.h_nc, a.Ad, a.N, a.C, a.inv_nu);

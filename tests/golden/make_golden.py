@@ -8,6 +8,9 @@ HIP library. Rerun after any change of the oracle's arithmetic or the inputs:
 single_3000.npz  3,000-atom periodic box at 0.1 atoms/A^3 (jittered lattice,
                  0.3 A noise), 4 species, r_c 5 A, l_max 3, 128 channels,
                  2 layers: per-structure energy, per-atom energies, forces.
+scale_sub_2000.npz  the independent 2,000-atom periodic box of the
+                 100,000-atom configuration (r_c 6 A, l_max 3, 128 channels,
+                 3 layers): energy, per-atom energies, forces.
 """
 import os
 import sys
@@ -32,7 +35,15 @@ def single_3000():
                         n_atoms=b.n_atoms)
 
 
-JOBS = {"single_3000": single_3000}
+def scale_sub_2000():
+    cfg, b = synth.scale_subbox()
+    m = om.Model(cfg, synth.model_weights(cfg, 5))
+    E, F, Ei = om.energy_forces(m, b, edge_chunk=4096)
+    np.savez_compressed(os.path.join(HERE, "scale_sub_2000.npz"), energy=E, forces=F, atom_energy=Ei,
+                        n_atoms=b.n_atoms)
+
+
+JOBS = {"single_3000": single_3000, "scale_sub_2000": scale_sub_2000}
 
 if __name__ == "__main__":
     torch.set_num_threads(os.cpu_count() or 1)
