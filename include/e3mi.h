@@ -208,15 +208,20 @@ int e3mi_hessian_vectors(e3mi_model* model, e3mi_graph* graph, const double* pos
  *     the exact species factorisation of its neighbour sum (its input is the
  *     embedding of the sender's species); results agree to rounding. */
 #define E3MI_FLAG_UNFACTORISED_FIRST_LAYER 1
-/*   E3MI_FLAG_UNFUSED_LAST_LAYER (2): evaluate the last layer (scalar outputs
- *     only, Section 4's tensor product restricted to the paths that reach the
- *     energy) with per-edge radial weights R in memory and separate radial /
- *     tensor-product kernels, instead of the fused kernels that never store
- *     R (the neighbour sum is taken as W3^T times a per-receiver product of
- *     hidden activations and contracted features); results agree to
- *     rounding. The fused path is only used in FP32 with two or more
- *     layers; the parameter-gradient pass always uses the unfused one. */
+/*   The last layer (scalar outputs only: Section 4's tensor product
+ *     restricted to the paths that reach the energy) has two evaluations
+ *     whose results agree to rounding. By default it keeps per-edge radial
+ *     weights R in memory and runs separate radial / tensor-product kernels
+ *     (measured faster on MI355X).
+ *   E3MI_FLAG_FUSED_LAST_LAYER (4) selects the fused kernels instead. They
+ *     never store R: the neighbour sum is taken as W3^T times a per-receiver
+ *     product of hidden activations and contracted features. They are used
+ *     only in FP32 with two or more layers; the parameter-gradient pass
+ *     always uses the per-edge form.
+ *   E3MI_FLAG_UNFUSED_LAST_LAYER (2) forces the per-edge form even when bit
+ *     4 is set. */
 #define E3MI_FLAG_UNFUSED_LAST_LAYER 2
+#define E3MI_FLAG_FUSED_LAST_LAYER 4
 int e3mi_model_set_flags(e3mi_model* model, int flags);
 
 /* Most bytes of per-edge radial weights R (and of their adjoint) that an

@@ -222,7 +222,7 @@ struct e3mi_model {
   std::unique_ptr<e3mi::DevBuf> emb, read1, read2, e0, qhead, qbias;
   // first layer factorised by species: U_l [S*64, C] and U_l^T [C, S*64] per output order
   bool first_factorised = true;
-  bool last_fused = true;
+  bool last_fused = false;  // per-edge last layer by default (faster here); flag 4 selects the fused one
   size_t r_chunk_bytes = size_t(8) << 30;  // most bytes of per-edge R (and dR) held at once
   std::unique_ptr<e3mi::DevBuf> U[4], UT[4];
   e3mi::Workspace ws;
@@ -1959,9 +1959,9 @@ int e3mi_model_set_r_chunk_bytes(e3mi_model* model, size_t bytes) {
 int e3mi_model_set_flags(e3mi_model* model, int flags) {
   E3MI_API_BEGIN
   E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
-  E3MI_REQUIRE((flags & ~3) == 0, E3MI_EINVAL, "unknown flag");
+  E3MI_REQUIRE((flags & ~7) == 0, E3MI_EINVAL, "unknown flag");
   model->first_factorised = (flags & 1) == 0;
-  model->last_fused = (flags & 2) == 0;
+  model->last_fused = (flags & 4) != 0 && (flags & 2) == 0;
   E3MI_API_END
 }
 

@@ -163,7 +163,6 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
                                                     int e_first, int e_end) {
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float dBs[kTile][NB + 1];
-  __shared__ float P1[kTile][kLd];
   __shared__ float P2[kTile][kLd];
   __shared__ float X[kTile][kLd];
   __shared__ float Ds[kTile][33];
@@ -186,24 +185,48 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
     }
   }
   __syncthreads();
-  layer1<NB>(Bs, W1, P1, X);  // P1 = pre1, X = H1
+  layer1<NB>(Bs, W1, nullptr, X);  // X = H1 (pre1 is recomputed at the end)
   __syncthreads();
   {
     const f32x16 acc = block_64<BF>(X, rb, W2, kH, cb);
 #pragma unroll
     for (int r = 0; r < 16; ++r) P2[rb + acc_row(r, lane)][cb + (lane & 31)] = acc[r];
   }
-  // dH2 = dR W3^T, K = PC, dR staged through LDS in chunks of 32 columns.
+  // dH2 = dR W3^T, K = PC, dR staged through LDS in slabs of 32 columns; the
+  // next slab (and, in FP32, its W3^T operands) is loaded into registers
+  // while the current one is multiplied.
   f32x16 acc = {};
+  const int srow = t >> 2, sc8 = (t & 3) * 8;
+  const bool sval = e0 + srow < E;
+  const float* dRrow = dR + (long)(e0 + srow - e_first) * PC + sc8;
+  float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+  float wb[16];
+  auto load_slab = [&](int kc) {
+    if (sval) {
+      p0 = *reinterpret_cast<const float4*>(dRrow + kc);
+      p1 = *reinterpret_cast<const float4*>(dRrow + kc + 4);
+    }
+    if constexpr (!BF) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) wb[i] = W3T[(kc + 2 * i + (lane >> 5)) * kH + cb + (lane & 31)];
+    }
+  };
+  load_slab(0);
   for (int kc = 0; kc < PC; kc += 32) {
     __syncthreads();
-    {
-      const int row = t >> 2, c8 = (t & 3) * 8;
-      const int e = e0 + row;
+    Ds[srow][sc8] = p0.x;
+    Ds[srow][sc8 + 1] = p0.y;
+    Ds[srow][sc8 + 2] = p0.z;
+    Ds[srow][sc8 + 3] = p0.w;
+    Ds[srow][sc8 + 4] = p1.x;
+    Ds[srow][sc8 + 5] = p1.y;
+    Ds[srow][sc8 + 6] = p1.z;
+    Ds[srow][sc8 + 7] = p1.w;
+    float wcur[16];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) Ds[row][c8 + q] = e < E ? dR[(long)(e - e_first) * PC + kc + c8 + q] : 0.0f;
-    }
+    for (int i = 0; i < 16; ++i) wcur[i] = wb[i];
     __syncthreads();
+    if (kc + 32 < PC) load_slab(kc + 32);
     if constexpr (BF) {
 #pragma unroll
       for (int kb = 0; kb < 32; kb += 16) {
@@ -217,12 +240,8 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
       }
     } else {
-#pragma unroll 4
-      for (int kk = 0; kk < 32; kk += 2) {
-        const float a = Ds[rb + (lane & 31)][kk + (lane >> 5)];
-        const float b = W3T[(kc + kk + (lane >> 5)) * kH + cb + (lane & 31)];
-        acc = mfma32(a, b, acc);
-      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc = mfma32(Ds[rb + (lane & 31)][2 * i + (lane >> 5)], wcur[i], acc);
     }
   }
   __syncthreads();
@@ -239,7 +258,10 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
-      P2[row][col] = a2[r] * silu_grad(P1[row][col]);
+      float p1 = 0.0f;
+#pragma unroll
+      for (int n = 0; n < NB; ++n) p1 += Bs[row][n] * W1[n * kH + col];
+      P2[row][col] = a2[r] * silu_grad(p1);
     }
   }
   __syncthreads();

@@ -165,9 +165,11 @@ def test_fused_last_layer_matches_unfused_path(lmax, channels):
     _, b = synth.single_config(n=500)
     m = model(cfg, 5)
     say(f"fused last layer l_max {lmax} C {channels}")
+    m.set_flags(fused_last_layer=True)
     E1, F1, Ei1, _ = gpu_energy_forces(m, b, skin=1.0)
-    m.set_flags(unfused_last_layer=True)
+    m.set_flags()
     E2, F2, Ei2, _ = gpu_energy_forces(m, b, skin=1.0)
+    assert not np.array_equal(F1, F2)  # the two evaluations really differ in order
     assert np.abs(Ei1 - Ei2).max() <= 1e-5 * np.abs(Ei2).max()
     assert abs(E1[0] - E2[0]) <= 1e-6 * abs(E2[0])
     assert np.abs(F1 - F2).max() <= 1e-4 * np.abs(F2).max()
