@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(256) k_tp_fwd(const int* __restrict__ row_ptr,
                                                 int e_first) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
-  const int i = i0 + blockIdx.x;
+  const int i = i0 + xcd_contiguous(blockIdx.x, gridDim.x);
   const int tpr = blockDim.x;
   float acc[CPT][NOUT];
 #pragma unroll
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
   __shared__ float red[4][16];
-  const int i = i0 + blockIdx.x;
+  const int i = i0 + xcd_contiguous(blockIdx.x, gridDim.x);
   const int tpr = blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float dai[CPT][NOUT];
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
                                                      int i0, int e_first) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NIN = PS::NIN, NY = PS::NY;
-  const int j = i0 + blockIdx.x;
+  const int j = i0 + xcd_contiguous(blockIdx.x, gridDim.x);
   const int tpr = blockDim.x;
   float acc[CPT][NIN];
 #pragma unroll
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(256) k_tp_dual_fwd(const int* __restrict__ row
                                                      int N, int C, float inv_nu) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
-  const int i = blockIdx.x;
+  const int i = xcd_contiguous(blockIdx.x, gridDim.x);
   const int tpr = blockDim.x;
   float acc[CPT][NOUT];
 #pragma unroll
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(256) k_tp_dual_bwd_edge(const int* __restrict_
                                                           float inv_nu) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
-  const int i = blockIdx.x;
+  const int i = xcd_contiguous(blockIdx.x, gridDim.x);
   const int tpr = blockDim.x;
   float ab[CPT][NOUT], ac[CPT][NOUT];
 #pragma unroll
@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(256) k_tp_dual_bwd_node(const int* __restrict_
                                                           float inv_nu) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NIN = PS::NIN, NY = PS::NY;
-  const int j = blockIdx.x;
+  const int j = xcd_contiguous(blockIdx.x, gridDim.x);
   const int tpr = blockDim.x;
   float accb[CPT][NIN], accc[CPT][NIN];
 #pragma unroll
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(256) k_tp_dual_geo(const int* __restrict__ row
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
   __shared__ float red[4][2 * 16];
-  const int i = blockIdx.x;
+  const int i = xcd_contiguous(blockIdx.x, gridDim.x);
   const int tpr = blockDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float ab[CPT][NOUT], ac[CPT][NOUT];
