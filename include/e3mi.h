@@ -352,6 +352,13 @@ size_t e3mi_footprint_bytes(const e3mi_model* model, int64_t n_atoms, int64_t n_
 int e3mi_profile_enable(e3mi_model* model, int enable);
 int e3mi_profile_query(e3mi_model* model, const char* stage, double* total_ms, int64_t* launches);
 
+/* Restrict the timing to one stage ("name" or "name@t"; NULL or "" for
+ * every stage): only its launches are bracketed by events, so a timed run
+ * can measure one kernel in place without the events of the others slowing
+ * the step down (each recorded pair costs a few microseconds of device
+ * time). Applies from the next launch; profile_enable keeps the selection. */
+int e3mi_profile_select(e3mi_model* model, const char* stage);
+
 /* Thread-local description of the last error ("" if none). */
 const char* e3mi_last_error(void);
 

@@ -62,8 +62,11 @@ class Model:
         except Exception:
             pass
 
-    def profile(self, enable: bool = True):
-        """Start (resetting counters) or stop per-stage HIP-event timing."""
+    def profile(self, enable: bool = True, only: str = None):
+        """Start (resetting counters) or stop per-stage HIP-event timing;
+        only: time just this stage ("name" or "name@t"), else every stage."""
+        if enable:
+            check(lib().e3mi_profile_select(self.handle, (only or "").encode()))
         check(lib().e3mi_profile_enable(self.handle, 1 if enable else 0))
 
     def stage_time(self, stage: str):

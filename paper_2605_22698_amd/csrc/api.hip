@@ -675,6 +675,21 @@ LastArgs last_args(e3mi_model* M, e3mi_graph* G, const LayerPlan& L, LayerWeight
   return la;
 }
 
+// "name" or "name@t" -> stage id (and layer t, -1 for every layer).
+int parse_stage(const char* stage, int* layer) {
+  std::string name(stage);
+  *layer = -1;
+  const size_t at = name.find('@');
+  if (at != std::string::npos) {
+    *layer = std::atoi(name.c_str() + at + 1);
+    name = name.substr(0, at);
+    E3MI_REQUIRE(*layer >= 0 && *layer < 8, E3MI_EINVAL, "layer of a stage must be in [0, 8)");
+  }
+  for (int k = 0; k < kNumStages; ++k)
+    if (name == kStageNames[k]) return k;
+  throw Error(E3MI_EINVAL, "unknown stage " + name);
+}
+
 // Receiver chunks of a layer evaluated with per-edge R in memory: each chunk's
 // edges hold at most the model's r_chunk_bytes of R (and of dR in the
 // adjoint), so R never needs the whole edge set at once. One chunk
@@ -2091,21 +2106,24 @@ int e3mi_profile_enable(e3mi_model* model, int enable) {
   E3MI_API_END
 }
 
+int e3mi_profile_select(e3mi_model* model, const char* stage) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
+  model->prof.only_stage = model->prof.only_layer = -1;
+  if (stage && *stage) {
+    int layer = -1;
+    model->prof.only_stage = e3mi::parse_stage(stage, &layer);
+    model->prof.only_layer = layer;
+  }
+  E3MI_API_END
+}
+
 int e3mi_profile_query(e3mi_model* model, const char* stage, double* total_ms, int64_t* launches) {
   E3MI_API_BEGIN
   E3MI_REQUIRE(model && stage && total_ms && launches, E3MI_EINVAL, "null argument");
   model->prof.drain();
-  std::string name(stage);
   int layer = -1;
-  const size_t at = name.find('@');
-  if (at != std::string::npos) {
-    layer = std::atoi(name.c_str() + at + 1);
-    name = name.substr(0, at);
-  }
-  int sid = -1;
-  for (int k = 0; k < e3mi::kNumStages; ++k)
-    if (name == e3mi::kStageNames[k]) sid = k;
-  E3MI_REQUIRE(sid >= 0, E3MI_EINVAL, "unknown stage " + name);
+  const int sid = e3mi::parse_stage(stage, &layer);
   double ms = 0.0;
   int64_t n = 0;
   for (int l = 0; l < 8; ++l) {

@@ -93,6 +93,13 @@ struct Profiler {
     hipEvent_t a, b;
   };
   bool on = false;
+  // record only this stage (-1: every stage) and, when >= 0, only this layer
+  int only_stage = -1, only_layer = -1;
+  bool wants(int stage_layer) const {
+    if (!on) return false;
+    if (only_stage >= 0 && stage_layer / 8 != only_stage) return false;
+    return only_layer < 0 || stage_layer % 8 == only_layer;
+  }
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   std::vector<double> ms;
@@ -143,7 +150,7 @@ struct ProfScope {
   hipStream_t st;
   hipEvent_t a = nullptr;
   ProfScope(Profiler* prof, int s, hipStream_t stream) : p(prof), stage(s), st(stream) {
-    if (p && p->on) {
+    if (p && p->wants(stage)) {
       a = p->get();
       E3MI_HIP(hipEventRecord(a, st));
     }
