@@ -615,11 +615,16 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
 template <int LMAX, int KIND>
 static void tp_cpt(int which, const TpArgs& a, hipStream_t st) {
   // Layers with every path keep one channel per thread (the accumulators of
-  // 99 outputs already fill the register file); the others take two.
+  // 99 outputs already fill the register file). The others run one channel
+  // per thread too (twice the workgroups: one receiver per workgroup leaves
+  // few waves per SIMD) except in the kernels that reduce over the
+  // workgroup's channels once per edge (the first-order edge adjoint's dY and
+  // the harmonic adjoints), which take the requested two.
   if constexpr (KIND == kFull) {
     if (a.cpt == 1) return tp_launch<LMAX, KIND, 1>(which, a, st);
   } else {
-    if (a.cpt == 1) return tp_launch<LMAX, KIND, 1>(which, a, st);
+    const bool reduces_per_edge = which == 1 || which == 6;
+    if (a.cpt == 1 || (a.cpt == 2 && !reduces_per_edge)) return tp_launch<LMAX, KIND, 1>(which, a, st);
     if (a.cpt == 2) return tp_launch<LMAX, KIND, 2>(which, a, st);
   }
   throw Error(E3MI_EUNSUPPORTED, "channels per thread not supported for this layer");
