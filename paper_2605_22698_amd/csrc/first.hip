@@ -211,7 +211,6 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
   constexpr int NC3 = (L3 + 1) * (L3 + 1);
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float X[kTile][kLd];   // H1, H2, then dP2
-  __shared__ float G2[kTile][kLd];  // P2, then silu'(P2)
   __shared__ float Ys[kTile][NC3 + 1];
   __shared__ float dYs[kTile][NC3 + 1];
   __shared__ int sp[kTile];
@@ -229,23 +228,33 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
   for (int e0 = row_ptr[i]; e0 < e1; e0 += kTile) {
     const int n_e = min(kTile, e1 - e0);
     __syncthreads();
-    for (int o = t; o < NN * kH; o += 256) U[o >> 6][o & 63] = dGi[o];
+    {
+      const float4* dG4 = reinterpret_cast<const float4*>(dGi);
+      for (int o = t; o < NN * kH / 4; o += 256) {
+        const float4 v = dG4[o];
+        float* u = &U[o >> 4][(o & 15) * 4];
+        u[0] = v.x;
+        u[1] = v.y;
+        u[2] = v.z;
+        u[3] = v.w;
+      }
+    }
     tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, nullptr, Ys, sp);
     __syncthreads();
     hidden1<NB>(Bs, W1, X);
     __syncthreads();
+    // H2 = silu(P2) replaces H1 in LDS; silu'(P2) of this wave's block stays in
+    // registers (the dH2 block below has the same rows and columns)
+    f32x16 sg;
     {
       const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
       const f32x16 a = block_64(X, rb, W2, kH, cb);
+      __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) G2[rb + acc_row(r, lane)][cb + (lane & 31)] = a[r];
-    }
-    __syncthreads();
-    for (int o = t; o < kTile * kH; o += 256) {
-      const int row = o >> 6, col = o & 63;
-      const float p2 = G2[row][col];
-      X[row][col] = siluf(p2);
-      G2[row][col] = silu_grad(p2);
+      for (int r = 0; r < 16; ++r) {
+        X[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(a[r]);
+        sg[r] = silu_grad(a[r]);
+      }
     }
     __syncthreads();
     // d(CY): blocks (edge block eb, column block nb) of D = H2 U^T
@@ -267,26 +276,37 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
         if (cd[k].s == sp[e]) dYs[e][cd[k].c] = a[r];
       }
     }
-    // dH2: block (eb = w & 1, qb = w >> 1), K over the (component, species) axis
+    // dH2: block (eb = w >> 1, qb = w & 1), K over the (component, species)
+    // axis; column n = kk + lane / 32 walks (c, s) incrementally
     f32x16 d2 = {};
     {
-      const int eb = w & 1, qb = w >> 1;
+      const int eb = w >> 1, qb = w & 1;
       const int e = eb * 32 + (lane & 31);
       const int se = sp[e];
+      int c = 0, s = lane >> 5;
+      if (s >= S) {
+        s -= S;
+        ++c;
+      }
       for (int kk = 0; kk < NN; kk += 2) {
-        const ColDecode c = decode(kk + (lane >> 5), NN, S);
-        const float a = (c.s == se) ? Ys[e][c.c] : 0.0f;
-        const float b = c.ok ? U[kk + (lane >> 5)][qb * 32 + (lane & 31)] : 0.0f;
+        const bool ok = c < NC3;
+        const float a = (ok && s == se) ? Ys[e][c] : 0.0f;
+        const float b = ok ? U[kk + (lane >> 5)][qb * 32 + (lane & 31)] : 0.0f;
         d2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d2, 0, 0, 0);
+        s += 2;
+        while (s >= S) {
+          s -= S;
+          ++c;
+        }
       }
     }
     __syncthreads();  // X (H2) and U (dG) no longer read
     {
-      const int eb = w & 1, qb = w >> 1;
+      const int eb = w >> 1, qb = w & 1;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int e = eb * 32 + acc_row(r, lane), q = qb * 32 + (lane & 31);
-        X[e][q] = d2[r] * G2[e][q];
+        X[e][q] = d2[r] * sg[r];
       }
     }
     __syncthreads();
@@ -371,7 +391,7 @@ static void first_launch(bool fwd, const int* row_ptr, const int* src, const flo
 // 64 of them, later reused for dP1). Kept within 64 KB.
 size_t first_lds_bytes(int l3max, int S64) {
   const size_t nc3 = (size_t)(l3max + 1) * (l3max + 1), S = (size_t)S64 / kH;
-  const size_t fixed = kTile * 9 * 4 + 2 * kTile * kLd * 4 + 2 * kTile * (nc3 + 1) * 4 + kTile * 4 + 4 * kTile * 4;
+  const size_t fixed = kTile * 9 * 4 + kTile * kLd * 4 + 2 * kTile * (nc3 + 1) * 4 + kTile * 4 + 4 * kTile * 4;
   return fixed + std::max(nc3 * S, (size_t)kTile) * kLd * 4;
 }
 

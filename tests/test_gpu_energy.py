@@ -159,6 +159,23 @@ def test_first_layer_factorisation_matches_per_edge_path():
     assert not np.array_equal(F1, F2)  # two different evaluation orders
 
 
+@pytest.mark.parametrize("n_species", [1, 5, 8])
+def test_first_layer_factorisation_other_species_counts(n_species):
+    # one species (every column of the (component, species) axis kept), an odd
+    # count and the largest the factorisation holds in LDS
+    cfg = synth.ModelConfig(lmax=3, channels=32, layers=2, n_species=n_species, cutoff=5.0,
+                            avg_neighbors=synth.nominal_neighbors(0.1, 5.0))
+    b = synth.jittered_lattice(300, 0.1, 0.3, n_species, np.random.default_rng(130 + n_species))
+    m = model(cfg, 131)
+    E1, F1, _, _ = gpu_energy_forces(m, b, skin=1.0)
+    m.set_flags(unfactorised_first_layer=True)
+    E2, F2, _, _ = gpu_energy_forces(m, b, skin=1.0)
+    say(f"species {n_species}: |dE| {abs(E1[0] - E2[0]):.1e}, max |dF| {np.abs(F1 - F2).max():.1e}")
+    assert abs(E1[0] - E2[0]) <= 1e-6 * abs(E2[0])
+    assert np.abs(F1 - F2).max() <= 1e-4 * np.abs(F2).max()
+    assert not np.array_equal(F1, F2)
+
+
 @pytest.mark.parametrize("lmax,channels", [(3, 128), (3, 64), (2, 32)])
 def test_fused_last_layer_matches_unfused_path(lmax, channels):
     cfg = synth.ModelConfig(lmax=lmax, channels=channels, layers=2, n_species=4, cutoff=5.0, avg_neighbors=52.36)
