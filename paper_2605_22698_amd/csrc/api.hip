@@ -524,9 +524,11 @@ void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
                 int out_nc, int N, hipStream_t st, bool bf16 = false) {
   const int C = M->cfg.channels;
   long gbase = 0;
+  GemmArgs grp[kMaxGemmGroup];
+  int n = 0;
   for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
     const int P3 = L.p_used_l3[l3], g = 2 * l3 + 1;
-    GemmArgs ga{};
+    GemmArgs& ga = grp[n++] = GemmArgs{};
     ga.a0 = RowMap{const_cast<float*>(A) + gbase, (long)g * P3 * C, (long)P3 * C, g};
     ga.b0 = W.mix[l3].as<float>();
     ga.ldb0 = C;
@@ -540,18 +542,20 @@ void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
     ga.c = RowMap{ht + (long)l3 * l3 * C, (long)out_nc * C, (long)C, g};
     ga.M = N * g;
     ga.Nc = C;
-    launch_gemm(ga, st, bf16);
     gbase += (long)N * g * P3 * C;
   }
+  launch_gemm_group(grp, n, st, bf16);
 }
 
 // After the product block: h~^L = B^L W_lin,L + h_in^L S_L for L <= lout.
 void launch_lin(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* B, const float* hin, float* ht,
                 int N, hipStream_t st, bool bf16) {
   const int C = M->cfg.channels;
+  GemmArgs grp[kMaxGemmGroup];
+  int n = 0;
   for (int l = 0; l <= L.lout; ++l) {
     const int g = 2 * l + 1;
-    GemmArgs ga{};
+    GemmArgs& ga = grp[n++] = GemmArgs{};
     ga.a0 = RowMap{const_cast<float*>(B) + (long)l * l * C, (long)L.nc_out * C, (long)C, g};
     ga.b0 = W.lin[l].as<float>();
     ga.ldb0 = C;
@@ -565,19 +569,21 @@ void launch_lin(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
     ga.c = RowMap{ht + (long)l * l * C, (long)L.nc_out * C, (long)C, g};
     ga.M = N * g;
     ga.Nc = C;
-    launch_gemm(ga, st, bf16);
   }
+  launch_gemm_group(grp, n, st, bf16);
 }
 
 // Adjoint of launch_lin: dB^L = dh~^L W_lin,L^T and (dprev not NULL) dprev^L = dh~^L S_L^T.
 void launch_lin_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* dht, float* dB, float* dprev,
                         int N, hipStream_t st, bool bf16) {
   const int C = M->cfg.channels;
+  GemmArgs grp[kMaxGemmGroup];
+  int n = 0;
   for (int l = 0; l <= L.lout; ++l) {
     const int g = 2 * l + 1;
     for (int which = 0; which < 2; ++which) {
       if (which == 1 && (!dprev || l > L.l1max)) continue;
-      GemmArgs ga{};
+      GemmArgs& ga = grp[n++] = GemmArgs{};
       ga.a0 = RowMap{const_cast<float*>(dht) + (long)l * l * C, (long)L.nc_out * C, (long)C, g};
       ga.b0 = which == 0 ? W.linT[l].as<float>() : W.selfT[l].as<float>();
       ga.ldb0 = C;
@@ -586,9 +592,9 @@ void launch_lin_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
                         : RowMap{dprev + (long)l * l * C, (long)L.nc_in * C, (long)C, g};
       ga.M = N * g;
       ga.Nc = C;
-      launch_gemm(ga, st, bf16);
     }
   }
+  launch_gemm_group(grp, n, st, bf16);
 }
 
 ProductArgs product_args(e3mi_model* M, e3mi_graph* G, const LayerPlan& L, LayerWeights& W, const float* at) {
@@ -610,9 +616,11 @@ void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
                         float* dprev, int N, hipStream_t st, bool bf16 = false) {
   const int C = M->cfg.channels;
   long gbase = 0;
+  GemmArgs grp[kMaxGemmGroup];
+  int n = 0;
   for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
     const int P3 = L.p_used_l3[l3], gg = 2 * l3 + 1;
-    GemmArgs ga{};
+    GemmArgs& ga = grp[n++] = GemmArgs{};
     ga.a0 = RowMap{const_cast<float*>(dht) + (long)l3 * l3 * C, (long)dht_nc * C, (long)C, gg};
     ga.b0 = W.mixT[l3].as<float>();
     ga.ldb0 = P3 * C;
@@ -620,13 +628,11 @@ void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
     ga.c = RowMap{dA + gbase, (long)gg * P3 * C, (long)P3 * C, gg};
     ga.M = N * gg;
     ga.Nc = P3 * C;
-    launch_gemm(ga, st, bf16);
     gbase += (long)N * gg * P3 * C;
   }
-  if (!dprev) return;
-  for (int l3 = 0; l3 <= std::min(L.l3max_used, L.l1max); ++l3) {
+  for (int l3 = 0; dprev && l3 <= std::min(L.l3max_used, L.l1max); ++l3) {
     const int gg = 2 * l3 + 1;
-    GemmArgs ga{};
+    GemmArgs& ga = grp[n++] = GemmArgs{};
     ga.a0 = RowMap{const_cast<float*>(dht) + (long)l3 * l3 * C, (long)dht_nc * C, (long)C, gg};
     ga.b0 = W.selfT[l3].as<float>();
     ga.ldb0 = C;
@@ -634,8 +640,8 @@ void launch_mix_adjoint(e3mi_model* M, const LayerPlan& L, LayerWeights& W, cons
     ga.c = RowMap{dprev + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, gg};
     ga.M = N * gg;
     ga.Nc = C;
-    launch_gemm(ga, st, bf16);
   }
+  launch_gemm_group(grp, n, st, bf16);
 }
 
 // Whether the energy/force path evaluates layer 1 through the species
@@ -835,9 +841,11 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
       const int mix_nc = prod ? L.nc_a : L.nc_out;
       {
         ProfScope ps(&M->prof, stage_id(kMixFwd, 1), st);
+        GemmArgs grp[kMaxGemmGroup];
+        int n = 0;
         for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
           const int g = 2 * l3 + 1;
-          GemmArgs ga{};
+          GemmArgs& ga = grp[n++] = GemmArgs{};
           ga.a0 = RowMap{G1 + (long)l3 * l3 * S64, (long)L.nc_a * S64, (long)S64, g};
           ga.b0 = M->U[l3]->as<float>();
           ga.ldb0 = C;
@@ -851,8 +859,8 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
           ga.c = RowMap{mix_out + (long)l3 * l3 * C, (long)mix_nc * C, (long)C, g};
           ga.M = N * g;
           ga.Nc = C;
-          launch_gemm(ga, st, bf16);
         }
+        launch_gemm_group(grp, n, st, bf16);
       }
       if (prod) product_tail(1, L, W, hin, ht);
       {
@@ -1015,9 +1023,11 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       float* dG1 = w.dG1->as<float>();
       {
         ProfScope ps(&M->prof, stage_id(kMixBwd, 1), st);
+        GemmArgs grp[kMaxGemmGroup];
+        int n = 0;
         for (int l3 = 0; l3 <= L.l3max_used; ++l3) {
           const int gg = 2 * l3 + 1;
-          GemmArgs ga{};
+          GemmArgs& ga = grp[n++] = GemmArgs{};
           ga.a0 = RowMap{const_cast<float*>(dmix) + (long)l3 * l3 * C, (long)dmix_nc * C, (long)C, gg};
           ga.b0 = M->UT[l3]->as<float>();
           ga.ldb0 = S64;
@@ -1025,8 +1035,8 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
           ga.c = RowMap{dG1 + (long)l3 * l3 * S64, (long)L.nc_a * S64, (long)S64, gg};
           ga.M = N * gg;
           ga.Nc = S64;
-          launch_gemm(ga, st, M->precision == E3MI_BF16_MIX);
         }
+        launch_gemm_group(grp, n, st, M->precision == E3MI_BF16_MIX);
       }
       {
         ProfScope ps(&M->prof, stage_id(kFirstBwd, 1), st);

@@ -25,47 +25,83 @@ __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 
 // operand pairs in slabs of 32 staged through LDS; the next slab is fetched
 // into registers while the current one is multiplied.
 constexpr int kSlab = 32;
+constexpr int kPer = kSlab / 16;  // float4 of each operand per thread and slab
+constexpr int kRowQ = kSlab / 4;  // float4 per row of an A slab
 
 struct Slab {
-  float4 a[2], b[2];
+  float4 a[kPer], b[kPer];
 };
 
-__device__ __forceinline__ void gemm_load_slab(const GemmArgs& a, int s, int s0, int bm, int bn, Slab& r) {
+// Slab s of the K loop (products 0 then 1) into registers: A through the row
+// pointers of the rows this thread stages (null past M), B row-major.
+__device__ __forceinline__ void gemm_load_slab(const GemmArgs& a, const float* const* ap0, const float* const* ap1,
+                                               int s, int s0, int bn, Slab& r) {
   const int t = threadIdx.x;
   const int op = s >= s0;
-  const RowMap am = op ? a.a1 : a.a0;
   const float* __restrict__ B = op ? a.b1 : a.b0;
   const int ldb = op ? a.ldb1 : a.ldb0;
   const int K = op ? a.k1 : a.k0;
   const int k0 = (op ? s - s0 : s) * kSlab;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < kPer; ++i) {
     const int idx = t + 256 * i;
-    const int row = idx >> 3, kq = (idx & 7) * 4, gr = bm + row;
-    r.a[i] = (gr < a.M && k0 + kq < K) ? *reinterpret_cast<const float4*>(am.base + row_off(am, gr) + k0 + kq)
-                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int kq = (idx % kRowQ) * 4;
+    const float* p = op ? ap1[i] : ap0[i];
+    r.a[i] = (p && k0 + kq < K) ? *reinterpret_cast<const float4*>(p + k0 + kq) : make_float4(0.f, 0.f, 0.f, 0.f);
     const int kr = idx >> 4, c4 = (idx & 15) * 4, gk = k0 + kr, gc = bn + c4;
     r.b[i] = (gk < K && gc < a.Nc) ? *reinterpret_cast<const float4*>(B + (long)gk * ldb + gc)
                                    : make_float4(0.f, 0.f, 0.f, 0.f);
   }
 }
 
+// Independent products of one group share a launch: workgroup b (after the
+// XCD-contiguous remapping, so that the column blocks of a row tile and
+// neighbouring row tiles meet in one L2) takes tile b - tile0[k] of product k,
+// column blocks fastest.
+struct GemmGroup {
+  GemmArgs g[kMaxGemmGroup];
+  int tile0[kMaxGemmGroup + 1];
+  int ncb[kMaxGemmGroup];
+  int n;
+};
+
 template <bool BF>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs a) {
+__global__ void __launch_bounds__(256) k_gemm(GemmGroup gg) {
   __shared__ float As[64][kSlab + 1];
   __shared__ float Bs[kSlab][65];
-  const int bm = blockIdx.x * 64, bn = blockIdx.y * 64;
+  __shared__ long coff[64];  // offsets of the tile's output rows (-1 past M)
+  const int b = xcd_contiguous(blockIdx.x, gridDim.x);
+  int gi = 0;
+  while (gi + 1 < gg.n && b >= gg.tile0[gi + 1]) ++gi;
+  const GemmArgs& a = gg.g[gi];
+  const int local = b - gg.tile0[gi];
+  const int bm = (local / gg.ncb[gi]) * 64, bn = (local % gg.ncb[gi]) * 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
   const int s0 = (a.k0 + kSlab - 1) / kSlab, ns = s0 + (a.k1 + kSlab - 1) / kSlab;
+  // row offsets (a division by the rows per atom each) once per tile, not per slab
+  if (t < 64) {
+    const int r = bm + t;
+    coff[t] = r < a.M ? row_off(a.c, r) : -1;
+  }
+  const float* ap0[kPer];
+  const float* ap1[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int gr = bm + (t + 256 * i) / kRowQ;
+    const bool in = gr < a.M;
+    ap0[i] = in ? a.a0.base + row_off(a.a0, gr) : nullptr;
+    ap1[i] = (in && a.k1 > 0) ? a.a1.base + row_off(a.a1, gr) : nullptr;
+  }
   f32x16 acc = {};
   Slab cur;
-  if (ns > 0) gemm_load_slab(a, 0, s0, bm, bn, cur);
+  if (ns > 0) gemm_load_slab(a, ap0, ap1, 0, s0, bn, cur);
+  else __syncthreads();
   for (int s = 0; s < ns; ++s) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < kPer; ++i) {
       const int idx = t + 256 * i;
-      const int row = idx >> 3, kq = (idx & 7) * 4;
+      const int row = idx / kRowQ, kq = (idx % kRowQ) * 4;
       As[row][kq] = cur.a[i].x;
       As[row][kq + 1] = cur.a[i].y;
       As[row][kq + 2] = cur.a[i].z;
@@ -77,7 +113,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs a) {
       Bs[kr][c4 + 3] = cur.b[i].w;
     }
     __syncthreads();
-    if (s + 1 < ns) gemm_load_slab(a, s + 1, s0, bm, bn, cur);
+    if (s + 1 < ns) gemm_load_slab(a, ap0, ap1, s + 1, s0, bn, cur);
     if constexpr (BF) {
 #pragma unroll
       for (int kb = 0; kb < kSlab; kb += 16) {
@@ -102,9 +138,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs a) {
   if (col < a.Nc) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int row = bm + rb + acc_row(r, lane);
-      if (row < a.M) {
-        float* p = a.c.base + row_off(a.c, row) + col;
+      const long o = coff[rb + acc_row(r, lane)];
+      if (o >= 0) {
+        float* p = a.c.base + o + col;
         *p = a.accumulate ? *p + acc[r] : acc[r];
       }
     }
@@ -248,15 +284,29 @@ inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-void launch_gemm(const GemmArgs& a, hipStream_t st, bool bf16) {
-  if (a.M == 0 || a.Nc == 0) return;
-  if ((a.k0 % 4) || (a.k1 % 4) || (a.Nc % 4) || (a.ldb0 % 4) || (a.k1 && (a.ldb1 % 4)))
-    throw Error(E3MI_EUNSUPPORTED, "GEMM dimensions must be multiples of 4");
-  dim3 grid(blocks(a.M, 64), blocks(a.Nc, 64));
+void launch_gemm(const GemmArgs& a, hipStream_t st, bool bf16) { launch_gemm_group(&a, 1, st, bf16); }
+
+void launch_gemm_group(const GemmArgs* a, int n, hipStream_t st, bool bf16) {
+  if (n < 1 || n > kMaxGemmGroup) throw Error(E3MI_EINVAL, "GEMM group size out of range");
+  GemmGroup gg{};
+  int tiles = 0, m = 0;
+  for (int k = 0; k < n; ++k) {
+    if (a[k].M == 0 || a[k].Nc == 0) continue;
+    if ((a[k].k0 % 4) || (a[k].k1 % 4) || (a[k].Nc % 4) || (a[k].ldb0 % 4) || (a[k].k1 && (a[k].ldb1 % 4)))
+      throw Error(E3MI_EUNSUPPORTED, "GEMM dimensions must be multiples of 4");
+    gg.g[m] = a[k];
+    gg.tile0[m] = tiles;
+    gg.ncb[m] = (int)blocks(a[k].Nc, 64);
+    tiles += (int)blocks(a[k].M, 64) * gg.ncb[m];
+    ++m;
+  }
+  if (m == 0) return;
+  gg.tile0[m] = tiles;
+  gg.n = m;
   if (bf16)
-    k_gemm<true><<<grid, 256, 0, st>>>(a);
+    k_gemm<true><<<tiles, 256, 0, st>>>(gg);
   else
-    k_gemm<false><<<grid, 256, 0, st>>>(a);
+    k_gemm<false><<<tiles, 256, 0, st>>>(gg);
 }
 void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st) {
   if (N == 0) return;

@@ -259,6 +259,10 @@ struct GemmArgs {
   int M, Nc, accumulate;
 };
 void launch_gemm(const GemmArgs& a, hipStream_t st, bool bf16 = false);
+// Up to kMaxGemmGroup independent products (no output read or written by
+// another of the group) in one launch.
+constexpr int kMaxGemmGroup = 8;
+void launch_gemm_group(const GemmArgs* a, int n, hipStream_t st, bool bf16 = false);
 void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st);
 void launch_gate_bwd(const float* ht, const float* dh, float* dht, int N, int nc, int C, hipStream_t st);
 void launch_embed(const int* species, const float* emb, float* h0, int N, int C, hipStream_t st);
