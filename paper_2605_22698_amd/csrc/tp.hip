@@ -30,6 +30,36 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// Sums of NV <= 16 per-lane values over the 64 lanes of a wave, by recursive
+// halving: each exchange over lane bits 5, 4, 3, 2 hands the partner the half
+// of the values this lane does not keep, so lane L ends with a partial of
+// value q = L >> 2, which the exchanges over bits 1 and 0 complete (17 lane
+// exchanges where 16 butterfly reductions take 96). Returns the total of
+// value lane >> 2 (zero for q >= NV).
+template <int NV>
+__device__ __forceinline__ float wave_sum_scatter16(const float* v) {
+  static_assert(NV <= 16, "at most 16 values");
+  const int lane = threadIdx.x & 63;
+  float a[8], b[4], c[2];
+  bool hi = lane & 32;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float lo_v = q < NV ? v[q] : 0.0f, hi_v = q + 8 < NV ? v[q + 8] : 0.0f;
+    a[q] = (hi ? hi_v : lo_v) + __shfl_xor(hi ? lo_v : hi_v, 32);
+  }
+  hi = lane & 16;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) b[q] = (hi ? a[q + 4] : a[q]) + __shfl_xor(hi ? a[q] : a[q + 4], 16);
+  hi = lane & 8;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) c[q] = (hi ? b[q + 2] : b[q]) + __shfl_xor(hi ? b[q] : b[q + 2], 8);
+  hi = lane & 4;
+  float d = (hi ? c[1] : c[0]) + __shfl_xor(hi ? c[0] : c[1], 4);
+  d += __shfl_xor(d, 2);
+  d += __shfl_xor(d, 1);
+  return d;
+}
+
 template <int LMAX, int KIND, int CPT>
 __global__ void __launch_bounds__(256) k_tp_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                 const float4* __restrict__ dvec, const float* __restrict__ R,
@@ -163,20 +193,12 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
     }
     // reduce dY over the channels of the workgroup
     if (tpr >= 64) {
-#pragma unroll
-      for (int q = 0; q < NY; ++q) dyp[q] = group_sum<64>(dyp[q]);
+      const float tot = wave_sum_scatter16<NY>(dyp);
+      const int q = lane >> 2;
       if (tpr == 64) {
-        if (lane < NY) {
-          float v = 0.0f;
-#pragma unroll
-          for (int q = 0; q < NY; ++q) v = lane == q ? dyp[q] : v;
-          dY[(long)e * 16 + lane] = v;
-        }
+        if ((lane & 3) == 0 && q < NY) dY[(long)e * 16 + q] = tot;
       } else {
-        if (lane == 0) {
-#pragma unroll
-          for (int q = 0; q < NY; ++q) red[wave][q] = dyp[q];
-        }
+        if ((lane & 3) == 0) red[wave][q] = tot;
         __syncthreads();
         if (threadIdx.x < NY) {
           float v = 0.0f;
@@ -540,17 +562,10 @@ __global__ void __launch_bounds__(256) k_tp_dual_geo(const int* __restrict__ row
     }
     // reduce over the channels of the workgroup
     if (tpr >= 64) {
-#pragma unroll
-      for (int q = 0; q < NY; ++q) {
-        yb[q] = group_sum<64>(yb[q]);
-        yc[q] = group_sum<64>(yc[q]);
-      }
-      if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < NY; ++q) {
-          red[wave][q] = yb[q];
-          red[wave][16 + q] = yc[q];
-        }
+      const float tb = wave_sum_scatter16<NY>(yb), tc = wave_sum_scatter16<NY>(yc);
+      if ((lane & 3) == 0) {
+        red[wave][lane >> 2] = tb;
+        red[wave][16 + (lane >> 2)] = tc;
       }
     } else {
 #pragma unroll
