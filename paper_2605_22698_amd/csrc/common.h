@@ -12,7 +12,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
 
-__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
+// logistic function with the hardware reciprocal (v_rcp_f32, 1 ulp) in place
+// of a correctly rounded division: 1 + exp(-x) >= 1, so no denormal input
+__device__ __forceinline__ float sigmoidf(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 __device__ __forceinline__ float siluf(float x) { return x * sigmoidf(x); }
 // d silu / dx = s + x s (1 - s)
 __device__ __forceinline__ float silu_grad(float x) {
