@@ -120,22 +120,36 @@ __device__ __forceinline__ void hidden1(const float (*Bs)[NB + 1], const float* 
   }
 }
 
-// Column n of the (component, species) axis: n = c S + s.
-struct ColDecode {
-  int c, s;
-  bool ok;
-};
-__device__ __forceinline__ ColDecode decode(int n, int NN, int S) {
-  ColDecode d;
-  d.ok = n < NN;
-  d.c = d.ok ? n / S : 0;
-  d.s = d.ok ? n - d.c * S : -1;
-  return d;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Forward: G_i[n = (c, s), q] = sum_e [z_j(e) = s] (CY)_e[c] H2_e[q], a product
-// over the receiver's edges on the matrix cores (A = species-masked CY^T,
-// B = H2), accumulated across tiles in registers.
+// The tile's edges grouped by sender species, a stable counting sort by wave
+// 0: rows perm[start[s] .. start[s] + cnt[s]) of the tile have z_j = s.
+__device__ __forceinline__ void species_lists(const int* sp, int n_e, int S, int* perm, int* start, int* cnt) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const bool valid = lane < n_e;
+    const int z = sp[lane];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int base = 0;
+    for (int s = 0; s < S; ++s) {
+      const unsigned long long m = __ballot(valid && z == s);
+      if (valid && z == s) perm[base + __popcll(m & below)] = lane;
+      if (lane == 0) {
+        start[s] = base;
+        cnt[s] = __popcll(m);
+      }
+      base += __popcll(m);
+    }
+  }
+}
+
+// Forward: G_i[n = (c, s), q] = sum_e [z_j(e) = s] (CY)_e[c] H2_e[q]. For each
+// species, a 16 (component) x 64 (q) product over that species' edges of the
+// tile on the matrix cores (16x16x4 steps over groups of 4 edges), accumulated
+// across tiles in registers; wave w takes species w and w + 4.
 template <int LMAX, int L3>
 __global__ void __launch_bounds__(256) k_first_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                    const float4* __restrict__ dvec, const int* __restrict__ species,
@@ -147,19 +161,23 @@ __global__ void __launch_bounds__(256) k_first_fwd(const int* __restrict__ row_p
   __shared__ float X[kTile][kLd];
   __shared__ float Ys[kTile][NC3 + 1];
   __shared__ int sp[kTile];
+  __shared__ int perm[kTile], start[8], cnt[8];
   const int i = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int NN = NC3 * S, NBLK = 2 * ((NN + 31) / 32);
-  f32x16 acc[2] = {f32x16{}, f32x16{}};
-  ColDecode cd[2];
+  const int NN = NC3 * S;
+  const int c = lane & 15, h = lane >> 4;
+  f32x4 acc[2][4];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) cd[k] = decode(((w + 4 * k) >> 1) * 32 + (lane & 31), NN, S);
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) acc[j][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int e1 = row_ptr[i + 1];
   for (int e0 = row_ptr[i]; e0 < e1; e0 += kTile) {
     const int n_e = min(kTile, e1 - e0);
     __syncthreads();
     tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, nullptr, Ys, sp);
     __syncthreads();
+    species_lists(sp, n_e, S, perm, start, cnt);
     hidden1<NB>(Bs, W1, X);
     __syncthreads();
     {
@@ -170,34 +188,39 @@ __global__ void __launch_bounds__(256) k_first_fwd(const int* __restrict__ row_p
       for (int r = 0; r < 16; ++r) X[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(a[r]);
     }
     __syncthreads();
-    for (int kk = 0; kk < n_e; kk += 2) {
-      const int e = kk + (lane >> 5);
-      const int se = sp[e];
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int blk = w + 4 * k;
-        if (blk >= NBLK) break;
-        const float a = (cd[k].s == se) ? Ys[e][cd[k].c] : 0.0f;
-        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, X[e][(blk & 1) * 32 + (lane & 31)], acc[k], 0, 0, 0);
+    for (int j = 0; j < 2; ++j) {
+      const int s = w + 4 * j;
+      if (s >= S) break;
+      const int s0 = start[s], ns = cnt[s];
+      for (int kk = 0; kk < ns; kk += 4) {
+        const int e = kk + h < ns ? perm[s0 + kk + h] : -1;
+        const float a = (e >= 0 && c < NC3) ? Ys[e][c] : 0.0f;
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[j][nb] = mfma16(a, e >= 0 ? X[e][nb * 16 + c] : 0.0f, acc[j][nb]);
       }
     }
   }
   float* Gi = G + (long)i * NN * kH;
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int blk = w + 4 * k;
-    if (blk >= NBLK) break;
+  for (int j = 0; j < 2; ++j) {
+    const int s = w + 4 * j;
+    if (s >= S) break;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int n = (blk >> 1) * 32 + acc_row(r, lane);
-      if (n < NN) Gi[n * kH + (blk & 1) * 32 + (lane & 31)] = acc[k][r];
+    for (int r = 0; r < 4; ++r) {
+      const int cc = 4 * h + r;
+      if (cc < NC3) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) Gi[(cc * S + s) * kH + nb * 16 + c] = acc[j][nb][r];
+      }
     }
   }
 }
 
-// Adjoint, from dG (= dh~ U^T) of the receiver, held in LDS as U[n][q]:
-//   d(CY)_e[c] = D[e, (c, z_j)],  D = H2 U^T          (matrix cores, all species)
-//   dH2[e, q]  = sum_n [z_j = s_n] (CY)_e[c_n] U[n, q]  (matrix cores)
+// Adjoint, from dG (= dh~ U^T) of the receiver, held in LDS as U[n][q]; for
+// the edges of each sender species s (blocks of 16, 16x16x4 matrix-core steps):
+//   d(CY)_e[c] = sum_q H2[e, q] U[(c, s), q]
+//   dH2[e, q]  = sum_c (CY)_e[c] U[(c, s), q]
 //   dP2 = dH2 o silu'(P2), dH1 = dP2 W2^T, dP1 = dH1 o silu'(B W1),
 //   dr = sum_n (dP1 . W1[n, :]) dB_n/dr, and d(CY) -> dY -> direction,
 // giving g_e = dE/dd_e (added to the other layers' contributions).
@@ -215,15 +238,14 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
   __shared__ float dYs[kTile][NC3 + 1];
   __shared__ int sp[kTile];
   __shared__ float drs[4][kTile];
+  __shared__ int perm[kTile], start[8], cnt[8];
   extern __shared__ float Ub[];     // [max(NN, 64)][kLd]: the receiver's dG, then dP1
   float (*U)[kLd] = reinterpret_cast<float (*)[kLd]>(Ub);
   const int i = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int NN = NC3 * S, NBLK = 2 * ((NN + 31) / 32);
+  const int NN = NC3 * S;
+  const int c16 = lane & 15, h4 = lane >> 4;
   const float* dGi = dG + (long)i * NN * kH;
-  ColDecode cd[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) cd[k] = decode(((w + 4 * k) >> 1) * 32 + (lane & 31), NN, S);
   const int e1 = row_ptr[i + 1];
   for (int e0 = row_ptr[i]; e0 < e1; e0 += kTile) {
     const int n_e = min(kTile, e1 - e0);
@@ -241,6 +263,7 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
     }
     tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, nullptr, Ys, sp);
     __syncthreads();
+    species_lists(sp, n_e, S, perm, start, cnt);
     hidden1<NB>(Bs, W1, X);
     __syncthreads();
     // H2 = silu(P2) replaces H1 in LDS; silu'(P2) of this wave's block stays in
@@ -257,56 +280,74 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
       }
     }
     __syncthreads();
-    // d(CY): blocks (edge block eb, column block nb) of D = H2 U^T
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int blk = w + 4 * k;
-      if (blk >= NBLK) break;
-      const int eb = blk & 1, n = (blk >> 1) * 32 + (lane & 31);
-      f32x16 a = {};
-#pragma unroll 8
-      for (int kk = 0; kk < kH; kk += 2) {
-        const int q = kk + (lane >> 5);
-        a = __builtin_amdgcn_mfma_f32_32x32x2f32(X[eb * 32 + (lane & 31)][q], cd[k].ok ? U[n][q] : 0.0f, a, 0, 0,
-                                                 0);
+    // Work items (species s, block of 16 of its edges), dealt to the waves in
+    // turn; blocks of 16 rows of perm (padded with -1).
+    int n_items = 0;
+    for (int s = 0; s < S; ++s) n_items += (cnt[s] + 15) >> 4;
+    auto item = [&](int it, int& s, int& eb) {
+      s = 0;
+      for (;; ++s) {
+        const int nb = (cnt[s] + 15) >> 4;
+        if (it < nb) break;
+        it -= nb;
+      }
+      eb = it;
+    };
+    // d(CY)_e[c] = sum_q H2[e, q] U[(c, s), q] for the edges of species s
+    // (16 edges x 16 components, K = 64 in steps of 4)
+    for (int it = w; it < n_items; it += 4) {
+      int s, eb;
+      item(it, s, eb);
+      const int s0 = start[s], ns = cnt[s];
+      const int ea = eb * 16 + c16 < ns ? perm[s0 + eb * 16 + c16] : -1;
+      f32x4 a = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+      for (int kk = 0; kk < kH; kk += 4) {
+        const int q = kk + h4;
+        a = mfma16(ea >= 0 ? X[ea][q] : 0.0f, c16 < NC3 ? U[c16 * S + s][q] : 0.0f, a);
       }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int e = eb * 32 + acc_row(r, lane);
-        if (cd[k].s == sp[e]) dYs[e][cd[k].c] = a[r];
+      for (int r = 0; r < 4; ++r) {
+        const int el = eb * 16 + 4 * h4 + r;
+        if (el < ns && c16 < NC3) dYs[perm[s0 + el]][c16] = a[r];
       }
     }
-    // dH2: block (eb = w >> 1, qb = w & 1), K over the (component, species)
-    // axis; column n = kk + lane / 32 walks (c, s) incrementally
-    f32x16 d2 = {};
-    {
-      const int eb = w >> 1, qb = w & 1;
-      const int e = eb * 32 + (lane & 31);
-      const int se = sp[e];
-      int c = 0, s = lane >> 5;
-      if (s >= S) {
-        s -= S;
-        ++c;
+    __syncthreads();  // H2 no longer read: X takes dH2
+    // dH2[e, q] = sum_c (CY)_e[c] U[(c, s), q] (16 edges x 64 q, K = NC3 <= 16)
+    for (int it = w; it < n_items; it += 4) {
+      int s, eb;
+      item(it, s, eb);
+      const int s0 = start[s], ns = cnt[s];
+      const int ea = eb * 16 + c16 < ns ? perm[s0 + eb * 16 + c16] : -1;
+      f32x4 a[4];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) a[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < NC3; kk += 4) {
+        const int cc = kk + h4;
+        const bool ok = cc < NC3;
+        const float av = (ea >= 0 && ok) ? Ys[ea][cc] : 0.0f;
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) a[nb] = mfma16(av, ok ? U[cc * S + s][nb * 16 + c16] : 0.0f, a[nb]);
       }
-      for (int kk = 0; kk < NN; kk += 2) {
-        const bool ok = c < NC3;
-        const float a = (ok && s == se) ? Ys[e][c] : 0.0f;
-        const float b = ok ? U[kk + (lane >> 5)][qb * 32 + (lane & 31)] : 0.0f;
-        d2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, d2, 0, 0, 0);
-        s += 2;
-        while (s >= S) {
-          s -= S;
-          ++c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int el = eb * 16 + 4 * h4 + r;
+        if (el < ns) {
+          const int e = perm[s0 + el];
+#pragma unroll
+          for (int nb = 0; nb < 4; ++nb) X[e][nb * 16 + c16] = a[nb][r];
         }
       }
     }
-    __syncthreads();  // X (H2) and U (dG) no longer read
+    __syncthreads();
     {
-      const int eb = w >> 1, qb = w & 1;
+      // dP2 = dH2 silu'(P2) in the P2 block layout (rows past the tile's edges zeroed)
+      const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int e = eb * 32 + acc_row(r, lane), q = qb * 32 + (lane & 31);
-        X[e][q] = d2[r] * sg[r];
+        const int e = rb + acc_row(r, lane), q = cb + (lane & 31);
+        X[e][q] = e < n_e ? X[e][q] * sg[r] : 0.0f;
       }
     }
     __syncthreads();
