@@ -209,6 +209,7 @@ struct Workspace {
   std::vector<int> rp_host;                            // pruned row pointer on the host (receiver chunks)
   bool rp_valid = false;
   std::unique_ptr<DevBuf> Bp, dat;                     // product block: B (or dB), dA~
+  std::unique_ptr<DevBuf> mixp;                        // partial products of a K-split channel mix
 };
 
 }  // namespace e3mi
@@ -548,6 +549,45 @@ void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
 }
 
 // After the product block: h~^L = B^L W_lin,L + h_in^L S_L for L <= lout.
+// Channel mix of a scalar-output layer split over K into independent partial
+// products of 128 K each (one grouped launch): with one scalar row per atom
+// the 64 x 64 output tiles are too few to fill the GPU for small systems, and
+// each workgroup then walks a fifth of the K slabs. The split depends on K
+// only, so an atom's result does not depend on what else is in the batch.
+// Partial j goes to part + j N C; returns the number of parts written.
+int mix_split_parts(int K) { return std::max(1, std::min(kMaxGemmGroup, K / 128)); }
+int launch_mix_scalar_split(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* A, const float* hin,
+                            float* part, int parts, int N, hipStream_t st, bool bf16) {
+  const int C = M->cfg.channels;
+  const int KA = L.p_used_l3[0] * C, KS = hin ? C : 0, K = KA + KS;
+  const int units = (K + 31) / 32;
+  GemmArgs grp[kMaxGemmGroup];
+  int n = 0;
+  for (int j = 0; j < parts; ++j) {
+    const int kb = std::min(K, units * j / parts * 32), ke = std::min(K, units * (j + 1) / parts * 32);
+    if (kb >= ke) continue;
+    GemmArgs& ga = grp[n] = GemmArgs{};
+    const int a_hi = std::min(ke, KA);
+    ga.a0 = RowMap{const_cast<float*>(A) + std::min(kb, KA), (long)KA, (long)KA, 1};
+    ga.b0 = W.mix[0].as<float>() + (long)std::min(kb, KA) * C;
+    ga.ldb0 = C;
+    ga.k0 = std::max(0, a_hi - kb);
+    const int s_lo = std::max(kb, KA) - KA, s_hi = ke - KA;
+    if (s_hi > s_lo) {
+      ga.a1 = RowMap{const_cast<float*>(hin) + s_lo, (long)L.nc_in * C, (long)C, 1};
+      ga.b1 = W.self_[0].as<float>() + (long)s_lo * C;
+      ga.ldb1 = C;
+      ga.k1 = s_hi - s_lo;
+    }
+    ga.c = RowMap{part + (long)n * N * C, (long)C, (long)C, 1};
+    ga.M = N;
+    ga.Nc = C;
+    ++n;
+  }
+  launch_gemm_group(grp, n, st, bf16);
+  return n;
+}
+
 void launch_lin(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* B, const float* hin, float* ht,
                 int N, hipStream_t st, bool bf16) {
   const int C = M->cfg.channels;
@@ -917,17 +957,26 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
       launch_tp(0, ta, st);
     }
     float* ht = w.ht[t]->as<float>();
+    const int split = (!prod && L.nc_out == 1) ? mix_split_parts(L.p_used_l3[0] * C + (hin ? C : 0)) : 1;
+    int n_parts = 0;
     {
       ProfScope ps(&M->prof, stage_id(kMixFwd, t), st);
-      if (prod)
+      if (prod) {
         launch_mix(M, L, W, A, nullptr, w.at[t]->as<float>(), L.nc_a, N, st, bf16);
-      else
+      } else if (split > 1) {
+        float* part = ensure(w.mixp, &M->alloc, sizeof(float) * (size_t)split * N * C).as<float>();
+        n_parts = launch_mix_scalar_split(M, L, W, A, hin, part, split, N, st, bf16);
+      } else {
         launch_mix(M, L, W, A, hin, ht, L.nc_out, N, st, bf16);
+      }
     }
     if (prod) product_tail(t, L, W, hin, ht);
     {
       ProfScope ps(&M->prof, stage_id(kGateFwd, t), st);
-      launch_gate_fwd(ht, w.h[t]->as<float>(), N, L.nc_out, C, st);
+      if (n_parts > 0)
+        launch_gate_fwd_sum(w.mixp->as<float>(), n_parts, ht, w.h[t]->as<float>(), N, C, st);
+      else
+        launch_gate_fwd(ht, w.h[t]->as<float>(), N, L.nc_out, C, st);
     }
   }
 }
@@ -1670,15 +1719,15 @@ void md_step(e3mi_md* D, int n_steps, double dt, double* energy_out, hipStream_t
   for (int s = 0; s < n_steps; ++s) {
     {
       ProfScope ps(&D->model->prof, stage_id(kMdUpdate), st);
-      launch_kick(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(), hk,
-                  D->N, st);
       if (!langevin) {
-        launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), dt, lim * lim, D->N,
-                     D->flag->as<int>(), st);
+        launch_kick_drift(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(),
+                          hk, D->x->as<double>(), G->x_ref->as<double>(), dt, lim * lim, D->N, D->flag->as<int>(),
+                          st);
       } else {
-        // BAOAB: half drift, Ornstein-Uhlenbeck velocity update, half drift
-        launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), 0.5 * dt,
-                     std::numeric_limits<double>::infinity(), D->N, D->flag->as<int>(), st);
+        // BAOAB: half kick and half drift, Ornstein-Uhlenbeck velocity update, half drift
+        launch_kick_drift(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(),
+                          hk, D->x->as<double>(), G->x_ref->as<double>(), 0.5 * dt,
+                          std::numeric_limits<double>::infinity(), D->N, D->flag->as<int>(), st);
         launch_ou(D->v->as<double>(), D->species->as<int>(), D->inv_mass->as<double>(), G->owner->as<int>(),
                   G->off_d->as<int64_t>(), D->seeds->as<uint64_t>(), D->step0->as<int64_t>(), D->steps, c1, c2,
                   kBoltzmannEv * D->temperature * kAccelUnit, D->N, st);
@@ -1699,11 +1748,15 @@ void md_step(e3mi_md* D, int n_steps, double dt, double* energy_out, hipStream_t
       md_rebuild(D, st);
     }
     energy_forces(D->model, G, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
+    // the last step of the call hands the energies out in its kick launch
+    // (unless a barostat move may still change them)
+    const bool copy_here = energy_out && s + 1 == n_steps && D->baro_interval <= 0;
     {
       ProfScope ps(&D->model->prof, stage_id(kMdUpdate), st);
-      launch_kick(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(), hk,
-                  D->N, st);
+      launch_kick_copy(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(), hk,
+                       D->N, D->energy->as<double>(), energy_out, copy_here ? D->S : 0, st);
     }
+    if (copy_here) energy_out = nullptr;
     D->steps++;
     if (D->baro_interval > 0) {
       // each structure proposes on its own schedule, so the moves do not

@@ -29,6 +29,41 @@ __global__ void k_kick(double* __restrict__ v, const float* __restrict__ F, cons
   v[3 * i + 2] += c * (double)F[3 * i + 2];
 }
 
+// Half kick followed by the drift with the kicked velocity (one pass over the
+// atoms; the arithmetic of k_kick then k_drift)
+__global__ void k_kick_drift(double* __restrict__ v, const float* __restrict__ F, const int* __restrict__ species,
+                             const double* __restrict__ inv_mass, double half_dt_kappa, double* __restrict__ x,
+                             const double* __restrict__ x_ref, double dt, double limit2, int N,
+                             int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double c = half_dt_kappa * inv_mass[species[i]];
+  double d2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double vk = v[3 * i + k] + c * (double)F[3 * i + k];
+    v[3 * i + k] = vk;
+    const double y = x[3 * i + k] + dt * vk;
+    x[3 * i + k] = y;
+    const double d = y - x_ref[3 * i + k];
+    d2 += d * d;
+  }
+  if (d2 > limit2) atomicOr(flag, 1);
+}
+
+// Half kick; threads below n_copy also copy the structures' energies out
+__global__ void k_kick_copy(double* __restrict__ v, const float* __restrict__ F, const int* __restrict__ species,
+                            const double* __restrict__ inv_mass, double half_dt_kappa, int N,
+                            const double* __restrict__ e_src, double* __restrict__ e_dst, int n_copy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_copy) e_dst[i] = e_src[i];
+  if (i >= N) return;
+  const double c = half_dt_kappa * inv_mass[species[i]];
+  v[3 * i] += c * (double)F[3 * i];
+  v[3 * i + 1] += c * (double)F[3 * i + 1];
+  v[3 * i + 2] += c * (double)F[3 * i + 2];
+}
+
 __global__ void k_drift(double* __restrict__ x, const double* __restrict__ v, const double* __restrict__ x_ref,
                         double dt, double limit2, int N, int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,6 +154,17 @@ void launch_kick(double* v, const float* F, const int* species, const double* in
                  hipStream_t st) {
   if (N == 0) return;
   k_kick<<<blocks(N, 256), 256, 0, st>>>(v, F, species, inv_mass, half_dt_kappa, N);
+}
+void launch_kick_drift(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa,
+                       double* x, const double* x_ref, double dt, double limit2, int N, int* flag, hipStream_t st) {
+  if (N == 0) return;
+  k_kick_drift<<<blocks(N, 256), 256, 0, st>>>(v, F, species, inv_mass, half_dt_kappa, x, x_ref, dt, limit2, N, flag);
+}
+void launch_kick_copy(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa,
+                      int N, const double* e_src, double* e_dst, int n_copy, hipStream_t st) {
+  const int n = std::max(N, n_copy);
+  if (n == 0) return;
+  k_kick_copy<<<blocks(n, 256), 256, 0, st>>>(v, F, species, inv_mass, half_dt_kappa, N, e_src, e_dst, n_copy);
 }
 void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N, int* flag,
                   hipStream_t st) {

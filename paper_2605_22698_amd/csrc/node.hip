@@ -160,6 +160,18 @@ __global__ void k_gate_fwd(const float* __restrict__ ht, float* __restrict__ h, 
   for (int c = 1; c < nc; ++c) dst[(long)c * C] = src[(long)c * C] * s;
 }
 
+// Scalar-only layer whose channel mix was split over K: h~ = the sum of the
+// partial products in order, then h = silu(h~).
+__global__ void k_gate_fwd_sum(const float* __restrict__ part, int n_parts, float* __restrict__ ht,
+                               float* __restrict__ h, long NC) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= NC) return;
+  float s0 = part[idx];
+  for (int p = 1; p < n_parts; ++p) s0 += part[p * NC + idx];
+  ht[idx] = s0;
+  h[idx] = s0 * sigmoidf(s0);
+}
+
 __global__ void k_gate_bwd(const float* __restrict__ ht, const float* __restrict__ dh, float* __restrict__ dht,
                            int N, int nc, int C) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -311,6 +323,10 @@ void launch_gemm_group(const GemmArgs* a, int n, hipStream_t st, bool bf16) {
 void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st) {
   if (N == 0) return;
   k_gate_fwd<<<blocks((long)N * C, 256), 256, 0, st>>>(ht, h, N, nc, C);
+}
+void launch_gate_fwd_sum(const float* part, int n_parts, float* ht, float* h, int N, int C, hipStream_t st) {
+  if (N == 0) return;
+  k_gate_fwd_sum<<<blocks((long)N * C, 256), 256, 0, st>>>(part, n_parts, ht, h, (long)N * C);
 }
 void launch_gate_bwd(const float* ht, const float* dh, float* dht, int N, int nc, int C, hipStream_t st) {
   if (N == 0) return;

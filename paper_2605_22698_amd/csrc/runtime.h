@@ -265,6 +265,8 @@ constexpr int kMaxGemmGroup = 8;
 void launch_gemm_group(const GemmArgs* a, int n, hipStream_t st, bool bf16 = false);
 void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st);
 void launch_gate_bwd(const float* ht, const float* dh, float* dht, int N, int nc, int C, hipStream_t st);
+// h~ [N, C] = sum of n_parts partial products [n_parts, N, C] in order; h = silu(h~)
+void launch_gate_fwd_sum(const float* part, int n_parts, float* ht, float* h, int N, int C, hipStream_t st);
 void launch_embed(const int* species, const float* emb, float* h0, int N, int C, hipStream_t st);
 void launch_readout(const float* h, int nc, const int* species, const float* Wr, const float* w2, const float* e0,
                     int N, int C, double* e_atom, float* dh, hipStream_t st, const float* wq = nullptr,
@@ -370,6 +372,12 @@ void launch_kick(double* v, const float* F, const int* species, const double* in
                  hipStream_t st);
 void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N, int* flag,
                   hipStream_t st);
+// k_kick then k_drift in one pass (same arithmetic)
+void launch_kick_drift(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa,
+                       double* x, const double* x_ref, double dt, double limit2, int N, int* flag, hipStream_t st);
+// k_kick, with the n_copy structure energies copied e_src -> e_dst in the same launch
+void launch_kick_copy(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa,
+                      int N, const double* e_src, double* e_dst, int n_copy, hipStream_t st);
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st);
 void launch_scale_positions(double* x, const int* owner, const double* lam, int N, hipStream_t st);
 void launch_restore_rows(double* x, const double* x_save, const int* owner, const int* keep, int N, hipStream_t st);
