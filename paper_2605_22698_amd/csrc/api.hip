@@ -210,6 +210,7 @@ struct Workspace {
   bool rp_valid = false;
   std::unique_ptr<DevBuf> Bp, dat;                     // product block: B (or dB), dA~
   std::unique_ptr<DevBuf> mixp;                        // partial products of a K-split channel mix
+  int last_parts = -1;  // last layer left before its gate: partial products in mixp (0: h~ in ht[T])
 };
 
 }  // namespace e3mi
@@ -784,7 +785,11 @@ void set_chunk(TpArgs& ta, const RChunk& ch) {
 // Primal forward pass: edge selection, embedding and every layer. Leaves
 // h^t, h~^t and R^t of every layer in the workspace; A in one shared buffer,
 // or per layer when keep_A (the parameter-gradient pass needs them).
-void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, hipStream_t st, bool bf16) {
+// defer_last_gate: a scalar-only last layer (no product block) stops at its
+// pre-gate values (ht, or the partial products in mixp; their count in
+// last_parts) for a readout that applies the gate itself.
+void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, hipStream_t st, bool bf16,
+                  bool defer_last_gate = false) {
   const Config& c = M->cfg;
   Allocator* a = &M->alloc;
   const int N = G->N, S = G->S, C = c.channels, T = c.layers;
@@ -922,6 +927,10 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
         ProfScope ps(&M->prof, stage_id(kMixFwd, t), st);
         launch_mix(M, L, W, A, hin, ht, L.nc_out, N, st, bf16);
       }
+      if (defer_last_gate && t == T && L.nc_out == 1) {
+        w.last_parts = 0;
+        continue;
+      }
       {
         ProfScope ps(&M->prof, stage_id(kGateFwd, t), st);
         launch_gate_fwd(ht, w.h[t]->as<float>(), N, L.nc_out, C, st);
@@ -971,6 +980,10 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
       }
     }
     if (prod) product_tail(t, L, W, hin, ht);
+    if (defer_last_gate && t == T && !prod && L.nc_out == 1) {
+      w.last_parts = n_parts;
+      continue;
+    }
     {
       ProfScope ps(&M->prof, stage_id(kGateFwd, t), st);
       if (n_parts > 0)
@@ -994,7 +1007,12 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     E3MI_HIP(hipMemsetAsync(energy, 0, sizeof(double) * S, st));
     return;
   }
-  forward_pass(M, G, pos, false, st, M->precision == E3MI_BF16_MIX);
+  const bool coulomb = c.coulomb;
+  // the readout applies the last layer's gate and its adjoint itself, unless
+  // the charge adjoint must still be added to dE/dh between the two
+  const bool gate_in_readout = T >= 2 && !coulomb && c.correlation != 2 && M->plans[T - 1].nc_out == 1;
+  w.last_parts = -1;
+  forward_pass(M, G, pos, false, st, M->precision == E3MI_BF16_MIX, gate_in_readout);
   const int* row_ptr = G->row_ptr_x->as<int>();
   const int* src = G->src_x->as<int>();
   const float4* dvec = G->dvec_x->as<float4>();
@@ -1002,14 +1020,20 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
   float* A = w.A->as<float>();
   float* dcur = w.dh_a->as<float>();
   float* dother = w.dh_b->as<float>();
-  const bool coulomb = c.coulomb;
   if (coulomb) {
     E3MI_REQUIRE(G->ctiles, E3MI_EINVAL, "graph was built for a model without the Coulomb term");
     for (auto* b : {&w.q_raw, &w.q, &w.pot}) ensure(*b, &M->alloc, sizeof(float) * (size_t)N);
     ensure(w.fc, &M->alloc, sizeof(float) * 3 * (size_t)N);
     ensure(w.pot_mean, &M->alloc, sizeof(float) * (size_t)S);
   }
-  {
+  if (gate_in_readout) {
+    E3MI_REQUIRE(w.last_parts >= 0, E3MI_EINVAL, "internal: last layer was not left before its gate");
+    ProfScope ps(&M->prof, stage_id(kReadout), st);
+    launch_readout_gated(w.last_parts > 0 ? w.mixp->as<float>() : w.ht[T]->as<float>(), w.last_parts, species,
+                         M->read1->as<float>(), M->read2->as<float>(), M->e0->as<float>(), N, C,
+                         w.e_atom->as<double>(), w.dht->as<float>(), st);
+    launch_energy(w.e_atom->as<double>(), G->off_d->as<int64_t>(), S, energy, st);
+  } else {
     ProfScope ps(&M->prof, stage_id(kReadout), st);
     launch_readout(w.h[T]->as<float>(), M->plans[T - 1].nc_out, species, M->read1->as<float>(),
                    M->read2->as<float>(), M->e0->as<float>(), N, C, w.e_atom->as<double>(), dcur, st,
@@ -1044,7 +1068,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     LayerWeights& W = *M->lw[t - 1];
     const float* hin = w.h[t - 1]->as<float>();
     const int PCu = L.p_used * C;
-    {
+    if (!(gate_in_readout && t == T)) {
       ProfScope ps(&M->prof, stage_id(kGateBwd, t), st);
       launch_gate_bwd(w.ht[t]->as<float>(), dcur, dht, N, L.nc_out, C, st);
     }

@@ -37,6 +37,36 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sums of NV <= 16 per-lane values over the 64 lanes of a wave, by recursive
+// halving: each exchange over lane bits 5, 4, 3, 2 hands the partner the half
+// of the values this lane does not keep, so lane L ends with a partial of
+// value q = L >> 2, which the exchanges over bits 1 and 0 complete (17 lane
+// exchanges where 16 butterfly reductions take 96). Returns the total of
+// value lane >> 2 (zero for q >= NV).
+template <int NV>
+__device__ __forceinline__ float wave_sum_scatter16(const float* v) {
+  static_assert(NV <= 16, "at most 16 values");
+  const int lane = threadIdx.x & 63;
+  float a[8], b[4], c[2];
+  bool hi = lane & 32;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float lo_v = q < NV ? v[q] : 0.0f, hi_v = q + 8 < NV ? v[q + 8] : 0.0f;
+    a[q] = (hi ? hi_v : lo_v) + __shfl_xor(hi ? lo_v : hi_v, 32);
+  }
+  hi = lane & 16;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) b[q] = (hi ? a[q + 4] : a[q]) + __shfl_xor(hi ? a[q] : a[q + 4], 16);
+  hi = lane & 8;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) c[q] = (hi ? b[q + 2] : b[q]) + __shfl_xor(hi ? b[q] : b[q + 2], 8);
+  hi = lane & 4;
+  float d = (hi ? c[1] : c[0]) + __shfl_xor(hi ? c[0] : c[1], 4);
+  d += __shfl_xor(d, 2);
+  d += __shfl_xor(d, 1);
+  return d;
+}
+
 // Real spherical harmonics of a unit vector, component normalised
 // (sum_m Y_lm^2 = 2l + 1), index l*l + m + l. Only orders <= LMAX are written.
 template <int LMAX>

@@ -243,6 +243,52 @@ __global__ void __launch_bounds__(256) k_readout(const float* __restrict__ h, in
   }
 }
 
+// Readout of a scalar-only last layer straight from its pre-gate values x (the
+// sum of n_parts partial products [n_parts, N, C], or h~ itself when n_parts
+// is 0), with the gate and its adjoint folded in: h = silu(x),
+// E_i = w2 . silu(W_r^T h) + E0[z_i], dh~ = (W_r g) o silu'(x).
+__global__ void __launch_bounds__(256) k_readout_gated(const float* __restrict__ xt, int n_parts,
+                                                       const int* __restrict__ species, const float* __restrict__ Wr,
+                                                       const float* __restrict__ w2, const float* __restrict__ e0,
+                                                       int N, int C, double* __restrict__ e_atom,
+                                                       float* __restrict__ dht) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;
+  const long NC = (long)N * C;
+  auto x_of = [&](int k) {
+    float x = xt[(long)i * C + k];
+    for (int p = 1; p < n_parts; ++p) x += xt[p * NC + (long)i * C + k];
+    return x;
+  };
+  float pre[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) pre[q] = 0.0f;
+  for (int k = lane; k < C; k += 64) {
+    const float x = x_of(k);
+    const float hv = x * sigmoidf(x);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pre[q] += hv * Wr[k * 16 + q];
+  }
+  // lane L holds the pre-activation of hidden unit L / 4
+  const float pq = wave_sum_scatter16<16>(pre);
+  const int q0 = lane >> 2;
+  float e = (lane & 3) == 0 ? w2[q0] * siluf(pq) : 0.0f;
+#pragma unroll
+  for (int off = 4; off < 64; off <<= 1) e += __shfl_xor(e, off);
+  if (lane == 0) e_atom[i] = (double)e + (double)e0[species[i]];
+  const float gl = w2[q0] * silu_grad(pq);
+  float gq[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) gq[q] = __shfl(gl, 4 * q);
+  for (int k = lane; k < C; k += 64) {
+    float s = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s += Wr[k * 16 + q] * gq[q];
+    dht[(long)i * C + k] = s * silu_grad(x_of(k));
+  }
+}
+
 __global__ void __launch_bounds__(256) k_energy(const double* __restrict__ e_atom, const int64_t* __restrict__ off,
                                                 double* __restrict__ energy) {
   __shared__ double red[256];
@@ -341,6 +387,11 @@ void launch_readout(const float* h, int nc, const int* species, const float* Wr,
                     float* q_raw) {
   if (N == 0) return;
   k_readout<<<blocks((long)N * 64, 256), 256, 0, st>>>(h, nc, species, Wr, w2, e0, N, C, e_atom, dh, wq, bq, q_raw);
+}
+void launch_readout_gated(const float* xt, int n_parts, const int* species, const float* Wr, const float* w2,
+                          const float* e0, int N, int C, double* e_atom, float* dht, hipStream_t st) {
+  if (N == 0) return;
+  k_readout_gated<<<blocks((long)N * 64, 256), 256, 0, st>>>(xt, n_parts, species, Wr, w2, e0, N, C, e_atom, dht);
 }
 void launch_energy(const double* e_atom, const int64_t* off, int S, double* energy, hipStream_t st) {
   k_energy<<<S, 256, 0, st>>>(e_atom, off, energy);

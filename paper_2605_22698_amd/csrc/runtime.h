@@ -271,6 +271,11 @@ void launch_embed(const int* species, const float* emb, float* h0, int N, int C,
 void launch_readout(const float* h, int nc, const int* species, const float* Wr, const float* w2, const float* e0,
                     int N, int C, double* e_atom, float* dh, hipStream_t st, const float* wq = nullptr,
                     const float* bq = nullptr, float* q_raw = nullptr);
+// Readout of a scalar-only last layer from its pre-gate values (the sum of
+// n_parts partial products [n_parts, N, C], or h~ [N, C] when n_parts is 0),
+// the gate and its adjoint folded in: writes E_i and dE/dh~ [N, C]
+void launch_readout_gated(const float* xt, int n_parts, const int* species, const float* Wr, const float* w2,
+                          const float* e0, int N, int C, double* e_atom, float* dht, hipStream_t st);
 void launch_energy(const double* e_atom, const int64_t* off, int S, double* energy, hipStream_t st);
 void launch_forces(const int* row_ptr, const int* rev, const float4* g, int N, float* F, hipStream_t st,
                    const float* extra = nullptr);
