@@ -1120,7 +1120,10 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     }
     {
       ProfScope ps(&M->prof, stage_id(kMixBwd, t), st);
-      if (t > 1 && !prod) E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+      // the per-edge node adjoint writes the components of dh the self
+      // connection's adjoint leaves alone, so only the fused layer needs dh cleared
+      if (t > 1 && !prod && fused_last(M, L, false, bf16))
+        E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
       launch_mix_adjoint(M, L, W, dmix, dmix_nc, A, (t > 1 && !prod) ? dother : nullptr, N, st, bf16);
     }
     if (fused_last(M, L, false, M->precision == E3MI_BF16_MIX)) {
@@ -1156,6 +1159,10 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     ta.inv_nu = inv_nu;
     ta.dh = dother;
     ta.dh_nc = L.nc_in;
+    if (!prod) {
+      const int l_sc = std::min(L.l3max_used, L.l1max);  // orders the self-connection adjoint wrote
+      ta.dh_acc = (l_sc + 1) * (l_sc + 1);
+    }
     // with more than one chunk R is recomputed chunk by chunk (the forward
     // pass kept only the last chunk)
     const std::vector<RChunk> chunks = r_chunks(M, G, PCu, st);

@@ -213,6 +213,7 @@ struct TpArgs {
   float* dY;
   float* dh;
   int dh_nc;
+  int dh_acc;  // node adjoint: components below dh_acc are accumulated, the rest written (<= 0: all accumulated)
   int N, C;
   float inv_nu;
   // second-order (parameter-gradient) passes

@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
                                                      const float4* __restrict__ dvec, const float* __restrict__ R,
                                                      int r_stride, const float* __restrict__ dA,
                                                      float* __restrict__ dh, int dh_nc, int N, int C, float inv_nu,
-                                                     int i0, int e_first) {
+                                                     int i0, int e_first, int dh_acc) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NIN = PS::NIN, NY = PS::NY;
   const int j = i0 + xcd_contiguous(blockIdx.x, gridDim.x);
@@ -238,8 +238,16 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int k = threadIdx.x + c * tpr;
+    // components below dh_acc (all when dh_acc <= 0) are added to, the others
+    // written (zero past the paths' inputs)
 #pragma unroll
-    for (int q = 0; q < NIN; ++q) dh[((long)j * dh_nc + q) * C + k] += acc[c][q] * inv_nu;
+    for (int q = 0; q < NIN; ++q) {
+      float* o = dh + ((long)j * dh_nc + q) * C + k;
+      *o = (dh_acc <= 0 || q < dh_acc) ? *o + acc[c][q] * inv_nu : acc[c][q] * inv_nu;
+    }
+    if (dh_acc > 0)
+      for (int q = NIN; q < dh_nc; ++q)
+        if (q >= dh_acc) dh[((long)j * dh_nc + q) * C + k] = 0.0f;
   }
 }
 
@@ -582,7 +590,7 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
                                                         a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first);
   else if (which == 2)
     k_tp_bwd_node<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
-                                                        a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first);
+                                                        a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first, a.dh_acc);
   else if (which == 3)
     k_tp_dual_fwd<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.R, a.Rd, a.r_stride, a.h,
                                                          a.hd, a.h_nc, a.Ad, a.N, a.C, a.inv_nu);
