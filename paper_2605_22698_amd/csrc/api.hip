@@ -244,6 +244,10 @@ struct e3mi_graph {
   // electrostatics: total charge per structure, and (structure, first atom) per 64-atom tile
   std::unique_ptr<e3mi::DevBuf> charge, ctiles;
   int n_ctiles = 0, c_waves = 1;
+  // cell-list scratch kept between rebuilds (grown as needed), and the grid
+  // plans last uploaded (re-sent only when they change)
+  std::unique_ptr<e3mi::DevBuf> bb, plan_d, cell_count, cell_start, cell_fill, cell_atoms, atom_cell, wrap, err;
+  std::vector<e3mi::GridPlan> plan_h;
 };
 
 struct e3mi_md {
@@ -351,10 +355,9 @@ void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
   for (int s = 0; s < S; ++s)
     for (int k = 0; k < 3; ++k) any_open |= !G->pbc_h[3 * s + k];
   if (any_open && N) {
-    DevBuf bb(a);
-    bb.ensure(sizeof(double) * 6 * S);
-    launch_bbox(pos, G->off_d->as<int64_t>(), S, bb.as<double>(), st);
-    E3MI_HIP(hipMemcpyAsync(bbox.data(), bb.p, sizeof(double) * 6 * S, hipMemcpyDeviceToHost, st));
+    double* bb = ensure(G->bb, a, sizeof(double) * 6 * S).as<double>();
+    launch_bbox(pos, G->off_d->as<int64_t>(), S, bb, st);
+    E3MI_HIP(hipMemcpyAsync(bbox.data(), bb, sizeof(double) * 6 * S, hipMemcpyDeviceToHost, st));
     E3MI_HIP(hipStreamSynchronize(st));
   }
   std::vector<double> cell9((size_t)9 * S, 0.0);
@@ -363,20 +366,25 @@ void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
   std::vector<GridPlan> plans;
   int n_cells = 0;
   fill_plan(M->cfg, S, G->off_h, cell9.data(), G->pbc_h.data(), bbox, rc_eff, plans, n_cells);
-  auto plan_d = upload(a, plans.data(), sizeof(GridPlan) * plans.size());
-
-  DevBuf cell_count(a), cell_start(a), cell_fill(a), cell_atoms(a), atom_cell(a), wrap(a), err(a);
-  cell_count.ensure(sizeof(int) * (n_cells + 1));
-  cell_start.ensure(sizeof(int) * (n_cells + 1));
-  cell_fill.ensure(sizeof(int) * (n_cells + 1));
-  cell_atoms.ensure(sizeof(int) * (N + 1));
-  atom_cell.ensure(sizeof(int) * (N + 1));
-  wrap.ensure(sizeof(int) * 3 * (N + 1));
-  err.ensure(sizeof(int));
+  const size_t plan_bytes = sizeof(GridPlan) * plans.size();
+  if (!G->plan_d || G->plan_h.size() != plans.size() ||
+      std::memcmp(G->plan_h.data(), plans.data(), plan_bytes) != 0) {
+    ensure(G->plan_d, a, plan_bytes);
+    if (plan_bytes) E3MI_HIP(hipMemcpy(G->plan_d->p, plans.data(), plan_bytes, hipMemcpyHostToDevice));
+    G->plan_h = plans;
+  }
+  DevBuf& plan_d = *G->plan_d;
+  DevBuf& cell_count = ensure(G->cell_count, a, sizeof(int) * (n_cells + 1));
+  DevBuf& cell_start = ensure(G->cell_start, a, sizeof(int) * (n_cells + 1));
+  DevBuf& cell_fill = ensure(G->cell_fill, a, sizeof(int) * (n_cells + 1));
+  DevBuf& cell_atoms = ensure(G->cell_atoms, a, sizeof(int) * (N + 1));
+  DevBuf& atom_cell = ensure(G->atom_cell, a, sizeof(int) * (N + 1));
+  DevBuf& wrap = ensure(G->wrap, a, sizeof(int) * 3 * (N + 1));
+  DevBuf& err = ensure(G->err, a, sizeof(int));
   E3MI_HIP(hipMemsetAsync(cell_count.p, 0, sizeof(int) * (n_cells + 1), st));
   E3MI_HIP(hipMemsetAsync(cell_fill.p, 0, sizeof(int) * (n_cells + 1), st));
   E3MI_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
-  launch_bin(pos, G->owner->as<int>(), plan_d->as<GridPlan>(), N, atom_cell.as<int>(), wrap.as<int>(),
+  launch_bin(pos, G->owner->as<int>(), plan_d.as<GridPlan>(), N, atom_cell.as<int>(), wrap.as<int>(),
              cell_count.as<int>(), st);
   launch_exclusive_scan(cell_count.as<int>(), cell_start.as<int>(), n_cells, st);
   launch_bin_fill(atom_cell.as<int>(), cell_start.as<int>(), N, cell_fill.as<int>(), cell_atoms.as<int>(), st);
@@ -384,7 +392,7 @@ void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
   const double rc2 = rc_eff * rc_eff;
   ensure(G->cnt, a, sizeof(int) * (N + 1));
   ensure(G->row_ptr, a, sizeof(int) * (N + 1));
-  launch_edges(false, pos, G->owner->as<int>(), plan_d->as<GridPlan>(), atom_cell.as<int>(), wrap.as<int>(),
+  launch_edges(false, pos, G->owner->as<int>(), plan_d.as<GridPlan>(), atom_cell.as<int>(), wrap.as<int>(),
                cell_start.as<int>(), cell_atoms.as<int>(), nullptr, N, rc2, G->cnt->as<int>(), nullptr,
                err.as<int>(), st);
   launch_exclusive_scan(G->cnt->as<int>(), G->row_ptr->as<int>(), N, st);
@@ -397,7 +405,7 @@ void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
   ensure(G->src, a, sizeof(int) * (E + 1));
   ensure(G->shift, a, sizeof(int) * (E + 1));
   ensure(G->rev, a, sizeof(int) * (E + 1));
-  launch_edges(true, pos, G->owner->as<int>(), plan_d->as<GridPlan>(), atom_cell.as<int>(), wrap.as<int>(),
+  launch_edges(true, pos, G->owner->as<int>(), plan_d.as<GridPlan>(), atom_cell.as<int>(), wrap.as<int>(),
                cell_start.as<int>(), cell_atoms.as<int>(), G->row_ptr->as<int>(), N, rc2, nullptr,
                G->keys->as<uint64_t>(), err.as<int>(), st);
   launch_sort_rows(G->row_ptr->as<int>(), N, G->keys->as<uint64_t>(), G->src->as<int>(), G->shift->as<int>(), st);
