@@ -47,6 +47,23 @@ def test_packed_periodic_batch():
     check_forces(F, Fr)
 
 
+@pytest.mark.parametrize("unfactorised", [False, True])
+def test_single_layer_model(unfactorised):
+    # one interaction layer: it is both the first layer (embedding input) and
+    # the scalar-output last layer, with its own gate before the readout
+    cfg = synth.ModelConfig(lmax=3, channels=32, layers=1, n_species=3, cutoff=5.0,
+                            avg_neighbors=synth.nominal_neighbors(0.1, 5.0))
+    b = synth.jittered_lattice(120, 0.1, 0.3, 3, np.random.default_rng(47))
+    m = model(cfg, 48)
+    if unfactorised:
+        m.set_flags(unfactorised_first_layer=True)
+    E, F, Ei, _ = gpu_energy_forces(m, b, skin=1.0)
+    Er, Fr, Eir = _oracle(cfg, 48, b)
+    e = check_energy(E, Er, Eir)
+    f = check_forces(F, Fr)
+    say(f"single layer (unfactorised {unfactorised}): energy rel err {e:.2e}, force err {f[0]:.2e} eV/A")
+
+
 def test_three_layer_full_middle_layer():
     # 3 layers: the middle layer runs all 23 paths of l_max 3.
     cfg = synth.ModelConfig(lmax=3, channels=128, layers=3, n_species=4, cutoff=6.0,
