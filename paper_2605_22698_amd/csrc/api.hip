@@ -557,12 +557,11 @@ void launch_mix(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float*
   launch_gemm_group(grp, n, st, bf16);
 }
 
-// After the product block: h~^L = B^L W_lin,L + h_in^L S_L for L <= lout.
 // Channel mix of a scalar-output layer split over K into independent partial
 // products of 128 K each (one grouped launch): with one scalar row per atom
 // the 64 x 64 output tiles are too few to fill the GPU for small systems, and
-// each workgroup then walks a fifth of the K slabs. The split depends on K
-// only, so an atom's result does not depend on what else is in the batch.
+// each workgroup then walks only its part of the K slabs. The split depends
+// on K only, so an atom's result does not depend on what else is in the batch.
 // Partial j goes to part + j N C; returns the number of parts written.
 int mix_split_parts(int K) { return std::max(1, std::min(kMaxGemmGroup, K / 128)); }
 int launch_mix_scalar_split(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* A, const float* hin,
@@ -597,6 +596,7 @@ int launch_mix_scalar_split(e3mi_model* M, const LayerPlan& L, LayerWeights& W, 
   return n;
 }
 
+// After the product block: h~^L = B^L W_lin,L + h_in^L S_L for L <= lout.
 void launch_lin(e3mi_model* M, const LayerPlan& L, LayerWeights& W, const float* B, const float* hin, float* ht,
                 int N, hipStream_t st, bool bf16) {
   const int C = M->cfg.channels;

@@ -261,7 +261,8 @@ struct GemmArgs {
 };
 void launch_gemm(const GemmArgs& a, hipStream_t st, bool bf16 = false);
 // Up to kMaxGemmGroup independent products (no output read or written by
-// another of the group) in one launch.
+// another of the group) in one launch. With l_max <= 3 a layer's groups hold
+// at most 4 + 4 products (one per output order, plus the self connection's).
 constexpr int kMaxGemmGroup = 8;
 void launch_gemm_group(const GemmArgs* a, int n, hipStream_t st, bool bf16 = false);
 void launch_gate_fwd(const float* ht, float* h, int N, int nc, int C, hipStream_t st);
