@@ -391,8 +391,10 @@ def main():
                     help="only run plain 256 MiB device-to-device copies (PMC byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(separate structures or requests would go to separate GPUs; one large structure would shard by "
+              "spatial domains with a halo exchange of boundary features per layer).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
