@@ -30,9 +30,11 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
-// The scalar-output layer's forward runs best at three waves per SIMD: more
-// receivers in flight spread the sender gathers over more than an XCD's L2
-// holds (measured: 0.141 ms uncapped, 0.134 ms at three, 0.144 ms at two).
+// The scalar-output layer's forward is compiled for at most three waves per
+// SIMD: the compiler then schedules its edge loop with 88 registers instead
+// of 72 (the hardware still holds five waves) and it runs faster (0.134 ms
+// against 0.141 on the 3,000-atom step). Holding residency at three or two
+// waves for real, by reserving LDS, is slower (0.167, 0.196 ms).
 template <int LMAX, int KIND, int CPT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIND == kLast ? 3 : 10))) k_tp_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                 const float4* __restrict__ dvec, const float* __restrict__ R,
