@@ -136,3 +136,49 @@ def test_npt_without_moves_is_langevin():
     xb, vb, bb, _, dec = omd.langevin_npt(force, x0, v0, np.array([[9.0, 9.0, 9.0]]), m, 0.5, 10, 300.0, 0.1,
                                           [0, 6], [3], [0], 1.0, 100, 0.01, [4], [0])
     assert not dec and np.array_equal(xa, xb) and np.array_equal(va, vb) and np.array_equal(bb, [[9.0, 9.0, 9.0]])
+
+
+def test_npt_schedule_is_per_structure_and_packing_independent():
+    # Batched independent simulations (Section 5.5): each structure proposes a
+    # volume move after the steps that bring its OWN step count (step0 + steps
+    # taken) to a multiple of the interval, and a structure's trajectory is the
+    # same alone and packed with another on a different phase.
+    rng_np = np.random.default_rng(41)
+    n = (5, 4)
+    off = [0, n[0], n[0] + n[1]]
+    x0 = rng_np.uniform(0.0, 8.0, size=(sum(n), 3))
+    v0 = rng_np.normal(size=(sum(n), 3)) * 0.01
+    m = np.full(sum(n), 12.0)
+    boxes0 = np.array([[8.0, 8.0, 8.0], [7.5, 7.5, 7.5]])
+    kspring = 0.05
+
+    def force(x, boxes, offsets=off):
+        # each structure in a harmonic well at its box centre (energy changes with the volume)
+        E = np.zeros(len(offsets) - 1)
+        F = np.zeros_like(x)
+        for s in range(len(offsets) - 1):
+            a, b = offsets[s], offsets[s + 1]
+            d = x[a:b] - 0.5 * boxes[s]
+            E[s] = 0.5 * kspring * np.sum(d * d)
+            F[a:b] = -kspring * d
+        return E, F
+
+    interval, steps = 5, 13
+    step0, seeds, bseeds, move0 = [0, 3], [11, 12], [21, 22], [0, 7]
+    xp, vp, bp, Ep, dec = omd.langevin_npt(force, x0, v0, boxes0, m, 0.5, steps, 300.0, 0.05, off, seeds, step0,
+                                           2000.0, interval, 0.02, bseeds, move0)
+    # structure 0 proposes after its steps 5 and 10; structure 1 (3 steps in) after 2, 7 and 12
+    assert [s for s, _ in dec] == [1, 0, 1, 0, 1]
+    for s in range(2):
+        a, b = off[s], off[s + 1]
+        lo = [0, b - a]
+
+        def force_s(x, boxes, s=s):
+            return force(x, boxes, offsets=lo)
+        xs, vs, bs, Es, ds = omd.langevin_npt(force_s, x0[a:b], v0[a:b], boxes0[s:s + 1], m[a:b], 0.5, steps, 300.0,
+                                              0.05, lo, [seeds[s]], [step0[s]], 2000.0, interval, 0.02, [bseeds[s]],
+                                              [move0[s]])
+        assert np.array_equal(xs, xp[a:b]) and np.array_equal(vs, vp[a:b]) and np.array_equal(bs[0], bp[s])
+        assert [acc for _, acc in ds] == [acc for q, acc in dec if q == s]
+        assert [float(e[0]) for e in Es] == [float(e[s]) for e in Ep]
+    assert not np.array_equal(bp, boxes0)  # some move was accepted

@@ -216,3 +216,127 @@ def test_loss_gradients_match_central_differences():
                 vals.append(om.loss_and_grads(om.Model(cfg, w2), b, e_ref, f_ref)[0])
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(fd - grads[name][idx]) < 1e-7 + 1e-5 * abs(fd), (name, idx, fd, grads[name][idx])
+
+
+# ---- gate, readout and the neighbour sum pinned by limits and reductions ----
+
+def _np_silu(x):
+    return x / (1.0 + np.exp(-x))
+
+
+def _np_sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def _gate_features(lam, cfg, w, b):
+    """First-layer output features when the self connection of the scalars
+    is lam * identity (embedding entries are positive, so lam drives every
+    channel's pre-gate scalar towards +-infinity)."""
+    m = om.Model(cfg, w)
+    m.w["self_1_0"] = torch.eye(cfg.channels, dtype=torch.float64) * lam
+    feats = []
+    om.energy_forces(m, b, features=feats)
+    return feats[0].detach().numpy()  # [N, C, (lmax+1)^2]
+
+
+def test_gate_limits_and_form():
+    # MACE's gate (Appendix F, gate_nodes): h[0] = silu(h~[0]), h[l>0] =
+    # h~[l] sigmoid(h~[0]) per channel. In layer 1 the self connection only
+    # touches l = 0, so h~[l>0] does not depend on lam while h~[0] = a + lam e.
+    cfg = small_cfg(lmax=2, channels=5, layers=1, n_species=2)
+    w = synth.model_weights(cfg, 31)
+    w["emb"] = np.random.default_rng(32).uniform(0.5, 1.5, size=w["emb"].shape)
+    b = synth.uniform_cluster(7, 6.0, 1.0, 2, np.random.default_rng(33))
+    e = w["emb"][b.species]                           # [N, C] = h0 of every atom
+    hp, hp2, hm = (_gate_features(lam, cfg, w, b) for lam in (60.0, 120.0, -60.0))
+    # l > 0: unchanged in the +infinity limit, gone in the -infinity limit
+    vec = slice(1, None)
+    assert np.abs(hp[:, :, vec]).max() > 1e-3
+    np.testing.assert_allclose(hp[:, :, vec], hp2[:, :, vec], rtol=0, atol=1e-14)
+    assert np.abs(hm[:, :, vec]).max() < 1e-10 * np.abs(hp[:, :, vec]).max()
+    # l = 0: silu is x at +infinity (slope one, no offset) and 0 at -infinity
+    np.testing.assert_allclose(hp2[:, :, 0] - hp[:, :, 0], 60.0 * e, rtol=1e-12)
+    assert np.abs(hm[:, :, 0]).max() < 1e-10
+    # at a finite lam the exact forms, with a = h~[0] - lam e recovered from +infinity
+    a = hp[:, :, 0] - 60.0 * e
+    lam = 0.37
+    h = _gate_features(lam, cfg, w, b)
+    x = a + lam * e
+    np.testing.assert_allclose(h[:, :, 0], _np_silu(x), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(h[:, :, vec], hp[:, :, vec] * _np_sigmoid(x)[:, :, None], rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("unit", [0, 5, 15])
+def test_readout_one_hidden_unit(unit):
+    # Readout 16x0e -> 0e (Appendix F): E_i = w2 . silu(W_r^T h_i[0]) + E0[z_i].
+    # With w2 one-hot at `unit` the energy of atom i is silu of one column of
+    # W_r against its final scalar features, plus E0. Square W_r (C = 16), so
+    # a transposed W_r would not fail on shapes.
+    cfg = small_cfg(lmax=2, channels=16, layers=2, n_species=3)
+    w = synth.model_weights(cfg, 34)
+    w["read2"] = np.zeros((16, 1))
+    w["read2"][unit, 0] = 1.0
+    w["e0"] = np.array([-1.25, 0.5, 3.0])
+    m = om.Model(cfg, w)
+    b = synth.uniform_cluster(9, 7.0, 1.0, 3, np.random.default_rng(35))
+    feats = []
+    _, _, Ei = om.energy_forces(m, b, features=feats)
+    h0 = feats[-1][:, :, 0].detach().numpy()
+    expect = _np_silu(h0 @ w["read1"][:, unit]) + w["e0"][b.species]
+    np.testing.assert_allclose(Ei, expect, rtol=1e-13, atol=1e-14)
+
+
+def _np_radial(r, rc, n_basis, p, W1, W2, W3):
+    """R(r) of one edge: Bessel functions through scipy's spherical j0 times
+    the polynomial envelope, then the two-hidden-layer MLP without biases."""
+    from scipy.special import spherical_jn
+    n = np.arange(1, n_basis + 1)
+    k = n * math.pi / rc
+    bes = math.sqrt(2.0 / rc) * k * spherical_jn(0, k * r)
+    x = r / rc
+    u = np.polynomial.polynomial.polyval(x, [1.0] + [0.0] * (p - 1) +
+                                         [-(p + 1) * (p + 2) / 2.0, p * (p + 2), -p * (p + 1) / 2.0])
+    B = bes * (u if x < 1.0 else 0.0)
+    return _np_silu(_np_silu(B @ W1) @ W2) @ W3
+
+
+def test_lmax0_single_layer_is_a_pair_potential():
+    # At l_max = 0 with one layer, the only path is (0,0,0) (Y_0 = 1, C = 1),
+    # so the neighbour sum is A_i = nu^-1 sum_{j != i, r_ij < r_c} R(r_ij) h0_j.
+    # Scale the channel mix by eps: to first order in eps the readout is
+    # linear in A, and dE/deps at 0 = sum over ordered pairs of
+    # phi_{z_i z_j}(r_ij) with phi_ab(r) = nu^-1 sum_k R_k(r) emb[b,k] (W g_a)_k,
+    # g_a the gradient of the atom energy with respect to h~ at h~ = emb[a] S.
+    cfg = synth.ModelConfig(lmax=0, channels=4, layers=1, n_species=2, cutoff=4.0, avg_neighbors=3.7)
+    w = synth.model_weights(cfg, 36)
+    b = synth.uniform_cluster(11, 6.0, 1.0, 2, np.random.default_rng(37))
+    m = om.Model(cfg, w)
+    eps = torch.zeros((), dtype=torch.float64, requires_grad=True)
+    m.w["mix_1_0"] = torch.tensor(w["mix_1_0"]) * eps
+    dst, src, shv = om._edges(b, cfg.cutoff)
+    pos = torch.tensor(b.pos)
+    sp = torch.from_numpy(b.species.astype(np.int64))
+    E = m.node_energies(pos, sp, dst, src, shv).sum()
+    (dE,) = torch.autograd.grad(E, eps)
+
+    # independent pair sum: all ordered pairs by brute force
+    Wr, w2 = w["read1"], w["read2"][:, 0]
+
+    def g_of(a):
+        x = w["emb"][a] @ w["self_1_0"]
+        dsilu = lambda t: _np_sigmoid(t) * (1.0 + t * (1.0 - _np_sigmoid(t)))
+        y = _np_silu(x) @ Wr
+        return dsilu(x) * (Wr @ (dsilu(y) * w2))
+
+    g = [g_of(a) for a in range(2)]
+    total = 0.0
+    for i in range(b.n_atoms):
+        for j in range(b.n_atoms):
+            r = float(np.linalg.norm(b.pos[j] - b.pos[i]))
+            if i == j or r >= cfg.cutoff:
+                continue
+            R = _np_radial(r, cfg.cutoff, cfg.n_basis, cfg.envelope_p, w["rad1_1"], w["rad2_1"], w["rad3_1"])
+            a, c = int(b.species[i]), int(b.species[j])
+            total += float(np.sum(R * w["emb"][c] * (w["mix_1_0"] @ g[a]))) / cfg.avg_neighbors
+    assert abs(total) > 1e-3
+    assert abs(float(dE) - total) <= 1e-12 * max(1.0, abs(total)), (float(dE), total)
