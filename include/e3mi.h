@@ -134,7 +134,7 @@ int e3mi_model_destroy(e3mi_model* model);
  *   n_structures   S >= 1
  *   atom_offsets   host int64 [S+1], non-decreasing, atom_offsets[0] = 0
  *   pos            device FP64 [N, 3]
- *   species        device int32 [N], values in [0, n_species)
+ *   species        device int32 [N], values in [0, n_species) (EINVAL otherwise)
  *   cell           host FP64 [S, 3, 3], rows are lattice vectors; must be
  *                  diagonal (orthorhombic) on periodic axes, else EUNSUPPORTED
  *   pbc            host uint8 [S, 3], periodic flags
@@ -254,10 +254,14 @@ int e3mi_graph_set_total_charge(e3mi_graph* graph, const double* total_charge);
  * e3mi_build_graph plus: vel device FP64 [N, 3] (angstrom/fs), masses host
  * FP64 [n_species] (amu), rebuild_every >= 1 (steps between neighbour
  * rebuilds). Positions are kept as integrated (never wrapped; image indices
- * must stay within +-127 cells, else EOVERFLOW at the next rebuild). The device
- * tracks each atom's displacement since the last rebuild; when a scheduled
- * rebuild finds that some atom moved more than skin/2 in the interval, it is
- * counted as a skin violation and the interval is halved from then on.
+ * must stay within +-127 cells, else EOVERFLOW at the next rebuild). The lists
+ * are rebuilt every rebuild_every steps, and early on any step whose drift
+ * takes an atom more than skin/2 from its position at the last build (counted
+ * as a skin violation): that step's force evaluation and final kick are redone
+ * on the new lists, so every step's forces see every pair inside the cutoff.
+ * To keep redone steps rare, each drift also forecasts the largest
+ * displacement after the next drift (|x - x_build| + dt |v|); when that
+ * reaches skin/2 the next step rebuilds before its force evaluation.
  * pos/vel are copied; the caller's buffers are not referenced afterwards.
  * Synchronises `stream`. */
 int e3mi_md_create(e3mi_model* model, int n_structures, const int64_t* atom_offsets,
@@ -270,7 +274,9 @@ int e3mi_md_create(e3mi_model* model, int n_structures, const int64_t* atom_offs
  * with kappa = 0.009648533 A/fs^2 per (eV/A)/amu, positions and velocities in
  * FP64. energy_out: device FP64 [S], potential energy after the last step, or
  * NULL. Synchronises `stream` when a neighbour rebuild is due (every
- * rebuild_every steps). */
+ * rebuild_every steps); on the other steps the host waits until the device has
+ * done the step's drift (to check the skin, above), while the step's force
+ * evaluation stays queued. */
 int e3mi_md_step(e3mi_md* md, int n_steps, double dt_fs, double* energy_out, void* stream);
 
 /* Switch the integrator to Langevin dynamics (Section 5.5: the NVT
@@ -327,7 +333,8 @@ int e3mi_md_set_total_charge(e3mi_md* md, const double* total_charge, void* stre
 int e3mi_md_state(const e3mi_md* md, double* pos, double* vel, float* forces, void* stream);
 
 /* Counters of an MD state (any output may be NULL): steps taken, neighbour
- * rebuilds done, skin violations detected. */
+ * rebuilds done (scheduled and early), skin violations (steps redone after an
+ * early rebuild). */
 int e3mi_md_stats(const e3mi_md* md, int64_t* steps, int64_t* rebuilds, int64_t* skin_violations);
 int e3mi_md_destroy(e3mi_md* md);
 

@@ -91,6 +91,19 @@ class Model:
         w = weights.detach().to("cpu", dtype=__import__("torch").float64).contiguous().numpy() \
             if hasattr(weights, "detach") else np.ascontiguousarray(weights, dtype=np.float64)
         check(lib().e3mi_model_set_weights(self.handle, w.ctypes.data, w.size))
+        self._uploaded = None
+
+    def _use_weights(self, weights):
+        """Make `weights` (a tensor) the device weights unless they already are,
+        judged by value (an in-place update through .data leaves the version
+        counter alone); returns the snapshot of what is now on the device."""
+        import torch
+        w = weights.detach()
+        last = getattr(self, "_uploaded", None)
+        if last is None or last.shape != w.shape or last.device != w.device or not torch.equal(last, w):
+            self.set_weights(w)
+            self._uploaded = w.clone()
+        return self._uploaded
 
     def param_grad(self, graph: "Graph", pos, grad_energy, grad_forces, stream=None):
         """dL/dweights (FP64 device vector) for upstream dL/dE [S] and dL/dF [N,3]."""
@@ -258,6 +271,15 @@ class MD:
         cell = np.ascontiguousarray(cell, dtype=np.float64).reshape(-1, 3, 3)
         pbc = np.ascontiguousarray(pbc, dtype=np.uint8).reshape(-1, 3)
         masses = np.ascontiguousarray(masses, dtype=np.float64)
+        n_species = int(__import__("json").loads(model.config_json)["n_species"])
+        for name, t in (("pos", pos), ("vel", vel)):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or tuple(t.shape) != (self.n_atoms, 3):
+                raise ValueError(f"{name} must be a float64 tensor of shape [{self.n_atoms}, 3]")
+        if not isinstance(species, torch.Tensor) or tuple(species.shape) != (self.n_atoms,) or \
+                species.dtype not in (torch.int32, torch.int64):
+            raise ValueError(f"species must be an integer tensor of shape [{self.n_atoms}]")
+        if masses.shape != (n_species,):
+            raise ValueError(f"masses must hold one value per species ({n_species})")
         pos, vel = pos.contiguous(), vel.contiguous()
         species = species.to(torch.int32).contiguous()
         h = ctypes.c_void_p()
@@ -345,10 +367,9 @@ def _energy_forces_function():
 
         @staticmethod
         def forward(ctx, weights, pos, model, graph):
-            key = (weights.data_ptr(), weights._version, weights.device)
-            if getattr(model, "_weights_key", None) != key:
-                model.set_weights(weights)
-                model._weights_key = key
+            # the weights this forward used, kept for its backward (the model's
+            # device weights may have changed by then)
+            ctx.weights = model._use_weights(weights)
             E, F, _ = model.energy_forces(graph, pos)
             ctx.model, ctx.graph = model, graph
             ctx.save_for_backward(pos)
@@ -358,6 +379,7 @@ def _energy_forces_function():
         def backward(ctx, gE, gF):
             (pos,) = ctx.saved_tensors
             m = ctx.model
+            m._use_weights(ctx.weights)
             if gE is None:
                 gE = torch.zeros(ctx.graph.n_structures, dtype=torch.float64, device=m.device)
             if gF is None:

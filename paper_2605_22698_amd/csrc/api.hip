@@ -260,7 +260,20 @@ struct e3mi_md {
   double cutoff = 0, skin = 0;
   int rebuild_every = 1, since_build = 0;
   int64_t steps = 0, rebuilds = 0, skin_violations = 0;
-  std::unique_ptr<e3mi::DevBuf> x, v, F, species, inv_mass, energy, flag;
+  std::unique_ptr<e3mi::DevBuf> x, v, F, species, inv_mass, energy, flag, v_prev;
+  // skin guard: the drift raises flag[0] to the stamp of a step on which an
+  // atom is more than skin/2 from its position at the last build, and
+  // flag[1 + stamp % 2] to its forecast of the largest displacement after the
+  // next step; the host reads both through flag_host (pinned) once drift_ev
+  // has passed
+  unsigned long long* flag_host = nullptr;
+  hipEvent_t drift_ev = nullptr;
+  unsigned long long stamp = 0;
+  bool rebuild_next = false;  // the forecast reached skin/2: rebuild before the next evaluation
+  ~e3mi_md() {
+    if (flag_host) (void)hipHostFree(flag_host);
+    if (drift_ev) (void)hipEventDestroy(drift_ev);
+  }
   // Langevin (BAOAB) when gamma > 0: per-structure seeds and step offsets
   double temperature = 0, gamma = 0;
   std::unique_ptr<e3mi::DevBuf> seeds, step0;
@@ -497,9 +510,11 @@ e3mi_graph* new_graph(e3mi_model* M, int S, const int64_t* off, const double* po
     flag.ensure(sizeof(int));
     E3MI_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
     launch_nonfinite(pos, 3 * G->N, flag.as<int>(), st);
+    launch_species_range(G->species->as<int>(), G->N, M->cfg.n_species, flag.as<int>(), st);
     int fh = 0;
     E3MI_HIP(hipMemcpyAsync(&fh, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
     E3MI_HIP(hipStreamSynchronize(st));
+    E3MI_REQUIRE(!(fh & 8), E3MI_EINVAL, "species outside [0, n_species)");
     E3MI_REQUIRE(!fh, E3MI_ENAN, "positions are not finite");
   }
   build_lists(G.get(), pos, st);
@@ -1694,6 +1709,7 @@ void md_rebuild(e3mi_md* D, hipStream_t st) {
   ProfScope ps(&D->model->prof, stage_id(kGraphBuild), st);
   build_lists(G, D->x->as<double>(), st);
   D->since_build = 0;
+  D->rebuild_next = false;
   D->rebuilds++;
 }
 
@@ -1735,8 +1751,13 @@ e3mi_md* new_md(e3mi_model* M, int S, const int64_t* off, const double* pos, con
   D->energy = std::make_unique<DevBuf>(a);
   D->energy->ensure(sizeof(double) * S);
   D->flag = std::make_unique<DevBuf>(a);
-  D->flag->ensure(sizeof(int));
-  E3MI_HIP(hipMemsetAsync(D->flag->p, 0, sizeof(int), st));
+  D->flag->ensure(3 * sizeof(unsigned long long));
+  E3MI_HIP(hipMemsetAsync(D->flag->p, 0, 3 * sizeof(unsigned long long), st));
+  D->v_prev = std::make_unique<DevBuf>(a);
+  D->v_prev->ensure(n3);
+  E3MI_HIP(hipHostMalloc((void**)&D->flag_host, 3 * sizeof(unsigned long long), hipHostMallocDefault));
+  for (int k = 0; k < 3; ++k) D->flag_host[k] = 0;
+  E3MI_HIP(hipEventCreateWithFlags(&D->drift_ev, hipEventDisableTiming));
   D->off_h.assign(off, off + S + 1);
   D->cell_h.assign(cell, cell + 9 * (size_t)S);
   D->pbc_h.assign(pbc, pbc + 3 * (size_t)S);
@@ -1755,45 +1776,74 @@ void md_step(e3mi_md* D, int n_steps, double dt, double* energy_out, hipStream_t
   const double lim = 0.5 * D->skin;
   const bool langevin = D->gamma > 0;
   const double c1 = std::exp(-D->gamma * dt), c2 = std::sqrt(std::max(0.0, 1.0 - c1 * c1));
+  unsigned long long* flag = reinterpret_cast<unsigned long long*>(D->flag->p);
   for (int s = 0; s < n_steps; ++s) {
+    const unsigned long long stamp = ++D->stamp;
+    unsigned long long* probe = flag + 1 + (stamp & 1);
+    unsigned long long* probe_next = flag + 1 + ((stamp + 1) & 1);
     {
       ProfScope ps(&D->model->prof, stage_id(kMdUpdate), st);
       if (!langevin) {
         launch_kick_drift(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(),
-                          hk, D->x->as<double>(), G->x_ref->as<double>(), dt, lim * lim, D->N, D->flag->as<int>(),
+                          hk, D->x->as<double>(), G->x_ref->as<double>(), dt, lim * lim, D->N, flag, stamp, probe, dt,
                           st);
       } else {
         // BAOAB: half kick and half drift, Ornstein-Uhlenbeck velocity update, half drift
         launch_kick_drift(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(),
                           hk, D->x->as<double>(), G->x_ref->as<double>(), 0.5 * dt,
-                          std::numeric_limits<double>::infinity(), D->N, D->flag->as<int>(), st);
+                          std::numeric_limits<double>::infinity(), D->N, flag, stamp, nullptr, 0.0, st);
         launch_ou(D->v->as<double>(), D->species->as<int>(), D->inv_mass->as<double>(), G->owner->as<int>(),
                   G->off_d->as<int64_t>(), D->seeds->as<uint64_t>(), D->step0->as<int64_t>(), D->steps, c1, c2,
                   kBoltzmannEv * D->temperature * kAccelUnit, D->N, st);
-        launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), 0.5 * dt, lim * lim, D->N,
-                     D->flag->as<int>(), st);
+        launch_drift(D->x->as<double>(), D->v->as<double>(), G->x_ref->as<double>(), 0.5 * dt, lim * lim, D->N, flag,
+                     stamp, probe, dt, st);
       }
     }
-    if (++D->since_build >= D->rebuild_every) {
-      int fh = 0;
-      E3MI_HIP(hipMemcpyAsync(&fh, D->flag->p, sizeof(int), hipMemcpyDeviceToHost, st));
-      E3MI_HIP(hipStreamSynchronize(st));
-      if (fh) {
-        // an atom travelled more than skin/2 within the interval: rebuild more often
-        D->skin_violations++;
-        D->rebuild_every = std::max(1, D->rebuild_every / 2);
-        E3MI_HIP(hipMemsetAsync(D->flag->p, 0, sizeof(int), st));
-      }
+    // Rebuild every rebuild_every steps, and early on any step whose drift
+    // takes an atom more than skin/2 from where the lists were built (a pair
+    // could then be inside the cutoff without being listed). The early check
+    // is decided before the step's results count: the force evaluation is
+    // queued at once, the host waits only for the drift (so the device keeps
+    // the evaluation to work on), and if the drift overran, the velocities are
+    // put back to before the kick and the evaluation and kick are redone on
+    // new lists. A rebuild does not change the selected edges or their order,
+    // so the redone step equals one whose lists were exact throughout. So that
+    // redoing stays rare, the drift's forecast of the next step's largest
+    // displacement brings the rebuild forward to the next step when it
+    // reaches skin/2.
+    const bool scheduled = ++D->since_build >= D->rebuild_every || D->rebuild_next;
+    if (scheduled) {
       md_rebuild(D, st);
+    } else {
+      E3MI_HIP(hipMemcpyAsync(D->flag_host, flag, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+      E3MI_HIP(hipEventRecord(D->drift_ev, st));
     }
-    energy_forces(D->model, G, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
     // the last step of the call hands the energies out in its kick launch
     // (unless a barostat move may still change them)
     const bool copy_here = energy_out && s + 1 == n_steps && D->baro_interval <= 0;
-    {
+    auto force_and_kick = [&]() {
+      energy_forces(D->model, G, D->x->as<double>(), D->energy->as<double>(), D->F->as<float>(), nullptr, st);
       ProfScope ps(&D->model->prof, stage_id(kMdUpdate), st);
       launch_kick_copy(D->v->as<double>(), D->F->as<float>(), D->species->as<int>(), D->inv_mass->as<double>(), hk,
-                       D->N, D->energy->as<double>(), energy_out, copy_here ? D->S : 0, st);
+                       D->N, D->energy->as<double>(), energy_out, copy_here ? D->S : 0,
+                       scheduled ? nullptr : D->v_prev->as<double>(), probe_next, st);
+    };
+    force_and_kick();
+    if (!scheduled) {
+      E3MI_HIP(hipEventSynchronize(D->drift_ev));
+      const volatile unsigned long long* fh = D->flag_host;
+      if (fh[0] == stamp) {
+        D->skin_violations++;
+        if (D->N)
+          E3MI_HIP(hipMemcpyAsync(D->v->p, D->v_prev->p, sizeof(double) * 3 * D->N, hipMemcpyDeviceToDevice, st));
+        md_rebuild(D, st);
+        force_and_kick();
+      } else {
+        const unsigned long long bits = fh[1 + (stamp & 1)];
+        double f;
+        std::memcpy(&f, &bits, sizeof f);
+        D->rebuild_next = f > lim;
+      }
     }
     if (copy_here) energy_out = nullptr;
     D->steps++;
@@ -1884,6 +1934,7 @@ void barostat_move(e3mi_md* D, const std::vector<int>& active, hipStream_t st) {
   }
   E3MI_HIP(hipStreamSynchronize(st));  // the host vectors above must outlive the copies
   D->since_build = 0;
+  D->rebuild_next = false;
 }
 
 void md_set_barostat(e3mi_md* D, double pressure_bar, int interval, double fraction, const double* dv_max,

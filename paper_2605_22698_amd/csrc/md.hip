@@ -3,7 +3,13 @@
 // forces arrive in FP32 from the interaction.
 //   kick:  v += (dt/2) kappa F / m
 //   drift: x += dt v, and flag any atom that moved more than skin/2 since the
-//          neighbour lists were built (they must then be rebuilt)
+//          neighbour lists were built (they must then be rebuilt): the flag
+//          takes the maximum of the step stamps that overran, so the host
+//          tells a new overrun from an old one without clearing it. The drift
+//          also records max over atoms of |x - x_ref| + dt_next |v|, a
+//          forecast of the displacement after the next step's drift (the
+//          velocity changes little in one step), which lets the host rebuild
+//          before an overrun instead of redoing the step after it.
 // Langevin dynamics (Section 5.5: the NVT integrator, batched systems with
 // independent seeds) adds the Ornstein-Uhlenbeck velocity update of the BAOAB
 // splitting,
@@ -18,6 +24,18 @@
 
 namespace e3mi {
 namespace {
+
+// Largest forecast of the wave into *probe (non-negative doubles order like
+// their bit patterns); one atomic per wave.
+__device__ __forceinline__ void record_forecast(double f, unsigned long long* probe) {
+  unsigned long long b = __double_as_longlong(f);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(b, off, 64);
+    b = o > b ? o : b;
+  }
+  if ((threadIdx.x & 63) == 0 && b) atomicMax(probe, b);
+}
 
 __global__ void k_kick(double* __restrict__ v, const float* __restrict__ F, const int* __restrict__ species,
                        const double* __restrict__ inv_mass, double half_dt_kappa, int N) {
@@ -34,55 +52,84 @@ __global__ void k_kick(double* __restrict__ v, const float* __restrict__ F, cons
 __global__ void k_kick_drift(double* __restrict__ v, const float* __restrict__ F, const int* __restrict__ species,
                              const double* __restrict__ inv_mass, double half_dt_kappa, double* __restrict__ x,
                              const double* __restrict__ x_ref, double dt, double limit2, int N,
-                             int* __restrict__ flag) {
+                             unsigned long long* __restrict__ flag, unsigned long long stamp,
+                             unsigned long long* __restrict__ probe, double dt_next) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double c = half_dt_kappa * inv_mass[species[i]];
-  double d2 = 0.0;
+  double forecast = 0.0;
+  if (i < N) {
+    const double c = half_dt_kappa * inv_mass[species[i]];
+    double d2 = 0.0, v2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double vk = v[3 * i + k] + c * (double)F[3 * i + k];
-    v[3 * i + k] = vk;
-    const double y = x[3 * i + k] + dt * vk;
-    x[3 * i + k] = y;
-    const double d = y - x_ref[3 * i + k];
-    d2 += d * d;
+    for (int k = 0; k < 3; ++k) {
+      const double vk = v[3 * i + k] + c * (double)F[3 * i + k];
+      v[3 * i + k] = vk;
+      const double y = x[3 * i + k] + dt * vk;
+      x[3 * i + k] = y;
+      const double d = y - x_ref[3 * i + k];
+      d2 += d * d;
+      v2 += vk * vk;
+    }
+    if (d2 > limit2) atomicMax(flag, stamp);
+    forecast = sqrt(d2) + dt_next * sqrt(v2);
   }
-  if (d2 > limit2) atomicOr(flag, 1);
+  if (probe) record_forecast(forecast, probe);
 }
 
-// Half kick; threads below n_copy also copy the structures' energies out
+// Half kick; threads below n_copy also copy the structures' energies out.
+// v_prev (may be NULL) receives the velocities before the kick, so that the
+// step's force evaluation and kick can be redone; probe_clear (may be NULL) is
+// zeroed for the next step's forecast.
 __global__ void k_kick_copy(double* __restrict__ v, const float* __restrict__ F, const int* __restrict__ species,
                             const double* __restrict__ inv_mass, double half_dt_kappa, int N,
-                            const double* __restrict__ e_src, double* __restrict__ e_dst, int n_copy) {
+                            const double* __restrict__ e_src, double* __restrict__ e_dst, int n_copy,
+                            double* __restrict__ v_prev, unsigned long long* __restrict__ probe_clear) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && probe_clear) *probe_clear = 0;
   if (i < n_copy) e_dst[i] = e_src[i];
   if (i >= N) return;
   const double c = half_dt_kappa * inv_mass[species[i]];
-  v[3 * i] += c * (double)F[3 * i];
-  v[3 * i + 1] += c * (double)F[3 * i + 1];
-  v[3 * i + 2] += c * (double)F[3 * i + 2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double vk = v[3 * i + k];
+    if (v_prev) v_prev[3 * i + k] = vk;
+    v[3 * i + k] = vk + c * (double)F[3 * i + k];
+  }
 }
 
 __global__ void k_drift(double* __restrict__ x, const double* __restrict__ v, const double* __restrict__ x_ref,
-                        double dt, double limit2, int N, int* __restrict__ flag) {
+                        double dt, double limit2, int N, unsigned long long* __restrict__ flag,
+                        unsigned long long stamp, unsigned long long* __restrict__ probe, double dt_next) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  double d2 = 0.0;
+  double forecast = 0.0;
+  if (i < N) {
+    double d2 = 0.0, v2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double y = x[3 * i + k] + dt * v[3 * i + k];
-    x[3 * i + k] = y;
-    const double d = y - x_ref[3 * i + k];
-    d2 += d * d;
+    for (int k = 0; k < 3; ++k) {
+      const double vk = v[3 * i + k];
+      const double y = x[3 * i + k] + dt * vk;
+      x[3 * i + k] = y;
+      const double d = y - x_ref[3 * i + k];
+      d2 += d * d;
+      v2 += vk * vk;
+    }
+    if (d2 > limit2) atomicMax(flag, stamp);
+    forecast = sqrt(d2) + dt_next * sqrt(v2);
   }
-  if (d2 > limit2) atomicOr(flag, 1);
+  if (probe) record_forecast(forecast, probe);
 }
 
 __global__ void k_nonfinite(const double* __restrict__ x, int n, int* __restrict__ flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (!isfinite(x[i])) atomicOr(flag, 4);
+}
+
+// Species outside [0, n_species) would index past the per-species tables
+__global__ void k_species_range(const int* __restrict__ species, int n, int n_species, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int z = species[i];
+  if (z < 0 || z >= n_species) atomicOr(flag, 8);
 }
 
 // Philox4x64 block function, 10 rounds.
@@ -156,20 +203,25 @@ void launch_kick(double* v, const float* F, const int* species, const double* in
   k_kick<<<blocks(N, 256), 256, 0, st>>>(v, F, species, inv_mass, half_dt_kappa, N);
 }
 void launch_kick_drift(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa,
-                       double* x, const double* x_ref, double dt, double limit2, int N, int* flag, hipStream_t st) {
+                       double* x, const double* x_ref, double dt, double limit2, int N, unsigned long long* flag,
+                       unsigned long long stamp, unsigned long long* probe, double dt_next, hipStream_t st) {
   if (N == 0) return;
-  k_kick_drift<<<blocks(N, 256), 256, 0, st>>>(v, F, species, inv_mass, half_dt_kappa, x, x_ref, dt, limit2, N, flag);
+  k_kick_drift<<<blocks(N, 256), 256, 0, st>>>(v, F, species, inv_mass, half_dt_kappa, x, x_ref, dt, limit2, N, flag,
+                                               stamp, probe, dt_next);
 }
 void launch_kick_copy(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa,
-                      int N, const double* e_src, double* e_dst, int n_copy, hipStream_t st) {
-  const int n = std::max(N, n_copy);
+                      int N, const double* e_src, double* e_dst, int n_copy, double* v_prev,
+                      unsigned long long* probe_clear, hipStream_t st) {
+  const int n = std::max(std::max(N, n_copy), probe_clear ? 1 : 0);
   if (n == 0) return;
-  k_kick_copy<<<blocks(n, 256), 256, 0, st>>>(v, F, species, inv_mass, half_dt_kappa, N, e_src, e_dst, n_copy);
+  k_kick_copy<<<blocks(n, 256), 256, 0, st>>>(v, F, species, inv_mass, half_dt_kappa, N, e_src, e_dst, n_copy,
+                                              v_prev, probe_clear);
 }
-void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N, int* flag,
+void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N,
+                  unsigned long long* flag, unsigned long long stamp, unsigned long long* probe, double dt_next,
                   hipStream_t st) {
   if (N == 0) return;
-  k_drift<<<blocks(N, 256), 256, 0, st>>>(x, v, x_ref, dt, limit2, N, flag);
+  k_drift<<<blocks(N, 256), 256, 0, st>>>(x, v, x_ref, dt, limit2, N, flag, stamp, probe, dt_next);
 }
 void launch_ou(double* v, const int* species, const double* inv_mass, const int* owner, const int64_t* offsets,
                const uint64_t* seeds, const int64_t* step0, int64_t step, double c1, double c2, double kT_kappa, int N,
@@ -188,6 +240,10 @@ void launch_restore_rows(double* x, const double* x_save, const int* owner, cons
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st) {
   if (n == 0) return;
   k_nonfinite<<<blocks(n, 256), 256, 0, st>>>(x, n, flag);
+}
+void launch_species_range(const int* species, int n, int n_species, int* flag, hipStream_t st) {
+  if (n == 0) return;
+  k_species_range<<<blocks(n, 256), 256, 0, st>>>(species, n, n_species, flag);
 }
 
 }  // namespace e3mi

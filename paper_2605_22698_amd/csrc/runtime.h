@@ -377,15 +377,24 @@ void launch_last(bool fwd, const LastArgs& a, hipStream_t st);
 // ---- MD (md.hip) -----------------------------------------------------------------------
 void launch_kick(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa, int N,
                  hipStream_t st);
-void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N, int* flag,
+// the drifts raise *flag to `stamp` when an atom is more than sqrt(limit2) from
+// x_ref, and (probe not NULL) raise *probe to the bits of the largest
+// |x - x_ref| + dt_next |v| over the atoms
+void launch_drift(double* x, const double* v, const double* x_ref, double dt, double limit2, int N,
+                  unsigned long long* flag, unsigned long long stamp, unsigned long long* probe, double dt_next,
                   hipStream_t st);
 // k_kick then k_drift in one pass (same arithmetic)
 void launch_kick_drift(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa,
-                       double* x, const double* x_ref, double dt, double limit2, int N, int* flag, hipStream_t st);
-// k_kick, with the n_copy structure energies copied e_src -> e_dst in the same launch
+                       double* x, const double* x_ref, double dt, double limit2, int N, unsigned long long* flag,
+                       unsigned long long stamp, unsigned long long* probe, double dt_next, hipStream_t st);
+// k_kick, with the n_copy structure energies copied e_src -> e_dst in the same
+// launch; v_prev (may be NULL) receives the velocities before the kick;
+// probe_clear (may be NULL) is set to 0
 void launch_kick_copy(double* v, const float* F, const int* species, const double* inv_mass, double half_dt_kappa,
-                      int N, const double* e_src, double* e_dst, int n_copy, hipStream_t st);
+                      int N, const double* e_src, double* e_dst, int n_copy, double* v_prev,
+                      unsigned long long* probe_clear, hipStream_t st);
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st);
+void launch_species_range(const int* species, int n, int n_species, int* flag, hipStream_t st);
 void launch_scale_positions(double* x, const int* owner, const double* lam, int N, hipStream_t st);
 void launch_restore_rows(double* x, const double* x_save, const int* owner, const int* keep, int N, hipStream_t st);
 void launch_ou(double* v, const int* species, const double* inv_mass, const int* owner, const int64_t* offsets,

@@ -64,6 +64,8 @@ class GpuExecutor:
                  friction_per_fs: float = 0.0, pressure_bar: Optional[float] = None, barostat_interval: int = 25,
                  volume_fraction: float = 0.01):
         import torch
+        if pressure_bar is not None and not friction_per_fs > 0:
+            raise ValueError("NPT (a pressure) needs the Langevin thermostat: give friction_per_fs > 0")
         self.torch = torch
         self.model = model
         self.masses = np.asarray(masses, dtype=np.float64)
@@ -144,18 +146,21 @@ class GpuExecutor:
 
 @dataclasses.dataclass
 class ServingStats:
-    step_ms: List[float] = dataclasses.field(default_factory=list)
-    atoms_per_step: List[int] = dataclasses.field(default_factory=list)
+    step_ms: List[float] = dataclasses.field(default_factory=list)   # device time of each packed step
+    iter_ms: List[float] = dataclasses.field(default_factory=list)   # wall time of each engine iteration,
+    atoms_per_step: List[int] = dataclasses.field(default_factory=list)  # repack (if any) included
     repacks: int = 0
     rejected: int = 0
     wall_s: float = 0.0
 
     def summary(self) -> dict:
         ms = np.asarray(self.step_ms) if self.step_ms else np.zeros(1)
+        it = np.asarray(self.iter_ms) if self.iter_ms else np.zeros(1)
         atom_steps = float(np.sum(self.atoms_per_step))
         busy = float(np.sum(ms)) / 1e3
         return {"steps": len(self.step_ms), "p50_ms": float(np.percentile(ms, 50)),
-                "p99_ms": float(np.percentile(ms, 99)), "atom_steps": atom_steps,
+                "p99_ms": float(np.percentile(ms, 99)), "p50_iter_ms": float(np.percentile(it, 50)),
+                "p99_iter_ms": float(np.percentile(it, 99)), "atom_steps": atom_steps,
                 "atom_steps_per_s": atom_steps / self.wall_s if self.wall_s > 0 else 0.0,
                 "atom_steps_per_busy_s": atom_steps / busy if busy > 0 else 0.0,
                 "repacks": self.repacks, "rejected": self.rejected, "wall_s": self.wall_s}
@@ -198,7 +203,8 @@ class Server:
         """Serve until every submitted request is finished or rejected."""
         t0 = self.clock()
         while self.pending or self.active:
-            now = self.clock() - t0
+            t_iter = self.clock()
+            now = t_iter - t0
             running = [r for r in self.active if r.steps_done < r.n_steps]
             finished = len(running) < len(self.active)
             if finished or self._head_fits(now, running):
@@ -232,6 +238,7 @@ class Server:
                     idle_wait(max(0.0, self.pending[0].arrival - (self.clock() - t0)))
                 continue
             self.stats.step_ms.append(self.ex.step())
+            self.stats.iter_ms.append(1e3 * (self.clock() - t_iter))
             self.stats.atoms_per_step.append(sum(r.n_atoms for r in self.active))
             for r in self.active:
                 r.steps_done += 1

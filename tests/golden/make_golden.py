@@ -11,6 +11,14 @@ single_3000.npz  3,000-atom periodic box at 0.1 atoms/A^3 (jittered lattice,
 scale_sub_2000.npz  the independent 2,000-atom periodic box of the
                  100,000-atom configuration (r_c 6 A, l_max 3, 128 channels,
                  3 layers): energy, per-atom energies, forces.
+grad_batch_64.npz  the differentiation batch (64 periodic boxes of 20-200
+                 atoms, 5 species, l_max 3, 64 channels, 2 layers, seeded
+                 N(0, 1) targets): loss = mean_s (E_s - E_s*)^2 +
+                 sum_i |F_i - F_i*|^2 / (3 sum N) and its gradient with
+                 respect to every weight (flat, in the library's order),
+                 with the energies and forces. The loss is a sum of
+                 per-structure terms, so the oracle evaluates each structure
+                 alone, with that structure's share of the normalisation.
 """
 import os
 import sys
@@ -43,7 +51,26 @@ def scale_sub_2000():
                         n_atoms=b.n_atoms)
 
 
-JOBS = {"single_3000": single_3000, "scale_sub_2000": scale_sub_2000}
+def grad_batch_64():
+    cfg, b, e_ref, f_ref = synth.differentiation_config()
+    m = om.Model(cfg, synth.model_weights(cfg, 3))
+    S, n3 = b.n_structures, 3 * b.n_atoms
+    loss, flat, E, F = 0.0, None, np.zeros(S), np.zeros((b.n_atoms, 3))
+    for s in range(S):
+        a, z = int(b.offsets[s]), int(b.offsets[s + 1])
+        bs = b.structure(s)
+        ls, gs = om.loss_and_grads(m, bs, e_ref[s:s + 1], f_ref[a:z], w_energy=1.0 / S,
+                                   w_forces=3.0 * (z - a) / n3)
+        loss += ls
+        g = synth.flatten_weights(cfg, gs)
+        flat = g if flat is None else flat + g
+        Es, Fs, _ = om.energy_forces(m, bs)
+        E[s], F[a:z] = Es[0], Fs
+    np.savez_compressed(os.path.join(HERE, "grad_batch_64.npz"), loss=loss, grad=flat, energy=E, forces=F,
+                        n_atoms=b.n_atoms)
+
+
+JOBS = {"single_3000": single_3000, "scale_sub_2000": scale_sub_2000, "grad_batch_64": grad_batch_64}
 
 if __name__ == "__main__":
     torch.set_num_threads(os.cpu_count() or 1)

@@ -75,3 +75,31 @@ def test_null_handles(lib):
     assert lib.e3mi_graph_info(None, None, None) == -1
     assert lib.e3mi_footprint_bytes(None, 10, 10) == 0
     assert lib.e3mi_model_destroy(None) == 0
+
+
+def test_md_binding_rejects_bad_state_before_the_library():
+    # the MD binding checks shapes and dtypes of the state and the mass table
+    # before any call into the library (no device needed)
+    import torch
+    import paper_2605_22698_amd as e3
+
+    class _FakeModel:
+        config_json = synth.tiny_config()[0].to_json()
+        handle = None
+
+    cfg, b = synth.tiny_config()
+    n = b.n_atoms
+    pos = torch.tensor(b.pos, dtype=torch.float64)
+    vel = torch.zeros((n, 3), dtype=torch.float64)
+    sp = torch.tensor(b.species, dtype=torch.int32)
+    masses = synth.SPECIES_MASS[:cfg.n_species]
+    bad = [
+        dict(pos=pos.float()), dict(pos=pos[:-1]), dict(vel=vel.float()), dict(vel=vel[:, :2]),
+        dict(species=sp[:-1]), dict(species=sp.double()), dict(masses=synth.SPECIES_MASS[:cfg.n_species + 1]),
+    ]
+    for change in bad:
+        args = dict(pos=pos, vel=vel, species=sp, masses=masses)
+        args.update(change)
+        with pytest.raises(ValueError):
+            e3.MD(_FakeModel(), b.offsets, args["pos"], args["vel"], args["species"], args["masses"], b.cell, b.pbc,
+                  cfg.cutoff)

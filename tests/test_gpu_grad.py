@@ -1,11 +1,15 @@
 """Parameter gradients of an energy + force loss (second order through F):
-the library's pass behind torch.autograd vs the oracle's double backward."""
+the library's pass behind torch.autograd vs the oracle's double backward.
+Bound: relative L2 error of the whole gradient <= 1e-4, and <= 1e-3 per
+weight tensor."""
+import os
+
 import numpy as np
 import pytest
 
 import synth
 from oracle import model as om
-from tests.gpu_util import device, say
+from tests.gpu_util import check_energy, check_forces, device, record, say
 
 pytestmark = pytest.mark.gpu
 
@@ -28,15 +32,19 @@ def _gpu_loss_grads(cfg, seed_key, b, e_ref, f_ref, w_e=1.0, w_f=1.0, skin=0.5):
     return loss.item(), w.grad.cpu().numpy()
 
 
-def _compare(cfg, seed_key, b, e_ref, f_ref, w_e=1.0, w_f=1.0, rel=2e-4):
+def _compare(cfg, seed_key, b, e_ref, f_ref, w_e=1.0, w_f=1.0, rel=1e-4):
     loss_g, grad_g = _gpu_loss_grads(cfg, seed_key, b, e_ref, f_ref, w_e, w_f)
     m = om.Model(cfg, synth.model_weights(cfg, seed_key))
     loss_o, grads_o = om.loss_and_grads(m, b, e_ref, f_ref, w_e, w_f)
     flat_o = synth.flatten_weights(cfg, grads_o)
     assert abs(loss_g - loss_o) <= 1e-5 * abs(loss_o)
     tot = np.linalg.norm(grad_g - flat_o) / np.linalg.norm(flat_o)
-    say(f"  loss {loss_o:.6e}; gradient rel L2 error {tot:.2e}")
+    record("gradient", loss_rel=abs(loss_g - loss_o) / abs(loss_o), grad_rel_l2=float(tot), bound=rel)
     assert tot <= rel
+    _per_tensor(cfg, grad_g, flat_o)
+
+
+def _per_tensor(cfg, grad_g, flat_o):
     off = 0
     for name, shape, _ in synth.weight_shapes(cfg):
         n = int(np.prod(shape))
@@ -75,3 +83,84 @@ def test_open_cluster_lmax3_three_layers():
     rng = np.random.default_rng(62)
     b = synth.uniform_cluster(20, 8.0, 1.0, 3, rng)
     _compare(cfg, 9, b, rng.standard_normal(1), rng.standard_normal((20, 3)) * 0.01)
+
+
+def test_differentiation_batch_64_structures_golden():
+    # the full differentiation batch: 64 periodic boxes of 20-200 atoms, against
+    # the oracle's loss and gradient stored by tests/golden/make_golden.py
+    import torch
+    import paper_2605_22698_amd as e3
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_batch_64.npz"))
+    cfg, b, e_ref, f_ref = synth.differentiation_config()
+    say(f"grad: 64-structure batch N={b.n_atoms}")
+    d = device()
+    wflat = synth.flatten_weights(cfg, synth.model_weights(cfg, 3))
+    m = e3.Model(cfg.to_json(), wflat, device=d)
+    pos = torch.tensor(b.pos, dtype=torch.float64, device=d)
+    g = m.build_graph(b.offsets, pos, torch.tensor(b.species, dtype=torch.int32, device=d), b.cell, b.pbc,
+                      cfg.cutoff, 0.5)
+    w = torch.tensor(wflat, dtype=torch.float64, device=d, requires_grad=True)
+    E, F = e3.energy_forces(w, pos, m, g)
+    loss = (torch.mean((E - torch.tensor(e_ref, device=d)) ** 2)
+            + torch.sum((F.double() - torch.tensor(f_ref, device=d)) ** 2) / F.numel())
+    loss.backward()
+    torch.cuda.synchronize()
+    Eh, Fh = E.detach().cpu().numpy(), F.detach().double().cpu().numpy()
+    for s in range(b.n_structures):
+        check_energy(Eh[s:s + 1], ref["energy"][s:s + 1], None)
+    check_forces(Fh, ref["forces"])
+    lo, go = float(ref["loss"]), ref["grad"]
+    gg = w.grad.cpu().numpy()
+    tot = np.linalg.norm(gg - go) / np.linalg.norm(go)
+    record("gradient", loss_rel=abs(loss.item() - lo) / abs(lo), grad_rel_l2=float(tot), bound=1e-4)
+    assert abs(loss.item() - lo) <= 1e-5 * abs(lo)
+    assert tot <= 1e-4
+    _per_tensor(cfg, gg, go)
+
+
+def test_weights_changed_in_place_and_between_forward_and_backward():
+    # a change through .data keeps the tensor's version counter; a second
+    # forward with other weights before the first backward must not change
+    # what the first backward differentiates
+    import torch
+    import paper_2605_22698_amd as e3
+    cfg, b, e_ref, f_ref = synth.differentiation_config(2, 20, 40)
+    d = device()
+    w0 = synth.flatten_weights(cfg, synth.model_weights(cfg, 3))
+    w1 = synth.flatten_weights(cfg, synth.model_weights(cfg, 4))
+    m = e3.Model(cfg.to_json(), w0, device=d)
+    pos = torch.tensor(b.pos, dtype=torch.float64, device=d)
+    g = m.build_graph(b.offsets, pos, torch.tensor(b.species, dtype=torch.int32, device=d), b.cell, b.pbc,
+                      cfg.cutoff, 0.5)
+
+    def loss_of(E, F):
+        return (torch.mean((E - torch.tensor(e_ref, device=d)) ** 2)
+                + torch.sum((F.double() - torch.tensor(f_ref, device=d)) ** 2) / F.numel())
+
+    def reference(wv):
+        mm = e3.Model(cfg.to_json(), wv, device=d)
+        ww = torch.tensor(wv, dtype=torch.float64, device=d, requires_grad=True)
+        gg = mm.build_graph(b.offsets, pos, torch.tensor(b.species, dtype=torch.int32, device=d), b.cell, b.pbc,
+                            cfg.cutoff, 0.5)
+        E, F = e3.energy_forces(ww, pos, mm, gg)
+        loss_of(E, F).backward()
+        return E.detach().cpu().numpy(), ww.grad.cpu().numpy()
+
+    E_ref0, G_ref0 = reference(w0)
+    E_ref1, G_ref1 = reference(w1)
+    w = torch.tensor(w0, dtype=torch.float64, device=d, requires_grad=True)
+    E, F = e3.energy_forces(w, pos, m, g)
+    assert np.array_equal(E.detach().cpu().numpy(), E_ref0)
+    w.data.copy_(torch.tensor(w1, device=d))          # in place, version counter unchanged
+    E, F = e3.energy_forces(w, pos, m, g)
+    assert np.array_equal(E.detach().cpu().numpy(), E_ref1)
+    # two forwards, then the first one's backward
+    wa = torch.tensor(w0, dtype=torch.float64, device=d, requires_grad=True)
+    wb = torch.tensor(w1, dtype=torch.float64, device=d, requires_grad=True)
+    Ea, Fa = e3.energy_forces(wa, pos, m, g)
+    Eb, Fb = e3.energy_forces(wb, pos, m, g)
+    loss_of(Ea, Fa).backward()
+    loss_of(Eb, Fb).backward()
+    torch.cuda.synchronize()
+    assert np.array_equal(wa.grad.cpu().numpy(), G_ref0)
+    assert np.array_equal(wb.grad.cpu().numpy(), G_ref1)

@@ -101,3 +101,20 @@ def test_rejects_triclinic_and_nan(m):
     assert ei.value.code == -5
     with pytest.raises(e3.E3miError):
         m.build_graph(b.offsets, pos, sp, b.cell, b.pbc, 4.0, 0.0)   # below the model cutoff
+
+
+def test_rejects_species_out_of_range(m):
+    # species index the per-species tables: values outside [0, n_species)
+    # are rejected by the graph build (and so by MD creation) with EINVAL
+    import paper_2605_22698_amd as e3
+    b = synth.jittered_lattice(20, 0.1, 0.3, 3, np.random.default_rng(2))
+    pos, sp = to_dev(b)
+    n_species = synth.ModelConfig.from_json(m.config_json).n_species
+    for v in (-1, n_species, 1 << 20):
+        bad = sp.clone()
+        bad[7] = v
+        with pytest.raises(e3.E3miError) as ei:
+            m.build_graph(b.offsets, pos, bad, b.cell, b.pbc, 5.0, 0.0)
+        assert ei.value.code == -1 and "species" in str(ei.value)
+    g = m.build_graph(b.offsets, pos, sp, b.cell, b.pbc, 5.0, 0.0)   # the model is still usable
+    assert g.n_skin_edges > 0

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import check_energy, check_forces, gpu_energy_forces, model, say
+from tests.gpu_util import check_atom_energies, check_energy, check_forces, gpu_energy_forces, model, record, say
 
 pytestmark = pytest.mark.gpu
 
@@ -38,15 +38,18 @@ def test_scale_subbox_against_oracle(chunk_bytes):
     if chunk_bytes:
         m32.set_r_chunk_bytes(chunk_bytes)
         m16.set_r_chunk_bytes(chunk_bytes)
-    E32, F32, _, _ = gpu_energy_forces(m32, b, skin=1.0)
-    E16, F16, _, _ = gpu_energy_forces(m16, b, skin=1.0)
+    E32, F32, Ei32, _ = gpu_energy_forces(m32, b, skin=1.0)
+    E16, F16, Ei16, _ = gpu_energy_forces(m16, b, skin=1.0)
     e = check_energy(E32, ref["energy"], ref["atom_energy"])
+    ea = check_atom_energies(Ei32, ref["atom_energy"])
     f = check_forces(F32, ref["forces"])
     fmax = np.abs(ref["forces"]).max()
     e16 = abs(E16[0] - ref["energy"][0]) / b.n_atoms
+    ea16 = np.abs(Ei16 - ref["atom_energy"]).max() / np.abs(ref["atom_energy"]).max()
     f16 = np.abs(F16 - ref["forces"]).max() / fmax
-    say(f"sub-box (chunk {chunk_bytes}): FP32 energy rel err {e:.2e}, force err {f[0]:.2e} eV/A; "
-        f"BF16 energy err {e16:.2e} eV/atom, force err {f16:.2e} of max |F|")
+    record("bf16", energy_eV_per_atom=float(e16), atom_energy_rel_to_max=float(ea16), force_rel_to_max=float(f16))
+    say(f"sub-box (chunk {chunk_bytes}): FP32 energy rel err {e:.2e}, atom energies {ea:.2e} of max, force err "
+        f"{f[0]:.2e} eV/A; BF16 energy err {e16:.2e} eV/atom, force err {f16:.2e} of max |F|")
     assert e16 < 1e-3 and f16 < 5e-2
 
 

@@ -126,3 +126,34 @@ def test_rejects_request_that_can_never_fit_and_respects_slots():
     srv, ex, stats = _serve(reqs + [big], budget=100 * 200, max_active=2)
     assert big.rejected and stats.rejected == 1
     assert all(r.steps_done == r.n_steps for r in srv.done if not r.rejected)
+
+
+def test_iteration_latency_includes_repacks():
+    # a repack (new packed state) costs 5 ms of virtual time here: the
+    # per-iteration wall times include it, the device step times do not
+    reqs = _requests(12, seed=4)
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    plain_launch = ex.launch
+
+    def slow_launch(parts):
+        clock.t += 5e-3
+        plain_launch(parts)
+    ex.launch = slow_launch
+    srv = Server(ex, 10 ** 9, clock=clock)
+    for r in reqs:
+        srv.submit(r)
+    stats = srv.run(idle_wait=clock.wait)
+    s = stats.summary()
+    assert len(stats.iter_ms) == len(stats.step_ms) == s["steps"]
+    assert all(it >= st - 1e-9 for it, st in zip(stats.iter_ms, stats.step_ms))
+    # every repack but the last (which empties the pack) precedes a step
+    assert sum(it - st > 4.9 for it, st in zip(stats.iter_ms, stats.step_ms)) == stats.repacks - 1
+    assert s["p99_iter_ms"] > s["p99_ms"]
+
+
+def test_pressure_without_thermostat_is_rejected():
+    import pytest
+    from paper_2605_22698_amd.serving import GpuExecutor
+    with pytest.raises(ValueError, match="Langevin"):
+        GpuExecutor(None, [1.0], 5.0, pressure_bar=1.0)
