@@ -89,10 +89,17 @@ def work_model(cfg, t, E, N):
                          E * (16 + 4 * PC + 64 + 32))
     # tensor product + neighbour sum: R streamed once, h read and A written once per atom
     out["tp_fwd"] = (E * tp_flops, E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
-    out["tp_bwd_edge"] = (E * (tp_flops + 2 * C * sum(nz for *_, nz in ps) + 2 * C * nout),
-                          E * (8 * PC + 16 + 4 + 64) + N * 4 * C * (nc_in + nout))
-    out["tp_bwd_node"] = (E * 2 * C * sum(nz + 2 * l3 + 1 for (_, _, l3, nz) in ps),
-                          E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
+    edge_adj = E * (tp_flops + 2 * C * sum(nz for *_, nz in ps) + 2 * C * nout)
+    node_adj = E * 2 * C * sum(nz + 2 * l3 + 1 for (_, _, l3, nz) in ps)
+    if t == cfg.layers and C in (64, 128, 256):
+        # scalar-output layer: the sender-side adjoint (tps.hip) gives dR, dY
+        # and dh in one pass: R read once, dR and dY written, edge vector, sender
+        # and reverse index per edge; h, dA and dh (read and written) once per atom
+        out["tp_bwd_edge"] = (edge_adj + (node_adj if t > 1 else 0),
+                              E * (8 * PC + 64 + 16 + 4 + 4) + N * 4 * C * (nc_in + nout + (2 * nc_in if t > 1 else 0)))
+    else:
+        out["tp_bwd_edge"] = (edge_adj, E * (8 * PC + 16 + 4 + 64) + N * 4 * C * (nc_in + nout))
+        out["tp_bwd_node"] = (node_adj, E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
     return out
 
 

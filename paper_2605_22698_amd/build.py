@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libe3mi.so")
-SOURCES = ["graph.hip", "tp.hip", "radial.hip", "first.hip", "last.hip", "node.hip", "md.hip", "grad.hip", "coulomb.hip", "product.hip", "api.hip"]
+SOURCES = ["graph.hip", "tp.hip", "tps.hip", "radial.hip", "first.hip", "last.hip", "node.hip", "md.hip", "grad.hip", "coulomb.hip", "product.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

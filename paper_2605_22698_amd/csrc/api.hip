@@ -1189,7 +1189,31 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     // with more than one chunk R is recomputed chunk by chunk (the forward
     // pass kept only the last chunk)
     const std::vector<RChunk> chunks = r_chunks(M, G, PCu, st);
+    ta.rev = G->rev_x->as<int>();
+    // scalar-output layer: the sender-side adjoint gives dR, dY and dh in one
+    // pass (chunk by chunk: a chunk's receivers are the senders whose rows it holds)
+    const bool sender_side = tps_supported(ta);
     for (const RChunk& ch : chunks) {
+      if (sender_side) {
+        if (chunks.size() > 1) {
+          ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
+          launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
+                            W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->as<float>(), rc, p_env, bf16, st, ch.e0,
+                            ch.e1);
+        }
+        set_chunk(ta, ch);
+        TpArgs ts = ta;
+        if (t == 1) ts.dh = nullptr;
+        {
+          ProfScope ps(&M->prof, stage_id(kTpBwdEdge, t), st);
+          launch_tps_sender(ts, st);
+        }
+        ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
+        launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
+                          W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->as<float>(), w.dY->as<float>(), g,
+                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1);
+        continue;
+      }
       if (chunks.size() > 1) {
         ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
         launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),

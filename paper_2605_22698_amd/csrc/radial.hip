@@ -478,6 +478,8 @@ __global__ void __launch_bounds__(256) k_radial_dual_bwd(const int* __restrict__
 
 inline int tiles(long n) { return (int)((n + kTile - 1) / kTile); }
 
+
+
 }  // namespace
 
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,

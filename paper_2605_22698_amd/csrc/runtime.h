@@ -232,12 +232,17 @@ struct TpArgs {
   // receiver chunk (first-order kernels 0-2): receivers i0 .. i0 + n_recv - 1
   // (n_recv 0: all N from i0 = 0), R and dR indexed from edge e_first
   int i0, n_recv, e_first;
+  const int* rev;  // reverse edge of each edge (-1: pruned), for the sender-side adjoint
 };
 // which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...),
 //        3 tangent forward (Ad), 4 second-order edge adjoint (Rb, Rc),
 //        5 second-order node adjoint (hb, hc += ...),
 //        6 adjoints of the harmonics and their tangent (Yb, Yc) for Hessian-vector products
 void launch_tp(int which, const TpArgs& a, hipStream_t st);
+// scalar-output layer with R of every edge in memory (tps.hip): the
+// sender-side adjoint, dR and dY of pass 1 and, when a.dh is set, dh of pass 2
+bool tps_supported(const TpArgs& a);
+void launch_tps_sender(const TpArgs& a, hipStream_t st);
 
 // ---- per-atom stages (node.hip) -----------------------------------------------------
 // Rows of a matrix whose row r lives at base + (r / g) * s_atom + (r % g) * s_m

@@ -16,7 +16,7 @@ grad_batch_64.npz  the differentiation batch (64 periodic boxes of 20-200
                  N(0, 1) targets): loss = mean_s (E_s - E_s*)^2 +
                  sum_i |F_i - F_i*|^2 / (3 sum N) and its gradient with
                  respect to every weight (flat, in the library's order),
-                 with the energies and forces. The loss is a sum of
+                 with the energies, per-atom energies and forces. The loss is a sum of
                  per-structure terms, so the oracle evaluates each structure
                  alone, with that structure's share of the normalisation.
 """
@@ -55,7 +55,7 @@ def grad_batch_64():
     cfg, b, e_ref, f_ref = synth.differentiation_config()
     m = om.Model(cfg, synth.model_weights(cfg, 3))
     S, n3 = b.n_structures, 3 * b.n_atoms
-    loss, flat, E, F = 0.0, None, np.zeros(S), np.zeros((b.n_atoms, 3))
+    loss, flat, E, F, Ei = 0.0, None, np.zeros(S), np.zeros((b.n_atoms, 3)), np.zeros(b.n_atoms)
     for s in range(S):
         a, z = int(b.offsets[s]), int(b.offsets[s + 1])
         bs = b.structure(s)
@@ -64,10 +64,10 @@ def grad_batch_64():
         loss += ls
         g = synth.flatten_weights(cfg, gs)
         flat = g if flat is None else flat + g
-        Es, Fs, _ = om.energy_forces(m, bs)
-        E[s], F[a:z] = Es[0], Fs
+        Es, Fs, Eis = om.energy_forces(m, bs)
+        E[s], F[a:z], Ei[a:z] = Es[0], Fs, Eis
     np.savez_compressed(os.path.join(HERE, "grad_batch_64.npz"), loss=loss, grad=flat, energy=E, forces=F,
-                        n_atoms=b.n_atoms)
+                        atom_energy=Ei, n_atoms=b.n_atoms)
 
 
 JOBS = {"single_3000": single_3000, "scale_sub_2000": scale_sub_2000, "grad_batch_64": grad_batch_64}

@@ -73,9 +73,9 @@ def test_nve_energy_conservation():
     say(f"NVE 400 steps: max |dE_total| {drift:.3e} eV (KE {ke:.3f} eV)")
     assert drift < 1e-4 * ke
     steps, rebuilds, violations = md.stats()
-    # every 20 steps, plus one early rebuild per step that overran skin/2
-    assert steps == 400 and rebuilds >= violations
-    assert violations > 0 or rebuilds == 20
+    # at least every 20 steps; earlier when the forecast displacement reaches
+    # skin/2, or after a step that overran it
+    assert steps == 400 and rebuilds >= 20 and rebuilds >= violations
 
 
 @pytest.mark.parametrize("skin", [0.0, 0.1])
