@@ -510,7 +510,8 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": nbytes / avg_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic("k_" + s)
+    # the last layer's edge adjoint stage is the sender-side kernel (tps.hip)
+    roof["traffic"] = measured_traffic("k_tps_bwd_sender" if (s, t) == ("tp_bwd_edge", cfg.layers) else "k_" + s)
     roof["kernel"] = f"{s} (layer {t})"
     roof["avg_launch_ms"] = tot / n
     roof["algorithmic_per_launch"] = {"flops": flops, "bytes": nbytes, "edges": n_edges}
