@@ -166,6 +166,26 @@ int e3mi_graph_copy_edges(const e3mi_graph* graph, int32_t* row_ptr, int32_t* sr
 int e3mi_energy_forces(e3mi_model* model, e3mi_graph* graph, const double* pos, double* energy,
                        float* forces, double* atom_energy, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * evaluation as e3mi_energy_forces, same arguments and results, with every
+ * per-call workspace buffer taken from a static device array of
+ * E3MI_STATIC_SCRATCH_BYTES (128 MiB) that the library holds on each GPU it
+ * runs on until the process ends. Calls no device allocator (the model's
+ * allocator callbacks included) and clears memory with kernels, not memsets.
+ * The graph must have been built beforehand (e3mi_build_graph allocates).
+ * Errors: ENOMEM when the evaluation needs more than the array (outputs are
+ * then unspecified; roughly N x 16 x C x 4 bytes per feature buffer plus
+ * 4 x P x C bytes per edge for each layer's radial weights and their adjoint),
+ * EINVAL when a layer's per-edge radial weights would have to be split into
+ * receiver chunks. The array keeps the last call's contents; every buffer the
+ * evaluation reads is written first. All calls on one GPU share the array:
+ * calls that overlap in time on one GPU race, so issue them in order on one
+ * stream. The model's own workspace is left as it was. */
+#define E3MI_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+int e3mi_energy_forces_static(e3mi_model* model, e3mi_graph* graph, const double* pos, double* energy,
+                              float* forces, double* atom_energy, void* stream);
+
 /* Gradient of a loss L(E, F) with respect to the weights, given the upstream
  * gradients grad_energy = dL/dE (device FP64 [S]) and grad_forces = dL/dF
  * (device FP32 [N, 3]): writes dL/dtheta = sum_s dL/dE_s dE_s/dtheta +

@@ -41,6 +41,7 @@ SIGNATURES = {
     "e3mi_graph_info": (ctypes.c_int, [_p, _i64p, _i64p]),
     "e3mi_graph_copy_edges": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
     "e3mi_energy_forces": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p]),
+    "e3mi_energy_forces_static": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p]),
     "e3mi_graph_last_edge_count": (ctypes.c_int, [_p, _i64p, _p]),
     "e3mi_param_grad": (ctypes.c_int, [_p, _p, _p, _p, _p, _p, _p]),
     "e3mi_hessian_vector": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),

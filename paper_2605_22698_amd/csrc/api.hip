@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1027,7 +1028,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
   const int p_env = c.envelope_p;
   Workspace& w = M->ws;
   if (N == 0) {
-    E3MI_HIP(hipMemsetAsync(energy, 0, sizeof(double) * S, st));
+    launch_zero(energy, sizeof(double) * S, st);
     return;
   }
   const bool coulomb = c.coulomb;
@@ -1102,7 +1103,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     if (prod) {
       {
         ProfScope ps(&M->prof, stage_id(kMixBwd, t), st);
-        if (t > 1) E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+        if (t > 1) launch_zero(dother, sizeof(float) * (size_t)N * L.nc_in * C, st);
         launch_lin_adjoint(M, L, W, dht, w.Bp->as<float>(), t > 1 ? dother : nullptr, N, st, bf16);
       }
       ProductArgs pa = product_args(M, G, L, W, w.at[t]->as<float>());
@@ -1146,7 +1147,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       // the per-edge node adjoint writes the components of dh the self
       // connection's adjoint leaves alone, so only the fused layer needs dh cleared
       if (t > 1 && !prod && fused_last(M, L, false, bf16))
-        E3MI_HIP(hipMemsetAsync(dother, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+        launch_zero(dother, sizeof(float) * (size_t)N * L.nc_in * C, st);
       launch_mix_adjoint(M, L, W, dmix, dmix_nc, A, (t > 1 && !prod) ? dother : nullptr, N, st, bf16);
     }
     if (fused_last(M, L, false, M->precision == E3MI_BF16_MIX)) {
@@ -2016,6 +2017,74 @@ void set_error(const std::string& m) { g_last_error = m; }
 }  // namespace
 }  // namespace e3mi
 
+// ---- evaluation without allocation ----------------------------------------------------
+// Per-call workspace for callers that cannot allocate: a static device array,
+// held by every GPU the library runs on until the process ends. Host code uses
+// its device address (from hipGetSymbolAddress, per device), never its name.
+constexpr size_t kStaticScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace e3mi {
+namespace {
+
+std::mutex g_scratch_mu;
+std::array<char*, 64> g_scratch_ptr{};
+
+// the array's address on the current device (looked up once per device)
+char* static_scratch() {
+  int dev = 0;
+  E3MI_HIP(hipGetDevice(&dev));
+  E3MI_REQUIRE(dev >= 0 && dev < (int)g_scratch_ptr.size(), E3MI_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    E3MI_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    E3MI_REQUIRE(p != nullptr, E3MI_EDEVICE, "static scratch has no device address");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// energy_forces with every workspace buffer carved from the static scratch:
+// the model's own workspace and allocator are set aside for the call and put
+// back afterwards (also on error).
+void energy_forces_static(e3mi_model* M, e3mi_graph* G, const double* pos, double* energy, float* forces,
+                          double* atom_energy, hipStream_t st) {
+  // layers with per-edge R must hold every edge's R at once (receiver chunks
+  // read the row pointer back to the host)
+  for (int t = 1; t <= M->cfg.layers; ++t) {
+    const LayerPlan& L = M->plans[t - 1];
+    if ((t == 1 && factorised_first(M)) || fused_last(M, L, false, M->precision == E3MI_BF16_MIX)) continue;
+    E3MI_REQUIRE(r_chunk_edges(M, G->E, L.p_used * M->cfg.channels) >= (size_t)(G->E + 1), E3MI_EINVAL,
+                 "the per-edge radial weights of every edge must fit the model's R budget at once");
+  }
+  char* base = static_scratch();
+  Workspace saved = std::move(M->ws);
+  const Allocator saved_alloc = M->alloc;
+  const bool prof_on = M->prof.on;
+  M->ws = Workspace{};
+  M->alloc.arena = base;
+  M->alloc.arena_bytes = kStaticScratchBytes;
+  M->alloc.arena_used = 0;
+  M->prof.on = false;  // timing events are not allocated either
+  auto restore = [&] {
+    M->ws = Workspace{};  // the carved buffers are released while the arena is in place (no frees)
+    M->alloc = saved_alloc;
+    M->ws = std::move(saved);
+    M->prof.on = prof_on;
+  };
+  try {
+    energy_forces(M, G, pos, energy, forces, atom_energy, st);
+  } catch (...) {
+    restore();
+    throw;
+  }
+  restore();
+}
+
+}  // namespace
+}  // namespace e3mi
+
 // ---- C ABI -----------------------------------------------------------------------------------
 
 #define E3MI_API_BEGIN \
@@ -2109,6 +2178,17 @@ int e3mi_energy_forces(e3mi_model* model, e3mi_graph* graph, const double* pos, 
   E3MI_REQUIRE(graph->model == model, E3MI_EINVAL, "graph was built for another model");
   E3MI_REQUIRE(graph->N == 0 || pos, E3MI_EINVAL, "null positions");
   e3mi::energy_forces(model, graph, pos, energy, forces, atom_energy, e3mi::as_stream(stream));
+  E3MI_HIP(hipGetLastError());
+  E3MI_API_END
+}
+
+int e3mi_energy_forces_static(e3mi_model* model, e3mi_graph* graph, const double* pos, double* energy,
+                              float* forces, double* atom_energy, void* stream) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model && graph && energy && forces, E3MI_EINVAL, "null argument");
+  E3MI_REQUIRE(graph->model == model, E3MI_EINVAL, "graph was built for another model");
+  E3MI_REQUIRE(graph->N == 0 || pos, E3MI_EINVAL, "null positions");
+  e3mi::energy_forces_static(model, graph, pos, energy, forces, atom_energy, e3mi::as_stream(stream));
   E3MI_HIP(hipGetLastError());
   E3MI_API_END
 }

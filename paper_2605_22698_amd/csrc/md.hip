@@ -19,6 +19,8 @@
 // counter (step, index of the atom within its structure, 0, 0), turned into
 // normals by Box-Muller on the uniforms ((x >> 11) + 1/2) 2^-53. A structure's
 // noise is thus independent of what else is packed with it.
+#include <algorithm>
+
 #include "common.h"
 #include "runtime.h"
 
@@ -193,6 +195,10 @@ __global__ void k_restore_rows(double* __restrict__ x, const double* __restrict_
   x[3 * i + 2] = x_save[3 * i + 2];
 }
 
+__global__ void k_zero(unsigned* __restrict__ p, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
 inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
@@ -236,6 +242,11 @@ void launch_scale_positions(double* x, const int* owner, const double* lam, int 
 void launch_restore_rows(double* x, const double* x_save, const int* owner, const int* keep, int N, hipStream_t st) {
   if (N == 0) return;
   k_restore_rows<<<blocks(N, 256), 256, 0, st>>>(x, x_save, owner, keep, N);
+}
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const long n = (long)(bytes / 4);
+  if (n == 0) return;
+  k_zero<<<std::min(blocks(n, 256), 4096), 256, 0, st>>>(static_cast<unsigned*>(p), n);
 }
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st) {
   if (n == 0) return;

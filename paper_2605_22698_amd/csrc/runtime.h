@@ -35,8 +35,21 @@ struct Allocator {
   e3mi_alloc_fn alloc = nullptr;
   e3mi_free_fn free_fn = nullptr;
   void* ctx = nullptr;
+  // arena mode (arena not NULL): hand out consecutive 256-byte aligned pieces
+  // of [arena, arena + arena_bytes) and never free; nothing is allocated
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
   void* get(size_t bytes) {
     if (bytes == 0) bytes = 256;
+    if (arena) {
+      const size_t need = (bytes + 255) & ~(size_t)255;
+      if (need > arena_bytes - arena_used)
+        throw Error(E3MI_ENOMEM, "the evaluation needs more than the static scratch of " +
+                                     std::to_string(arena_bytes) + " bytes");
+      void* p = arena + arena_used;
+      arena_used += need;
+      return p;
+    }
     void* p = nullptr;
     if (alloc) {
       p = alloc(bytes, ctx);
@@ -47,7 +60,7 @@ struct Allocator {
     return p;
   }
   void put(void* p) {
-    if (!p) return;
+    if (!p || arena) return;
     if (free_fn) {
       free_fn(p, ctx);
     } else if (!alloc) {
@@ -399,6 +412,8 @@ void launch_kick_copy(double* v, const float* F, const int* species, const doubl
                       int N, const double* e_src, double* e_dst, int n_copy, double* v_prev,
                       unsigned long long* probe_clear, hipStream_t st);
 void launch_nonfinite(const double* x, int n, int* flag, hipStream_t st);
+// zero `bytes` (a multiple of 4) at p with a kernel (no memset node in a captured graph)
+void launch_zero(void* p, size_t bytes, hipStream_t st);
 void launch_species_range(const int* species, int n, int n_species, int* flag, hipStream_t st);
 void launch_scale_positions(double* x, const int* owner, const double* lam, int N, hipStream_t st);
 void launch_restore_rows(double* x, const double* x_save, const int* owner, const int* keep, int N, hipStream_t st);
