@@ -211,6 +211,7 @@ struct Workspace {
   bool rp_valid = false;
   std::unique_ptr<DevBuf> Bp, dat;                     // product block: B (or dB), dA~
   std::unique_ptr<DevBuf> mixp;                        // partial products of a K-split channel mix
+  std::unique_ptr<DevBuf> msg;                         // per-edge sender-gradient messages of a full layer
   int last_parts = -1;  // last layer left before its gate: partial products in mixp (0: h~ in ht[T])
 };
 
@@ -1187,6 +1188,13 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       const int l_sc = std::min(L.l3max_used, L.l1max);  // orders the self-connection adjoint wrote
       ta.dh_acc = (l_sc + 1) * (l_sc + 1);
     }
+    // layers with every path: the edge adjoint, which holds dA_i, also writes
+    // each edge's sender-gradient message (16 x C values per edge), which a
+    // node pass adds up per sender, instead of a node adjoint gathering the
+    // receivers' dA rows (99 x C values per edge)
+    const bool use_msg = L.kind == 1 && t > 1;  // kind 1: every path
+    if (use_msg)
+      ta.msg = ensure(w.msg, &M->alloc, sizeof(float) * r_chunk_edges(M, Ecap, PCu) * L.nc_in * C).as<float>();
     // with more than one chunk R is recomputed chunk by chunk (the forward
     // pass kept only the last chunk)
     const std::vector<RChunk> chunks = r_chunks(M, G, PCu, st);
@@ -1234,7 +1242,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       }
       if (t > 1) {
         ProfScope ps(&M->prof, stage_id(kTpBwdNode, t), st);
-        launch_tp(2, ta, st);
+        launch_tp(use_msg ? 7 : 2, ta, st);
       }
     }
     if (t > 1) std::swap(dcur, dother);
@@ -1266,6 +1274,7 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
     }
     if (fused_last(M, L, false, bf16)) continue;  // no per-edge R
     b += E * L.p_used * C * 4;
+    if (L.kind == 1 && t > 1) b += E * L.nc_in * C * 4;  // sender-gradient messages of a full layer
     pc_max = std::max(pc_max, (size_t)L.p_used * C);
   }
   b += N * a_max * 4 + E * pc_max * 4 + E * (64 + 16) + 3 * N * NC * C * 4 + N * 8;

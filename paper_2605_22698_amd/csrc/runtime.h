@@ -245,12 +245,15 @@ struct TpArgs {
   // receiver chunk (first-order kernels 0-2): receivers i0 .. i0 + n_recv - 1
   // (n_recv 0: all N from i0 = 0), R and dR indexed from edge e_first
   int i0, n_recv, e_first;
-  const int* rev;  // reverse edge of each edge (-1: pruned), for the sender-side adjoint
+  const int* rev;  // reverse edge of each edge (-1: pruned), for the sender-side adjoint and pass 7
+  float* msg;      // per-edge sender-gradient messages [edges of the chunk, NIN, C] (passes 1 and 7), or NULL
 };
 // which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...),
 //        3 tangent forward (Ad), 4 second-order edge adjoint (Rb, Rc),
 //        5 second-order node adjoint (hb, hc += ...),
-//        6 adjoints of the harmonics and their tangent (Yb, Yc) for Hessian-vector products
+//        6 adjoints of the harmonics and their tangent (Yb, Yc) for Hessian-vector products,
+//        7 node adjoint from the messages that pass 1 wrote (msg set), for the
+//          chunk's receivers [i0, i0 + n_recv) as senders' partners
 void launch_tp(int which, const TpArgs& a, hipStream_t st);
 // scalar-output layer with R of every edge in memory (tps.hip): the
 // sender-side adjoint, dR and dY of pass 1 and, when a.dh is set, dh of pass 2

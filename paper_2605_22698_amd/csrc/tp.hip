@@ -99,13 +99,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIN
   }
 }
 
-template <int LMAX, int KIND, int CPT>
+// MSG: also write each edge's share of its sender's gradient,
+//   msg[e, l1 m1, k] = nu^-1 sum_p R[e,p,k] sum_{m2 m3} C^p Y_e[l2 m2] dA[i,p,k,m3],
+// at row e - e_first, for k_tp_msg_node to add up per sender.
+template <int LMAX, int KIND, int CPT, bool MSG>
 __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                      const float4* __restrict__ dvec, const float* __restrict__ R,
                                                      int r_stride, const float* __restrict__ h, int h_nc,
                                                      const float* __restrict__ dA, float* __restrict__ dR,
                                                      float* __restrict__ dY, int N, int C, float inv_nu, int i0,
-                                                     int e_first) {
+                                                     int e_first, float* __restrict__ msg) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
   __shared__ float red[4][16];
@@ -143,9 +146,11 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int k = threadIdx.x + c * tpr;
-      float hv[NIN];
+      float hv[NIN], mv[MSG ? NIN : 1];
 #pragma unroll
       for (int q = 0; q < NIN; ++q) hv[q] = hj[q * C + k];
+#pragma unroll
+      for (int q = 0; q < (MSG ? NIN : 1); ++q) mv[q] = 0.0f;
       static_for<NP>([&](auto pi) {
         constexpr int g = PS::T.id[pi];
         constexpr int l1 = kL1[g], l2 = kL2[g], l3 = kL3[g];
@@ -157,14 +162,22 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
         for (int m = 0; m < 2 * l3 + 1; ++m) tm[m] = 0.0f;
         static_for<nz>([&](auto z) {
           constexpr int q = z0 + z;
-          tm[kM3[q]] += hv[l1 * l1 + kM1[q]] * (kC[q] * Y[l2 * l2 + kM2[q]]);
-          dyp[l2 * l2 + kM2[q]] += kC[q] * (hv[l1 * l1 + kM1[q]] * (rp * dai[c][off + kM3[q]]));
+          const float cy = kC[q] * Y[l2 * l2 + kM2[q]];
+          const float rd = rp * dai[c][off + kM3[q]];
+          tm[kM3[q]] += hv[l1 * l1 + kM1[q]] * cy;
+          dyp[l2 * l2 + kM2[q]] += kC[q] * (hv[l1 * l1 + kM1[q]] * rd);
+          if constexpr (MSG) mv[l1 * l1 + kM1[q]] += rd * cy;
         });
         float s = 0.0f;
 #pragma unroll
         for (int m = 0; m < 2 * l3 + 1; ++m) s += dai[c][off + m] * tm[m];
         dRe[pi * C + k] = s;
       });
+      if constexpr (MSG) {
+        float* me = msg + (long)(e - e_first) * NIN * C + k;
+#pragma unroll
+        for (int q = 0; q < NIN; ++q) me[q * C] = mv[q];
+      }
     }
     // reduce dY over the channels of the workgroup
     if (tpr >= 64) {
@@ -251,6 +264,54 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
       *o = (dh_acc <= 0 || q < dh_acc) ? *o + acc[c][q] * inv_nu : acc[c][q] * inv_nu;
     }
     if (dh_acc > 0)
+      for (int q = NIN; q < dh_nc; ++q)
+        if (q >= dh_acc) dh[((long)j * dh_nc + q) * C + k] = 0.0f;
+  }
+}
+
+// Sender gradient from the edges' messages: dh[j] continues from its stored
+// value (from init, the first chunk, or the previous chunk) and adds msg of
+// j's outgoing edges e = rev(e2), e2 over the run of j's row whose senders
+// (the receivers of e) lie in this chunk's receivers [c0, c1), in row order.
+// Rows are sorted by sender, so the runs of successive chunks follow each
+// other along the row and every sender's sum is the same sequence of
+// additions whatever the chunking. init: components below dh_acc (all when
+// dh_acc <= 0) start from dh, the others from zero (components NIN..dh_nc-1
+// past dh_acc are zeroed).
+template <int NIN>
+__global__ void __launch_bounds__(256) k_tp_msg_node(const int* __restrict__ row_ptr, const int* __restrict__ src,
+                                                     const int* __restrict__ rev, const float* __restrict__ msg,
+                                                     float* __restrict__ dh, int dh_nc, int C, int c0, int c1,
+                                                     int e_first, int init, int dh_acc) {
+  const int j = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int a = row_ptr[j], b = row_ptr[j + 1];
+  // the run: first entry with src >= c0 .. first entry with src >= c1
+  auto lower = [&](int v) {
+    int lo = a, hi = b;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (src[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  const int r0 = lower(c0), r1 = lower(c1);
+  for (int k = threadIdx.x; k < C; k += blockDim.x) {
+    float acc[NIN];
+#pragma unroll
+    for (int q = 0; q < NIN; ++q) {
+      const bool keep = !init || dh_acc <= 0 || q < dh_acc;
+      acc[q] = keep ? dh[((long)j * dh_nc + q) * C + k] : 0.0f;
+    }
+    for (int e2 = r0; e2 < r1; ++e2) {
+      const int e = rev[e2];
+      if (e < 0) continue;
+      const float* me = msg + (long)(e - e_first) * NIN * C + k;
+#pragma unroll
+      for (int q = 0; q < NIN; ++q) acc[q] += me[q * C];
+    }
+#pragma unroll
+    for (int q = 0; q < NIN; ++q) dh[((long)j * dh_nc + q) * C + k] = acc[q];
+    if (init && dh_acc > 0)
       for (int q = NIN; q < dh_nc; ++q)
         if (q >= dh_acc) dh[((long)j * dh_nc + q) * C + k] = 0.0f;
   }
@@ -590,9 +651,20 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
   if (which == 0)
     k_tp_fwd<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.A, a.N,
                                                    a.C, a.inv_nu, a.i0, a.e_first);
+  else if (which == 1 && a.msg)
+    k_tp_bwd_edge<LMAX, KIND, CPT, true><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc,
+                                                              a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first,
+                                                              a.msg);
   else if (which == 1)
-    k_tp_bwd_edge<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.dA,
-                                                        a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first);
+    k_tp_bwd_edge<LMAX, KIND, CPT, false><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
+                                                               a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0,
+                                                               a.e_first, nullptr);
+  else if (which == 7) {
+    using PS = PathSet<LMAX, KIND>;
+    const int c1 = a.n_recv > 0 ? a.i0 + a.n_recv : a.N;
+    k_tp_msg_node<PS::NIN><<<a.N, 128, 0, st>>>(a.row_ptr, a.src, a.rev, a.msg, a.dh, a.dh_nc, a.C, a.i0, c1,
+                                                 a.e_first, a.i0 == 0 ? 1 : 0, a.dh_acc);
+  }
   else if (which == 2)
     k_tp_bwd_node<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
                                                         a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first, a.dh_acc);
