@@ -28,7 +28,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12        # bytes/s
 PEAK_FP32_MFMA = 157.3e12
-PEAK_FP32_VALU = 157.3e12
+PEAK_FP32_VALU = 157.3e12           # datasheet, counts packed FP32
+PEAK_FP32_VALU_NONPACKED = 78.65e12  # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+# kernels that run a stage in place of the general one: (stage, last layer) -> kernel
+KERNEL_OF_STAGE = {("tp_bwd_edge", True): "k_tps_bwd_sender", ("tp_bwd_node", False): "k_tp_msg_node"}
 KAPPA = 0.009648533
 
 
@@ -50,7 +53,9 @@ def cg_nnz():
 def layer_paths(cfg, t):
     L1, L2, L3, NZ = cg_nnz()
     l1max = 0 if t == 1 else cfg.lmax
-    l3max = 0 if t == cfg.layers else cfg.lmax
+    # the last layer evaluates its scalar outputs only, except with the product
+    # block (which needs every order of A~)
+    l3max = 0 if t == cfg.layers and getattr(cfg, "correlation", 1) != 2 else cfg.lmax
     return [(L1[g], L2[g], L3[g], NZ[g]) for g in range(len(L1))
             if L1[g] <= l1max and L2[g] <= cfg.lmax and L3[g] <= l3max]
 
@@ -91,12 +96,19 @@ def work_model(cfg, t, E, N):
     out["tp_fwd"] = (E * tp_flops, E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
     edge_adj = E * (tp_flops + 2 * C * sum(nz for *_, nz in ps) + 2 * C * nout)
     node_adj = E * 2 * C * sum(nz + 2 * l3 + 1 for (_, _, l3, nz) in ps)
-    if t == cfg.layers and C in (64, 128, 256):
+    if t == cfg.layers and C in (64, 128, 256) and getattr(cfg, "correlation", 1) != 2:
         # scalar-output layer: the sender-side adjoint (tps.hip) gives dR, dY
         # and dh in one pass: R read once, dR and dY written, edge vector, sender
         # and reverse index per edge; h, dA and dh (read and written) once per atom
         out["tp_bwd_edge"] = (edge_adj + (node_adj if t > 1 else 0),
                               E * (8 * PC + 64 + 16 + 4 + 4) + N * 4 * C * (nc_in + nout + (2 * nc_in if t > 1 else 0)))
+    elif t > 1:
+        # every path: the edge adjoint also writes each edge's sender-gradient
+        # message (nc_in x C values); the node pass reads the messages of each
+        # sender's edges (and the reverse index) and reads/writes dh once
+        out["tp_bwd_edge"] = (edge_adj + 2 * E * C * sum(nz for *_, nz in ps),
+                              E * (8 * PC + 16 + 4 + 64 + 4 * nc_in * C) + N * 4 * C * (nc_in + nout))
+        out["tp_bwd_node"] = (E * nc_in * C, E * (4 * nc_in * C + 8) + N * 4 * C * 2 * nc_in)
     else:
         out["tp_bwd_edge"] = (edge_adj, E * (8 * PC + 16 + 4 + 64) + N * 4 * C * (nc_in + nout))
         out["tp_bwd_node"] = (node_adj, E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
@@ -123,16 +135,18 @@ def measured_traffic(kernel, summary="md_step_3000_hbm_traffic.md"):
     return None
 
 
-def serving_run(e3, synth, torch, dev, n_requests, log):
+def serving_run(e3, synth, torch, dev, n_requests, n_steps, log):
     """Continuous-batching MD: Poisson arrivals, atom counts log-uniform in
     [50, 5000], 0.1 atoms/A^3, 4 species, l_max 3, 128 channels, FP32,
-    0.5 fs steps at 300 K, rebuild every 20 steps, 100 steps per request;
-    arrival rate set so the offered load is about 80% of a measured capacity."""
+    0.5 fs steps at 300 K, rebuild every 20 steps, n_steps steps per request;
+    arrival rate set so the offered load is about 80% of a measured capacity.
+    Run twice: with the device's memory as the admission budget, and with a
+    budget of about four mean-size requests or the largest one (requests then
+    queue)."""
     from paper_2605_22698_amd.serving import GpuExecutor, Request, Server
     cfg = synth.serving_model()
     m = e3.Model(cfg.to_json(), synth.flatten_weights(cfg, synth.model_weights(cfg, 4)), device=dev)
     reqs = synth.serving_requests(n_requests, rate_per_s=1.0)
-    n_steps = 100
     mean_atoms = float(np.mean([r[1].n_atoms for r in reqs]))
     # capacity probe: one packed batch of the first requests
     ex = GpuExecutor(m, synth.SPECIES_MASS[:4], cfg.cutoff)
@@ -145,17 +159,33 @@ def serving_run(e3, synth, torch, dev, n_requests, log):
     cap = sum(p["pos"].shape[0] for p in probe) / (ms / 1e3)          # atom-steps/s
     rate = 0.8 * cap / (mean_atoms * n_steps)                          # requests/s
     arr = np.cumsum(np.random.default_rng(synth.MASTER_SEED).exponential(1.0 / rate, size=len(reqs)))
-    srv = Server(GpuExecutor(m, synth.SPECIES_MASS[:4], cfg.cutoff), budget_bytes=int(200e9))
-    for k, ((_, b, v), t) in enumerate(zip(reqs, arr)):
-        srv.submit(Request(k, float(t), b.pos, v, b.species, b.cell[0], b.pbc[0], n_steps))
-    stats = srv.run(idle_wait=lambda dt: time.sleep(min(dt, 0.01)))
-    summ = stats.summary()
-    waits = [r.admitted_at - r.arrival for r in srv.done if r.admitted_at is not None]
-    log(f"serving: {summ}")
-    return {"requests": len(reqs), "steps_per_request": n_steps, "mean_atoms": mean_atoms,
-            "arrival_rate_per_s": rate, "p50_step_ms": summ["p50_ms"], "p99_step_ms": summ["p99_ms"],
-            "atom_steps_per_s": summ["atom_steps_per_s"], "atom_steps_per_busy_s": summ["atom_steps_per_busy_s"],
-            "repacks": summ["repacks"], "p50_queue_wait_s": float(np.percentile(waits, 50)) if waits else 0.0}
+    device_bytes = int(torch.cuda.get_device_properties(dev).total_memory)
+    # about four mean-size requests, and never less than the largest one (none is refused)
+    small = int(ex.footprint(int(max(4 * mean_atoms, 1.1 * max(r[1].n_atoms for r in reqs)))))
+    out = {"requests": len(reqs), "steps_per_request": n_steps, "mean_atoms": mean_atoms, "arrival_rate_per_s": rate,
+           "note": "step_ms: device time of each packed step; iter_ms: wall time of each engine iteration, "
+                   "repacks included"}
+    for name, budget in (("device_budget", device_bytes), ("small_budget", small)):
+        srv = Server(GpuExecutor(m, synth.SPECIES_MASS[:4], cfg.cutoff), budget_bytes=budget)
+        for k, ((_, b, v), t) in enumerate(zip(reqs, arr)):
+            srv.submit(Request(k, float(t), b.pos, v, b.species, b.cell[0], b.pbc[0], n_steps))
+        stats = srv.run(idle_wait=lambda dt: time.sleep(min(dt, 0.01)))
+        summ = stats.summary()
+        waits = [r.admitted_at - r.arrival for r in srv.done if r.admitted_at is not None]
+        lat = [r.finished_at - r.arrival for r in srv.done if r.finished_at is not None]
+        log(f"serving ({name}): {summ}")
+        out[name] = {"budget_bytes": budget, "rejected": summ["rejected"],
+                     "p50_step_ms": summ["p50_ms"], "p99_step_ms": summ["p99_ms"],
+                     "p50_iter_ms": summ["p50_iter_ms"], "p99_iter_ms": summ["p99_iter_ms"],
+                     "atom_steps_per_s": summ["atom_steps_per_s"],
+                     "atom_steps_per_busy_s": summ["atom_steps_per_busy_s"], "repacks": summ["repacks"],
+                     "p50_queue_wait_s": float(np.percentile(waits, 50)) if waits else 0.0,
+                     "p99_queue_wait_s": float(np.percentile(waits, 99)) if waits else 0.0,
+                     "p50_request_latency_s": float(np.percentile(lat, 50)) if lat else 0.0,
+                     "p99_request_latency_s": float(np.percentile(lat, 99)) if lat else 0.0,
+                     "wall_s": summ["wall_s"]}
+    m.close()
+    return out
 
 
 def product_work(cfg, t, N):
@@ -233,6 +263,67 @@ def product_run(e3, synth, torch, dev, n_atoms, steps, warmup, log):
     return out
 
 
+def grad_run(e3, synth, torch, dev, reps, log, cpu_baseline=True):
+    """Training step of the differentiation batch (64 periodic boxes of 20-200
+    atoms, 5 species, l_max 3, 64 channels, 2 layers, FP32): loss = energy MSE
+    + force MSE against seeded targets and its gradient with respect to every
+    weight through the autograd Function (forward: energy+forces; backward:
+    the library's second-order pass), timed per evaluation; the FP64 oracle's
+    loss and gradient timed on a bounded sample of the batch's structures."""
+    cfg, b, e_ref, f_ref = synth.differentiation_config()
+    wflat = synth.flatten_weights(cfg, synth.model_weights(cfg, 3))
+    m = e3.Model(cfg.to_json(), wflat, device=dev)
+    pos = torch.tensor(b.pos, dtype=torch.float64, device=dev)
+    g = m.build_graph(b.offsets, pos, torch.tensor(b.species, dtype=torch.int32, device=dev), b.cell, b.pbc,
+                      cfg.cutoff, 0.5)
+    w = torch.tensor(wflat, dtype=torch.float64, device=dev, requires_grad=True)
+    et = torch.tensor(e_ref, device=dev)
+    ft = torch.tensor(f_ref, device=dev)
+
+    def step():
+        w.grad = None
+        E, F = e3.energy_forces(w, pos, m, g)
+        loss = torch.mean((E - et) ** 2) + torch.sum((F.double() - ft) ** 2) / F.numel()
+        loss.backward()
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / reps
+    out = {"workload": f"loss + parameter gradients of {b.n_structures} periodic boxes of 20-200 atoms "
+                       f"({b.n_atoms} atoms), 5 species, l_max 3, 64 channels, 2 layers, FP32",
+           "ms_per_evaluation": 1e3 * dt, "structures_per_s": b.n_structures / dt, "atoms_per_s": b.n_atoms / dt,
+           "weights": int(w.numel()), "evaluations": reps}
+    ref_path = os.path.join(ROOT, "tests", "golden", "grad_batch_64.npz")
+    if os.path.exists(ref_path):
+        ref = np.load(ref_path)
+        loss = step()
+        gg = w.grad.cpu().numpy()
+        out["errors_vs_oracle"] = {"loss_rel": abs(loss.item() - float(ref["loss"])) / abs(float(ref["loss"])),
+                                   "grad_rel_l2": float(np.linalg.norm(gg - ref["grad"]) / np.linalg.norm(ref["grad"]))}
+    if cpu_baseline:
+        import torch as _t
+        from oracle import model as om
+        _t.set_num_threads(min(os.cpu_count() or 1, 64))
+        om_model = om.Model(cfg, synth.model_weights(cfg, 3))
+        k = 4
+        sub = synth.concat([b.structure(s) for s in range(k)])
+        tc = time.perf_counter()
+        om.loss_and_grads(om_model, sub, e_ref[:k], f_ref[:int(b.offsets[k])])
+        tcpu = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": sub.n_atoms / tcpu, "unit": "atoms/s (loss + gradient)",
+                               "cores": _t.get_num_threads(), "kind": "oracle",
+                               "sample": f"one FP64 loss + gradient of the batch's first {k} structures "
+                                         f"({sub.n_atoms} atoms), {tcpu:.1f} s"}
+    log(f"grad: {out['ms_per_evaluation']:.2f} ms per loss+gradient of {b.n_atoms} atoms")
+    m.close()
+    return out
+
+
 def hessian_run(e3, synth, torch, dev, n_atoms, reps, log):
     """Hessian-vector products: full Hessians of a batch of small open
     molecules (at most 31 atoms, the sizes of the paper's Hessian study) from
@@ -275,10 +366,41 @@ def hessian_run(e3, synth, torch, dev, n_atoms, reps, log):
     return out
 
 
-def scale_run(e3, synth, torch, dev, steps, warmup, log):
+def oracle_errors(E, F, Ei, ref):
+    """Errors of one GPU evaluation against a stored oracle result (energy
+    relative to |E| and to sum |E_i|, per-atom energies relative to max |E_i|,
+    forces max-abs and relative to max |F|)."""
+    dE = abs(float(E[0]) - float(ref["energy"][0]))
+    sum_ei = float(np.abs(ref["atom_energy"]).sum())
+    dF = float(np.abs(F - ref["forces"]).max())
+    return {"energy_rel_to_E": dE / abs(float(ref["energy"][0])), "energy_rel_to_sum_abs_Ei": dE / sum_ei,
+            "energy_eV_per_atom": dE / len(ref["atom_energy"]),
+            "atom_energy_rel_to_max": float(np.abs(Ei - ref["atom_energy"]).max() / np.abs(ref["atom_energy"]).max()),
+            "force_max_abs_eV_per_A": dF, "force_rel_to_max": dF / float(np.abs(ref["forces"]).max())}
+
+
+def gpu_errors(e3, torch, dev, cfg, w, b, ref, prec):
+    m = e3.Model(cfg.to_json(), w, precision=prec, device=dev)
+    pos = torch.tensor(b.pos, dtype=torch.float64, device=dev)
+    g = m.build_graph(b.offsets, pos, torch.tensor(b.species, dtype=torch.int32, device=dev), b.cell, b.pbc,
+                      cfg.cutoff, 1.0)
+    E, F, Ei = m.energy_forces(g, pos, atom_energy=True)
+    torch.cuda.synchronize()
+    out = oracle_errors(E.cpu().numpy(), F.double().cpu().numpy(), Ei.cpu().numpy(), ref)
+    g.close()
+    m.close()
+    return out
+
+
+def scale_run(e3, synth, torch, dev, steps, warmup, log, cpu_baseline=True):
     """The 100,000-atom, 3-layer box (r_c 6 A): MD atom-steps/s in FP32 and in
-    BF16 mode. Its middle layer keeps per-edge R, about 106 GB in FP32 for
-    the 9 million edges, so it runs in receiver chunks of at most 8 GiB."""
+    BF16 mode over `steps` timed steps (neighbour lists rebuilt every 20 steps
+    or earlier, so a rebuild falls inside the timed region once steps >= 20);
+    the dominant stage of an FP32 step against its roofline; the errors of
+    both precisions against the FP64 oracle on the independent 2,000-atom box;
+    the oracle timed on a bounded sample. Its middle layer keeps per-edge R,
+    about 106 GB in FP32 for the 9 million edges, so it runs in receiver
+    chunks of at most 8 GiB."""
     cfg, b = synth.scale_config()
     w = synth.flatten_weights(cfg, synth.model_weights(cfg, 5))
     vel = synth.maxwell_boltzmann(b, 300.0, synth.seed_for(5, 9))
@@ -293,19 +415,101 @@ def scale_run(e3, synth, torch, dev, steps, warmup, log):
         md = e3.MD(m, b.offsets, pos_d, vel_d, sp_d, synth.SPECIES_MASS[:4], b.cell, b.pbc, cfg.cutoff, 1.0, 20)
         md.step(warmup, 0.5, energy)
         torch.cuda.synchronize()
+        _, r0, _ = md.stats()
         t1 = time.perf_counter()
         md.step(steps, 0.5, energy)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
+        _, r1, v1 = md.stats()
         out[f"value_{name}"] = b.n_atoms * steps / dt
         out[f"ms_per_step_{name}"] = 1e3 * dt / steps
+        out[f"rebuilds_in_timed_{name}"] = r1 - r0
         out[f"energy_eV_{name}"] = energy.item()
+        if name == "fp32":
+            # stage split of two fully timed steps; the dominant stage's roofline
+            # (per step: a chunked layer launches its stages once per chunk)
+            m.profile(True)
+            md.step(2, 0.5, energy)
+            torch.cuda.synchronize()
+            m.profile(False)
+            xpos, _, _ = md.state()
+            g = m.build_graph(b.offsets, xpos, sp_d, b.cell, b.pbc, cfg.cutoff, 0.0)
+            m.energy_forces(g, xpos)
+            n_edges = g.last_edge_count()
+            g.close()
+            best, stage = None, {}
+            for t in range(1, cfg.layers + 1):
+                for st_name, (flops, nbytes) in work_model(cfg, t, n_edges, b.n_atoms).items():
+                    tot, n = m.stage_time(f"{st_name}@{t}")
+                    if n == 0:
+                        continue
+                    stage[f"{st_name}@{t}"] = tot / 2
+                    # a layer in receiver chunks recomputes R chunk by chunk in
+                    # the adjoint: its radial forward covers every edge twice per step
+                    chunks = m.stage_time(f"tp_fwd@{t}")[1] / 2
+                    passes = 2 if st_name == "radial_fwd" and chunks > 1 else 1
+                    if best is None or tot > best[0]:
+                        best = (tot, n, st_name, t, flops * passes, nbytes * passes)
+            tot, n, st_name, t, flops, nbytes = best
+            step_s = tot / 2 / 1e3
+            t_hbm, t_alu = nbytes / PEAK_HBM, flops / PEAK_FP32_VALU
+            mfma = st_name.startswith("radial") or st_name.startswith("first")
+            if mfma and flops / PEAK_FP32_MFMA > t_hbm:
+                roof = {"bound": "mfma", "achieved": flops / step_s / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                        "unit": "TFLOP/s"}
+            elif not mfma and t_alu > t_hbm:
+                roof = {"bound": "alu", "achieved": flops / step_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                        "unit": "TFLOP/s"}
+            else:
+                roof = {"bound": "hbm", "achieved": nbytes / step_s / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+            roof["frac"] = roof["achieved"] / roof["peak"]
+            if not mfma:
+                # the VALU peak above counts packed FP32, which this build does not emit
+                roof["frac_of_nonpacked_alu"] = flops / step_s / PEAK_FP32_VALU_NONPACKED
+            kern = KERNEL_OF_STAGE.get((st_name, t == cfg.layers), "k_" + st_name)
+            traffic = measured_traffic(kern, "scale_100k_hbm_traffic.md")
+            roof["traffic"] = None if traffic is None else traffic * n / 2
+            roof["kernel"] = f"{st_name} (layer {t}), {kern}"
+            roof["launches_per_step"] = n / 2
+            roof["ms_per_step"] = tot / 2
+            roof["algorithmic_per_step"] = {"flops": flops, "bytes": nbytes, "edges": n_edges}
+            out["roofline"] = roof
+            out["stage_ms_per_step"] = stage
         md.close()
         m.close()
         torch.cuda.empty_cache()
         log(f"100k box {name}: {out[f'value_{name}']:.3e} atom-steps/s ({out[f'ms_per_step_{name}']:.0f} ms/step)")
     out["bf16_over_fp32"] = out["value_bf16"] / out["value_fp32"]
+    # errors against the FP64 oracle on the independent 2,000-atom box
+    ref_path = os.path.join(ROOT, "tests", "golden", "scale_sub_2000.npz")
+    if os.path.exists(ref_path):
+        ref = np.load(ref_path)
+        cfg_s, bs = synth.scale_subbox()
+        ws = synth.flatten_weights(cfg_s, synth.model_weights(cfg_s, 5))
+        out["errors_vs_oracle_2000_atoms"] = {
+            "fp32": gpu_errors(e3, torch, dev, cfg_s, ws, bs, ref, e3.FP32),
+            "bf16": gpu_errors(e3, torch, dev, cfg_s, ws, bs, ref, e3.BF16_MIX)}
+    if cpu_baseline:
+        out["cpu_baseline"] = oracle_sample(synth, cfg, 500, 5, 5, 4096,
+                                            "box of the same recipe and model (r_c 6 A, 3 layers)")
     return out
+
+
+def oracle_sample(synth, cfg, n_atoms, seed_key, weight_key, chunk, what):
+    """One FP64 oracle energy+forces evaluation of an n-atom periodic box on the
+    host cores (neighbour list excluded), as atom-steps/s."""
+    import torch as _t
+    from oracle import model as om
+    _t.set_num_threads(min(os.cpu_count() or 1, 64))
+    bs = synth.jittered_lattice(n_atoms, synth.DENSITY, 0.3, cfg.n_species, synth.seed_for(seed_key, 13))
+    om_model = om.Model(cfg, synth.model_weights(cfg, weight_key))
+    edges = om._edges(bs, cfg.cutoff)
+    tc = time.perf_counter()
+    om.energy_forces(om_model, bs, edges=edges, edge_chunk=chunk)
+    tcpu = time.perf_counter() - tc
+    return {"value": bs.n_atoms / tcpu, "unit": "atom-steps/s", "cores": _t.get_num_threads(), "kind": "oracle",
+            "sample": f"one FP64 energy+forces evaluation of a {bs.n_atoms}-atom periodic {what} "
+                      f"(neighbour list excluded), {tcpu:.1f} s"}
 
 
 COULOMB_FLOPS_PER_PAIR = 20  # distance 8, rsqrt 1, potential 2, force factor 3, force 6
@@ -368,6 +572,7 @@ def coulomb_run(e3, synth, torch, dev, steps, warmup, log):
     flops = float(n_big) * (n_big - 1) * COULOMB_FLOPS_PER_PAIR
     out["roofline"] = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                        "unit": "TFLOP/s", "frac": flops / avg_s / PEAK_FP32_VALU,
+                       "frac_of_nonpacked_alu": flops / avg_s / PEAK_FP32_VALU_NONPACKED,
                        "traffic": measured_traffic("k_coulomb<16>", "coulomb_hbm_traffic.md"),
                        "kernel": f"k_coulomb, one open cluster of {n_big} atoms", "avg_launch_ms": tot / n,
                        "algorithmic_per_launch": {"flops": flops, "pairs": n_big * (n_big - 1)}}
@@ -385,7 +590,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-atoms", type=int, default=400)
     ap.add_argument("--no-extras", action="store_true", help="skip the BF16 and serving side measurements")
-    ap.add_argument("--serving-requests", type=int, default=16)
+    ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-steps", type=int, default=200, help="MD steps per serving request")
+    ap.add_argument("--scale-steps", type=int, default=20,
+                    help="timed steps of the 100,000-atom box (a rebuild falls inside from 20 on)")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only run the differentiation-batch measurement (loss + parameter gradients)")
     ap.add_argument("--coulomb-only", action="store_true",
                     help="only run the electrostatics measurement (for profiling its kernels)")
     ap.add_argument("--scale-only", action="store_true",
@@ -419,7 +629,12 @@ def main():
                           "bytes_written_per_launch": dst.numel() * 4, "launches": 10}), flush=True)
         return
     if args.scale_only:
-        print(json.dumps({"scale": scale_run(e3, synth, torch, dev, args.steps, args.warmup, log)}), flush=True)
+        print(json.dumps({"scale": scale_run(e3, synth, torch, dev, args.steps, args.warmup, log,
+                                             not args.no_cpu_baseline)}), flush=True)
+        return
+    if args.grad_only:
+        print(json.dumps({"grad": grad_run(e3, synth, torch, dev, args.steps, log, not args.no_cpu_baseline)}),
+              flush=True)
         return
     if args.hessian_only:
         print(json.dumps({"hessian": hessian_run(e3, synth, torch, dev, args.atoms, args.steps, log)}), flush=True)
@@ -530,8 +745,15 @@ def main():
         md16.step(k16, dt, energy)
         torch.cuda.synchronize()
         t16 = time.perf_counter() - t1
-        extras["bf16"] = {"value": b.n_atoms * k16 / t16, "ms_per_step": 1e3 * t16 / k16, "steps": k16}
+        extras["bf16"] = {"value": b.n_atoms * k16 / t16, "ms_per_step": 1e3 * t16 / k16, "steps": k16,
+                          "speedup_over_fp32": (b.n_atoms * k16 / t16) / value}
         md16.close()
+        ref_path = os.path.join(ROOT, "tests", "golden", "single_3000.npz")
+        if args.atoms == 3000 and os.path.exists(ref_path):
+            # both precisions against the FP64 oracle on the starting structure
+            ref = np.load(ref_path)
+            extras["bf16"]["errors_vs_oracle"] = gpu_errors(e3, torch, dev, cfg, w, b, ref, e3.BF16_MIX)
+            extras["fp32_errors_vs_oracle"] = gpu_errors(e3, torch, dev, cfg, w, b, ref, e3.FP32)
         # NPT: Langevin (300 K, 0.01/fs) with a Monte Carlo volume move every 25 steps at 1 bar
         mdp = e3.MD(m, b.offsets, pos_d, vel_d, sp_d, masses, b.cell, b.pbc, cfg.cutoff, skin, rebuild_every)
         mdp.set_langevin(300.0, 0.01, [2026])
@@ -548,11 +770,12 @@ def main():
                          "barostat": "Langevin 300 K, friction 0.01/fs, volume move every 25 steps at 1 bar",
                          "proposals": prop, "accepted": acc}
         mdp.close()
-        extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, log)
+        extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, args.serving_steps, log)
         extras["coulomb"] = coulomb_run(e3, synth, torch, dev, max(20, args.steps // 2), args.warmup, log)
         extras["product"] = product_run(e3, synth, torch, dev, args.atoms, max(20, args.steps // 4), args.warmup, log)
+        extras["grad"] = grad_run(e3, synth, torch, dev, 20, log, not args.no_cpu_baseline)
         extras["hessian"] = hessian_run(e3, synth, torch, dev, args.atoms, 20, log)
-        extras["scale"] = scale_run(e3, synth, torch, dev, 5, 2, log)
+        extras["scale"] = scale_run(e3, synth, torch, dev, args.scale_steps, 2, log, not args.no_cpu_baseline)
 
     # ---- oracle on the host cores (bounded sample) ----
     cpu = None
