@@ -213,6 +213,7 @@ struct Workspace {
   std::unique_ptr<DevBuf> mixp;                        // partial products of a K-split channel mix
   std::unique_ptr<DevBuf> msg;                         // per-edge sender-gradient messages of a full layer
   int last_parts = -1;  // last layer left before its gate: partial products in mixp (0: h~ in ht[T])
+  bool r_bf16 = false;  // the last forward pass stored R and dR in BF16 where r_bf16_layer says so
 };
 
 }  // namespace e3mi
@@ -762,6 +763,12 @@ int parse_stage(const char* stage, int* layer) {
   throw Error(E3MI_EINVAL, "unknown stage " + name);
 }
 
+// Per-edge R and dR of a layer in BF16 (BF16 mode, first-order pass), except
+// in layers with every path: their tensor-product kernels are bound by the
+// contraction over 99 outputs, not by R traffic, and the BF16 conversions push
+// their adjoint past two waves per SIMD (one wave halves its speed).
+bool r_bf16_layer(const Workspace& w, const LayerPlan& L) { return w.r_bf16 && L.kind != 1; }
+
 // Receiver chunks of a layer evaluated with per-edge R in memory: each chunk's
 // edges hold at most the model's r_chunk_bytes of R (and of dR in the
 // adjoint), so R never needs the whole edge set at once. One chunk
@@ -836,11 +843,13 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
   const int* species = G->species->as<int>();
 
   // ---- workspace (grows, never shrinks) ----
+  w.r_bf16 = bf16 && !keep_A;
   w.h.resize(T + 1);
   w.ht.resize(T + 1);
   w.R.resize(T + 1);
   ensure(w.h[0], a, sizeof(float) * (size_t)N * C);
-  long a_max = 0, pc_max = 0;
+  long a_max = 0;
+  size_t dr_bytes = 0;
   for (int t = 1; t <= T; ++t) {
     const LayerPlan& L = M->plans[t - 1];
     ensure(w.h[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
@@ -850,15 +859,16 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     if (fused_last(M, L, keep_A, bf16)) continue;
     // the second-order pass keeps R of every edge; otherwise at most one chunk
     const size_t r_edges = keep_A ? (size_t)(Ecap + 1) : r_chunk_edges(M, Ecap, L.p_used * C);
-    ensure(w.R[t], a, sizeof(float) * r_edges * L.p_used * C);
-    pc_max = std::max(pc_max, (long)L.p_used * C);
+    const size_t r_elem = r_bf16_layer(w, L) ? 2 : 4;
+    ensure(w.R[t], a, r_elem * r_edges * L.p_used * C);
+    dr_bytes = std::max(dr_bytes, r_elem * r_chunk_edges(M, Ecap, L.p_used * C) * L.p_used * C);
   }
   ensure(w.A, a, sizeof(float) * (size_t)N * a_max);
   if (keep_A) {
     w.Al.resize(T + 1);
     for (int t = 1; t <= T; ++t) ensure(w.Al[t], a, sizeof(float) * (size_t)N * M->plans[t - 1].a_per_atom);
   }
-  if (pc_max) ensure(w.dR, a, sizeof(float) * r_chunk_edges(M, Ecap, (int)pc_max) * pc_max);
+  if (dr_bytes) ensure(w.dR, a, dr_bytes);
   ensure(w.dY, a, sizeof(float) * 16 * (size_t)(Ecap + 1));
   ensure(w.g, a, sizeof(float4) * (size_t)(Ecap + 1));
   ensure(w.dh_a, a, sizeof(float) * (size_t)N * NC * C);
@@ -962,10 +972,12 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
       }
       continue;
     }
-    float* R = w.R[t]->as<float>();
+    float* R = w.R[t]->as<float>();  // BF16 values when r_bf16
     const int PCu = L.p_used * C;
     const std::vector<RChunk> chunks = keep_A ? std::vector<RChunk>{RChunk{0, N, 0, -1}} : r_chunks(M, G, PCu, st);
     TpArgs ta{};
+    const bool lr_bf16 = r_bf16_layer(w, L);
+    ta.r_bf16 = lr_bf16 ? 1 : 0;
     ta.lmax = c.lmax;
     ta.kind = L.kind;
     ta.cpt = cpt_for(L, C);
@@ -984,7 +996,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
       {
         ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
         launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                          W.rad3.as<float>(), L.p_full * C, PCu, R, rc, p_env, bf16, st, ch.e0, ch.e1);
+                          W.rad3.as<float>(), L.p_full * C, PCu, R, lr_bf16, rc, p_env, bf16, st, ch.e0, ch.e1);
       }
       set_chunk(ta, ch);
       ProfScope ps(&M->prof, stage_id(kTpFwd, t), st);
@@ -1164,8 +1176,11 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       std::swap(dcur, dother);
       continue;
     }
-    const float* R = w.R[t]->as<float>();
+    const float* R = w.R[t]->as<float>();  // BF16 values when r_bf16
+    const bool r_bf16 = r_bf16_layer(w, L);
     TpArgs ta{};
+    const bool lr_bf16 = r_bf16_layer(w, L);
+    ta.r_bf16 = lr_bf16 ? 1 : 0;
     ta.lmax = c.lmax;
     ta.kind = L.kind;
     ta.cpt = cpt_for(L, C);
@@ -1207,7 +1222,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
         if (chunks.size() > 1) {
           ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
           launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                            W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->as<float>(), rc, p_env, bf16, st, ch.e0,
+                            W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->p, r_bf16, rc, p_env, bf16, st, ch.e0,
                             ch.e1);
         }
         set_chunk(ta, ch);
@@ -1219,14 +1234,14 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
         }
         ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
         launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                          W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->as<float>(), w.dY->as<float>(), g,
+                          W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->p, r_bf16, w.dY->as<float>(), g,
                           t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1);
         continue;
       }
       if (chunks.size() > 1) {
         ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
         launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                          W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->as<float>(), rc, p_env, bf16, st, ch.e0,
+                          W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->p, r_bf16, rc, p_env, bf16, st, ch.e0,
                           ch.e1);
       }
       set_chunk(ta, ch);
@@ -1237,7 +1252,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       {
         ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
         launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                          W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->as<float>(), w.dY->as<float>(), g,
+                          W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->p, r_bf16, w.dY->as<float>(), g,
                           t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1);
       }
       if (t > 1) {

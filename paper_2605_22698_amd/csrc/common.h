@@ -12,6 +12,59 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
 
+// Per-edge radial weights R and their adjoint dR are stored as FP32, or as
+// BF16 (rounded to nearest even) in the BF16 mode; arithmetic is FP32.
+__device__ __forceinline__ float ldr(const float* p) { return *p; }
+__device__ __forceinline__ float ldr(const __bf16* p) { return (float)*p; }
+__device__ __forceinline__ void str(float* p, float v) { *p = v; }
+__device__ __forceinline__ void str(__bf16* p, float v) { *p = (__bf16)v; }
+// n consecutive stored values (n = 1, 2, 4 or 8) as floats, one vector load
+template <int n>
+__device__ __forceinline__ void ldr_n(const float* p, float* v) {
+  if constexpr (n == 1) {
+    v[0] = p[0];
+  } else if constexpr (n == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < n; q += 4) {
+      const float4 t = *reinterpret_cast<const float4*>(p + q);
+      v[q] = t.x;
+      v[q + 1] = t.y;
+      v[q + 2] = t.z;
+      v[q + 3] = t.w;
+    }
+  }
+}
+template <int n>
+__device__ __forceinline__ void ldr_n(const __bf16* p, float* v) {
+  typedef __bf16 bvec __attribute__((ext_vector_type(n)));
+  const bvec t = *reinterpret_cast<const bvec*>(p);
+#pragma unroll
+  for (int q = 0; q < n; ++q) v[q] = (float)t[q];
+}
+template <int n>
+__device__ __forceinline__ void str_n(float* p, const float* v) {
+  if constexpr (n == 1) {
+    p[0] = v[0];
+  } else if constexpr (n == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < n; q += 4) *reinterpret_cast<float4*>(p + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+  }
+}
+template <int n>
+__device__ __forceinline__ void str_n(__bf16* p, const float* v) {
+  typedef __bf16 bvec __attribute__((ext_vector_type(n)));
+  bvec t;
+#pragma unroll
+  for (int q = 0; q < n; ++q) t[q] = (__bf16)v[q];
+  *reinterpret_cast<bvec*>(p) = t;
+}
+
 // logistic function with the hardware reciprocal (v_rcp_f32, 1 ulp) in place
 // of a correctly rounded division: 1 + exp(-x) >= 1, so no denormal input
 __device__ __forceinline__ float sigmoidf(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }

@@ -109,11 +109,11 @@ __device__ __forceinline__ void block_64x2(const float (*X)[kLd], const float* _
   }
 }
 
-template <int NB, bool BF>
+template <int NB, bool BF, class RS>
 __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W3, int ld3, int PC,
-                                                    float* __restrict__ R, float rc, int p, int e_first, int e_end) {
+                                                    RS* __restrict__ R, float rc, int p, int e_first, int e_end) {
   // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); R is
   // indexed from e_first
   __shared__ float Bs[kTile][NB + 1];
@@ -148,17 +148,17 @@ __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ d
     for (int r = 0; r < 16; ++r) {
       const int row = acc_row(r, lane);
       const int ea = e0 + row, eb = e0 + 32 + row;
-      if (ea < E) R[(long)(ea - e_first) * PC + cc + (lane & 31)] = a0[r];
-      if (eb < E) R[(long)(eb - e_first) * PC + cc + (lane & 31)] = a1[r];
+      if (ea < E) str(R + (long)(ea - e_first) * PC + cc + (lane & 31), a0[r]);
+      if (eb < E) str(R + (long)(eb - e_first) * PC + cc + (lane & 31), a1[r]);
     }
   }
 }
 
-template <int NB, int LMAX, bool BF>
+template <int NB, int LMAX, bool BF, class RS>
 __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W2T, const float* __restrict__ W3T,
-                                                    int PC, const float* __restrict__ dR, const float* __restrict__ dY,
+                                                    int PC, const RS* __restrict__ dR, const float* __restrict__ dY,
                                                     float4* __restrict__ g, int accumulate, float rc, int p,
                                                     int e_first, int e_end) {
   __shared__ float Bs[kTile][NB + 1];
@@ -198,13 +198,15 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   f32x16 acc = {};
   const int srow = t >> 2, sc8 = (t & 3) * 8;
   const bool sval = e0 + srow < E;
-  const float* dRrow = dR + (long)(e0 + srow - e_first) * PC + sc8;
+  const RS* dRrow = dR + (long)(e0 + srow - e_first) * PC + sc8;
   float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
   float wb[16];
   auto load_slab = [&](int kc) {
     if (sval) {
-      p0 = *reinterpret_cast<const float4*>(dRrow + kc);
-      p1 = *reinterpret_cast<const float4*>(dRrow + kc + 4);
+      float v[8];
+      ldr_n<8>(dRrow + kc, v);
+      p0 = make_float4(v[0], v[1], v[2], v[3]);
+      p1 = make_float4(v[4], v[5], v[6], v[7]);
     }
     if constexpr (!BF) {
 #pragma unroll
@@ -483,45 +485,61 @@ inline int tiles(long n) { return (int)((n + kTile - 1) / kTile); }
 }  // namespace
 
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
-                       const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, bool bf16,
-                       hipStream_t st, int e_first, int e_end) {
+                       const float* W2, const float* W3, int ld3, int PC, void* R, bool r_bf16, float rc, int p,
+                       bool bf16, hipStream_t st, int e_first, int e_end) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (PC % 32) throw Error(E3MI_EUNSUPPORTED, "paths x channels must be a multiple of 32");
   const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
   if (grid == 0) return;
-  if (bf16)
-    k_radial_fwd<8, true><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p, e_first, e_end);
+  if (r_bf16 && bf16)
+    k_radial_fwd<8, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
+                                                        static_cast<__bf16*>(R), rc, p, e_first, e_end);
+  else if (r_bf16)
+    throw Error(E3MI_EINVAL, "BF16 radial weights need the BF16 mode");
+  else if (bf16)
+    k_radial_fwd<8, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
+                                                       static_cast<float*>(R), rc, p, e_first, e_end);
   else
-    k_radial_fwd<8, false><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC, R, rc, p, e_first, e_end);
+    k_radial_fwd<8, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
+                                                        static_cast<float*>(R), rc, p, e_first, e_end);
 }
 
 template <int LMAX>
-static void radial_bwd_l(bool bf16, long e_cap, const float4* dvec, const int* row_ptr_x, int N, const float* W1,
-                         const float* W2, const float* W2T, const float* W3T, int PC, const float* dR, const float* dY,
-                         float4* g, int accumulate, float rc, int p, hipStream_t st, int e_first, int e_end) {
+static void radial_bwd_l(bool bf16, bool r_bf16, long e_cap, const float4* dvec, const int* row_ptr_x, int N,
+                         const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
+                         const float* dY, float4* g, int accumulate, float rc, int p, hipStream_t st, int e_first,
+                         int e_end) {
   const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
   if (grid == 0) return;
-  if (bf16)
-    k_radial_bwd<8, LMAX, true><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g,
-                                                      accumulate, rc, p, e_first, e_end);
+  if (r_bf16 && bf16)
+    k_radial_bwd<8, LMAX, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
+                                                              static_cast<const __bf16*>(dR), dY, g, accumulate, rc,
+                                                              p, e_first, e_end);
+  else if (r_bf16)
+    throw Error(E3MI_EINVAL, "BF16 radial weights need the BF16 mode");
+  else if (bf16)
+    k_radial_bwd<8, LMAX, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
+                                                             static_cast<const float*>(dR), dY, g, accumulate, rc, p,
+                                                             e_first, e_end);
   else
-    k_radial_bwd<8, LMAX, false><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g,
-                                                               accumulate, rc, p, e_first, e_end);
+    k_radial_bwd<8, LMAX, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
+                                                              static_cast<const float*>(dR), dY, g, accumulate, rc,
+                                                              p, e_first, e_end);
 }
 
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
-                       const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
-                       const float* dY, float4* g, int accumulate, float rc, int p, bool bf16, hipStream_t st,
-                       int e_first, int e_end) {
+                       const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
+                       bool r_bf16, const float* dY, float4* g, int accumulate, float rc, int p, bool bf16,
+                       hipStream_t st, int e_first, int e_end) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (lmax == 3)
-    radial_bwd_l<3>(bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st, e_first,
-                    e_end);
+    radial_bwd_l<3>(bf16, r_bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st,
+                    e_first, e_end);
   else if (lmax == 2)
-    radial_bwd_l<2>(bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st, e_first,
-                    e_end);
+    radial_bwd_l<2>(bf16, r_bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st,
+                    e_first, e_end);
   else
     throw Error(E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
 }

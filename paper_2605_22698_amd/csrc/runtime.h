@@ -247,6 +247,7 @@ struct TpArgs {
   int i0, n_recv, e_first;
   const int* rev;  // reverse edge of each edge (-1: pruned), for the sender-side adjoint and pass 7
   float* msg;      // per-edge sender-gradient messages [edges of the chunk, NIN, C] (passes 1 and 7), or NULL
+  int r_bf16;      // R and dR stored as BF16 (passes 0 and 1, and the sender-side adjoint)
 };
 // which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...),
 //        3 tangent forward (Ad), 4 second-order edge adjoint (Rb, Rc),
@@ -336,13 +337,14 @@ void launch_coulomb_dq(const int64_t* off, const int* owner, int S, int N, const
                        const float* wq, int C, float* dh, hipStream_t st);
 
 // ---- radial MLP (radial.hip) ---------------------------------------------------------
+// R (dR) is FP32, or BF16 when r_bf16 is set
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
-                       const float* W2, const float* W3, int ld3, int PC, float* R, float rc, int p, bool bf16,
-                       hipStream_t st, int e_first = 0, int e_end = -1);
+                       const float* W2, const float* W3, int ld3, int PC, void* R, bool r_bf16, float rc, int p,
+                       bool bf16, hipStream_t st, int e_first = 0, int e_end = -1);
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
-                       const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const float* dR,
-                       const float* dY, float4* g, int accumulate, float rc, int p, bool bf16, hipStream_t st,
-                       int e_first = 0, int e_end = -1);
+                       const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
+                       bool r_bf16, const float* dY, float4* g, int accumulate, float rc, int p, bool bf16,
+                       hipStream_t st, int e_first = 0, int e_end = -1);
 
 // ---- second-order passes (radial.hip, grad.hip) -------------------------------------
 void launch_radial_dual_fwd(int n_basis, const float4* dvec, const float4* dd, const int* row_ptr_x, int N, long e_cap,

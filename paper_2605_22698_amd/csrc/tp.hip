@@ -35,9 +35,9 @@ __device__ __forceinline__ float group_sum(float v) {
 // of 72 (the hardware still holds five waves) and it runs faster (0.134 ms
 // against 0.141 on the 3,000-atom step). Holding residency at three or two
 // waves for real, by reserving LDS, is slower (0.167, 0.196 ms).
-template <int LMAX, int KIND, int CPT>
+template <int LMAX, int KIND, int CPT, class RS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIND == kLast ? 3 : 10))) k_tp_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
-                                                const float4* __restrict__ dvec, const float* __restrict__ R,
+                                                const float4* __restrict__ dvec, const RS* __restrict__ R,
                                                 int r_stride, const float* __restrict__ h, int h_nc,
                                                 float* __restrict__ A, int N, int C, float inv_nu, int i0,
                                                 int e_first) {
@@ -57,20 +57,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIN
     const float ir = 1.0f / d.w;
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const float* Re = R + (long)(e - e_first) * r_stride;
+    const RS* Re = R + (long)(e - e_first) * r_stride;
     const float* hj = h + (long)j * h_nc * C;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int k = threadIdx.x + c * tpr;
-      float hv[NIN];
+      float hv[NIN], rv[NP];
 #pragma unroll
       for (int q = 0; q < NIN; ++q) hv[q] = hj[q * C + k];
+      // every path's weight of the edge in one batch of loads
+#pragma unroll
+      for (int q = 0; q < NP; ++q) rv[q] = ldr(Re + q * C + k);
       static_for<NP>([&](auto pi) {
         constexpr int g = PS::T.id[pi];
         constexpr int l1 = kL1[g], l2 = kL2[g], l3 = kL3[g];
         constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
         constexpr int off = PS::T.off[pi];
-        const float rp = Re[pi * C + k];
+        const float rp = rv[pi];
         float tm[2 * l3 + 1];
 #pragma unroll
         for (int m = 0; m < 2 * l3 + 1; ++m) tm[m] = 0.0f;
@@ -102,11 +105,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIN
 // MSG: also write each edge's share of its sender's gradient,
 //   msg[e, l1 m1, k] = nu^-1 sum_p R[e,p,k] sum_{m2 m3} C^p Y_e[l2 m2] dA[i,p,k,m3],
 // at row e - e_first, for k_tp_msg_node to add up per sender.
-template <int LMAX, int KIND, int CPT, bool MSG>
-__global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row_ptr, const int* __restrict__ src,
-                                                     const float4* __restrict__ dvec, const float* __restrict__ R,
+// Layers with every path hold 99 adjoint values per channel: the compiler is
+// asked for two waves per SIMD (at most 256 registers); one wave per SIMD
+// halves the kernel's speed.
+template <int LMAX, int KIND, int CPT, bool MSG, class RS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == kFull ? 2 : 1, 10))) k_tp_bwd_edge(const int* __restrict__ row_ptr, const int* __restrict__ src,
+                                                     const float4* __restrict__ dvec, const RS* __restrict__ R,
                                                      int r_stride, const float* __restrict__ h, int h_nc,
-                                                     const float* __restrict__ dA, float* __restrict__ dR,
+                                                     const float* __restrict__ dA, RS* __restrict__ dR,
                                                      float* __restrict__ dY, int N, int C, float inv_nu, int i0,
                                                      int e_first, float* __restrict__ msg) {
   using PS = PathSet<LMAX, KIND>;
@@ -137,8 +143,8 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
     const float ir = 1.0f / d.w;
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const float* Re = R + (long)(e - e_first) * r_stride;
-    float* dRe = dR + (long)(e - e_first) * r_stride;
+    const RS* Re = R + (long)(e - e_first) * r_stride;
+    RS* dRe = dR + (long)(e - e_first) * r_stride;
     const float* hj = h + (long)j * h_nc * C;
     float dyp[NY];
 #pragma unroll
@@ -146,9 +152,11 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int k = threadIdx.x + c * tpr;
-      float hv[NIN], mv[MSG ? NIN : 1];
+      float hv[NIN], mv[MSG ? NIN : 1], rv[NP];
 #pragma unroll
       for (int q = 0; q < NIN; ++q) hv[q] = hj[q * C + k];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) rv[q] = ldr(Re + q * C + k);
 #pragma unroll
       for (int q = 0; q < (MSG ? NIN : 1); ++q) mv[q] = 0.0f;
       static_for<NP>([&](auto pi) {
@@ -156,7 +164,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
         constexpr int l1 = kL1[g], l2 = kL2[g], l3 = kL3[g];
         constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
         constexpr int off = PS::T.off[pi];
-        const float rp = Re[pi * C + k];
+        const float rp = rv[pi];
         float tm[2 * l3 + 1];
 #pragma unroll
         for (int m = 0; m < 2 * l3 + 1; ++m) tm[m] = 0.0f;
@@ -171,7 +179,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
         float s = 0.0f;
 #pragma unroll
         for (int m = 0; m < 2 * l3 + 1; ++m) s += dai[c][off + m] * tm[m];
-        dRe[pi * C + k] = s;
+        str(dRe + pi * C + k, s);
       });
       if constexpr (MSG) {
         float* me = msg + (long)(e - e_first) * NIN * C + k;
@@ -208,9 +216,9 @@ __global__ void __launch_bounds__(256) k_tp_bwd_edge(const int* __restrict__ row
   }
 }
 
-template <int LMAX, int KIND, int CPT>
+template <int LMAX, int KIND, int CPT, class RS>
 __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row_ptr, const int* __restrict__ src,
-                                                     const float4* __restrict__ dvec, const float* __restrict__ R,
+                                                     const float4* __restrict__ dvec, const RS* __restrict__ R,
                                                      int r_stride, const float* __restrict__ dA,
                                                      float* __restrict__ dh, int dh_nc, int N, int C, float inv_nu,
                                                      int i0, int e_first, int dh_acc) {
@@ -230,7 +238,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
     const float ir = -1.0f / d.w;  // direction of the reverse edge
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const float* Re = R + (long)(e - e_first) * r_stride;
+    const RS* Re = R + (long)(e - e_first) * r_stride;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int k = threadIdx.x + c * tpr;
@@ -240,7 +248,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
         constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
         constexpr int rank = PS::T.rank[pi];
         constexpr int P3 = PS::T.np_l3[l3];
-        const float rp = Re[pi * C + k];
+        const float rp = ldr(Re + pi * C + k);
         const float* base = dA + a_group_base<PS>(l3, N, C);
         float dav[2 * l3 + 1];
 #pragma unroll
@@ -648,26 +656,46 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
   const int nr = a.n_recv > 0 ? a.n_recv : a.N;  // receivers of this launch
   if (which <= 2 && a.n_recv == 0 && (a.i0 != 0 || a.e_first != 0))
     throw Error(E3MI_EINVAL, "tensor product: receiver offset without a receiver count");
-  if (which == 0)
-    k_tp_fwd<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.A, a.N,
-                                                   a.C, a.inv_nu, a.i0, a.e_first);
+  if (a.r_bf16 && which > 2 && which != 7)
+    throw Error(E3MI_EINVAL, "tensor product: BF16 radial weights only in the first-order passes");
+  const __bf16* Rb = reinterpret_cast<const __bf16*>(a.R);
+  __bf16* dRb = reinterpret_cast<__bf16*>(a.dR);
+  if (which == 0 && a.r_bf16)
+    k_tp_fwd<LMAX, KIND, CPT, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h, a.h_nc, a.A,
+                                                           a.N, a.C, a.inv_nu, a.i0, a.e_first);
+  else if (which == 0)
+    k_tp_fwd<LMAX, KIND, CPT, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.A,
+                                                          a.N, a.C, a.inv_nu, a.i0, a.e_first);
+  else if (which == 1 && a.r_bf16 && a.msg)
+    k_tp_bwd_edge<LMAX, KIND, CPT, true, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h,
+                                                                      a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu,
+                                                                      a.i0, a.e_first, a.msg);
+  else if (which == 1 && a.r_bf16)
+    k_tp_bwd_edge<LMAX, KIND, CPT, false, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h,
+                                                                       a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu,
+                                                                       a.i0, a.e_first, nullptr);
   else if (which == 1 && a.msg)
-    k_tp_bwd_edge<LMAX, KIND, CPT, true><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc,
-                                                              a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first,
-                                                              a.msg);
+    k_tp_bwd_edge<LMAX, KIND, CPT, true, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
+                                                                     a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu,
+                                                                     a.i0, a.e_first, a.msg);
   else if (which == 1)
-    k_tp_bwd_edge<LMAX, KIND, CPT, false><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
-                                                               a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0,
-                                                               a.e_first, nullptr);
+    k_tp_bwd_edge<LMAX, KIND, CPT, false, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
+                                                                      a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu,
+                                                                      a.i0, a.e_first, nullptr);
   else if (which == 7) {
     using PS = PathSet<LMAX, KIND>;
     const int c1 = a.n_recv > 0 ? a.i0 + a.n_recv : a.N;
     k_tp_msg_node<PS::NIN><<<a.N, 128, 0, st>>>(a.row_ptr, a.src, a.rev, a.msg, a.dh, a.dh_nc, a.C, a.i0, c1,
                                                  a.e_first, a.i0 == 0 ? 1 : 0, a.dh_acc);
   }
+  else if (which == 2 && a.r_bf16)
+    k_tp_bwd_node<LMAX, KIND, CPT, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.dA, a.dh,
+                                                                a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first,
+                                                                a.dh_acc);
   else if (which == 2)
-    k_tp_bwd_node<LMAX, KIND, CPT><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
-                                                        a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first, a.dh_acc);
+    k_tp_bwd_node<LMAX, KIND, CPT, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
+                                                               a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first,
+                                                               a.dh_acc);
   else if (which == 3)
     k_tp_dual_fwd<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.R, a.Rd, a.r_stride, a.h,
                                                          a.hd, a.h_nc, a.Ad, a.N, a.C, a.inv_nu);

@@ -32,40 +32,12 @@
 namespace e3mi {
 namespace {
 
-template <int CH>
-__device__ __forceinline__ void ld_ch(const float* __restrict__ p, float* v) {
-  if constexpr (CH == 1) {
-    v[0] = p[0];
-  } else if constexpr (CH == 2) {
-    const float2 t = *reinterpret_cast<const float2*>(p);
-    v[0] = t.x;
-    v[1] = t.y;
-  } else {
-    const float4 t = *reinterpret_cast<const float4*>(p);
-    v[0] = t.x;
-    v[1] = t.y;
-    v[2] = t.z;
-    v[3] = t.w;
-  }
-}
-
-template <int CH>
-__device__ __forceinline__ void st_ch(float* __restrict__ p, const float* v) {
-  if constexpr (CH == 1) {
-    p[0] = v[0];
-  } else if constexpr (CH == 2) {
-    *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
-  } else {
-    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-  }
-}
-
-template <int LMAX, int KIND, int CH, bool DH>
+template <int LMAX, int KIND, int CH, bool DH, class RS>
 __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                        const int* __restrict__ rev, const float4* __restrict__ dvec,
-                                                       const float* __restrict__ R, int r_stride,
+                                                       const RS* __restrict__ R, int r_stride,
                                                        const float* __restrict__ h, int h_nc,
-                                                       const float* __restrict__ dA, float* __restrict__ dR,
+                                                       const float* __restrict__ dA, RS* __restrict__ dR,
                                                        float* __restrict__ dY, float* __restrict__ dh, int dh_nc,
                                                        int dh_acc, int C, float inv_nu, int i0, int e_first) {
   using PS = PathSet<LMAX, KIND>;
@@ -79,7 +51,7 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
   {
     const float* hj = h + (long)j * h_nc * C + k0;
 #pragma unroll
-    for (int q = 0; q < NIN; ++q) ld_ch<CH>(hj + q * C, hv[q]);
+    for (int q = 0; q < NIN; ++q) ldr_n<CH>(hj + q * C, hv[q]);
   }
   float acc[NA][CH];
 #pragma unroll
@@ -88,10 +60,10 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
     for (int c = 0; c < CH; ++c) acc[q][c] = 0.0f;
   const int e1 = row_ptr[j + 1];
   for (int e2 = row_ptr[j]; e2 < e1; ++e2) {
-    float* dRe = dR + (long)(e2 - e_first) * r_stride + k0;
+    RS* dRe = dR + (long)(e2 - e_first) * r_stride + k0;
     if (rev[e2] < 0) {  // the edge i <- j is not in i's list
       const float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      static_for<NP>([&](auto pi) { st_ch<CH>(dRe + pi * C, z); });
+      static_for<NP>([&](auto pi) { str_n<CH>(dRe + pi * C, z); });
       if (lane < 16) dY[(long)e2 * 16 + lane] = 0.0f;
       continue;
     }
@@ -100,7 +72,7 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
     const float ir = -1.0f / d.w;  // d_e = -d_e2
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const float* Re = R + (long)(e2 - e_first) * r_stride + k0;
+    const RS* Re = R + (long)(e2 - e_first) * r_stride + k0;
     const float* dAi = dA + (long)i * NP * C + k0;
     float dyp[NY];
 #pragma unroll
@@ -111,8 +83,8 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
       constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
       constexpr int rank = PS::T.rank[pi];
       float rp[CH], da[CH], s[CH];
-      ld_ch<CH>(Re + pi * C, rp);
-      ld_ch<CH>(dAi + rank * C, da);
+      ldr_n<CH>(Re + pi * C, rp);
+      ldr_n<CH>(dAi + rank * C, da);
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
         const float dai = da[c] * inv_nu;
@@ -127,7 +99,7 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
         });
         s[c] = dai * t;
       }
-      st_ch<CH>(dRe + pi * C, s);
+      str_n<CH>(dRe + pi * C, s);
     });
     const float tot = wave_sum_scatter16<NY>(dyp);
     const int q = lane >> 2;
@@ -143,30 +115,38 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
       float* o = dh + ((long)j * dh_nc + q) * C + k0;
       float v[CH];
       const bool add = dh_acc <= 0 || q < dh_acc;
-      if (add) ld_ch<CH>(o, v);
+      if (add) ldr_n<CH>(o, v);
 #pragma unroll
       for (int c = 0; c < CH; ++c) v[c] = (add ? v[c] : 0.0f) + acc[q][c];
-      st_ch<CH>(o, v);
+      str_n<CH>(o, v);
     }
     if (dh_acc > 0)
       for (int q = NIN; q < dh_nc; ++q)
         if (q >= dh_acc) {
           const float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-          st_ch<CH>(dh + ((long)j * dh_nc + q) * C + k0, z);
+          str_n<CH>(dh + ((long)j * dh_nc + q) * C + k0, z);
         }
   }
 }
 
+template <int LMAX, int KIND, int CH, class RS>
+void sender_launch_rs(const TpArgs& a, int nr, hipStream_t st) {
+  const RS* R = reinterpret_cast<const RS*>(a.R);
+  RS* dR = reinterpret_cast<RS*>(a.dR);
+  if (a.dh)
+    k_tps_bwd_sender<LMAX, KIND, CH, true, RS><<<nr, 64, 0, st>>>(a.row_ptr, a.src, a.rev, a.dvec, R, a.r_stride, a.h,
+                                                                  a.h_nc, a.dA, dR, a.dY, a.dh, a.dh_nc, a.dh_acc, a.C,
+                                                                  a.inv_nu, a.i0, a.e_first);
+  else
+    k_tps_bwd_sender<LMAX, KIND, CH, false, RS><<<nr, 64, 0, st>>>(a.row_ptr, a.src, a.rev, a.dvec, R, a.r_stride,
+                                                                   a.h, a.h_nc, a.dA, dR, a.dY, nullptr, 0, 0, a.C,
+                                                                   a.inv_nu, a.i0, a.e_first);
+}
+
 template <int LMAX, int KIND, int CH>
 void sender_launch(const TpArgs& a, int nr, hipStream_t st) {
-  if (a.dh)
-    k_tps_bwd_sender<LMAX, KIND, CH, true><<<nr, 64, 0, st>>>(a.row_ptr, a.src, a.rev, a.dvec, a.R, a.r_stride, a.h,
-                                                              a.h_nc, a.dA, a.dR, a.dY, a.dh, a.dh_nc, a.dh_acc, a.C,
-                                                              a.inv_nu, a.i0, a.e_first);
-  else
-    k_tps_bwd_sender<LMAX, KIND, CH, false><<<nr, 64, 0, st>>>(a.row_ptr, a.src, a.rev, a.dvec, a.R, a.r_stride, a.h,
-                                                               a.h_nc, a.dA, a.dR, a.dY, nullptr, 0, 0, a.C,
-                                                               a.inv_nu, a.i0, a.e_first);
+  if (a.r_bf16) return sender_launch_rs<LMAX, KIND, CH, __bf16>(a, nr, st);
+  sender_launch_rs<LMAX, KIND, CH, float>(a, nr, st);
 }
 
 template <int LMAX, int KIND>
