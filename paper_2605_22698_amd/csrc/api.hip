@@ -212,6 +212,8 @@ struct Workspace {
   std::unique_ptr<DevBuf> Bp, dat;                     // product block: B (or dB), dA~
   std::unique_ptr<DevBuf> mixp;                        // partial products of a K-split channel mix
   std::unique_ptr<DevBuf> msg;                         // per-edge sender-gradient messages of a full layer
+  std::unique_ptr<DevBuf> touched;                     // per atom: tag of the last chunk that sent it a message
+  unsigned msg_tag = 0;
   int last_parts = -1;  // last layer left before its gate: partial products in mixp (0: h~ in ht[T])
   bool r_bf16 = false;  // the last forward pass stored R and dR in BF16 where r_bf16_layer says so
 };
@@ -1208,8 +1210,10 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     // node pass adds up per sender, instead of a node adjoint gathering the
     // receivers' dA rows (99 x C values per edge)
     const bool use_msg = L.kind == 1 && t > 1;  // kind 1: every path
-    if (use_msg)
+    if (use_msg) {
       ta.msg = ensure(w.msg, &M->alloc, sizeof(float) * r_chunk_edges(M, Ecap, PCu) * L.nc_in * C).as<float>();
+      ta.touched = ensure(w.touched, &M->alloc, sizeof(int) * ((size_t)N + 1)).as<int>();
+    }
     // with more than one chunk R is recomputed chunk by chunk (the forward
     // pass kept only the last chunk)
     const std::vector<RChunk> chunks = r_chunks(M, G, PCu, st);
@@ -1245,6 +1249,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
                           ch.e1);
       }
       set_chunk(ta, ch);
+      ta.tag = (int)(++w.msg_tag & 0x7fffffffu);
       {
         ProfScope ps(&M->prof, stage_id(kTpBwdEdge, t), st);
         launch_tp(1, ta, st);

@@ -248,6 +248,8 @@ struct TpArgs {
   const int* rev;  // reverse edge of each edge (-1: pruned), for the sender-side adjoint and pass 7
   float* msg;      // per-edge sender-gradient messages [edges of the chunk, NIN, C] (passes 1 and 7), or NULL
   int r_bf16;      // R and dR stored as BF16 (passes 0 and 1, and the sender-side adjoint)
+  int* touched;    // with msg: per atom, set to `tag` for every sender of the chunk's edges (pass 1), read by pass 7
+  int tag;
 };
 // which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...),
 //        3 tangent forward (Ad), 4 second-order edge adjoint (Rb, Rc),

@@ -114,7 +114,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND =
                                                      int r_stride, const float* __restrict__ h, int h_nc,
                                                      const float* __restrict__ dA, RS* __restrict__ dR,
                                                      float* __restrict__ dY, int N, int C, float inv_nu, int i0,
-                                                     int e_first, float* __restrict__ msg) {
+                                                     int e_first, float* __restrict__ msg, int* __restrict__ touched,
+                                                     int tag) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
   __shared__ float red[4][16];
@@ -139,6 +140,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND =
   const int e1 = row_ptr[i + 1];
   for (int e = row_ptr[i]; e < e1; ++e) {
     const int j = src[e];
+    if (MSG && threadIdx.x == 0) touched[j] = tag;  // j receives a message from this chunk
     const float4 d = dvec[e];
     const float ir = 1.0f / d.w;
     float Y[NY];
@@ -290,8 +292,12 @@ template <int NIN>
 __global__ void __launch_bounds__(256) k_tp_msg_node(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                      const int* __restrict__ rev, const float* __restrict__ msg,
                                                      float* __restrict__ dh, int dh_nc, int C, int c0, int c1,
-                                                     int e_first, int init, int dh_acc) {
+                                                     int e_first, int init, int dh_acc,
+                                                     const int* __restrict__ touched, int tag) {
   const int j = xcd_contiguous(blockIdx.x, gridDim.x);
+  // after the first chunk, only senders this chunk's edge adjoint sent to
+  // (touched carries the chunk's tag; another value can only add an empty run)
+  if (!init && touched[j] != tag) return;
   const int a = row_ptr[j], b = row_ptr[j + 1];
   // the run: first entry with src >= c0 .. first entry with src >= c1
   auto lower = [&](int v) {
@@ -669,24 +675,24 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
   else if (which == 1 && a.r_bf16 && a.msg)
     k_tp_bwd_edge<LMAX, KIND, CPT, true, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h,
                                                                       a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu,
-                                                                      a.i0, a.e_first, a.msg);
+                                                                      a.i0, a.e_first, a.msg, a.touched, a.tag);
   else if (which == 1 && a.r_bf16)
     k_tp_bwd_edge<LMAX, KIND, CPT, false, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h,
                                                                        a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu,
-                                                                       a.i0, a.e_first, nullptr);
+                                                                       a.i0, a.e_first, nullptr, nullptr, 0);
   else if (which == 1 && a.msg)
     k_tp_bwd_edge<LMAX, KIND, CPT, true, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
                                                                      a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu,
-                                                                     a.i0, a.e_first, a.msg);
+                                                                     a.i0, a.e_first, a.msg, a.touched, a.tag);
   else if (which == 1)
     k_tp_bwd_edge<LMAX, KIND, CPT, false, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
                                                                       a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu,
-                                                                      a.i0, a.e_first, nullptr);
+                                                                      a.i0, a.e_first, nullptr, nullptr, 0);
   else if (which == 7) {
     using PS = PathSet<LMAX, KIND>;
     const int c1 = a.n_recv > 0 ? a.i0 + a.n_recv : a.N;
     k_tp_msg_node<PS::NIN><<<a.N, 128, 0, st>>>(a.row_ptr, a.src, a.rev, a.msg, a.dh, a.dh_nc, a.C, a.i0, c1,
-                                                 a.e_first, a.i0 == 0 ? 1 : 0, a.dh_acc);
+                                                 a.e_first, a.i0 == 0 ? 1 : 0, a.dh_acc, a.touched, a.tag);
   }
   else if (which == 2 && a.r_bf16)
     k_tp_bwd_node<LMAX, KIND, CPT, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.dA, a.dh,
