@@ -115,18 +115,37 @@ def work_model(cfg, t, E, N):
     return out
 
 
-def measured_traffic(kernel, summary="md_step_3000_hbm_traffic.md"):
+def fp32_row_pattern(cfg, kern, t):
+    """The FP32-mode instantiation of a per-edge kernel of layer t, as the
+    100,000-atom traffic summary lists it: the radial kernels serve several
+    layers (rows split by layer), the tensor-product kernels are per layer
+    kind by their template arguments (1: every path, 2: scalar outputs)."""
+    kind = 2 if t == cfg.layers else 1
+    if kern.startswith("k_radial"):
+        return re.escape(kern) + r"<8, (\d+, )?false, float> \[layer %d\]" % t
+    if kern in ("k_tp_fwd", "k_tp_bwd_edge", "k_tps_bwd_sender"):
+        return re.escape(kern) + r"<%d, %d, \d+(, (true|false))?, float>" % (cfg.lmax, kind)
+    return re.escape(kern) + r"(<.*>)?"
+
+
+def measured_traffic(kernel, summary="md_step_3000_hbm_traffic.md", pattern=None):
     """HBM bytes per launch of a kernel (FETCH_SIZE + WRITE_SIZE,
     copy-calibrated) from a committed counter summary, or None when the
     kernel's source file has changed since the counters were taken. kernel:
-    the name as listed, with its template arguments or without (any)."""
+    the name as listed, with its template arguments or without (the first
+    listed); pattern (a regular expression), when given, must match the
+    listed name whole instead."""
     import hashlib
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     for line in open(path):
         m = re.match(r"\|\s*`([^`]+)`\s*\|\s*\d+\s*\|\s*([\d.]+)\s*\|\s*([\d.]+)\s*\|\s*(\S+)\s*\|\s*(\S+)", line)
-        if not m or kernel not in (m.group(1), m.group(1).split("<")[0]):
+        if not m:
+            continue
+        name = m.group(1)
+        hit = re.fullmatch(pattern, name) if pattern else kernel in (name, name.split("<")[0])
+        if not hit:
             continue
         src = os.path.join(ROOT, "paper_2605_22698_amd", "csrc", m.group(4))
         if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != m.group(5):
@@ -467,7 +486,7 @@ def scale_run(e3, synth, torch, dev, steps, warmup, log, cpu_baseline=True):
                 # the VALU peak above counts packed FP32, which this build does not emit
                 roof["frac_of_nonpacked_alu"] = flops / step_s / PEAK_FP32_VALU_NONPACKED
             kern = KERNEL_OF_STAGE.get((st_name, t == cfg.layers), "k_" + st_name)
-            traffic = measured_traffic(kern, "scale_100k_hbm_traffic.md")
+            traffic = measured_traffic(kern, "scale_100k_hbm_traffic.md", fp32_row_pattern(cfg, kern, t))
             roof["traffic"] = None if traffic is None else traffic * n / 2
             roof["kernel"] = f"{st_name} (layer {t}), {kern}"
             roof["launches_per_step"] = n / 2
