@@ -94,8 +94,9 @@ typedef void (*e3mi_free_fn)(void* ptr, void* ctx);
  *   over the couplings p = (l1 <= l2, L) of the CG table (natural parity,
  *   ordered by L, then l1, then l2; L <= lmax, only L = 0 in the last layer),
  *   then h~^L = B^L W_lin,L + h_in^L W_self,L and the gate. Every layer then
- *   computes every order of A (no fused scalar-only last layer), and
- *   e3mi_param_grad fails with E3MI_EUNSUPPORTED.
+ *   computes every order of A (no fused scalar-only last layer). The
+ *   second-order passes (e3mi_param_grad, e3mi_hessian_vector) carry the
+ *   block's tangent B_dot = f'(A~) A~_dot and its reverse.
  * Readings of the paper behind each key: Appendix F tables (l_max, channels,
  * layers, num_rbf 8, radial net of 2 hidden layers of 64 with swish,
  * polynomial envelope, gate nonlinearity, readout 16x0e -> 0e, cutoff 5 A).
@@ -211,7 +212,7 @@ int e3mi_param_grad(e3mi_model* model, e3mi_graph* graph, const double* pos, con
  * pass over primal and tangent values) with the reverse pass continued
  * through every layer's harmonics and radial basis to the positions; no
  * weight gradients are formed. Errors: E3MI_EUNSUPPORTED for models with the
- * Coulomb term or the product block. Asynchronous on `stream`. */
+ * Coulomb term. Asynchronous on `stream`. */
 int e3mi_hessian_vector(e3mi_model* model, e3mi_graph* graph, const double* pos, const float* v, float* hv,
                         void* stream);
 

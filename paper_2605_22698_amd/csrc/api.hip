@@ -210,6 +210,10 @@ struct Workspace {
   std::vector<int> rp_host;                            // pruned row pointer on the host (receiver chunks)
   bool rp_valid = false;
   std::unique_ptr<DevBuf> Bp, dat;                     // product block: B (or dB), dA~
+  // product block, second-order pass: A~_dot and B_dot per layer; adjoints of
+  // B, B_dot, A~, A~_dot; per-atom weight-gradient rows
+  std::vector<std::unique_ptr<DevBuf>> atd, Bpd;
+  std::unique_ptr<DevBuf> Bpb, Bpc, atb, atc, dwp;
   std::unique_ptr<DevBuf> mixp;                        // partial products of a K-split channel mix
   std::unique_ptr<DevBuf> msg;                         // per-edge sender-gradient messages of a full layer
   std::unique_ptr<DevBuf> touched;                     // per atom: tag of the last chunk that sent it a message
@@ -1509,8 +1513,7 @@ void second_order(e3mi_model* M, e3mi_graph* G, const double* pos, const double*
   Workspace& w = M->ws;
   E3MI_REQUIRE(!c.coulomb, E3MI_EUNSUPPORTED,
                "second-order passes (parameter gradients, Hessian-vector products) of the Coulomb term are not implemented");
-  E3MI_REQUIRE(c.correlation == 1, E3MI_EUNSUPPORTED,
-               "second-order passes (parameter gradients, Hessian-vector products) of the product block are not implemented");
+  const bool prod = c.correlation == 2;
   const WeightOffsets off = weight_offsets(c);
   if (out) E3MI_HIP(hipMemsetAsync(out, 0, sizeof(double) * off.total, st));
   if (N == 0) return;
@@ -1550,6 +1553,19 @@ void second_order(e3mi_model* M, e3mi_graph* G, const double* pos, const double*
     for (auto* v : {&w.Ygb, &w.Ygc}) ensure(*v, a, sizeof(float) * E1 * 16);
     ensure(w.ghv, a, sizeof(float4) * E1);
   }
+  if (prod) {
+    w.atd.resize(T + 1);
+    w.Bpd.resize(T + 1);
+    long dw_max = 0;
+    for (int t = 1; t <= T; ++t) {
+      const LayerPlan& L = M->plans[t - 1];
+      ensure(w.atd[t], a, sizeof(float) * (size_t)N * L.nc_a * C);
+      ensure(w.Bpd[t], a, sizeof(float) * (size_t)N * (L.lout + 1) * (L.lout + 1) * C);
+      dw_max = std::max(dw_max, (long)(L.lout + 1 + L.n_prod) * C);
+    }
+    for (auto* v : {&w.Bpb, &w.Bpc, &w.atb, &w.atc}) ensure(*v, a, sizeof(float) * (size_t)N * NC * C);
+    if (out) ensure(w.dwp, a, sizeof(float) * (size_t)N * dw_max);
+  }
 
   // ---- tangent forward along v = gF ----
   launch_edge_tangent(row_ptr, src, dvec, gF, N, w.dd->as<float4>(), st);
@@ -1581,9 +1597,19 @@ void second_order(e3mi_model* M, e3mi_graph* G, const double* pos, const double*
     ta.C = C;
     ta.inv_nu = inv_nu;
     launch_tp(3, ta, st);
-    launch_mix(M, L, W, w.Ad[t]->as<float>(), t > 1 ? w.hd[t - 1]->as<float>() : nullptr, w.htd[t]->as<float>(),
-               L.nc_out, N,
-               st);
+    if (prod) {
+      // A~_dot = A_dot W_mix (no self connection), B_dot, then h~_dot = B_dot W_lin + h_dot S
+      launch_mix(M, L, W, w.Ad[t]->as<float>(), nullptr, w.atd[t]->as<float>(), L.nc_a, N, st);
+      ProductArgs pa = product_args(M, G, L, W, w.at[t]->as<float>());
+      pa.atd = w.atd[t]->as<float>();
+      pa.Bd = w.Bpd[t]->as<float>();
+      launch_product_jvp(pa, st);
+      launch_lin(M, L, W, w.Bpd[t]->as<float>(), t > 1 ? w.hd[t - 1]->as<float>() : nullptr, w.htd[t]->as<float>(),
+                 N, st, false);
+    } else {
+      launch_mix(M, L, W, w.Ad[t]->as<float>(), t > 1 ? w.hd[t - 1]->as<float>() : nullptr,
+                 w.htd[t]->as<float>(), L.nc_out, N, st);
+    }
     launch_gate_dual_fwd(w.ht[t]->as<float>(), w.htd[t]->as<float>(), w.hd[t]->as<float>(), N, L.nc_out, C, st);
   }
 
@@ -1614,27 +1640,74 @@ void second_order(e3mi_model* M, e3mi_graph* G, const double* pos, const double*
     const float* hin = w.h[t - 1]->as<float>();
     const float* hdin = t > 1 ? w.hd[t - 1]->as<float>() : nullptr;
     launch_gate_dual_bwd(w.ht[t]->as<float>(), w.htd[t]->as<float>(), hb, hc, xb, xc, N, L.nc_out, C, st);
-    // weight gradients of the channel mix and the self connection
+    // weight gradients of the self connection (orders present in both h^{t-1} and h~)
+    for (int l = 0; l <= (out ? std::min(L.l1max, prod ? L.lout : L.l3max_used) : -1); ++l) {
+      const int g = 2 * l + 1;
+      launch_gemm_tn(RowMap{const_cast<float*>(hin) + (long)l * l * C, (long)L.nc_in * C, (long)C, g},
+                     RowMap{xb + (long)l * l * C, (long)L.nc_out * C, (long)C, g},
+                     hdin ? RowMap{const_cast<float*>(hdin) + (long)l * l * C, (long)L.nc_in * C, (long)C, g}
+                          : RowMap{nullptr, 0, 0, 1},
+                     RowMap{xc + (long)l * l * C, (long)L.nc_out * C, (long)C, g}, (long)N * g, nullptr, C, C,
+                     partial, out + off.self_[t - 1][l], C, st);
+    }
+    E3MI_HIP(hipMemsetAsync(hb2, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+    if (t > 1) E3MI_HIP(hipMemsetAsync(hc2, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
+    // the mix's output adjoints (of A~ or h~, and of their tangents)
+    const float* mb = xb;
+    const float* mc = xc;
+    int m_nc = L.nc_out;
+    if (prod) {
+      // h~ = B W_lin + h^{t-1} S: adjoints of B and B_dot (and of h^{t-1},
+      // h_dot^{t-1} through S), W_lin's gradient from B and B_dot
+      float* Bt = w.Bp->as<float>();
+      ProductArgs pa = product_args(M, G, L, W, w.at[t]->as<float>());
+      pa.atd = w.atd[t]->as<float>();
+      if (out) {
+        pa.B = Bt;
+        launch_product(true, pa, st);  // B again (the forward pass keeps one layer's)
+        for (int l = 0; l <= L.lout; ++l) {
+          const int g = 2 * l + 1, nb = (L.lout + 1) * (L.lout + 1);
+          launch_gemm_tn(RowMap{Bt + (long)l * l * C, (long)nb * C, (long)C, g},
+                         RowMap{xb + (long)l * l * C, (long)L.nc_out * C, (long)C, g},
+                         RowMap{w.Bpd[t]->as<float>() + (long)l * l * C, (long)nb * C, (long)C, g},
+                         RowMap{xc + (long)l * l * C, (long)L.nc_out * C, (long)C, g}, (long)N * g, nullptr, C, C,
+                         partial, out + off.lin[t - 1][l], C, st);
+        }
+      }
+      launch_lin_adjoint(M, L, W, xb, w.Bpb->as<float>(), hb2, N, st, false);
+      launch_lin_adjoint(M, L, W, xc, w.Bpc->as<float>(), t > 1 ? hc2 : nullptr, N, st, false);
+      pa.Bb = w.Bpb->as<float>();
+      pa.Bc = w.Bpc->as<float>();
+      pa.atb = w.atb->as<float>();
+      pa.atc = w.atc->as<float>();
+      pa.dw = out ? w.dwp->as<float>() : nullptr;
+      launch_product_dual_bwd(pa, st);
+      if (out) {
+        const long ldw = (long)(L.lout + 1 + L.n_prod) * C;
+        launch_group_sum(pa.dw, ldw, G->species->as<int>(), c.n_species, N, (L.lout + 1) * C, out + off.sym1[t - 1],
+                         (long)(L.lout + 1) * C, st);
+        launch_group_sum(pa.dw + (long)(L.lout + 1) * C, ldw, G->species->as<int>(), c.n_species, N, L.n_prod * C,
+                         out + off.sym2[t - 1], (long)L.n_prod * C, st);
+      }
+      mb = w.atb->as<float>();
+      mc = w.atc->as<float>();
+      m_nc = L.nc_a;
+    }
+    // weight gradients of the channel mix
     long gbase = 0;
     for (int l3 = 0; l3 <= (out ? L.l3max_used : -1); ++l3) {
       const int P3 = L.p_used_l3[l3], g = 2 * l3 + 1;
-      const RowMap xbr{xb + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
-      const RowMap xcr{xc + (long)l3 * l3 * C, (long)L.nc_out * C, (long)C, g};
-      launch_gemm_tn(RowMap{w.Al[t]->as<float>() + gbase, (long)g * P3 * C, (long)P3 * C, g}, xbr,
-                     RowMap{w.Ad[t]->as<float>() + gbase, (long)g * P3 * C, (long)P3 * C, g}, xcr, (long)N * g,
+      launch_gemm_tn(RowMap{w.Al[t]->as<float>() + gbase, (long)g * P3 * C, (long)P3 * C, g},
+                     RowMap{const_cast<float*>(mb) + (long)l3 * l3 * C, (long)m_nc * C, (long)C, g},
+                     RowMap{w.Ad[t]->as<float>() + gbase, (long)g * P3 * C, (long)P3 * C, g},
+                     RowMap{const_cast<float*>(mc) + (long)l3 * l3 * C, (long)m_nc * C, (long)C, g}, (long)N * g,
                      nullptr, P3 * C, C, partial, out + off.mix[t - 1][l3], C, st);
-      if (l3 <= L.l1max)
-        launch_gemm_tn(RowMap{const_cast<float*>(hin) + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, g}, xbr,
-                       hdin ? RowMap{const_cast<float*>(hdin) + (long)l3 * l3 * C, (long)L.nc_in * C, (long)C, g}
-                            : RowMap{nullptr, 0, 0, 1},
-                       xcr, (long)N * g, nullptr, C, C, partial, out + off.self_[t - 1][l3], C, st);
       gbase += (long)N * g * P3 * C;
     }
-    // adjoints of A and A_dot; of h^{t-1} and h_dot^{t-1} through the self connection
-    E3MI_HIP(hipMemsetAsync(hb2, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
-    if (t > 1) E3MI_HIP(hipMemsetAsync(hc2, 0, sizeof(float) * (size_t)N * L.nc_in * C, st));
-    launch_mix_adjoint(M, L, W, xb, L.nc_out, w.Ab->as<float>(), hb2, N, st);
-    launch_mix_adjoint(M, L, W, xc, L.nc_out, w.Ac->as<float>(), t > 1 ? hc2 : nullptr, N, st);
+    // adjoints of A and A_dot; of h^{t-1} and h_dot^{t-1} through the self
+    // connection (without the product block, the mix holds it)
+    launch_mix_adjoint(M, L, W, mb, m_nc, w.Ab->as<float>(), prod ? nullptr : hb2, N, st);
+    launch_mix_adjoint(M, L, W, mc, m_nc, w.Ac->as<float>(), (!prod && t > 1) ? hc2 : nullptr, N, st);
     // tensor product: adjoints of R and R_dot, then of h and h_dot
     TpArgs ta{};
     ta.lmax = c.lmax;

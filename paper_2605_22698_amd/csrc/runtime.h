@@ -322,9 +322,20 @@ struct ProductArgs {
   float* B = nullptr;              // forward output [N, (lout+1)^2, C]
   const float* dB = nullptr;       // adjoint input  [N, (lout+1)^2, C]
   float* dat = nullptr;            // adjoint output [N, (lmax+1)^2, C] (overwritten)
+  // second-order pass: tangent A~_dot and B_dot, adjoints of B and B_dot, of
+  // A~ and A~_dot, and (optional) per-atom weight-gradient rows
+  const float* atd = nullptr;      // [N, (lmax+1)^2, C]
+  float* Bd = nullptr;             // [N, (lout+1)^2, C] (overwritten)
+  const float* Bb = nullptr;       // [N, (lout+1)^2, C]
+  const float* Bc = nullptr;       // [N, (lout+1)^2, C]
+  float* atb = nullptr;            // [N, (lmax+1)^2, C] (overwritten)
+  float* atc = nullptr;            // [N, (lmax+1)^2, C] (overwritten)
+  float* dw = nullptr;             // [N, lout+1+pairs, C]: d/dw1 then d/dw2 of atom i (overwritten)
 };
 int product_pair_count(int lmax, int lout);
 void launch_product(bool fwd, const ProductArgs& p, hipStream_t st);
+void launch_product_jvp(const ProductArgs& p, hipStream_t st);
+void launch_product_dual_bwd(const ProductArgs& p, hipStream_t st);
 
 // ---- electrostatics of open structures (coulomb.hip) ---------------------------------
 // q~ = q - (sum_s q - Q_s) / N_s per structure

@@ -85,6 +85,20 @@ def test_open_cluster_lmax3_three_layers():
     _compare(cfg, 9, b, rng.standard_normal(1), rng.standard_normal((20, 3)) * 0.01)
 
 
+@pytest.mark.parametrize("lmax,C,layers", [(2, 32, 2), (3, 64, 3)])
+def test_product_block(lmax, C, layers):
+    # correlation 2: gradients of w1, w2 and W_lin, and everything upstream of
+    # the block through its tangent and reverse
+    cfg = synth.ModelConfig(lmax=lmax, channels=C, layers=layers, n_species=4, cutoff=5.0,
+                            avg_neighbors=synth.nominal_neighbors(0.1, 5.0), correlation=2)
+    rng = np.random.default_rng(63 + layers)
+    b = synth.concat([synth.jittered_lattice(n, 0.1, 0.3, 4, rng) for n in (36, 25)])
+    say(f"grad: product block lmax {lmax} C {C} layers {layers} N={b.n_atoms}")
+    e_ref = rng.standard_normal(2)
+    f_ref = rng.standard_normal((b.n_atoms, 3)) * 0.01
+    _compare(cfg, 10, b, e_ref, f_ref)
+
+
 def test_differentiation_batch_64_structures_golden():
     # the full differentiation batch: 64 periodic boxes of 20-200 atoms, against
     # the oracle's loss and gradient stored by tests/golden/make_golden.py

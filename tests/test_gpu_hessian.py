@@ -121,10 +121,26 @@ def test_identities_on_a_large_open_cluster():
 def test_unsupported_models_are_rejected():
     import torch
     import paper_2605_22698_amd as e3
-    for extra in ({"coulomb": True}, {"correlation": 2}):
-        cfg = synth.ModelConfig(lmax=2, channels=32, layers=2, n_species=3, cutoff=5.0, avg_neighbors=10.0, **extra)
-        m = model(cfg, 118)
-        b = synth.open_box(12, 3, np.random.default_rng(119))
-        g, pos = _graph(m, b)
-        with pytest.raises(e3.E3miError):
-            m.hessian_vector(g, pos, torch.zeros((12, 3), device=device()))
+    cfg = synth.ModelConfig(lmax=2, channels=32, layers=2, n_species=3, cutoff=5.0, avg_neighbors=10.0,
+                            coulomb=True)
+    m = model(cfg, 118)
+    b = synth.open_box(12, 3, np.random.default_rng(119))
+    g, pos = _graph(m, b)
+    with pytest.raises(e3.E3miError):
+        m.hessian_vector(g, pos, torch.zeros((12, 3), device=device()))
+
+
+@pytest.mark.parametrize("lmax,C,layers", [(2, 32, 2), (3, 64, 3)])
+def test_product_block_against_oracle(lmax, C, layers):
+    # the product block's tangent and its reverse (correlation 2): every layer
+    # with every order of A; the middle layer of three has all output orders
+    cfg = synth.ModelConfig(lmax=lmax, channels=C, layers=layers, n_species=4, cutoff=5.0,
+                            avg_neighbors=synth.nominal_neighbors(0.1, 5.0), correlation=2)
+    rng = np.random.default_rng(120 + layers)
+    b = synth.concat([synth.jittered_lattice(n, 0.1, 0.3, 4, rng) for n in (40, 27)])
+    m = model(cfg, 121)
+    w = synth.model_weights(cfg, 121)
+    for k in range(2):
+        v = rng.normal(size=b.pos.shape)
+        _check(_hv(m, b, v, skin=0.5), om.hessian_vector(om.Model(cfg, w), b, v),
+               f"product block lmax {lmax} C {C} layers {layers} v{k}")
