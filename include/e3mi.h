@@ -252,9 +252,18 @@ int e3mi_model_set_flags(e3mi_model* model, int flags);
  * receivers (the adjoint then recomputes R per chunk), so a 100,000-atom,
  * 9-million-edge, 3-layer model (about 106 GB of R per layer in FP32, Section
  * 4's tensor product at scale) runs in bounded memory. The chunking reads the
- * pruned row pointer back to the host once per call. Results agree with the
- * unchunked evaluation to rounding (bitwise when there is one chunk). */
+ * pruned row pointer back to the host once per call. Results are bitwise
+ * those of the unchunked evaluation (each receiver's and each sender's sums
+ * run in the same order whatever the chunks). */
 int e3mi_model_set_r_chunk_bytes(e3mi_model* model, size_t bytes);
+
+/* Most bytes of per-edge R kept for every edge, summed over the layers
+ * evaluated in receiver chunks (default 160 GiB of the 288 GB of HBM; 0:
+ * never). Layers are taken in order while the sum fits; such a layer's
+ * forward pass writes every chunk's R into one buffer and its adjoint reads
+ * it there instead of recomputing R chunk by chunk (dR and the sender
+ * messages stay chunk-sized). Results are bitwise the same either way. */
+int e3mi_model_set_r_keep_bytes(e3mi_model* model, size_t bytes);
 
 /* Replace the weights (host FP64, same configuration and layout as at
  * creation), e.g. after an optimiser step. Synchronises the device first. */

@@ -86,6 +86,11 @@ class Model:
         """Most bytes of per-edge radial weights held at once; see e3mi_model_set_r_chunk_bytes."""
         check(lib().e3mi_model_set_r_chunk_bytes(self.handle, int(n_bytes)))
 
+    def set_r_keep_bytes(self, n_bytes: int) -> None:
+        """Most bytes of per-edge radial weights kept whole across a chunked
+        layer's forward pass and adjoint; see e3mi_model_set_r_keep_bytes."""
+        check(lib().e3mi_model_set_r_keep_bytes(self.handle, int(n_bytes)))
+
     def set_weights(self, weights) -> None:
         """Replace the weights (FP64 vector in the documented layout; any device)."""
         w = weights.detach().to("cpu", dtype=__import__("torch").float64).contiguous().numpy() \

@@ -47,6 +47,7 @@ SIGNATURES = {
     "e3mi_hessian_vector": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
     "e3mi_hessian_vectors": (ctypes.c_int, [_p, _p, _p, ctypes.c_int, _p, _p, _p]),
     "e3mi_model_set_r_chunk_bytes": (ctypes.c_int, [_p, ctypes.c_size_t]),
+    "e3mi_model_set_r_keep_bytes": (ctypes.c_int, [_p, ctypes.c_size_t]),
     "e3mi_profile_select": (ctypes.c_int, [_p, ctypes.c_char_p]),
     "e3mi_model_set_weights": (ctypes.c_int, [_p, _p, ctypes.c_size_t]),
     "e3mi_model_set_flags": (ctypes.c_int, [_p, ctypes.c_int]),

@@ -220,6 +220,9 @@ struct Workspace {
   unsigned msg_tag = 0;
   int last_parts = -1;  // last layer left before its gate: partial products in mixp (0: h~ in ht[T])
   bool r_bf16 = false;  // the last forward pass stored R and dR in BF16 where r_bf16_layer says so
+  // per layer: evaluated in receiver chunks with R of every edge kept (the
+  // adjoint reads chunk c's R at its first edge instead of recomputing it)
+  std::vector<char> r_whole;
 };
 
 }  // namespace e3mi
@@ -235,6 +238,9 @@ struct e3mi_model {
   bool first_factorised = true;
   bool last_fused = false;  // per-edge last layer by default (faster here); flag 4 selects the fused one
   size_t r_chunk_bytes = size_t(8) << 30;  // most bytes of per-edge R (and dR) held at once
+  // most bytes of per-edge R kept whole, summed over the layers that run in
+  // receiver chunks: such a layer's adjoint then reads R instead of recomputing it
+  size_t r_keep_bytes = size_t(160) << 30;
   std::unique_ptr<e3mi::DevBuf> U[4], UT[4];
   e3mi::Workspace ws;
   e3mi::Profiler prof;
@@ -814,6 +820,12 @@ std::vector<RChunk> r_chunks(e3mi_model* M, e3mi_graph* G, int PCu, hipStream_t 
   return out;
 }
 
+// R of a chunk: the buffer itself, or for a layer whose R is kept whole, the
+// chunk's first edge within it
+void* chunk_r(const Workspace& w, int t, void* R, const RChunk& ch, int PCu, size_t elem) {
+  return w.r_whole[t] && ch.e1 >= 0 ? static_cast<char*>(R) + (size_t)ch.e0 * PCu * elem : R;
+}
+
 void set_chunk(TpArgs& ta, const RChunk& ch) {
   ta.i0 = ch.e1 < 0 ? 0 : ch.i0;
   ta.n_recv = ch.e1 < 0 ? 0 : ch.i1 - ch.i0;
@@ -855,7 +867,8 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
   w.R.resize(T + 1);
   ensure(w.h[0], a, sizeof(float) * (size_t)N * C);
   long a_max = 0;
-  size_t dr_bytes = 0;
+  size_t dr_bytes = 0, kept = 0;
+  w.r_whole.assign(T + 1, 0);
   for (int t = 1; t <= T; ++t) {
     const LayerPlan& L = M->plans[t - 1];
     ensure(w.h[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
@@ -863,11 +876,18 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     a_max = std::max(a_max, L.a_per_atom);
     if (t == 1 && factorised_first(M) && !keep_A) continue;
     if (fused_last(M, L, keep_A, bf16)) continue;
-    // the second-order pass keeps R of every edge; otherwise at most one chunk
-    const size_t r_edges = keep_A ? (size_t)(Ecap + 1) : r_chunk_edges(M, Ecap, L.p_used * C);
+    // the second-order pass keeps R of every edge; otherwise one chunk, or
+    // every edge's while the layers' kept R stays within r_keep_bytes
+    const size_t chunk_edges = r_chunk_edges(M, Ecap, L.p_used * C);
     const size_t r_elem = r_bf16_layer(w, L) ? 2 : 4;
+    const size_t all_bytes = r_elem * (size_t)(Ecap + 1) * L.p_used * C;
+    if (!keep_A && chunk_edges < (size_t)(Ecap + 1) && kept + all_bytes <= M->r_keep_bytes) {
+      w.r_whole[t] = 1;
+      kept += all_bytes;
+    }
+    const size_t r_edges = keep_A || w.r_whole[t] ? (size_t)(Ecap + 1) : chunk_edges;
     ensure(w.R[t], a, r_elem * r_edges * L.p_used * C);
-    dr_bytes = std::max(dr_bytes, r_elem * r_chunk_edges(M, Ecap, L.p_used * C) * L.p_used * C);
+    dr_bytes = std::max(dr_bytes, r_elem * chunk_edges * L.p_used * C);
   }
   ensure(w.A, a, sizeof(float) * (size_t)N * a_max);
   if (keep_A) {
@@ -999,12 +1019,14 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     ta.C = C;
     ta.inv_nu = inv_nu;
     for (const RChunk& ch : chunks) {
+      void* Rc = chunk_r(w, t, R, ch, PCu, lr_bf16 ? 2 : 4);
       {
         ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
         launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                          W.rad3.as<float>(), L.p_full * C, PCu, R, lr_bf16, rc, p_env, bf16, st, ch.e0, ch.e1);
+                          W.rad3.as<float>(), L.p_full * C, PCu, Rc, lr_bf16, rc, p_env, bf16, st, ch.e0, ch.e1);
       }
       set_chunk(ta, ch);
+      ta.R = static_cast<const float*>(Rc);
       ProfScope ps(&M->prof, stage_id(kTpFwd, t), st);
       launch_tp(0, ta, st);
     }
@@ -1219,15 +1241,17 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       ta.touched = ensure(w.touched, &M->alloc, sizeof(int) * ((size_t)N + 1)).as<int>();
     }
     // with more than one chunk R is recomputed chunk by chunk (the forward
-    // pass kept only the last chunk)
+    // pass kept only the last chunk), unless it was kept whole
     const std::vector<RChunk> chunks = r_chunks(M, G, PCu, st);
+    const bool recompute = chunks.size() > 1 && !w.r_whole[t];
     ta.rev = G->rev_x->as<int>();
     // scalar-output layer: the sender-side adjoint gives dR, dY and dh in one
     // pass (chunk by chunk: a chunk's receivers are the senders whose rows it holds)
     const bool sender_side = tps_supported(ta);
     for (const RChunk& ch : chunks) {
+      ta.R = static_cast<const float*>(chunk_r(w, t, w.R[t]->p, ch, PCu, r_bf16 ? 2 : 4));
       if (sender_side) {
-        if (chunks.size() > 1) {
+        if (recompute) {
           ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
           launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                             W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->p, r_bf16, rc, p_env, bf16, st, ch.e0,
@@ -1246,7 +1270,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
                           t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1);
         continue;
       }
-      if (chunks.size() > 1) {
+      if (recompute) {
         ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
         launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                           W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->p, r_bf16, rc, p_env, bf16, st, ch.e0,
@@ -1284,7 +1308,7 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
   size_t b = 0;
   b += E * (8 + 4 * 3) + E * (4 + 16 + 4 + 4 + 4);   // skin list + pruned list
   b += N * (4 * 4 + 24 + 8) + 64 * 1024;             // per-atom graph data
-  size_t a_max = 0, pc_max = 0;
+  size_t a_max = 0, dr_max = 0, msg_max = 0, kept = 0;
   b += N * C * 4;                                    // embedding
   const bool bf16 = M->precision == E3MI_BF16_MIX;
   for (int t = 1; t <= c.layers; ++t) {
@@ -1297,11 +1321,20 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
       continue;
     }
     if (fused_last(M, L, false, bf16)) continue;  // no per-edge R
-    b += E * L.p_used * C * 4;
-    if (L.kind == 1 && t > 1) b += E * L.nc_in * C * 4;  // sender-gradient messages of a full layer
-    pc_max = std::max(pc_max, (size_t)L.p_used * C);
+    // R (FP32 bound) of every edge, or of one receiver chunk unless kept whole;
+    // dR and the sender-gradient messages of a full layer per chunk
+    const size_t PCu = (size_t)L.p_used * C;
+    const size_t chunk = std::min(E, M->r_chunk_bytes / (PCu * 4));
+    bool whole = chunk >= E;
+    if (!whole && kept + E * PCu * 4 <= M->r_keep_bytes) {
+      whole = true;
+      kept += E * PCu * 4;
+    }
+    b += (whole ? E : chunk) * PCu * 4;
+    dr_max = std::max(dr_max, chunk * PCu * 4);
+    if (L.kind == 1 && t > 1) msg_max = std::max(msg_max, chunk * L.nc_in * C * 4);
   }
-  b += N * a_max * 4 + E * pc_max * 4 + E * (64 + 16) + 3 * N * NC * C * 4 + N * 8;
+  b += N * a_max * 4 + dr_max + msg_max + E * (64 + 16) + 3 * N * NC * C * 4 + N * 8;
   if (c.correlation == 2) b += 2 * N * NC * C * 4;  // B / dB and dA~
   return b;
 }
@@ -2327,6 +2360,13 @@ int e3mi_model_set_r_chunk_bytes(e3mi_model* model, size_t bytes) {
   E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
   E3MI_REQUIRE(bytes >= (size_t)1 << 20, E3MI_EINVAL, "the R chunk must be at least 1 MiB");
   model->r_chunk_bytes = bytes;
+  E3MI_API_END
+}
+
+int e3mi_model_set_r_keep_bytes(e3mi_model* model, size_t bytes) {
+  E3MI_API_BEGIN
+  E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
+  model->r_keep_bytes = bytes;
   E3MI_API_END
 }
 

@@ -287,14 +287,18 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
 // other along the row and every sender's sum is the same sequence of
 // additions whatever the chunking. init: components below dh_acc (all when
 // dh_acc <= 0) start from dh, the others from zero (components NIN..dh_nc-1
-// past dh_acc are zeroed).
+// past dh_acc are zeroed). Block b is sender b (no XCD remapping): the
+// senders a chunk touches are a compact index range (atoms are spatially
+// sorted), and consecutive blocks go to different XCDs, so that range
+// spreads over the whole chip. Messages are read four edges at a time (64
+// loads in flight per lane) and added in row order.
 template <int NIN>
 __global__ void __launch_bounds__(256) k_tp_msg_node(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                      const int* __restrict__ rev, const float* __restrict__ msg,
                                                      float* __restrict__ dh, int dh_nc, int C, int c0, int c1,
                                                      int e_first, int init, int dh_acc,
                                                      const int* __restrict__ touched, int tag) {
-  const int j = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int j = blockIdx.x;
   // after the first chunk, only senders this chunk's edge adjoint sent to
   // (touched carries the chunk's tag; another value can only add an empty run)
   if (!init && touched[j] != tag) return;
@@ -316,7 +320,26 @@ __global__ void __launch_bounds__(256) k_tp_msg_node(const int* __restrict__ row
       const bool keep = !init || dh_acc <= 0 || q < dh_acc;
       acc[q] = keep ? dh[((long)j * dh_nc + q) * C + k] : 0.0f;
     }
-    for (int e2 = r0; e2 < r1; ++e2) {
+    int e2 = r0;
+    for (; e2 + 4 <= r1; e2 += 4) {
+      int ev[4];
+      float mv[4][NIN];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) ev[u] = rev[e2 + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        // an edge without a reverse reads the chunk's first message, unused
+        const float* me = msg + (ev[u] >= 0 ? (long)(ev[u] - e_first) : 0L) * NIN * C + k;
+#pragma unroll
+        for (int q = 0; q < NIN; ++q) mv[u][q] = me[q * C];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < NIN; ++q)
+          if (ev[u] >= 0) acc[q] += mv[u][q];
+    }
+    for (; e2 < r1; ++e2) {
       const int e = rev[e2];
       if (e < 0) continue;
       const float* me = msg + (long)(e - e_first) * NIN * C + k;

@@ -82,9 +82,10 @@ def test_alone_equals_packed_bitwise():
         assert np.array_equal(Fs, F[a:z])
 
 
-def test_parameter_gradient_is_rejected():
+def test_energy_weight_gradient_against_oracle():
+    # dE/dtheta of the product-block model through e3mi_param_grad (gF = 0),
+    # against the oracle's loss (E - (E_o - 1/2))^2, whose gradient is dE/dtheta
     import torch
-    import paper_2605_22698_amd as e3
     cfg = _cfg(2, 32, n_species=3)
     _, b = synth.tiny_config()
     m = model(cfg, 89)
@@ -93,5 +94,11 @@ def test_parameter_gradient_is_rejected():
     g = m.build_graph(b.offsets, pos, sp, b.cell, b.pbc, cfg.cutoff, 0.0)
     gE = torch.ones(1, dtype=torch.float64, device=device())
     gF = torch.zeros((b.n_atoms, 3), dtype=torch.float32, device=device())
-    with pytest.raises(e3.E3miError):
-        m.param_grad(g, pos, gE, gF)
+    grad = m.param_grad(g, pos, gE, gF).cpu().numpy()
+    om_m = om.Model(cfg, synth.model_weights(cfg, 89))
+    E_o = om.energy(om_m, b)
+    _, go = om.loss_and_grads(om_m, b, E_o - 0.5, np.zeros((b.n_atoms, 3)), 1.0, 0.0)
+    ref = synth.flatten_weights(cfg, go)
+    err = np.linalg.norm(grad - ref) / np.linalg.norm(ref)
+    say(f"  dE/dtheta rel L2 err {err:.2e}")
+    assert err <= 1e-4

@@ -25,9 +25,11 @@ def test_chunked_layers_equal_unchunked(correlation):
     m = model(cfg, 122)
     E0, F0, Ei0, _ = gpu_energy_forces(m, b, skin=1.0)
     m.set_r_chunk_bytes(1 << 20)  # 1 MiB: 1 MiB / (23 paths x 64 ch x 4 B) = 178 edges per chunk
-    E1, F1, Ei1, _ = gpu_energy_forces(m, b, skin=1.0)
-    say(f"chunked (correlation {correlation}): max |dF| {np.abs(F1 - F0).max():.1e}")
-    assert np.array_equal(E0, E1) and np.array_equal(F0, F1) and np.array_equal(Ei0, Ei1)
+    for keep in (0, 1 << 40):     # R recomputed chunk by chunk in the adjoint / kept whole
+        m.set_r_keep_bytes(keep)
+        E1, F1, Ei1, _ = gpu_energy_forces(m, b, skin=1.0)
+        say(f"chunked (correlation {correlation}, keep {keep}): max |dF| {np.abs(F1 - F0).max():.1e}")
+        assert np.array_equal(E0, E1) and np.array_equal(F0, F1) and np.array_equal(Ei0, Ei1)
 
 
 @pytest.mark.parametrize("chunk_bytes", [None, 64 << 20])
@@ -54,11 +56,20 @@ def test_scale_subbox_against_oracle(chunk_bytes):
 
 
 def test_hundred_thousand_atoms_fp32_and_bf16():
+    import torch
     cfg, b = synth.scale_config()
     say(f"100k box: N={b.n_atoms}")
-    E32, F32, _, g = gpu_energy_forces(model(cfg, 5), b, skin=0.0)
+    # one model at a time: each keeps about 120 GB of per-edge R
+    m = model(cfg, 5)
+    E32, F32, _, g = gpu_energy_forces(m, b, skin=0.0)
     n_edges = g.last_edge_count()
-    E16, F16, _, _ = gpu_energy_forces(model(cfg, 5, precision=1), b, skin=0.0)
+    g.close()
+    m.close()
+    torch.cuda.empty_cache()
+    m = model(cfg, 5, precision=1)
+    E16, F16, _, g = gpu_energy_forces(m, b, skin=0.0)
+    g.close()
+    m.close()
     fmax = np.abs(F32).max()
     say(f"  edges {n_edges}; E32 {E32[0]:.6f}, E16 {E16[0]:.6f} eV; |sum F| {np.abs(F32.sum(0)).max():.2e}; "
         f"BF16 vs FP32: {abs(E16[0] - E32[0]) / b.n_atoms:.2e} eV/atom, "
