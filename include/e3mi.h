@@ -257,9 +257,9 @@ int e3mi_model_set_flags(e3mi_model* model, int flags);
  * run in the same order whatever the chunks). */
 int e3mi_model_set_r_chunk_bytes(e3mi_model* model, size_t bytes);
 
-/* Most bytes of per-edge R kept for every edge, summed over the layers
- * evaluated in receiver chunks (default 160 GiB of the 288 GB of HBM; 0:
- * never). Layers are taken in order while the sum fits; such a layer's
+/* Most bytes of per-edge R kept for every edge inside the cutoff, summed
+ * over the layers evaluated in receiver chunks (default 160 GiB of the 288 GB
+ * of HBM; 0: never). Layers are taken in order while the sum fits; such a layer's
  * forward pass writes every chunk's R into one buffer and its adjoint reads
  * it there instead of recomputing R chunk by chunk (dR and the sender
  * messages stay chunk-sized). Results are bitwise the same either way. */

@@ -796,19 +796,24 @@ size_t r_chunk_edges(const e3mi_model* M, long Ecap, int PCu) {
   return std::min<size_t>((size_t)(Ecap + 1), M->r_chunk_bytes / ((size_t)PCu * sizeof(float)));
 }
 
+// The pruned row pointer on the host, read back once per evaluation.
+const std::vector<int>& pruned_rows(e3mi_model* M, e3mi_graph* G, hipStream_t st) {
+  Workspace& w = M->ws;
+  if (!w.rp_valid) {
+    w.rp_host.resize((size_t)G->N + 1);
+    E3MI_HIP(hipMemcpyAsync(w.rp_host.data(), G->row_ptr_x->p, sizeof(int) * ((size_t)G->N + 1),
+                            hipMemcpyDeviceToHost, st));
+    E3MI_HIP(hipStreamSynchronize(st));
+    w.rp_valid = true;
+  }
+  return w.rp_host;
+}
+
 std::vector<RChunk> r_chunks(e3mi_model* M, e3mi_graph* G, int PCu, hipStream_t st) {
   const int N = G->N;
   const size_t cap = r_chunk_edges(M, G->E, PCu);
   if (cap >= (size_t)(G->E + 1)) return {RChunk{0, N, 0, -1}};
-  Workspace& w = M->ws;
-  if (!w.rp_valid) {
-    w.rp_host.resize((size_t)N + 1);
-    E3MI_HIP(hipMemcpyAsync(w.rp_host.data(), G->row_ptr_x->p, sizeof(int) * ((size_t)N + 1), hipMemcpyDeviceToHost,
-                            st));
-    E3MI_HIP(hipStreamSynchronize(st));
-    w.rp_valid = true;
-  }
-  const std::vector<int>& rp = w.rp_host;
+  const std::vector<int>& rp = pruned_rows(M, G, st);
   std::vector<RChunk> out;
   for (int i0 = 0; i0 < N;) {
     int i1 = i0 + 1;  // a receiver's row always fits (its edges are few)
@@ -876,16 +881,24 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     a_max = std::max(a_max, L.a_per_atom);
     if (t == 1 && factorised_first(M) && !keep_A) continue;
     if (fused_last(M, L, keep_A, bf16)) continue;
-    // the second-order pass keeps R of every edge; otherwise one chunk, or
-    // every edge's while the layers' kept R stays within r_keep_bytes
+    // the second-order pass keeps R of every edge (skin-list capacity);
+    // otherwise one chunk, or every edge inside the cutoff while the layers'
+    // kept R stays within r_keep_bytes
     const size_t chunk_edges = r_chunk_edges(M, Ecap, L.p_used * C);
     const size_t r_elem = r_bf16_layer(w, L) ? 2 : 4;
-    const size_t all_bytes = r_elem * (size_t)(Ecap + 1) * L.p_used * C;
-    if (!keep_A && chunk_edges < (size_t)(Ecap + 1) && kept + all_bytes <= M->r_keep_bytes) {
-      w.r_whole[t] = 1;
-      kept += all_bytes;
+    size_t r_edges = keep_A ? (size_t)(Ecap + 1) : chunk_edges;
+    if (!keep_A && chunk_edges < (size_t)(Ecap + 1)) {
+      // room for 1/8 more edges than this call has inside the cutoff, so
+      // that the count's drift between rebuilds does not reallocate
+      const size_t e_in = (size_t)pruned_rows(M, G, st)[N] + 1;
+      const size_t e_room = std::min((size_t)(Ecap + 1), e_in + e_in / 8);
+      const size_t all_bytes = r_elem * e_room * L.p_used * C;
+      if (kept + all_bytes <= M->r_keep_bytes) {
+        w.r_whole[t] = 1;
+        kept += all_bytes;
+        r_edges = std::max(r_edges, w.R[t] && w.R[t]->bytes >= r_elem * e_in * L.p_used * C ? e_in : e_room);
+      }
     }
-    const size_t r_edges = keep_A || w.r_whole[t] ? (size_t)(Ecap + 1) : chunk_edges;
     ensure(w.R[t], a, r_elem * r_edges * L.p_used * C);
     dr_bytes = std::max(dr_bytes, r_elem * chunk_edges * L.p_used * C);
   }
@@ -1321,8 +1334,9 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
       continue;
     }
     if (fused_last(M, L, false, bf16)) continue;  // no per-edge R
-    // R (FP32 bound) of every edge, or of one receiver chunk unless kept whole;
-    // dR and the sender-gradient messages of a full layer per chunk
+    // R (FP32 bound) of every edge, or of one receiver chunk unless kept whole
+    // (n_edges stands for the edges inside the cutoff); dR and the
+    // sender-gradient messages of a full layer per chunk
     const size_t PCu = (size_t)L.p_used * C;
     const size_t chunk = std::min(E, M->r_chunk_bytes / (PCu * 4));
     bool whole = chunk >= E;
