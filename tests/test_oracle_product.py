@@ -161,3 +161,44 @@ def test_product_model_features_are_equivariant_and_energy_invariant():
             D = cg.wigner_d(l, R)
             np.testing.assert_allclose(h1[:, :, l * l:(l + 1) ** 2], h0[:, :, l * l:(l + 1) ** 2] @ D.T,
                                        atol=1e-12)
+
+
+def test_product_model_hessian_vector_matches_differences_of_forces():
+    # the second-order quantities of the correlation-2 model: H v against
+    # central differences of the forces along v
+    cfg = _cfg(lmax=2, C=4, layers=2)
+    m = _model_with(cfg, seed=7)
+    b = synth.uniform_cluster(10, 6.0, 0.9, 2, np.random.default_rng(71))
+    v = np.random.default_rng(72).normal(size=b.pos.shape)
+    hv = om.hessian_vector(m, b, v)
+    h = 1e-4
+
+    def forces(pos):
+        bb = synth.Batch(np.asarray(pos), b.species, b.cell, b.pbc, b.offsets, b.charge)
+        return om.energy_forces(m, bb)[1]
+
+    fd = -(forces(b.pos + h * v) - forces(b.pos - h * v)) / (2 * h)
+    assert np.abs(hv - fd).max() < 1e-6 * max(1.0, np.abs(hv).max())
+
+
+def test_product_model_loss_gradients_match_central_differences():
+    # the weights of the block (w1, w2, the linear after it) and one upstream
+    # of it, through the force term of the loss
+    cfg = _cfg(lmax=2, C=4, layers=2)
+    w = synth.model_weights(cfg, 8)
+    rng = np.random.default_rng(73)
+    b = synth.concat([synth.jittered_lattice(n, 0.1, 0.3, 2, rng) for n in (10, 14)])
+    e_ref = rng.standard_normal(2)
+    f_ref = rng.standard_normal((b.n_atoms, 3))
+    loss, grads = om.loss_and_grads(om.Model(cfg, w), b, e_ref, f_ref)
+    h = 1e-5
+    for name in ["sym1_1", "sym2_1", "lin_1_1", "sym2_2", "lin_2_0", "mix_1_2"]:
+        for _ in range(2):
+            idx = tuple(int(rng.integers(0, s)) for s in w[name].shape)
+            vals = []
+            for sgn in (1, -1):
+                w2 = {k: v.copy() for k, v in w.items()}
+                w2[name][idx] += sgn * h
+                vals.append(om.loss_and_grads(om.Model(cfg, w2), b, e_ref, f_ref)[0])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - grads[name][idx]) < 1e-7 + 1e-5 * abs(fd), (name, idx, fd, grads[name][idx])
