@@ -17,18 +17,19 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-@pytest.mark.parametrize("correlation", [1, 2])
-def test_chunked_layers_equal_unchunked(correlation):
+@pytest.mark.parametrize("correlation,precision", [(1, 0), (2, 0), (1, 1)])
+def test_chunked_layers_equal_unchunked(correlation, precision):
     cfg = synth.ModelConfig(lmax=3, channels=64, layers=3, n_species=4, cutoff=5.0,
                             avg_neighbors=synth.nominal_neighbors(0.1, 5.0), correlation=correlation)
     b = synth.jittered_lattice(400, 0.1, 0.3, 4, np.random.default_rng(121))
-    m = model(cfg, 122)
+    m = model(cfg, 122, precision=precision)
     E0, F0, Ei0, _ = gpu_energy_forces(m, b, skin=1.0)
     m.set_r_chunk_bytes(1 << 20)  # 1 MiB: 1 MiB / (23 paths x 64 ch x 4 B) = 178 edges per chunk
     for keep in (0, 1 << 40):     # R recomputed chunk by chunk in the adjoint / kept whole
         m.set_r_keep_bytes(keep)
         E1, F1, Ei1, _ = gpu_energy_forces(m, b, skin=1.0)
-        say(f"chunked (correlation {correlation}, keep {keep}): max |dF| {np.abs(F1 - F0).max():.1e}")
+        say(f"chunked (correlation {correlation}, precision {precision}, keep {keep}): "
+            f"max |dF| {np.abs(F1 - F0).max():.1e}")
         assert np.array_equal(E0, E1) and np.array_equal(F0, F1) and np.array_equal(Ei0, Ei1)
 
 
