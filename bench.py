@@ -230,8 +230,9 @@ def product_work(cfg, t, N):
 
 def product_run(e3, synth, torch, dev, n_atoms, steps, warmup, log):
     """MD of the single-structure box with the product block of body order 2
-    (MACE's symmetric contraction, correlation 2) in both layers, against the
-    same box without it; the dominant product kernel against HBM."""
+    (MACE's symmetric contraction, correlation 2) in both layers; the dominant
+    product kernel against HBM; one Hessian-vector product and one
+    parameter gradient of that model on the box."""
     cfg1, b = synth.single_config(n=n_atoms)
     cfg = synth.ModelConfig(**{**cfg1.__dict__, "correlation": 2})
     vel = synth.maxwell_boltzmann(b, 300.0, synth.seed_for(2, 9))
@@ -276,9 +277,31 @@ def product_run(e3, synth, torch, dev, n_atoms, steps, warmup, log):
                        "traffic": measured_traffic(f"k_{s}", "product_hbm_traffic.md"),
                        "kernel": f"{s} (layer {t})", "avg_launch_ms": ms,
                        "algorithmic_per_launch": {"flops": flops, "bytes": nbytes}}
+    # the block's second-order pass on the same box: one Hessian-vector
+    # product, and the weight gradient of an energy + force loss
+    xpos, _, _ = md.state()
+    g = m.build_graph(b.offsets, xpos, sp_d, b.cell, b.pbc, cfg.cutoff, 0.0)
+    v = torch.randn((b.n_atoms, 3), generator=torch.Generator().manual_seed(11)).to(device=dev, dtype=torch.float32)
+    gE = torch.ones(1, dtype=torch.float64, device=dev)
+    gF = (0.01 * v).contiguous()
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / k
+    out["ms_hessian_vector_product"] = 1e3 * timed(lambda: m.hessian_vector(g, xpos, v), 5)
+    out["ms_param_grad"] = 1e3 * timed(lambda: m.param_grad(g, xpos, gE, gF), 5)
+    out["ms_energy_forces"] = 1e3 * timed(lambda: m.energy_forces(g, xpos), 10)
+    g.close()
     md.close()
     log(f"product block: {out['value']:.3e} atom-steps/s; {s}@{t} {ms:.4f} ms, "
-        f"{out['roofline']['achieved']:.0f} GB/s ({out['roofline']['frac']:.1%})")
+        f"{out['roofline']['achieved']:.0f} GB/s ({out['roofline']['frac']:.1%}); "
+        f"Hessian-vector product {out['ms_hessian_vector_product']:.2f} ms, "
+        f"parameter gradient {out['ms_param_grad']:.2f} ms")
     return out
 
 
