@@ -305,6 +305,48 @@ def product_run(e3, synth, torch, dev, n_atoms, steps, warmup, log):
     return out
 
 
+def nve_run(e3, synth, torch, dev, n_atoms, steps, log):
+    """Energy conservation of the MD path: NVE from 300 K on the
+    single-structure box (0.5 fs, skin 1 A, rebuild every 20 steps) in FP32
+    and in BF16 mode; the total energy (potential + kinetic, FP64) sampled
+    every 100 steps. Reported: its largest deviation from the start and the
+    slope of a least-squares line, per atom."""
+    cfg, b = synth.single_config(n=n_atoms)
+    vel = synth.maxwell_boltzmann(b, 300.0, synth.seed_for(2, 9))
+    w = synth.flatten_weights(cfg, synth.model_weights(cfg, 2))
+    mass = synth.SPECIES_MASS[b.species][:, None]
+    amu_A2_fs2_to_eV = 1.0 / KAPPA
+    out = {"workload": f"NVE from 300 K, {b.n_atoms}-atom periodic box (the benchmark box), 0.5 fs, "
+                       f"{steps} steps, skin 1 A, rebuild every 20 steps", "steps": steps}
+    for name, prec in (("fp32", e3.FP32), ("bf16", e3.BF16_MIX)):
+        m = e3.Model(cfg.to_json(), w, precision=prec, device=dev)
+        md = e3.MD(m, b.offsets, torch.tensor(b.pos, dtype=torch.float64, device=dev),
+                   torch.tensor(vel, dtype=torch.float64, device=dev),
+                   torch.tensor(b.species, dtype=torch.int32, device=dev), synth.SPECIES_MASS[:4], b.cell, b.pbc,
+                   cfg.cutoff, 1.0, 20)
+        energy = torch.empty(1, dtype=torch.float64, device=dev)
+        t_ps, tot = [], []
+        md.step(1, 0.5, energy)
+        for k in range(0, steps + 1, 100):
+            if k:
+                md.step(100, 0.5, energy)
+            _, v, _ = md.state()
+            ke = 0.5 * float(np.sum(mass * v.cpu().numpy() ** 2)) * amu_A2_fs2_to_eV
+            t_ps.append(k * 0.5e-3)
+            tot.append(energy.item() + ke)
+        tot = np.array(tot)
+        slope = float(np.polyfit(np.array(t_ps), tot, 1)[0])
+        _, rebuilds, violations = md.stats()
+        out[name] = {"max_dev_meV_per_atom": 1e3 * float(np.abs(tot - tot[0]).max()) / b.n_atoms,
+                     "drift_meV_per_atom_per_ps": 1e3 * slope / b.n_atoms,
+                     "rebuilds": rebuilds, "skin_violations": violations}
+        md.close()
+        m.close()
+        log(f"NVE {name}: max |dE| {out[name]['max_dev_meV_per_atom']:.4f} meV/atom, drift "
+            f"{out[name]['drift_meV_per_atom_per_ps']:.4f} meV/atom/ps")
+    return out
+
+
 def grad_run(e3, synth, torch, dev, reps, log, cpu_baseline=True):
     """Training step of the differentiation batch (64 periodic boxes of 20-200
     atoms, 5 species, l_max 3, 64 channels, 2 layers, FP32): loss = energy MSE
@@ -636,6 +678,8 @@ def main():
     ap.add_argument("--serving-steps", type=int, default=200, help="MD steps per serving request")
     ap.add_argument("--scale-steps", type=int, default=20,
                     help="timed steps of the 100,000-atom box (a rebuild falls inside from 20 on)")
+    ap.add_argument("--nve-only", action="store_true",
+                    help="only run the NVE energy-conservation measurement (--steps steps, FP32 and BF16)")
     ap.add_argument("--grad-only", action="store_true",
                     help="only run the differentiation-batch measurement (loss + parameter gradients)")
     ap.add_argument("--coulomb-only", action="store_true",
@@ -673,6 +717,9 @@ def main():
     if args.scale_only:
         print(json.dumps({"scale": scale_run(e3, synth, torch, dev, args.steps, args.warmup, log,
                                              not args.no_cpu_baseline)}), flush=True)
+        return
+    if args.nve_only:
+        print(json.dumps({"nve": nve_run(e3, synth, torch, dev, args.atoms, args.steps, log)}), flush=True)
         return
     if args.grad_only:
         print(json.dumps({"grad": grad_run(e3, synth, torch, dev, args.steps, log, not args.no_cpu_baseline)}),
@@ -812,6 +859,7 @@ def main():
                          "barostat": "Langevin 300 K, friction 0.01/fs, volume move every 25 steps at 1 bar",
                          "proposals": prop, "accepted": acc}
         mdp.close()
+        extras["nve"] = nve_run(e3, synth, torch, dev, args.atoms, 2000, log)
         extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, args.serving_steps, log)
         extras["coulomb"] = coulomb_run(e3, synth, torch, dev, max(20, args.steps // 2), args.warmup, log)
         extras["product"] = product_run(e3, synth, torch, dev, args.atoms, max(20, args.steps // 4), args.warmup, log)
