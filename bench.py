@@ -347,6 +347,56 @@ def nve_run(e3, synth, torch, dev, n_atoms, steps, log):
     return out
 
 
+def capture_run(e3, synth, torch, dev, reps, log):
+    """Launch-bound small inputs: energy+forces of the 24-atom cluster (l_max
+    2, 32 channels) and of a 100-atom periodic box (the benchmark model),
+    eager against a HIP graph of the allocation-free entry point replayed on
+    the same buffers; microseconds per evaluation."""
+    import ctypes
+    from paper_2605_22698_amd import _lib
+    out = {}
+    cases = [("tiny_24_atoms", synth.tiny_config()),
+             ("box_100_atoms", (synth.single_config(n=3000)[0],
+                                synth.jittered_lattice(100, 0.1, 0.3, 4, np.random.default_rng(7))))]
+    for name, (cfg, b) in cases:
+        m = e3.Model(cfg.to_json(), synth.flatten_weights(cfg, synth.model_weights(cfg, 1)), device=dev)
+        pos = torch.tensor(b.pos, dtype=torch.float64, device=dev)
+        sp = torch.tensor(b.species, dtype=torch.int32, device=dev)
+        g = m.build_graph(b.offsets, pos, sp, b.cell, b.pbc, cfg.cutoff, 1.0)
+        E = torch.empty(b.n_structures, dtype=torch.float64, device=dev)
+        F = torch.empty((b.n_atoms, 3), dtype=torch.float32, device=dev)
+
+        def static_call():
+            _lib.check(_lib.lib().e3mi_energy_forces_static(
+                m.handle, g.handle, _lib.ptr(pos), _lib.ptr(E), _lib.ptr(F), None,
+                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        static_call()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            with torch.cuda.graph(graph, stream=st):
+                static_call()
+        torch.cuda.current_stream().wait_stream(st)
+        torch.cuda.synchronize()
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return 1e6 * (time.perf_counter() - t1) / reps
+        out[name] = {"atoms": b.n_atoms, "eager_us": timed(lambda: m.energy_forces(g, pos)),
+                     "graph_replay_us": timed(graph.replay)}
+        g.close()
+        m.close()
+        log(f"{name}: eager {out[name]['eager_us']:.1f} us, graph replay {out[name]['graph_replay_us']:.1f} us")
+    return out
+
+
 def grad_run(e3, synth, torch, dev, reps, log, cpu_baseline=True):
     """Training step of the differentiation batch (64 periodic boxes of 20-200
     atoms, 5 species, l_max 3, 64 channels, 2 layers, FP32): loss = energy MSE
@@ -678,6 +728,8 @@ def main():
     ap.add_argument("--serving-steps", type=int, default=200, help="MD steps per serving request")
     ap.add_argument("--scale-steps", type=int, default=20,
                     help="timed steps of the 100,000-atom box (a rebuild falls inside from 20 on)")
+    ap.add_argument("--capture-only", action="store_true",
+                    help="only run the small-input eager / graph-replay measurement")
     ap.add_argument("--nve-only", action="store_true",
                     help="only run the NVE energy-conservation measurement (--steps steps, FP32 and BF16)")
     ap.add_argument("--grad-only", action="store_true",
@@ -717,6 +769,9 @@ def main():
     if args.scale_only:
         print(json.dumps({"scale": scale_run(e3, synth, torch, dev, args.steps, args.warmup, log,
                                              not args.no_cpu_baseline)}), flush=True)
+        return
+    if args.capture_only:
+        print(json.dumps({"launch_bound": capture_run(e3, synth, torch, dev, 200, log)}), flush=True)
         return
     if args.nve_only:
         print(json.dumps({"nve": nve_run(e3, synth, torch, dev, args.atoms, args.steps, log)}), flush=True)
@@ -860,6 +915,7 @@ def main():
                          "proposals": prop, "accepted": acc}
         mdp.close()
         extras["nve"] = nve_run(e3, synth, torch, dev, args.atoms, 2000, log)
+        extras["launch_bound"] = capture_run(e3, synth, torch, dev, 200, log)
         extras["serving"] = serving_run(e3, synth, torch, dev, args.serving_requests, args.serving_steps, log)
         extras["coulomb"] = coulomb_run(e3, synth, torch, dev, max(20, args.steps // 2), args.warmup, log)
         extras["product"] = product_run(e3, synth, torch, dev, args.atoms, max(20, args.steps // 4), args.warmup, log)
