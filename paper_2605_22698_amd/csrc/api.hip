@@ -192,6 +192,10 @@ inline int stage_id(Stage s, int layer = 0) { return (int)s * 8 + layer; }
 // ---- model -----------------------------------------------------------------------
 struct LayerWeights {
   DevBuf rad1, rad2, rad2T, rad3, rad3T, rad3u;
+  DevBuf rad2b, rad2Tb, rad3Tb, rad3ub;  // BF16 copies for the BF16 mode (see RadialBf16)
+  RadialBf16 bf16_view() const {
+    return RadialBf16{rad2Tb.as<__bf16>(), rad2b.as<__bf16>(), rad3Tb.as<__bf16>(), rad3ub.as<__bf16>()};
+  }
   DevBuf mix[4], mixT[4], self_[4], selfT[4];
   DevBuf sym1, sym2, lin[4], linT[4];  // product block
 };
@@ -315,6 +319,15 @@ std::unique_ptr<DevBuf> upload(Allocator* a, const void* host, size_t bytes) {
 
 std::unique_ptr<DevBuf> upload_f32(Allocator* a, const std::vector<float>& v) {
   return upload(a, v.data(), v.size() * sizeof(float));
+}
+
+// FP32 -> BF16 bits, rounded to nearest even (finite inputs; weights are
+// checked finite on upload)
+uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, sizeof(u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
 }
 
 std::vector<float> transpose(const std::vector<float>& m, int rows, int cols) {
@@ -1031,12 +1044,14 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     ta.N = N;
     ta.C = C;
     ta.inv_nu = inv_nu;
+    const RadialBf16 bfw = W.bf16_view();
     for (const RChunk& ch : chunks) {
       void* Rc = chunk_r(w, t, R, ch, PCu, lr_bf16 ? 2 : 4);
       {
         ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
         launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
-                          W.rad3.as<float>(), L.p_full * C, PCu, Rc, lr_bf16, rc, p_env, bf16, st, ch.e0, ch.e1);
+                          W.rad3.as<float>(), L.p_full * C, PCu, Rc, lr_bf16, rc, p_env, bf16, st, ch.e0, ch.e1,
+                          &bfw);
       }
       set_chunk(ta, ch);
       ta.R = static_cast<const float*>(Rc);
@@ -1257,6 +1272,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     // pass kept only the last chunk), unless it was kept whole
     const std::vector<RChunk> chunks = r_chunks(M, G, PCu, st);
     const bool recompute = chunks.size() > 1 && !w.r_whole[t];
+    const RadialBf16 bfw = W.bf16_view();
     ta.rev = G->rev_x->as<int>();
     // scalar-output layer: the sender-side adjoint gives dR, dY and dh in one
     // pass (chunk by chunk: a chunk's receivers are the senders whose rows it holds)
@@ -1268,7 +1284,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
           ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
           launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                             W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->p, r_bf16, rc, p_env, bf16, st, ch.e0,
-                            ch.e1);
+                            ch.e1, &bfw);
         }
         set_chunk(ta, ch);
         TpArgs ts = ta;
@@ -1280,14 +1296,14 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
         ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
         launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                           W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->p, r_bf16, w.dY->as<float>(), g,
-                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1);
+                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1, &bfw);
         continue;
       }
       if (recompute) {
         ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
         launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                           W.rad3.as<float>(), L.p_full * C, PCu, w.R[t]->p, r_bf16, rc, p_env, bf16, st, ch.e0,
-                          ch.e1);
+                          ch.e1, &bfw);
       }
       set_chunk(ta, ch);
       ta.tag = (int)(++w.msg_tag & 0x7fffffffu);
@@ -1299,7 +1315,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
         ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
         launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                           W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->p, r_bf16, w.dY->as<float>(), g,
-                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1);
+                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1, &bfw);
       }
       if (t > 1) {
         ProfScope ps(&M->prof, stage_id(kTpBwdNode, t), st);
@@ -1436,7 +1452,8 @@ void upload_weights(e3mi_model* M, const double* wts) {
     if ((int)M->lw.size() < t) {
       M->plans.push_back(L);
       auto Wn = std::make_unique<LayerWeights>();
-      for (DevBuf* b : {&Wn->rad1, &Wn->rad2, &Wn->rad2T, &Wn->rad3, &Wn->rad3T, &Wn->rad3u, &Wn->sym1, &Wn->sym2})
+      for (DevBuf* b : {&Wn->rad1, &Wn->rad2, &Wn->rad2T, &Wn->rad3, &Wn->rad3T, &Wn->rad3u, &Wn->rad2b, &Wn->rad2Tb,
+                        &Wn->rad3Tb, &Wn->rad3ub, &Wn->sym1, &Wn->sym2})
         b->a = a;
       for (int l = 0; l < 4; ++l)
         Wn->mix[l].a = Wn->mixT[l].a = Wn->self_[l].a = Wn->selfT[l].a = Wn->lin[l].a = Wn->linT[l].a = a;
@@ -1446,6 +1463,12 @@ void upload_weights(e3mi_model* M, const double* wts) {
     auto up = [&](DevBuf& b, const std::vector<float>& v) {
       b.ensure(v.size() * sizeof(float));
       E3MI_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
+    };
+    auto up16 = [&](DevBuf& b, const std::vector<float>& v) {
+      std::vector<uint16_t> h(v.size());
+      for (size_t k = 0; k < v.size(); ++k) h[k] = bf16_rne(v[k]);
+      b.ensure(h.size() * sizeof(uint16_t));
+      E3MI_HIP(hipMemcpy(b.p, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
     };
     const auto r1 = take((size_t)c.n_basis * H);
     const auto r2 = take((size_t)H * H);
@@ -1465,6 +1488,19 @@ void upload_weights(e3mi_model* M, const double* wts) {
       for (int col = 0; col < L.p_used * C; ++col)
         r3u[(size_t)k * L.p_used * C + col] = r3[(size_t)k * L.p_full * C + col];
     up(W->rad3u, r3u);
+    // BF16 copies (round to nearest even, as the device's conversion does)
+    up16(W->rad2b, r2);
+    up16(W->rad2Tb, transpose(r2, H, H));
+    up16(W->rad3Tb, r3t);
+    {
+      // W3 (used columns) in slabs of 32 columns: [PC / 32][64][32]
+      const int PCu = L.p_used * C;
+      std::vector<float> r3s((size_t)H * PCu);
+      for (int q = 0; q < H; ++q)
+        for (int col = 0; col < PCu; ++col)
+          r3s[((size_t)(col / 32) * H + q) * 32 + col % 32] = r3u[(size_t)q * PCu + col];
+      up16(W->rad3ub, r3s);
+    }
     for (int l3 = 0; l3 <= c.lmax; ++l3) {
       const int P3 = L.p_full_l3[l3];
       const auto m = take((size_t)P3 * C * C);

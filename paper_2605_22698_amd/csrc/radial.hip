@@ -47,77 +47,92 @@ __device__ __forceinline__ void layer1(const float (*Bs)[NB + 1], const float* _
 }
 
 // acc (32x32 block of the wave) = X[rb:rb+32, :] * W[:, cb:cb+32], K = 64,
-// X from LDS, W row-major [64][ldw] from global memory. BF: both operands
-// rounded to BF16 (nearest even) and multiplied on v_mfma_f32_32x32x16_bf16
-// (lane l supplies A[l%32][8 (l/32) .. +8] and B[8 (l/32) .. +8][l%32]),
-// FP32 accumulation either way.
-template <bool BF>
+// X from LDS, W row-major [64][ldw] from global memory, on the FP32 matrix
+// cores.
 __device__ __forceinline__ f32x16 block_64(const float (*X)[kLd], int rb, const float* __restrict__ W, int ldw, int cb) {
   const int lane = threadIdx.x & 63;
   f32x16 acc = {};
-  if constexpr (BF) {
-#pragma unroll
-    for (int kb = 0; kb < kH; kb += 16) {
-      const int k0 = kb + 8 * (lane >> 5);
-      bf16x8 a, b;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        a[q] = (__bf16)X[rb + (lane & 31)][k0 + q];
-        b[q] = (__bf16)W[(k0 + q) * ldw + cb + (lane & 31)];
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    }
-  } else {
 #pragma unroll 8
-    for (int kk = 0; kk < kH; kk += 2) {
-      const float a = X[rb + (lane & 31)][kk + (lane >> 5)];
-      const float b = W[(kk + (lane >> 5)) * ldw + cb + (lane & 31)];
-      acc = mfma32(a, b, acc);
-    }
+  for (int kk = 0; kk < kH; kk += 2) {
+    const float a = X[rb + (lane & 31)][kk + (lane >> 5)];
+    const float b = W[(kk + (lane >> 5)) * ldw + cb + (lane & 31)];
+    acc = mfma32(a, b, acc);
   }
   return acc;
 }
 
 // Two 32x32 row blocks (rows 0-31 and 32-63 of X) times W[:, cc:cc+32], K = 64.
-template <bool BF>
 __device__ __forceinline__ void block_64x2(const float (*X)[kLd], const float* __restrict__ W, int ldw, int cc,
                                            f32x16& a0, f32x16& a1) {
   const int lane = threadIdx.x & 63;
   a0 = f32x16{};
   a1 = f32x16{};
-  if constexpr (BF) {
-#pragma unroll
-    for (int kb = 0; kb < kH; kb += 16) {
-      const int k0 = kb + 8 * (lane >> 5);
-      bf16x8 x0, x1, b;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        b[q] = (__bf16)W[(k0 + q) * ldw + cc + (lane & 31)];
-        x0[q] = (__bf16)X[lane & 31][k0 + q];
-        x1[q] = (__bf16)X[32 + (lane & 31)][k0 + q];
-      }
-      a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, b, a0, 0, 0, 0);
-      a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, b, a1, 0, 0, 0);
-    }
-  } else {
 #pragma unroll 8
-    for (int kk = 0; kk < kH; kk += 2) {
-      const float b = W[(kk + (lane >> 5)) * ldw + cc + (lane & 31)];
-      a0 = mfma32(X[lane & 31][kk + (lane >> 5)], b, a0);
-      a1 = mfma32(X[32 + (lane & 31)][kk + (lane >> 5)], b, a1);
-    }
+  for (int kk = 0; kk < kH; kk += 2) {
+    const float b = W[(kk + (lane >> 5)) * ldw + cc + (lane & 31)];
+    a0 = mfma32(X[lane & 31][kk + (lane >> 5)], b, a0);
+    a1 = mfma32(X[32 + (lane & 31)][kk + (lane >> 5)], b, a1);
   }
+}
+
+// The BF16 mode's products: operands rounded to BF16 (nearest even) and
+// multiplied on v_mfma_f32_32x32x16_bf16 (lane l supplies A[l%32][8 (l/32) ..
+// +8] and B[8 (l/32) .. +8][l%32]), FP32 accumulation.
+// BF16 operands already rounded and laid out for the 32x32x16 steps: rows of
+// X in LDS as BF16 (row stride kLdb, 16-byte aligned), and the weights
+// transposed so that each output column's K values are contiguous (WT[col *
+// ldk + k]). Lane l then loads its 8 A and 8 B values with one 16-byte read
+// each; the values are the ones the conversions at use produce (round to
+// nearest even of the same FP32 numbers), so the results are the same.
+constexpr int kLdb = 72;
+__device__ __forceinline__ f32x16 block_64_bf(const __bf16 (*Xb)[kLdb], int rb, const __bf16* __restrict__ WT, int ldk,
+                                              int cb) {
+  const int lane = threadIdx.x & 63;
+  f32x16 acc = {};
+#pragma unroll
+  for (int kb = 0; kb < kH; kb += 16) {
+    const int k0 = kb + 8 * (lane >> 5);
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Xb[rb + (lane & 31)][k0]);
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(WT + (long)(cb + (lane & 31)) * ldk + k0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// rows 0-31 and 32-63 of Xb times the columns cc .. cc+31 of W (WT = W^T, K = 64)
+__device__ __forceinline__ void block_64x2_bf(const __bf16 (*Xb)[kLdb], const __bf16* __restrict__ WT, int cc,
+                                              f32x16& a0, f32x16& a1) {
+  const int lane = threadIdx.x & 63;
+  a0 = f32x16{};
+  a1 = f32x16{};
+#pragma unroll
+  for (int kb = 0; kb < kH; kb += 16) {
+    const int k0 = kb + 8 * (lane >> 5);
+    const bf16x8 b = *reinterpret_cast<const bf16x8*>(WT + (long)(cc + (lane & 31)) * kH + k0);
+    const bf16x8 x0 = *reinterpret_cast<const bf16x8*>(&Xb[lane & 31][k0]);
+    const bf16x8 x1 = *reinterpret_cast<const bf16x8*>(&Xb[32 + (lane & 31)][k0]);
+    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, b, a0, 0, 0, 0);
+    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, b, a1, 0, 0, 0);
+  }
+}
+
+// the 64 x 64 floats of X rounded into Xb (all 256 threads)
+__device__ __forceinline__ void to_bf16_tile(const float (*X)[kLd], __bf16 (*Xb)[kLdb]) {
+  for (int o = threadIdx.x; o < kTile * kH; o += 256) Xb[o >> 6][o & 63] = (__bf16)X[o >> 6][o & 63];
 }
 
 template <int NB, bool BF, class RS>
 __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W3, int ld3, int PC,
-                                                    RS* __restrict__ R, float rc, int p, int e_first, int e_end) {
+                                                    RS* __restrict__ R, float rc, int p, int e_first, int e_end,
+                                                    const __bf16* __restrict__ W2Tb,
+                                                    const __bf16* __restrict__ W3Tb) {
   // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); R is
-  // indexed from e_first
+  // indexed from e_first. BF: W2Tb = W2^T and W3Tb = W3^T (used columns) in BF16
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float H[kTile][kLd];
+  __shared__ __align__(16) __bf16 Hb[BF ? kTile : 1][kLdb];
   const int E = e_end >= 0 ? e_end : row_ptr_x[N];
   const int e0 = e_first + blockIdx.x * kTile;
   if (e0 >= E) return;
@@ -133,17 +148,33 @@ __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ d
   __syncthreads();
   layer1<NB>(Bs, W1, nullptr, H);
   __syncthreads();
+  if constexpr (BF) {
+    to_bf16_tile(H, Hb);
+    __syncthreads();
+  }
   {
     const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-    const f32x16 acc = block_64<BF>(H, rb, W2, kH, cb);
+    f32x16 acc;
+    if constexpr (BF)
+      acc = block_64_bf(Hb, rb, W2Tb, kH, cb);
+    else
+      acc = block_64(H, rb, W2, kH, cb);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) H[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(acc[r]);
+    for (int r = 0; r < 16; ++r) {
+      if constexpr (BF)
+        Hb[rb + acc_row(r, lane)][cb + (lane & 31)] = (__bf16)siluf(acc[r]);
+      else
+        H[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(acc[r]);
+    }
   }
   __syncthreads();
   for (int cc = w * 32; cc < PC; cc += 128) {
     f32x16 a0, a1;
-    block_64x2<BF>(H, W3, ld3, cc, a0, a1);
+    if constexpr (BF)
+      block_64x2_bf(Hb, W3Tb, cc, a0, a1);
+    else
+      block_64x2(H, W3, ld3, cc, a0, a1);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = acc_row(r, lane);
@@ -160,12 +191,18 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
                                                     const float* __restrict__ W2T, const float* __restrict__ W3T,
                                                     int PC, const RS* __restrict__ dR, const float* __restrict__ dY,
                                                     float4* __restrict__ g, int accumulate, float rc, int p,
-                                                    int e_first, int e_end) {
+                                                    int e_first, int e_end, const __bf16* __restrict__ W2Tb,
+                                                    const __bf16* __restrict__ W2b,
+                                                    const __bf16* __restrict__ W3ub) {
+  // BF: W2Tb = W2^T, W2b = W2 and W3ub = W3 (used columns) in BF16, W3 in
+  // slabs of 32 columns: W3ub[((c / 32) * 64 + q) * 32 + c % 32] = W3[q][c]
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float dBs[kTile][NB + 1];
   __shared__ float P2[kTile][kLd];
   __shared__ float X[kTile][kLd];
-  __shared__ float Ds[kTile][33];
+  __shared__ float Ds[BF ? 1 : kTile][33];
+  __shared__ __align__(16) __bf16 Xb[BF ? kTile : 1][kLdb];
+  __shared__ __align__(16) __bf16 Dsb[BF ? kTile : 1][40];
   // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); dR is
   // indexed from e_first, dY and g by edge
   const int E = e_end >= 0 ? e_end : row_ptr_x[N];
@@ -187,8 +224,16 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   __syncthreads();
   layer1<NB>(Bs, W1, nullptr, X);  // X = H1 (pre1 is recomputed at the end)
   __syncthreads();
+  if constexpr (BF) {
+    to_bf16_tile(X, Xb);
+    __syncthreads();
+  }
   {
-    const f32x16 acc = block_64<BF>(X, rb, W2, kH, cb);
+    f32x16 acc;
+    if constexpr (BF)
+      acc = block_64_bf(Xb, rb, W2Tb, kH, cb);
+    else
+      acc = block_64(X, rb, W2, kH, cb);
 #pragma unroll
     for (int r = 0; r < 16; ++r) P2[rb + acc_row(r, lane)][cb + (lane & 31)] = acc[r];
   }
@@ -216,14 +261,27 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   load_slab(0);
   for (int kc = 0; kc < PC; kc += 32) {
     __syncthreads();
-    Ds[srow][sc8] = p0.x;
-    Ds[srow][sc8 + 1] = p0.y;
-    Ds[srow][sc8 + 2] = p0.z;
-    Ds[srow][sc8 + 3] = p0.w;
-    Ds[srow][sc8 + 4] = p1.x;
-    Ds[srow][sc8 + 5] = p1.y;
-    Ds[srow][sc8 + 6] = p1.z;
-    Ds[srow][sc8 + 7] = p1.w;
+    if constexpr (BF) {
+      bf16x8 v;
+      v[0] = (__bf16)p0.x;
+      v[1] = (__bf16)p0.y;
+      v[2] = (__bf16)p0.z;
+      v[3] = (__bf16)p0.w;
+      v[4] = (__bf16)p1.x;
+      v[5] = (__bf16)p1.y;
+      v[6] = (__bf16)p1.z;
+      v[7] = (__bf16)p1.w;
+      *reinterpret_cast<bf16x8*>(&Dsb[srow][sc8]) = v;
+    } else {
+      Ds[srow][sc8] = p0.x;
+      Ds[srow][sc8 + 1] = p0.y;
+      Ds[srow][sc8 + 2] = p0.z;
+      Ds[srow][sc8 + 3] = p0.w;
+      Ds[srow][sc8 + 4] = p1.x;
+      Ds[srow][sc8 + 5] = p1.y;
+      Ds[srow][sc8 + 6] = p1.z;
+      Ds[srow][sc8 + 7] = p1.w;
+    }
     float wcur[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) wcur[i] = wb[i];
@@ -233,12 +291,8 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
 #pragma unroll
       for (int kb = 0; kb < 32; kb += 16) {
         const int k0 = kb + 8 * (lane >> 5);
-        bf16x8 a, b;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          a[q] = (__bf16)Ds[rb + (lane & 31)][k0 + q];
-          b[q] = (__bf16)W3T[(kc + k0 + q) * kH + cb + (lane & 31)];
-        }
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Dsb[rb + (lane & 31)][k0]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(W3ub + ((long)(kc >> 5) * kH + cb + (lane & 31)) * 32 + k0);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
       }
     } else {
@@ -251,12 +305,20 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
-    X[row][col] = acc[r] * silu_grad(P2[row][col]);
+    const float v = acc[r] * silu_grad(P2[row][col]);
+    if constexpr (BF)
+      Xb[row][col] = (__bf16)v;
+    else
+      X[row][col] = v;
   }
   __syncthreads();
   {
     // dH1 = dpre2 W2^T ; dpre1 = dH1 * silu'(pre1) -> P2
-    const f32x16 a2 = block_64<BF>(X, rb, W2T, kH, cb);
+    f32x16 a2;
+    if constexpr (BF)
+      a2 = block_64_bf(Xb, rb, W2b, kH, cb);
+    else
+      a2 = block_64(X, rb, W2T, kH, cb);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
@@ -368,8 +430,8 @@ __global__ void __launch_bounds__(256) k_radial_dual_fwd(const float4* __restric
   __syncthreads();
   {
     const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-    const f32x16 a = block_64<false>(X, rb, W2, kH, cb);
-    const f32x16 ad = block_64<false>(Xt, rb, W2, kH, cb);
+    const f32x16 a = block_64(X, rb, W2, kH, cb);
+    const f32x16 ad = block_64(Xt, rb, W2, kH, cb);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -463,8 +525,8 @@ __global__ void __launch_bounds__(256) k_radial_dual_bwd(const int* __restrict__
     Xc[row][col] = pc;
   }
   __syncthreads();
-  const f32x16 hb = block_64<false>(X, rb, W2T, kH, cb);
-  const f32x16 hc = block_64<false>(Xc, rb, W2T, kH, cb);
+  const f32x16 hb = block_64(X, rb, W2T, kH, cb);
+  const f32x16 hc = block_64(Xc, rb, W2T, kH, cb);
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = rb + acc_row(r, lane), col = cb + (lane & 31);
@@ -486,60 +548,64 @@ inline int tiles(long n) { return (int)((n + kTile - 1) / kTile); }
 
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
                        const float* W2, const float* W3, int ld3, int PC, void* R, bool r_bf16, float rc, int p,
-                       bool bf16, hipStream_t st, int e_first, int e_end) {
+                       bool bf16, hipStream_t st, int e_first, int e_end, const RadialBf16* wb) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (PC % 32) throw Error(E3MI_EUNSUPPORTED, "paths x channels must be a multiple of 32");
+  if (r_bf16 && !bf16) throw Error(E3MI_EINVAL, "BF16 radial weights need the BF16 mode");
+  if (bf16 && !(wb && wb->W2T && wb->W3T)) throw Error(E3MI_EINVAL, "BF16 mode: BF16 radial weights missing");
   const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
   if (grid == 0) return;
-  if (r_bf16 && bf16)
+  if (r_bf16)
     k_radial_fwd<8, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
-                                                        static_cast<__bf16*>(R), rc, p, e_first, e_end);
-  else if (r_bf16)
-    throw Error(E3MI_EINVAL, "BF16 radial weights need the BF16 mode");
+                                                        static_cast<__bf16*>(R), rc, p, e_first, e_end, wb->W2T,
+                                                        wb->W3T);
   else if (bf16)
     k_radial_fwd<8, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
-                                                       static_cast<float*>(R), rc, p, e_first, e_end);
+                                                       static_cast<float*>(R), rc, p, e_first, e_end, wb->W2T,
+                                                       wb->W3T);
   else
     k_radial_fwd<8, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
-                                                        static_cast<float*>(R), rc, p, e_first, e_end);
+                                                        static_cast<float*>(R), rc, p, e_first, e_end, nullptr,
+                                                        nullptr);
 }
 
 template <int LMAX>
 static void radial_bwd_l(bool bf16, bool r_bf16, long e_cap, const float4* dvec, const int* row_ptr_x, int N,
                          const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
                          const float* dY, float4* g, int accumulate, float rc, int p, hipStream_t st, int e_first,
-                         int e_end) {
+                         int e_end, const RadialBf16* wb) {
   const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
   if (grid == 0) return;
-  if (r_bf16 && bf16)
+  if (r_bf16)
     k_radial_bwd<8, LMAX, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
                                                               static_cast<const __bf16*>(dR), dY, g, accumulate, rc,
-                                                              p, e_first, e_end);
-  else if (r_bf16)
-    throw Error(E3MI_EINVAL, "BF16 radial weights need the BF16 mode");
+                                                              p, e_first, e_end, wb->W2T, wb->W2, wb->W3u);
   else if (bf16)
     k_radial_bwd<8, LMAX, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
                                                              static_cast<const float*>(dR), dY, g, accumulate, rc, p,
-                                                             e_first, e_end);
+                                                             e_first, e_end, wb->W2T, wb->W2, wb->W3u);
   else
     k_radial_bwd<8, LMAX, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
                                                               static_cast<const float*>(dR), dY, g, accumulate, rc,
-                                                              p, e_first, e_end);
+                                                              p, e_first, e_end, nullptr, nullptr, nullptr);
 }
 
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
                        bool r_bf16, const float* dY, float4* g, int accumulate, float rc, int p, bool bf16,
-                       hipStream_t st, int e_first, int e_end) {
+                       hipStream_t st, int e_first, int e_end, const RadialBf16* wb) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
+  if (r_bf16 && !bf16) throw Error(E3MI_EINVAL, "BF16 radial weights need the BF16 mode");
+  if (bf16 && !(wb && wb->W2T && wb->W2 && wb->W3u))
+    throw Error(E3MI_EINVAL, "BF16 mode: BF16 radial weights missing");
   if (lmax == 3)
     radial_bwd_l<3>(bf16, r_bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st,
-                    e_first, e_end);
+                    e_first, e_end, wb);
   else if (lmax == 2)
     radial_bwd_l<2>(bf16, r_bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st,
-                    e_first, e_end);
+                    e_first, e_end, wb);
   else
     throw Error(E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
 }

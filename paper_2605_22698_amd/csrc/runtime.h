@@ -351,13 +351,23 @@ void launch_coulomb_dq(const int64_t* off, const int* owner, int S, int N, const
 
 // ---- radial MLP (radial.hip) ---------------------------------------------------------
 // R (dR) is FP32, or BF16 when r_bf16 is set
+// BF16 copies of a layer's radial weights (rounded to nearest even), laid out
+// for the BF16 matrix-core steps: W2^T and W2 [64][64], W3^T [PC][64] and W3
+// (used columns) in slabs of 32 columns, [PC / 32][64][32]. Needed when bf16
+// is set.
+struct RadialBf16 {
+  const __bf16* W2T = nullptr;
+  const __bf16* W2 = nullptr;
+  const __bf16* W3T = nullptr;
+  const __bf16* W3u = nullptr;
+};
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
                        const float* W2, const float* W3, int ld3, int PC, void* R, bool r_bf16, float rc, int p,
-                       bool bf16, hipStream_t st, int e_first = 0, int e_end = -1);
+                       bool bf16, hipStream_t st, int e_first = 0, int e_end = -1, const RadialBf16* wb = nullptr);
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
                        bool r_bf16, const float* dY, float4* g, int accumulate, float rc, int p, bool bf16,
-                       hipStream_t st, int e_first = 0, int e_end = -1);
+                       hipStream_t st, int e_first = 0, int e_end = -1, const RadialBf16* wb = nullptr);
 
 // ---- second-order passes (radial.hip, grad.hip) -------------------------------------
 void launch_radial_dual_fwd(int n_basis, const float4* dvec, const float4* dd, const int* row_ptr_x, int N, long e_cap,
