@@ -87,25 +87,30 @@ __device__ __forceinline__ void tile_geometry(const float4* __restrict__ dvec, c
                                               float (*Bs)[NB + 1], float (*dBs)[NB + 1],
                                               float (*Ys)[(L3 + 1) * (L3 + 1) + 1], int* sp) {
   constexpr int NC3 = (L3 + 1) * (L3 + 1);
-  const int t = threadIdx.x;
-  if (t < kTile) {
-    const int e = e0 + t;
-    const bool valid = e < e1;
-    const float4 d = valid ? dvec[e] : make_float4(0.f, 0.f, 1.f, rc);
+  // three waves in parallel: the basis (wave 0), the harmonics (wave 1) and
+  // the senders' species (wave 2) of the tile's 64 edges
+  const int t = threadIdx.x, te = t & 63, part = t >> 6;
+  const int e = e0 + te;
+  const bool valid = e < e1;
+  if (part == 0) {
+    const float r = valid ? dvec[e].w : rc;
     float b[NB], db[NB];
-    radial_basis<NB>(d.w, rc, p, b, dBs ? db : nullptr);
+    radial_basis<NB>(r, rc, p, b, dBs ? db : nullptr);
 #pragma unroll
     for (int n = 0; n < NB; ++n) {
-      Bs[t][n] = b[n];
-      if (dBs) dBs[t][n] = db[n];
+      Bs[te][n] = b[n];
+      if (dBs) dBs[te][n] = db[n];
     }
+  } else if (part == 1) {
+    const float4 d = valid ? dvec[e] : make_float4(0.f, 0.f, 1.f, rc);
     float Y[(LMAX + 1) * (LMAX + 1)], CY[NC3];
     const float ir = 1.0f / d.w;
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
     cg_apply<L3>(Y, CY);
 #pragma unroll
-    for (int c = 0; c < NC3; ++c) Ys[t][c] = valid ? CY[c] : 0.0f;
-    sp[t] = valid ? species[src[e]] : 0;
+    for (int c = 0; c < NC3; ++c) Ys[te][c] = valid ? CY[c] : 0.0f;
+  } else if (part == 2) {
+    sp[te] = valid ? species[src[e]] : 0;
   }
 }
 
