@@ -283,10 +283,18 @@ __device__ __forceinline__ void radial_basis(float r, float rc, int p, float* B,
   const float pref = sqrtf(2.0f / rc);
   const float inv_r = 1.0f / r;
   const float w = 3.14159265358979f / rc;
+  // sin and cos of (n + 1) w r by angle addition from those of w r (one
+  // sincosf per edge instead of one per basis function)
+  float s1, c1;
+  sincosf(w * r, &s1, &c1);
+  float s = s1, c = c1;
 #pragma unroll
   for (int n = 0; n < NB; ++n) {
-    float s, c;
-    sincosf((n + 1) * w * r, &s, &c);
+    if (n > 0) {
+      const float sn = s * c1 + c * s1;
+      c = c * c1 - s * s1;
+      s = sn;
+    }
     const float b = pref * s * inv_r;
     B[n] = b * u;
     if (dB) {
