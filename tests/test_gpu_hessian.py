@@ -144,3 +144,32 @@ def test_product_block_against_oracle(lmax, C, layers):
         v = rng.normal(size=b.pos.shape)
         _check(_hv(m, b, v, skin=0.5), om.hessian_vector(om.Model(cfg, w), b, v),
                f"product block lmax {lmax} C {C} layers {layers} v{k}")
+
+
+@pytest.mark.parametrize("correlation", [1, 2])
+def test_isolated_atom_and_empty_structure(correlation):
+    # degenerate inputs of the second-order pass: an empty structure, and a
+    # structure with an isolated atom beside a small cluster; the Hessian-vector
+    # product against the oracle (zero rows for the isolated atom) and the
+    # parameter gradient finite
+    import torch
+    cfg = synth.ModelConfig(lmax=2, channels=32, layers=2, n_species=3, cutoff=5.0, avg_neighbors=10.0,
+                            correlation=correlation)
+    rng = np.random.default_rng(150)
+    cl = synth.uniform_cluster(8, 5.0, 1.0, 3, rng)
+    pos = np.concatenate([cl.pos, [[40.0, 40.0, 40.0]]])
+    sp = np.concatenate([cl.species, [1]]).astype(np.int32)
+    cells = (np.eye(3) * 100.0)[None].repeat(2, axis=0)
+    b = synth.Batch(pos, sp, cells, np.zeros((2, 3), np.uint8), np.array([0, 0, len(pos)]))
+    m = model(cfg, 151)
+    v = rng.normal(size=pos.shape)
+    hv = _hv(m, b, v)
+    ref = om.hessian_vector(om.Model(cfg, synth.model_weights(cfg, 151)), b, v)
+    _check(hv, ref, f"isolated atom, correlation {correlation}")
+    assert np.all(hv[-1] == 0.0)
+    g, posd = _graph(m, b)
+    gE = torch.ones(2, dtype=torch.float64, device=device())
+    gF = torch.tensor(v, dtype=torch.float32, device=device())
+    grad = m.param_grad(g, posd, gE, gF)
+    torch.cuda.synchronize()
+    assert torch.isfinite(grad).all()
