@@ -243,6 +243,17 @@ int e3mi_hessian_vectors(e3mi_model* model, e3mi_graph* graph, const double* pos
  *     4 is set. */
 #define E3MI_FLAG_UNFUSED_LAST_LAYER 2
 #define E3MI_FLAG_FUSED_LAST_LAYER 4
+/*   An edge and its reverse have exactly opposite vectors (the same FP64
+ *     difference of the two positions plus the image shift, negated), so
+ *     equal lengths and equal radial weights R. By default a layer whose edges are all in
+ *     memory at once (one receiver chunk) runs its radial MLP once per edge
+ *     pair, writing R to both edges' rows (the same bits as edge by edge),
+ *     and its adjoint once per pair on the sum of the two edges' dR (forces
+ *     agree with the edge-by-edge adjoint to rounding).
+ *   E3MI_FLAG_RADIAL_PER_EDGE (8) runs both per edge instead, as layers in
+ *     receiver chunks always do; results are then bitwise those of any
+ *     chunking. */
+#define E3MI_FLAG_RADIAL_PER_EDGE 8
 int e3mi_model_set_flags(e3mi_model* model, int flags);
 
 /* Most bytes of per-edge radial weights R (and of their adjoint) that an

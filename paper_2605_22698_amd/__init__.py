@@ -76,10 +76,10 @@ class Model:
         return ms.value, n.value
 
     def set_flags(self, unfactorised_first_layer: bool = False, unfused_last_layer: bool = False,
-                  fused_last_layer: bool = False) -> None:
+                  fused_last_layer: bool = False, radial_per_edge: bool = False) -> None:
         """Evaluation options; see e3mi_model_set_flags."""
         flags = (1 if unfactorised_first_layer else 0) | (2 if unfused_last_layer else 0) | \
-            (4 if fused_last_layer else 0)
+            (4 if fused_last_layer else 0) | (8 if radial_per_edge else 0)
         check(lib().e3mi_model_set_flags(self.handle, flags))
 
     def set_r_chunk_bytes(self, n_bytes: int) -> None:

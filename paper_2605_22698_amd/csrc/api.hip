@@ -241,6 +241,7 @@ struct e3mi_model {
   // first layer factorised by species: U_l [S*64, C] and U_l^T [C, S*64] per output order
   bool first_factorised = true;
   bool last_fused = false;  // per-edge last layer by default (faster here); flag 4 selects the fused one
+  bool edge_pairs = true;   // radial MLP and its adjoint once per edge pair (single-chunk layers); flag 8 clears
   size_t r_chunk_bytes = size_t(8) << 30;  // most bytes of per-edge R (and dR) held at once
   // most bytes of per-edge R kept whole, summed over the layers that run in
   // receiver chunks: such a layer's adjoint then reads R instead of recomputing it
@@ -260,6 +261,8 @@ struct e3mi_graph {
   std::vector<uint8_t> pbc_h;
   std::unique_ptr<e3mi::DevBuf> off_d, owner, box_d, pbc_d, species, row_ptr, src, shift, rev, keys;
   std::unique_ptr<e3mi::DevBuf> cnt, row_ptr_x, src_x, dvec_x, old_idx, new_idx, rev_x, x_ref;
+  // edges that own their pair {e, rev(e)} (pruned list), per receiver and in edge order
+  std::unique_ptr<e3mi::DevBuf> own_cnt, own_ptr, own;
   // electrostatics: total charge per structure, and (structure, first atom) per 64-atom tile
   std::unique_ptr<e3mi::DevBuf> charge, ctiles;
   int n_ctiles = 0, c_waves = 1;
@@ -464,6 +467,9 @@ void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
   ensure(G->old_idx, a, sizeof(int) * (E + 1));
   ensure(G->new_idx, a, sizeof(int) * (E + 1));
   ensure(G->rev_x, a, sizeof(int) * (E + 1));
+  ensure(G->own_cnt, a, sizeof(int) * (N + 1));
+  ensure(G->own_ptr, a, sizeof(int) * (N + 1));
+  ensure(G->own, a, sizeof(int) * (E + 1));
   ensure(G->x_ref, a, sizeof(double) * 3 * (N + 1));
   if (N) E3MI_HIP(hipMemcpyAsync(G->x_ref->p, pos, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
 }
@@ -561,7 +567,7 @@ void prune(e3mi_graph* G, const double* pos, hipStream_t st) {
                        G->shift->as<int>(), G->row_ptr_x->as<int>(), N, rc2, G->src_x->as<int>(),
                        G->dvec_x->as<float4>(), G->old_idx->as<int>(), G->new_idx->as<int>(), st);
   launch_prune_rev(G->row_ptr_x->as<int>(), N, G->old_idx->as<int>(), G->new_idx->as<int>(), G->rev->as<int>(),
-                   G->rev_x->as<int>(), st);
+                   G->rev_x->as<int>(), G->own_cnt->as<int>(), G->own_ptr->as<int>(), G->own->as<int>(), st);
 }
 
 // Channels per thread of the tensor-product kernels (threads per receiver = C / cpt).
@@ -844,6 +850,15 @@ void* chunk_r(const Workspace& w, int t, void* R, const RChunk& ch, int PCu, siz
   return w.r_whole[t] && ch.e1 >= 0 ? static_cast<char*>(R) + (size_t)ch.e0 * PCu * elem : R;
 }
 
+// The pair owners of the pruned list, used by a layer's radial passes when
+// the model runs them per edge pair and the chunk is the whole edge list.
+EdgePairs graph_pairs(const e3mi_graph* G) {
+  return EdgePairs{G->own->as<int>(), G->own_ptr->as<int>() + G->N, G->rev_x->as<int>()};
+}
+const EdgePairs* pairs_for(const e3mi_model* M, const RChunk& ch, const EdgePairs& p) {
+  return M->edge_pairs && ch.e1 < 0 ? &p : nullptr;
+}
+
 void set_chunk(TpArgs& ta, const RChunk& ch) {
   ta.i0 = ch.e1 < 0 ? 0 : ch.i0;
   ta.n_recv = ch.e1 < 0 ? 0 : ch.i1 - ch.i0;
@@ -1045,13 +1060,14 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     ta.C = C;
     ta.inv_nu = inv_nu;
     const RadialBf16 bfw = W.bf16_view();
+    const EdgePairs prs = graph_pairs(G);
     for (const RChunk& ch : chunks) {
       void* Rc = chunk_r(w, t, R, ch, PCu, lr_bf16 ? 2 : 4);
       {
         ProfScope ps(&M->prof, stage_id(kRadialFwd, t), st);
         launch_radial_fwd(c.n_basis, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                           W.rad3.as<float>(), L.p_full * C, PCu, Rc, lr_bf16, rc, p_env, bf16, st, ch.e0, ch.e1,
-                          &bfw);
+                          &bfw, pairs_for(M, ch, prs));
       }
       set_chunk(ta, ch);
       ta.R = static_cast<const float*>(Rc);
@@ -1273,6 +1289,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     const std::vector<RChunk> chunks = r_chunks(M, G, PCu, st);
     const bool recompute = chunks.size() > 1 && !w.r_whole[t];
     const RadialBf16 bfw = W.bf16_view();
+    const EdgePairs prs = graph_pairs(G);
     ta.rev = G->rev_x->as<int>();
     // scalar-output layer: the sender-side adjoint gives dR, dY and dh in one
     // pass (chunk by chunk: a chunk's receivers are the senders whose rows it holds)
@@ -1296,7 +1313,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
         ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
         launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                           W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->p, r_bf16, w.dY->as<float>(), g,
-                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1, &bfw);
+                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1, &bfw, pairs_for(M, ch, prs));
         continue;
       }
       if (recompute) {
@@ -1315,7 +1332,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
         ProfScope ps(&M->prof, stage_id(kRadialBwd, t), st);
         launch_radial_bwd(c.n_basis, c.lmax, dvec, row_ptr, N, Ecap, W.rad1.as<float>(), W.rad2.as<float>(),
                           W.rad2T.as<float>(), W.rad3T.as<float>(), PCu, w.dR->p, r_bf16, w.dY->as<float>(), g,
-                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1, &bfw);
+                          t != T ? 1 : 0, rc, p_env, bf16, st, ch.e0, ch.e1, &bfw, pairs_for(M, ch, prs));
       }
       if (t > 1) {
         ProfScope ps(&M->prof, stage_id(kTpBwdNode, t), st);
@@ -2423,9 +2440,10 @@ int e3mi_model_set_r_keep_bytes(e3mi_model* model, size_t bytes) {
 int e3mi_model_set_flags(e3mi_model* model, int flags) {
   E3MI_API_BEGIN
   E3MI_REQUIRE(model, E3MI_EINVAL, "null model");
-  E3MI_REQUIRE((flags & ~7) == 0, E3MI_EINVAL, "unknown flag");
+  E3MI_REQUIRE((flags & ~15) == 0, E3MI_EINVAL, "unknown flag");
   model->first_factorised = (flags & 1) == 0;
   model->last_fused = (flags & 4) != 0 && (flags & 2) == 0;
+  model->edge_pairs = (flags & 8) == 0;
   E3MI_API_END
 }
 

@@ -363,11 +363,50 @@ __global__ void __launch_bounds__(256) k_prune_compact(const double* __restrict_
   }
 }
 
-__global__ void k_prune_rev(const int* __restrict__ row_ptr_x, int N, const int* __restrict__ old_idx,
-                            const int* __restrict__ new_idx, const int* __restrict__ rev_skin, int* __restrict__ rev_x) {
-  const int E = row_ptr_x[N];
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x)
-    rev_x[e] = new_idx[rev_skin[old_idx[e]]];
+// The pruned reverse index, and per receiver the number of edges that own
+// their pair: e owns {e, rev(e)} when e < rev(e), or alone when its reverse
+// is not listed. The two edges of a pair have exactly opposite vectors and
+// equal lengths, so a function of the length is computed once per owner.
+__device__ __forceinline__ bool owns_pair(int e, int re) { return re < 0 || e < re; }
+
+__global__ void __launch_bounds__(256) k_prune_rev(const int* __restrict__ row_ptr_x, int N,
+                                                   const int* __restrict__ old_idx, const int* __restrict__ new_idx,
+                                                   const int* __restrict__ rev_skin, int* __restrict__ rev_x,
+                                                   int* __restrict__ own_cnt) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;
+  const int a = row_ptr_x[i], b = row_ptr_x[i + 1];
+  int total = 0;
+  for (int base = a; base < b; base += 64) {
+    const int e = base + lane;
+    bool own = false;
+    if (e < b) {
+      const int re = new_idx[rev_skin[old_idx[e]]];
+      rev_x[e] = re;
+      own = owns_pair(e, re);
+    }
+    total += __popcll(__ballot(own));
+  }
+  if (lane == 0) own_cnt[i] = total;
+}
+
+// the owners in edge order: own[own_ptr[i] + k] = the k-th owner of row i
+__global__ void __launch_bounds__(256) k_pair_owners(const int* __restrict__ row_ptr_x, int N,
+                                                     const int* __restrict__ rev_x, const int* __restrict__ own_ptr,
+                                                     int* __restrict__ own) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= N) return;
+  const int a = row_ptr_x[i], b = row_ptr_x[i + 1];
+  int out = own_ptr[i];
+  for (int base = a; base < b; base += 64) {
+    const int e = base + lane;
+    const bool o = e < b && owns_pair(e, rev_x[e]);
+    const uint64_t m = __ballot(o);
+    if (o) own[out + __popcll(m & ((1ull << lane) - 1ull))] = e;
+    out += __popcll(m);
+  }
 }
 
 inline int blocks(long n, int t) { return (int)((n + t - 1) / t); }
@@ -434,8 +473,14 @@ void launch_prune_compact(const double* pos, const int* owner, const double* box
                                                               src_x, dvec_x, old_idx, new_idx);
 }
 void launch_prune_rev(const int* row_ptr_x, int N, const int* old_idx, const int* new_idx, const int* rev_skin,
-                      int* rev_x, hipStream_t st) {
-  k_prune_rev<<<1024, 256, 0, st>>>(row_ptr_x, N, old_idx, new_idx, rev_skin, rev_x);
+                      int* rev_x, int* own_cnt, int* own_ptr, int* own, hipStream_t st) {
+  if (N == 0) {
+    launch_exclusive_scan(own_cnt, own_ptr, 0, st);  // own_ptr[0] = 0
+    return;
+  }
+  k_prune_rev<<<blocks((long)N * 64, 256), 256, 0, st>>>(row_ptr_x, N, old_idx, new_idx, rev_skin, rev_x, own_cnt);
+  launch_exclusive_scan(own_cnt, own_ptr, N, st);
+  k_pair_owners<<<blocks((long)N * 64, 256), 256, 0, st>>>(row_ptr_x, N, rev_x, own_ptr, own);
 }
 
 }  // namespace e3mi

@@ -12,6 +12,15 @@
 // output blocks). The edge count is read on the device (row_ptr_x[N]); the
 // grid is sized for the skin-list capacity and surplus tiles exit at once.
 //
+// An edge and its reverse have exactly opposite vectors, so equal lengths and
+// equal R. With the pair owners of the pruned list given (own[0 .. P), P on
+// the device), a tile holds 64 owners instead of 64 edges: the forward pass
+// computes R once per pair and stores it in both edges' rows, and the adjoint
+// takes dR of the pair's two edges summed (E depends on the pair's length
+// through both) through the MLP once; the length gradient goes to the owner's
+// g and each edge keeps its own harmonics term. F_i sums g_e - g_rev(e) over
+// i's edges, so the forces are those of the edge-by-edge adjoint (to rounding).
+//
 // MFMA 32x32x2 operand layout (wave64): lane l supplies A[l%32][l/32] and
 // B[l/32][l%32]; accumulator register r of lane l holds
 // D[8 (r/4) + 4 (l/32) + r%4][l%32].
@@ -122,24 +131,31 @@ __device__ __forceinline__ void to_bf16_tile(const float (*X)[kLd], __bf16 (*Xb)
 }
 
 template <int NB, bool BF, class RS>
-__global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1)))
+k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W3, int ld3, int PC,
                                                     RS* __restrict__ R, float rc, int p, int e_first, int e_end,
                                                     const __bf16* __restrict__ W2Tb,
-                                                    const __bf16* __restrict__ W3Tb) {
+                                                    const __bf16* __restrict__ W3Tb, const int* __restrict__ own,
+                                                    const int* __restrict__ n_own, const int* __restrict__ rev) {
   // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); R is
-  // indexed from e_first. BF: W2Tb = W2^T and W3Tb = W3^T (used columns) in BF16
+  // indexed from e_first. BF: W2Tb = W2^T and W3Tb = W3^T (used columns) in
+  // BF16. own: the tile's rows are pair owners (e_first = 0, e_end < 0)
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float H[kTile][kLd];
   __shared__ __align__(16) __bf16 Hb[BF ? kTile : 1][kLdb];
-  const int E = e_end >= 0 ? e_end : row_ptr_x[N];
-  const int e0 = e_first + blockIdx.x * kTile;
+  __shared__ int Es[kTile], Ps[kTile];  // the rows' edges and their pair partners (-1: none)
+  const int E = own ? *n_own : e_end >= 0 ? e_end : row_ptr_x[N];
+  const int e0 = (own ? 0 : e_first) + blockIdx.x * kTile;
   if (e0 >= E) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (t < kTile) {
-    const int e = e0 + t;
-    const float r = e < E ? dvec[e].w : rc;
+    const int q = e0 + t;
+    const int e = q < E ? (own ? own[q] : q) : -1;
+    Es[t] = e;
+    Ps[t] = own && e >= 0 ? rev[e] : -1;
+    const float r = e >= 0 ? dvec[e].w : rc;
     float b[NB];
     radial_basis<NB>(r, rc, p, b, nullptr);
 #pragma unroll
@@ -178,9 +194,14 @@ __global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ d
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = acc_row(r, lane);
-      const int ea = e0 + row, eb = e0 + 32 + row;
-      if (ea < E) str(R + (long)(ea - e_first) * PC + cc + (lane & 31), a0[r]);
-      if (eb < E) str(R + (long)(eb - e_first) * PC + cc + (lane & 31), a1[r]);
+      const int ea = Es[row], eb = Es[32 + row];
+      if (ea >= 0) str(R + (long)(ea - e_first) * PC + cc + (lane & 31), a0[r]);
+      if (eb >= 0) str(R + (long)(eb - e_first) * PC + cc + (lane & 31), a1[r]);
+      if (own) {
+        const int pa = Ps[row], pb = Ps[32 + row];
+        if (pa >= 0) str(R + (long)pa * PC + cc + (lane & 31), a0[r]);
+        if (pb >= 0) str(R + (long)pb * PC + cc + (lane & 31), a1[r]);
+      }
     }
   }
 }
@@ -193,7 +214,8 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
                                                     float4* __restrict__ g, int accumulate, float rc, int p,
                                                     int e_first, int e_end, const __bf16* __restrict__ W2Tb,
                                                     const __bf16* __restrict__ W2b,
-                                                    const __bf16* __restrict__ W3ub) {
+                                                    const __bf16* __restrict__ W3ub, const int* __restrict__ own,
+                                                    const int* __restrict__ n_own, const int* __restrict__ rev) {
   // BF: W2Tb = W2^T, W2b = W2 and W3ub = W3 (used columns) in BF16, W3 in
   // slabs of 32 columns: W3ub[((c / 32) * 64 + q) * 32 + c % 32] = W3[q][c]
   __shared__ float Bs[kTile][NB + 1];
@@ -203,16 +225,21 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   __shared__ float Ds[BF ? 1 : kTile][33];
   __shared__ __align__(16) __bf16 Xb[BF ? kTile : 1][kLdb];
   __shared__ __align__(16) __bf16 Dsb[BF ? kTile : 1][40];
+  __shared__ int Es[kTile], Ps[kTile];  // the rows' edges and their pair partners (-1: none)
   // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); dR is
-  // indexed from e_first, dY and g by edge
-  const int E = e_end >= 0 ? e_end : row_ptr_x[N];
-  const int e0 = e_first + blockIdx.x * kTile;
+  // indexed from e_first, dY and g by edge. own: the tile's rows are pair
+  // owners (e_first = 0, e_end < 0)
+  const int E = own ? *n_own : e_end >= 0 ? e_end : row_ptr_x[N];
+  const int e0 = (own ? 0 : e_first) + blockIdx.x * kTile;
   if (e0 >= E) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
   if (t < kTile) {
-    const int e = e0 + t;
-    const float r = e < E ? dvec[e].w : rc;
+    const int q = e0 + t;
+    const int e = q < E ? (own ? own[q] : q) : -1;
+    Es[t] = e;
+    Ps[t] = own && e >= 0 ? rev[e] : -1;
+    const float r = e >= 0 ? dvec[e].w : rc;
     float b[NB], db[NB];
     radial_basis<NB>(r, rc, p, b, db);
 #pragma unroll
@@ -240,11 +267,15 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   // dH2 = dR W3^T, K = PC, dR staged through LDS in slabs of 32 columns; the
   // next slab (and, in FP32, its W3^T operands) is loaded into registers
   // while the current one is multiplied.
+  // In pair mode a row's dR is the sum of its two edges' rows; the partner's
+  // slab is loaded beside the owner's and added when the slab is staged.
   f32x16 acc = {};
   const int srow = t >> 2, sc8 = (t & 3) * 8;
-  const bool sval = e0 + srow < E;
-  const RS* dRrow = dR + (long)(e0 + srow - e_first) * PC + sc8;
-  float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+  const int se = Es[srow], sp = Ps[srow];
+  const bool sval = se >= 0;
+  const RS* dRrow = dR + (long)(sval ? se - e_first : 0) * PC + sc8;
+  const RS* dRpart = dR + (long)(sp >= 0 ? sp : 0) * PC + sc8;
+  float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, q0 = p0, q1 = p0;
   float wb[16];
   auto load_slab = [&](int kc) {
     if (sval) {
@@ -252,6 +283,12 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
       ldr_n<8>(dRrow + kc, v);
       p0 = make_float4(v[0], v[1], v[2], v[3]);
       p1 = make_float4(v[4], v[5], v[6], v[7]);
+    }
+    if (sp >= 0) {
+      float v[8];
+      ldr_n<8>(dRpart + kc, v);
+      q0 = make_float4(v[0], v[1], v[2], v[3]);
+      q1 = make_float4(v[4], v[5], v[6], v[7]);
     }
     if constexpr (!BF) {
 #pragma unroll
@@ -261,6 +298,10 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   load_slab(0);
   for (int kc = 0; kc < PC; kc += 32) {
     __syncthreads();
+    if (sp >= 0) {
+      p0 = make_float4(p0.x + q0.x, p0.y + q0.y, p0.z + q0.z, p0.w + q0.w);
+      p1 = make_float4(p1.x + q1.x, p1.y + q1.y, p1.z + q1.z, p1.w + q1.w);
+    }
     if constexpr (BF) {
       bf16x8 v;
       v[0] = (__bf16)p0.x;
@@ -329,15 +370,21 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
     }
   }
   __syncthreads();
-  if (t < kTile) {
-    const int e = e0 + t;
-    if (e < E) {
+  // threads 0-63: the rows' edges (length gradient and harmonics term);
+  // threads 64-127 in pair mode: the partners (their harmonics term only)
+  if (t < 2 * kTile) {
+    const bool partner = t >= kTile;
+    const int row = t & (kTile - 1);
+    const int e = partner ? Ps[row] : Es[row];
+    if (e >= 0) {
       float dr = 0.0f;
+      if (!partner) {
 #pragma unroll
-      for (int n = 0; n < NB; ++n) {
-        float s = 0.0f;
-        for (int q = 0; q < kH; ++q) s += P2[t][q] * W1[n * kH + q];
-        dr += s * dBs[t][n];
+        for (int n = 0; n < NB; ++n) {
+          float s = 0.0f;
+          for (int q = 0; q < kH; ++q) s += P2[row][q] * W1[n * kH + q];
+          dr += s * dBs[row][n];
+        }
       }
       const float4 d = dvec[e];
       const float ir = 1.0f / d.w;
@@ -548,64 +595,78 @@ inline int tiles(long n) { return (int)((n + kTile - 1) / kTile); }
 
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
                        const float* W2, const float* W3, int ld3, int PC, void* R, bool r_bf16, float rc, int p,
-                       bool bf16, hipStream_t st, int e_first, int e_end, const RadialBf16* wb) {
+                       bool bf16, hipStream_t st, int e_first, int e_end, const RadialBf16* wb,
+                       const EdgePairs* pairs) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (PC % 32) throw Error(E3MI_EUNSUPPORTED, "paths x channels must be a multiple of 32");
   if (r_bf16 && !bf16) throw Error(E3MI_EINVAL, "BF16 radial weights need the BF16 mode");
   if (bf16 && !(wb && wb->W2T && wb->W3T)) throw Error(E3MI_EINVAL, "BF16 mode: BF16 radial weights missing");
+  if (pairs && (e_first != 0 || e_end >= 0 || !pairs->own || !pairs->n_own || !pairs->rev))
+    throw Error(E3MI_EINVAL, "radial MLP per edge pair: needs the whole edge list and the pair owners");
+  const int* own = pairs ? pairs->own : nullptr;
+  const int* n_own = pairs ? pairs->n_own : nullptr;
+  const int* rev = pairs ? pairs->rev : nullptr;
   const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
   if (grid == 0) return;
   if (r_bf16)
     k_radial_fwd<8, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
                                                         static_cast<__bf16*>(R), rc, p, e_first, e_end, wb->W2T,
-                                                        wb->W3T);
+                                                        wb->W3T, own, n_own, rev);
   else if (bf16)
     k_radial_fwd<8, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
                                                        static_cast<float*>(R), rc, p, e_first, e_end, wb->W2T,
-                                                       wb->W3T);
+                                                       wb->W3T, own, n_own, rev);
   else
     k_radial_fwd<8, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
                                                         static_cast<float*>(R), rc, p, e_first, e_end, nullptr,
-                                                        nullptr);
+                                                        nullptr, own, n_own, rev);
 }
 
 template <int LMAX>
 static void radial_bwd_l(bool bf16, bool r_bf16, long e_cap, const float4* dvec, const int* row_ptr_x, int N,
                          const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
                          const float* dY, float4* g, int accumulate, float rc, int p, hipStream_t st, int e_first,
-                         int e_end, const RadialBf16* wb) {
+                         int e_end, const RadialBf16* wb, const int* own, const int* n_own, const int* rev) {
   const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
   if (grid == 0) return;
   if (r_bf16)
     k_radial_bwd<8, LMAX, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
                                                               static_cast<const __bf16*>(dR), dY, g, accumulate, rc,
-                                                              p, e_first, e_end, wb->W2T, wb->W2, wb->W3u);
+                                                              p, e_first, e_end, wb->W2T, wb->W2, wb->W3u, own, n_own,
+                                                              rev);
   else if (bf16)
     k_radial_bwd<8, LMAX, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
                                                              static_cast<const float*>(dR), dY, g, accumulate, rc, p,
-                                                             e_first, e_end, wb->W2T, wb->W2, wb->W3u);
+                                                             e_first, e_end, wb->W2T, wb->W2, wb->W3u, own, n_own,
+                                                             rev);
   else
     k_radial_bwd<8, LMAX, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
                                                               static_cast<const float*>(dR), dY, g, accumulate, rc,
-                                                              p, e_first, e_end, nullptr, nullptr, nullptr);
+                                                              p, e_first, e_end, nullptr, nullptr, nullptr, own,
+                                                              n_own, rev);
 }
 
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
                        bool r_bf16, const float* dY, float4* g, int accumulate, float rc, int p, bool bf16,
-                       hipStream_t st, int e_first, int e_end, const RadialBf16* wb) {
+                       hipStream_t st, int e_first, int e_end, const RadialBf16* wb, const EdgePairs* pairs) {
   if (e_cap == 0) return;
   if (n_basis != 8) throw Error(E3MI_EUNSUPPORTED, "n_basis must be 8");
   if (r_bf16 && !bf16) throw Error(E3MI_EINVAL, "BF16 radial weights need the BF16 mode");
   if (bf16 && !(wb && wb->W2T && wb->W2 && wb->W3u))
     throw Error(E3MI_EINVAL, "BF16 mode: BF16 radial weights missing");
+  if (pairs && (e_first != 0 || e_end >= 0 || !pairs->own || !pairs->n_own || !pairs->rev))
+    throw Error(E3MI_EINVAL, "radial adjoint per edge pair: needs the whole edge list and the pair owners");
+  const int* own = pairs ? pairs->own : nullptr;
+  const int* n_own = pairs ? pairs->n_own : nullptr;
+  const int* rev = pairs ? pairs->rev : nullptr;
   if (lmax == 3)
     radial_bwd_l<3>(bf16, r_bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st,
-                    e_first, e_end, wb);
+                    e_first, e_end, wb, own, n_own, rev);
   else if (lmax == 2)
     radial_bwd_l<2>(bf16, r_bf16, e_cap, dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, dR, dY, g, accumulate, rc, p, st,
-                    e_first, e_end, wb);
+                    e_first, e_end, wb, own, n_own, rev);
   else
     throw Error(E3MI_EUNSUPPORTED, "lmax must be 2 or 3");
 }

@@ -207,8 +207,10 @@ void launch_prune_count(const double* pos, const int* owner, const double* box, 
 void launch_prune_compact(const double* pos, const int* owner, const double* box, const int* row_ptr,
                           const int* src, const int* shift, const int* row_ptr_x, int N, double rc2,
                           int* src_x, float4* dvec_x, int* old_idx, int* new_idx, hipStream_t st);
+// rev_x, and the pair owners (own_cnt [N], own_ptr [N + 1], own [E]; own_ptr[N]
+// is their count on the device)
 void launch_prune_rev(const int* row_ptr_x, int N, const int* old_idx, const int* new_idx,
-                      const int* rev_skin, int* rev_x, hipStream_t st);
+                      const int* rev_skin, int* rev_x, int* own_cnt, int* own_ptr, int* own, hipStream_t st);
 
 // ---- tensor product (tp.hip) ---------------------------------------------------
 struct TpArgs {
@@ -361,13 +363,23 @@ struct RadialBf16 {
   const __bf16* W3T = nullptr;
   const __bf16* W3u = nullptr;
 };
+// The pair owners of the pruned list (own [P], P = *n_own on the device) and
+// its reverse index: given, the radial MLP and its adjoint run once per edge
+// pair (whole edge list only).
+struct EdgePairs {
+  const int* own = nullptr;
+  const int* n_own = nullptr;
+  const int* rev = nullptr;
+};
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
                        const float* W2, const float* W3, int ld3, int PC, void* R, bool r_bf16, float rc, int p,
-                       bool bf16, hipStream_t st, int e_first = 0, int e_end = -1, const RadialBf16* wb = nullptr);
+                       bool bf16, hipStream_t st, int e_first = 0, int e_end = -1, const RadialBf16* wb = nullptr,
+                       const EdgePairs* pairs = nullptr);
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,
                        const float* W1, const float* W2, const float* W2T, const float* W3T, int PC, const void* dR,
                        bool r_bf16, const float* dY, float4* g, int accumulate, float rc, int p, bool bf16,
-                       hipStream_t st, int e_first = 0, int e_end = -1, const RadialBf16* wb = nullptr);
+                       hipStream_t st, int e_first = 0, int e_end = -1, const RadialBf16* wb = nullptr,
+                       const EdgePairs* pairs = nullptr);
 
 // ---- second-order passes (radial.hip, grad.hip) -------------------------------------
 void launch_radial_dual_fwd(int n_basis, const float4* dvec, const float4* dd, const int* row_ptr_x, int N, long e_cap,

@@ -90,7 +90,8 @@ def check_forces(F_gpu, F_ref, abs_tol=1e-4, rel_tol=1e-3):
     """Max-abs error <= abs_tol (eV/A) and <= rel_tol * max|F_ref|."""
     err = np.abs(np.asarray(F_gpu) - np.asarray(F_ref)).max()
     fmax = np.abs(F_ref).max()
-    record("forces", max_abs=float(err), rel_to_max_abs_F=float(err / fmax), bound_abs=abs_tol, bound_rel=rel_tol)
+    rel = float(err / fmax) if fmax > 0 else (0.0 if err == 0 else float("inf"))  # zero forces: exact
+    record("forces", max_abs=float(err), rel_to_max_abs_F=rel, bound_abs=abs_tol, bound_rel=rel_tol)
     assert err <= abs_tol, (err, fmax)
-    assert err <= rel_tol * fmax, (err, fmax, err / fmax)
-    return float(err), float(err / fmax)
+    assert err <= rel_tol * fmax, (err, fmax, rel)
+    return float(err), rel

@@ -1,6 +1,7 @@
 """Layers evaluated in receiver chunks (bounded per-edge memory) and the
 100,000-atom, 3-layer precision-at-scale configuration (r_c 6 A, l_max 3,
-128 channels): chunked = unchunked bitwise; the independent 2,000-atom
+128 channels): chunked = unchunked bitwise (radial adjoint per edge; per
+edge pair, the default for unchunked layers, to rounding); the independent 2,000-atom
 sub-box against the FP64 oracle in FP32 (energy <= 1e-5 relative, forces
 <= 1e-4 eV/A and <= 1e-3 of the largest force) and in BF16 (errors stated,
 bounded loosely); the full box in both precisions."""
@@ -23,14 +24,22 @@ def test_chunked_layers_equal_unchunked(correlation, precision):
                             avg_neighbors=synth.nominal_neighbors(0.1, 5.0), correlation=correlation)
     b = synth.jittered_lattice(400, 0.1, 0.3, 4, np.random.default_rng(121))
     m = model(cfg, 122, precision=precision)
+    # unchunked layers run the radial adjoint per edge pair by default (forces
+    # equal to rounding); per edge, as chunked layers do, they give the same bits
+    Ep, Fp, Eip, _ = gpu_energy_forces(m, b, skin=1.0)
+    m.set_flags(radial_per_edge=True)
     E0, F0, Ei0, _ = gpu_energy_forces(m, b, skin=1.0)
+    assert np.array_equal(E0, Ep) and np.array_equal(Ei0, Eip)
+    assert np.abs(Fp - F0).max() <= (1e-5 if precision == 0 else 1e-2) * np.abs(F0).max()
     m.set_r_chunk_bytes(1 << 20)  # 1 MiB: 1 MiB / (23 paths x 64 ch x 4 B) = 178 edges per chunk
-    for keep in (0, 1 << 40):     # R recomputed chunk by chunk in the adjoint / kept whole
-        m.set_r_keep_bytes(keep)
-        E1, F1, Ei1, _ = gpu_energy_forces(m, b, skin=1.0)
-        say(f"chunked (correlation {correlation}, precision {precision}, keep {keep}): "
-            f"max |dF| {np.abs(F1 - F0).max():.1e}")
-        assert np.array_equal(E0, E1) and np.array_equal(F0, F1) and np.array_equal(Ei0, Ei1)
+    for flags in ({"radial_per_edge": True}, {}):   # chunked layers ignore the pair mode
+        m.set_flags(**flags)
+        for keep in (0, 1 << 40):     # R recomputed chunk by chunk in the adjoint / kept whole
+            m.set_r_keep_bytes(keep)
+            E1, F1, Ei1, _ = gpu_energy_forces(m, b, skin=1.0)
+            say(f"chunked (correlation {correlation}, precision {precision}, keep {keep}, flags {flags}): "
+                f"max |dF| {np.abs(F1 - F0).max():.1e}")
+            assert np.array_equal(E0, E1) and np.array_equal(F0, F1) and np.array_equal(Ei0, Ei1)
 
 
 @pytest.mark.parametrize("chunk_bytes", [None, 64 << 20])
