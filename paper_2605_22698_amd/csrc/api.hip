@@ -227,6 +227,8 @@ struct Workspace {
   // per layer: evaluated in receiver chunks with R of every edge kept (the
   // adjoint reads chunk c's R at its first edge instead of recomputing it)
   std::vector<char> r_whole;
+  // per layer: R stored once per edge pair (row = the edge's pair index)
+  std::vector<char> r_compact;
 };
 
 }  // namespace e3mi
@@ -262,7 +264,7 @@ struct e3mi_graph {
   std::unique_ptr<e3mi::DevBuf> off_d, owner, box_d, pbc_d, species, row_ptr, src, shift, rev, keys;
   std::unique_ptr<e3mi::DevBuf> cnt, row_ptr_x, src_x, dvec_x, old_idx, new_idx, rev_x, x_ref;
   // edges that own their pair {e, rev(e)} (pruned list), per receiver and in edge order
-  std::unique_ptr<e3mi::DevBuf> own_cnt, own_ptr, own;
+  std::unique_ptr<e3mi::DevBuf> own_cnt, own_ptr, own, pair_of;
   // electrostatics: total charge per structure, and (structure, first atom) per 64-atom tile
   std::unique_ptr<e3mi::DevBuf> charge, ctiles;
   int n_ctiles = 0, c_waves = 1;
@@ -470,6 +472,7 @@ void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
   ensure(G->own_cnt, a, sizeof(int) * (N + 1));
   ensure(G->own_ptr, a, sizeof(int) * (N + 1));
   ensure(G->own, a, sizeof(int) * (E + 1));
+  ensure(G->pair_of, a, sizeof(int) * (E + 1));
   ensure(G->x_ref, a, sizeof(double) * 3 * (N + 1));
   if (N) E3MI_HIP(hipMemcpyAsync(G->x_ref->p, pos, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
 }
@@ -567,7 +570,8 @@ void prune(e3mi_graph* G, const double* pos, hipStream_t st) {
                        G->shift->as<int>(), G->row_ptr_x->as<int>(), N, rc2, G->src_x->as<int>(),
                        G->dvec_x->as<float4>(), G->old_idx->as<int>(), G->new_idx->as<int>(), st);
   launch_prune_rev(G->row_ptr_x->as<int>(), N, G->old_idx->as<int>(), G->new_idx->as<int>(), G->rev->as<int>(),
-                   G->rev_x->as<int>(), G->own_cnt->as<int>(), G->own_ptr->as<int>(), G->own->as<int>(), st);
+                   G->rev_x->as<int>(), G->own_cnt->as<int>(), G->own_ptr->as<int>(), G->own->as<int>(),
+                   G->pair_of->as<int>(), st);
 }
 
 // Channels per thread of the tensor-product kernels (threads per receiver = C / cpt).
@@ -852,11 +856,16 @@ void* chunk_r(const Workspace& w, int t, void* R, const RChunk& ch, int PCu, siz
 
 // The pair owners of the pruned list, used by a layer's radial passes when
 // the model runs them per edge pair and the chunk is the whole edge list.
-EdgePairs graph_pairs(const e3mi_graph* G) {
-  return EdgePairs{G->own->as<int>(), G->own_ptr->as<int>() + G->N, G->rev_x->as<int>()};
+EdgePairs graph_pairs(const e3mi_graph* G, bool compact = false) {
+  return EdgePairs{G->own->as<int>(), G->own_ptr->as<int>() + G->N, G->rev_x->as<int>(), compact ? 1 : 0};
 }
 const EdgePairs* pairs_for(const e3mi_model* M, const RChunk& ch, const EdgePairs& p) {
   return M->edge_pairs && ch.e1 < 0 ? &p : nullptr;
+}
+// R of a layer once per edge pair: the pair mode on a single chunk, in a
+// first-order evaluation (the second-order passes read R per edge)
+bool r_compact_for(const e3mi_model* M, const std::vector<RChunk>& chunks, bool keep_A) {
+  return M->edge_pairs && !keep_A && chunks.size() == 1 && chunks[0].e1 < 0;
 }
 
 void set_chunk(TpArgs& ta, const RChunk& ch) {
@@ -902,6 +911,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
   long a_max = 0;
   size_t dr_bytes = 0, kept = 0;
   w.r_whole.assign(T + 1, 0);
+  w.r_compact.assign(T + 1, 0);
   for (int t = 1; t <= T; ++t) {
     const LayerPlan& L = M->plans[t - 1];
     ensure(w.h[t], a, sizeof(float) * (size_t)N * L.nc_out * C);
@@ -1060,7 +1070,9 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     ta.C = C;
     ta.inv_nu = inv_nu;
     const RadialBf16 bfw = W.bf16_view();
-    const EdgePairs prs = graph_pairs(G);
+    w.r_compact[t] = r_compact_for(M, chunks, keep_A) ? 1 : 0;
+    const EdgePairs prs = graph_pairs(G, w.r_compact[t]);
+    ta.r_row = w.r_compact[t] ? G->pair_of->as<int>() : nullptr;
     for (const RChunk& ch : chunks) {
       void* Rc = chunk_r(w, t, R, ch, PCu, lr_bf16 ? 2 : 4);
       {
@@ -1291,6 +1303,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
     const RadialBf16 bfw = W.bf16_view();
     const EdgePairs prs = graph_pairs(G);
     ta.rev = G->rev_x->as<int>();
+    ta.r_row = w.r_compact[t] ? G->pair_of->as<int>() : nullptr;
     // scalar-output layer: the sender-side adjoint gives dR, dY and dh in one
     // pass (chunk by chunk: a chunk's receivers are the senders whose rows it holds)
     const bool sender_side = tps_supported(ta);

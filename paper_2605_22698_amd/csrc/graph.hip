@@ -391,10 +391,11 @@ __global__ void __launch_bounds__(256) k_prune_rev(const int* __restrict__ row_p
   if (lane == 0) own_cnt[i] = total;
 }
 
-// the owners in edge order: own[own_ptr[i] + k] = the k-th owner of row i
+// the owners in edge order, own[own_ptr[i] + k] = the k-th owner of row i,
+// and each edge's pair index (its owner's position in own)
 __global__ void __launch_bounds__(256) k_pair_owners(const int* __restrict__ row_ptr_x, int N,
                                                      const int* __restrict__ rev_x, const int* __restrict__ own_ptr,
-                                                     int* __restrict__ own) {
+                                                     int* __restrict__ own, int* __restrict__ pair_of) {
   const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (i >= N) return;
@@ -402,9 +403,15 @@ __global__ void __launch_bounds__(256) k_pair_owners(const int* __restrict__ row
   int out = own_ptr[i];
   for (int base = a; base < b; base += 64) {
     const int e = base + lane;
-    const bool o = e < b && owns_pair(e, rev_x[e]);
+    const int re = e < b ? rev_x[e] : -1;
+    const bool o = e < b && owns_pair(e, re);
     const uint64_t m = __ballot(o);
-    if (o) own[out + __popcll(m & ((1ull << lane) - 1ull))] = e;
+    if (o) {
+      const int p = out + __popcll(m & ((1ull << lane) - 1ull));
+      own[p] = e;
+      pair_of[e] = p;
+      if (re >= 0) pair_of[re] = p;
+    }
     out += __popcll(m);
   }
 }
@@ -473,14 +480,14 @@ void launch_prune_compact(const double* pos, const int* owner, const double* box
                                                               src_x, dvec_x, old_idx, new_idx);
 }
 void launch_prune_rev(const int* row_ptr_x, int N, const int* old_idx, const int* new_idx, const int* rev_skin,
-                      int* rev_x, int* own_cnt, int* own_ptr, int* own, hipStream_t st) {
+                      int* rev_x, int* own_cnt, int* own_ptr, int* own, int* pair_of, hipStream_t st) {
   if (N == 0) {
     launch_exclusive_scan(own_cnt, own_ptr, 0, st);  // own_ptr[0] = 0
     return;
   }
   k_prune_rev<<<blocks((long)N * 64, 256), 256, 0, st>>>(row_ptr_x, N, old_idx, new_idx, rev_skin, rev_x, own_cnt);
   launch_exclusive_scan(own_cnt, own_ptr, N, st);
-  k_pair_owners<<<blocks((long)N * 64, 256), 256, 0, st>>>(row_ptr_x, N, rev_x, own_ptr, own);
+  k_pair_owners<<<blocks((long)N * 64, 256), 256, 0, st>>>(row_ptr_x, N, rev_x, own_ptr, own, pair_of);
 }
 
 }  // namespace e3mi

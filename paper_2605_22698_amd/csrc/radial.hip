@@ -138,10 +138,12 @@ k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     RS* __restrict__ R, float rc, int p, int e_first, int e_end,
                                                     const __bf16* __restrict__ W2Tb,
                                                     const __bf16* __restrict__ W3Tb, const int* __restrict__ own,
-                                                    const int* __restrict__ n_own, const int* __restrict__ rev) {
+                                                    const int* __restrict__ n_own, const int* __restrict__ rev,
+                                                    int compact) {
   // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); R is
   // indexed from e_first. BF: W2Tb = W2^T and W3Tb = W3^T (used columns) in
-  // BF16. own: the tile's rows are pair owners (e_first = 0, e_end < 0)
+  // BF16. own: the tile's rows are pair owners (e_first = 0, e_end < 0),
+  // written to both edges' rows, or with `compact` to the pair's row
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float H[kTile][kLd];
   __shared__ __align__(16) __bf16 Hb[BF ? kTile : 1][kLdb];
@@ -194,6 +196,11 @@ k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = acc_row(r, lane);
+      if (compact) {
+        if (e0 + row < E) str(R + (long)(e0 + row) * PC + cc + (lane & 31), a0[r]);
+        if (e0 + 32 + row < E) str(R + (long)(e0 + 32 + row) * PC + cc + (lane & 31), a1[r]);
+        continue;
+      }
       const int ea = Es[row], eb = Es[32 + row];
       if (ea >= 0) str(R + (long)(ea - e_first) * PC + cc + (lane & 31), a0[r]);
       if (eb >= 0) str(R + (long)(eb - e_first) * PC + cc + (lane & 31), a1[r]);
@@ -607,20 +614,21 @@ void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, in
   const int* own = pairs ? pairs->own : nullptr;
   const int* n_own = pairs ? pairs->n_own : nullptr;
   const int* rev = pairs ? pairs->rev : nullptr;
+  const int compact = pairs ? pairs->compact : 0;
   const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
   if (grid == 0) return;
   if (r_bf16)
     k_radial_fwd<8, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
                                                         static_cast<__bf16*>(R), rc, p, e_first, e_end, wb->W2T,
-                                                        wb->W3T, own, n_own, rev);
+                                                        wb->W3T, own, n_own, rev, compact);
   else if (bf16)
     k_radial_fwd<8, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
                                                        static_cast<float*>(R), rc, p, e_first, e_end, wb->W2T,
-                                                       wb->W3T, own, n_own, rev);
+                                                       wb->W3T, own, n_own, rev, compact);
   else
     k_radial_fwd<8, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
                                                         static_cast<float*>(R), rc, p, e_first, e_end, nullptr,
-                                                        nullptr, own, n_own, rev);
+                                                        nullptr, own, n_own, rev, compact);
 }
 
 template <int LMAX>

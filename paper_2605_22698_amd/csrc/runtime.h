@@ -207,10 +207,11 @@ void launch_prune_count(const double* pos, const int* owner, const double* box, 
 void launch_prune_compact(const double* pos, const int* owner, const double* box, const int* row_ptr,
                           const int* src, const int* shift, const int* row_ptr_x, int N, double rc2,
                           int* src_x, float4* dvec_x, int* old_idx, int* new_idx, hipStream_t st);
-// rev_x, and the pair owners (own_cnt [N], own_ptr [N + 1], own [E]; own_ptr[N]
-// is their count on the device)
+// rev_x, the pair owners (own_cnt [N], own_ptr [N + 1], own [E]; own_ptr[N]
+// is their count on the device) and each edge's pair index (pair_of [E])
 void launch_prune_rev(const int* row_ptr_x, int N, const int* old_idx, const int* new_idx,
-                      const int* rev_skin, int* rev_x, int* own_cnt, int* own_ptr, int* own, hipStream_t st);
+                      const int* rev_skin, int* rev_x, int* own_cnt, int* own_ptr, int* own, int* pair_of,
+                      hipStream_t st);
 
 // ---- tensor product (tp.hip) ---------------------------------------------------
 struct TpArgs {
@@ -252,6 +253,9 @@ struct TpArgs {
   int r_bf16;      // R and dR stored as BF16 (passes 0 and 1, and the sender-side adjoint)
   int* touched;    // with msg: per atom, set to `tag` for every sender of the chunk's edges (pass 1), read by pass 7
   int tag;
+  // R rows per edge pair (passes 0-2 and the sender-side adjoint): edge e's
+  // weights in row r_row[e] (NULL: row e - e_first); dR stays per edge
+  const int* r_row;
 };
 // which: 0 forward, 1 edge adjoint (dR, dY), 2 node adjoint (dh += ...),
 //        3 tangent forward (Ad), 4 second-order edge adjoint (Rb, Rc),
@@ -365,11 +369,14 @@ struct RadialBf16 {
 };
 // The pair owners of the pruned list (own [P], P = *n_own on the device) and
 // its reverse index: given, the radial MLP and its adjoint run once per edge
-// pair (whole edge list only).
+// pair (whole edge list only). The forward pass writes R to both edges' rows,
+// or with `compact` once per pair, at row p for the owner own[p] (consumers
+// then find edge e's row through the pair index).
 struct EdgePairs {
   const int* own = nullptr;
   const int* n_own = nullptr;
   const int* rev = nullptr;
+  int compact = 0;
 };
 void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, int N, long e_cap, const float* W1,
                        const float* W2, const float* W3, int ld3, int PC, void* R, bool r_bf16, float rc, int p,

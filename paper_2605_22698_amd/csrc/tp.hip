@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIN
                                                 const float4* __restrict__ dvec, const RS* __restrict__ R,
                                                 int r_stride, const float* __restrict__ h, int h_nc,
                                                 float* __restrict__ A, int N, int C, float inv_nu, int i0,
-                                                int e_first) {
+                                                int e_first, const int* __restrict__ r_row) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
   const int i = i0 + xcd_contiguous(blockIdx.x, gridDim.x);
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIN
     const float ir = 1.0f / d.w;
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const RS* Re = R + (long)(e - e_first) * r_stride;
+    const RS* Re = R + (long)(r_row ? r_row[e] : e - e_first) * r_stride;
     const float* hj = h + (long)j * h_nc * C;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND =
                                                      const float* __restrict__ dA, RS* __restrict__ dR,
                                                      float* __restrict__ dY, int N, int C, float inv_nu, int i0,
                                                      int e_first, float* __restrict__ msg, int* __restrict__ touched,
-                                                     int tag) {
+                                                     int tag, const int* __restrict__ r_row) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NOUT = PS::NOUT, NIN = PS::NIN, NY = PS::NY;
   __shared__ float red[4][16];
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND =
     const float ir = 1.0f / d.w;
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const RS* Re = R + (long)(e - e_first) * r_stride;
+    const RS* Re = R + (long)(r_row ? r_row[e] : e - e_first) * r_stride;
     RS* dRe = dR + (long)(e - e_first) * r_stride;
     const float* hj = h + (long)j * h_nc * C;
     float dyp[NY];
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
                                                      const float4* __restrict__ dvec, const RS* __restrict__ R,
                                                      int r_stride, const float* __restrict__ dA,
                                                      float* __restrict__ dh, int dh_nc, int N, int C, float inv_nu,
-                                                     int i0, int e_first, int dh_acc) {
+                                                     int i0, int e_first, int dh_acc, const int* __restrict__ r_row) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NIN = PS::NIN, NY = PS::NY;
   const int j = i0 + xcd_contiguous(blockIdx.x, gridDim.x);
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
     const float ir = -1.0f / d.w;  // direction of the reverse edge
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const RS* Re = R + (long)(e - e_first) * r_stride;
+    const RS* Re = R + (long)(r_row ? r_row[e] : e - e_first) * r_stride;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int k = threadIdx.x + c * tpr;
@@ -687,30 +687,32 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
     throw Error(E3MI_EINVAL, "tensor product: receiver offset without a receiver count");
   if (a.r_bf16 && which > 2 && which != 7)
     throw Error(E3MI_EINVAL, "tensor product: BF16 radial weights only in the first-order passes");
+  if (a.r_row && which > 2 && which != 7)
+    throw Error(E3MI_EINVAL, "tensor product: R rows per edge pair only in the first-order passes");
   const __bf16* Rb = reinterpret_cast<const __bf16*>(a.R);
   __bf16* dRb = reinterpret_cast<__bf16*>(a.dR);
   if (which == 0 && a.r_bf16)
     k_tp_fwd<LMAX, KIND, CPT, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h, a.h_nc, a.A,
-                                                           a.N, a.C, a.inv_nu, a.i0, a.e_first);
+                                                           a.N, a.C, a.inv_nu, a.i0, a.e_first, a.r_row);
   else if (which == 0)
     k_tp_fwd<LMAX, KIND, CPT, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.A,
-                                                          a.N, a.C, a.inv_nu, a.i0, a.e_first);
+                                                          a.N, a.C, a.inv_nu, a.i0, a.e_first, a.r_row);
   else if (which == 1 && a.r_bf16 && a.msg)
     k_tp_bwd_edge<LMAX, KIND, CPT, true, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h,
                                                                       a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu,
-                                                                      a.i0, a.e_first, a.msg, a.touched, a.tag);
+                                                                      a.i0, a.e_first, a.msg, a.touched, a.tag, a.r_row);
   else if (which == 1 && a.r_bf16)
     k_tp_bwd_edge<LMAX, KIND, CPT, false, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h,
                                                                        a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu,
-                                                                       a.i0, a.e_first, nullptr, nullptr, 0);
+                                                                       a.i0, a.e_first, nullptr, nullptr, 0, a.r_row);
   else if (which == 1 && a.msg)
     k_tp_bwd_edge<LMAX, KIND, CPT, true, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
                                                                      a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu,
-                                                                     a.i0, a.e_first, a.msg, a.touched, a.tag);
+                                                                     a.i0, a.e_first, a.msg, a.touched, a.tag, a.r_row);
   else if (which == 1)
     k_tp_bwd_edge<LMAX, KIND, CPT, false, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
                                                                       a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu,
-                                                                      a.i0, a.e_first, nullptr, nullptr, 0);
+                                                                      a.i0, a.e_first, nullptr, nullptr, 0, a.r_row);
   else if (which == 7) {
     using PS = PathSet<LMAX, KIND>;
     const int c1 = a.n_recv > 0 ? a.i0 + a.n_recv : a.N;
@@ -720,11 +722,11 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
   else if (which == 2 && a.r_bf16)
     k_tp_bwd_node<LMAX, KIND, CPT, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.dA, a.dh,
                                                                 a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first,
-                                                                a.dh_acc);
+                                                                a.dh_acc, a.r_row);
   else if (which == 2)
     k_tp_bwd_node<LMAX, KIND, CPT, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
                                                                a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first,
-                                                               a.dh_acc);
+                                                               a.dh_acc, a.r_row);
   else if (which == 3)
     k_tp_dual_fwd<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.R, a.Rd, a.r_stride, a.h,
                                                          a.hd, a.h_nc, a.Ad, a.N, a.C, a.inv_nu);

@@ -32,6 +32,31 @@
 namespace e3mi {
 namespace {
 
+// dR and dY are streamed out with non-temporal stores (not kept in the
+// caches), so that they do not evict the R rows this pass still has to read
+template <int n>
+__device__ __forceinline__ void str_nt(float* p, const float* v) {
+  if constexpr (n == 1) {
+    __builtin_nontemporal_store(v[0], p);
+  } else if constexpr (n == 2) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(f2{v[0], v[1]}, reinterpret_cast<f2*>(p));
+  } else {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int q = 0; q < n; q += 4)
+      __builtin_nontemporal_store(f4{v[q], v[q + 1], v[q + 2], v[q + 3]}, reinterpret_cast<f4*>(p + q));
+  }
+}
+template <int n>
+__device__ __forceinline__ void str_nt(__bf16* p, const float* v) {
+  typedef __bf16 bvec __attribute__((ext_vector_type(n)));
+  bvec t;
+#pragma unroll
+  for (int q = 0; q < n; ++q) t[q] = (__bf16)v[q];
+  __builtin_nontemporal_store(t, reinterpret_cast<bvec*>(p));
+}
+
 template <int LMAX, int KIND, int CH, bool DH, class RS>
 __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                        const int* __restrict__ rev, const float4* __restrict__ dvec,
@@ -39,7 +64,8 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
                                                        const float* __restrict__ h, int h_nc,
                                                        const float* __restrict__ dA, RS* __restrict__ dR,
                                                        float* __restrict__ dY, float* __restrict__ dh, int dh_nc,
-                                                       int dh_acc, int C, float inv_nu, int i0, int e_first) {
+                                                       int dh_acc, int C, float inv_nu, int i0, int e_first,
+                                                       const int* __restrict__ r_row) {
   using PS = PathSet<LMAX, KIND>;
   constexpr int NP = PS::NP, NIN = PS::NIN, NY = PS::NY;
   constexpr int NA = DH ? NIN : 1;
@@ -63,8 +89,8 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
     RS* dRe = dR + (long)(e2 - e_first) * r_stride + k0;
     if (rev[e2] < 0) {  // the edge i <- j is not in i's list
       const float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-      static_for<NP>([&](auto pi) { str_n<CH>(dRe + pi * C, z); });
-      if (lane < 16) dY[(long)e2 * 16 + lane] = 0.0f;
+      static_for<NP>([&](auto pi) { str_nt<CH>(dRe + pi * C, z); });
+      if (lane < 16) __builtin_nontemporal_store(0.0f, dY + (long)e2 * 16 + lane);
       continue;
     }
     const int i = src[e2];
@@ -72,7 +98,7 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
     const float ir = -1.0f / d.w;  // d_e = -d_e2
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const RS* Re = R + (long)(e2 - e_first) * r_stride + k0;
+    const RS* Re = R + (long)(r_row ? r_row[e2] : e2 - e_first) * r_stride + k0;
     const float* dAi = dA + (long)i * NP * C + k0;
     float dyp[NY];
 #pragma unroll
@@ -99,13 +125,13 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
         });
         s[c] = dai * t;
       }
-      str_n<CH>(dRe + pi * C, s);
+      str_nt<CH>(dRe + pi * C, s);
     });
     const float tot = wave_sum_scatter16<NY>(dyp);
     const int q = lane >> 2;
     // (-1)^l for component q = l^2 + m + l: odd for q in 1..3 and 9..15
     const bool odd = (q >= 1 && q <= 3) || q >= 9;
-    if ((lane & 3) == 0 && q < NY) dY[(long)e2 * 16 + q] = odd ? -tot : tot;
+    if ((lane & 3) == 0 && q < NY) __builtin_nontemporal_store(odd ? -tot : tot, dY + (long)e2 * 16 + q);
   }
   if constexpr (DH) {
     // components below dh_acc (all when dh_acc <= 0) are added to, the others
@@ -136,11 +162,11 @@ void sender_launch_rs(const TpArgs& a, int nr, hipStream_t st) {
   if (a.dh)
     k_tps_bwd_sender<LMAX, KIND, CH, true, RS><<<nr, 64, 0, st>>>(a.row_ptr, a.src, a.rev, a.dvec, R, a.r_stride, a.h,
                                                                   a.h_nc, a.dA, dR, a.dY, a.dh, a.dh_nc, a.dh_acc, a.C,
-                                                                  a.inv_nu, a.i0, a.e_first);
+                                                                  a.inv_nu, a.i0, a.e_first, a.r_row);
   else
     k_tps_bwd_sender<LMAX, KIND, CH, false, RS><<<nr, 64, 0, st>>>(a.row_ptr, a.src, a.rev, a.dvec, R, a.r_stride,
                                                                    a.h, a.h_nc, a.dA, dR, a.dY, nullptr, 0, 0, a.C,
-                                                                   a.inv_nu, a.i0, a.e_first);
+                                                                   a.inv_nu, a.i0, a.e_first, a.r_row);
 }
 
 template <int LMAX, int KIND, int CH>
