@@ -256,7 +256,8 @@ struct e3mi_model {
 struct e3mi_graph {
   e3mi_model* model = nullptr;
   int S = 0, N = 0;
-  long E = 0;  // skin-list edges
+  long E = 0;       // skin-list edges
+  long E_room = 0;  // edges the edge buffers (and the models' edge workspaces) hold, >= E
   double cutoff = 0, skin = 0;
   std::vector<int64_t> off_h;
   std::vector<double> box_h;
@@ -447,10 +448,14 @@ void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
   E3MI_HIP(hipStreamSynchronize(st));
   E3MI_REQUIRE(E >= 0, E3MI_EOVERFLOW, "edge count overflow");
   G->E = E;
-  ensure(G->keys, a, sizeof(uint64_t) * (E + 1));
-  ensure(G->src, a, sizeof(int) * (E + 1));
-  ensure(G->shift, a, sizeof(int) * (E + 1));
-  ensure(G->rev, a, sizeof(int) * (E + 1));
+  // a list that outgrows its buffers on a rebuild gets 1/8 more room, so that
+  // the count's drift over a trajectory does not reallocate at every rebuild
+  if (E > G->E_room) G->E_room = G->E_room == 0 ? E : E + E / 8 + 64;
+  const long Er = G->E_room;
+  ensure(G->keys, a, sizeof(uint64_t) * (Er + 1));
+  ensure(G->src, a, sizeof(int) * (Er + 1));
+  ensure(G->shift, a, sizeof(int) * (Er + 1));
+  ensure(G->rev, a, sizeof(int) * (Er + 1));
   launch_edges(true, pos, G->owner->as<int>(), plan_d.as<GridPlan>(), atom_cell.as<int>(), wrap.as<int>(),
                cell_start.as<int>(), cell_atoms.as<int>(), G->row_ptr->as<int>(), N, rc2, nullptr,
                G->keys->as<uint64_t>(), err.as<int>(), st);
@@ -464,15 +469,15 @@ void build_lists(e3mi_graph* G, const double* pos, hipStream_t st) {
   E3MI_REQUIRE(!(errh & 2), E3MI_EDEVICE, "neighbour list is not symmetric");
   // pruned-list capacity and the reference positions for the skin check
   ensure(G->row_ptr_x, a, sizeof(int) * (N + 1));
-  ensure(G->src_x, a, sizeof(int) * (E + 1));
-  ensure(G->dvec_x, a, sizeof(float4) * (E + 1));
-  ensure(G->old_idx, a, sizeof(int) * (E + 1));
-  ensure(G->new_idx, a, sizeof(int) * (E + 1));
-  ensure(G->rev_x, a, sizeof(int) * (E + 1));
+  ensure(G->src_x, a, sizeof(int) * (Er + 1));
+  ensure(G->dvec_x, a, sizeof(float4) * (Er + 1));
+  ensure(G->old_idx, a, sizeof(int) * (Er + 1));
+  ensure(G->new_idx, a, sizeof(int) * (Er + 1));
+  ensure(G->rev_x, a, sizeof(int) * (Er + 1));
   ensure(G->own_cnt, a, sizeof(int) * (N + 1));
   ensure(G->own_ptr, a, sizeof(int) * (N + 1));
-  ensure(G->own, a, sizeof(int) * (E + 1));
-  ensure(G->pair_of, a, sizeof(int) * (E + 1));
+  ensure(G->own, a, sizeof(int) * (Er + 1));
+  ensure(G->pair_of, a, sizeof(int) * (Er + 1));
   ensure(G->x_ref, a, sizeof(double) * 3 * (N + 1));
   if (N) E3MI_HIP(hipMemcpyAsync(G->x_ref->p, pos, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st));
 }
@@ -885,7 +890,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
   const Config& c = M->cfg;
   Allocator* a = &M->alloc;
   const int N = G->N, S = G->S, C = c.channels, T = c.layers;
-  const long Ecap = G->E;
+  const long Ecap = G->E_room;  // edge capacity (>= the skin-list count)
   const int NC = (c.lmax + 1) * (c.lmax + 1);
   const float inv_nu = (float)(1.0 / c.avg_neighbors);
   const float rc = (float)c.cutoff;
@@ -1119,7 +1124,7 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
                    double* atom_energy, hipStream_t st) {
   const Config& c = M->cfg;
   const int N = G->N, S = G->S, C = c.channels, T = c.layers;
-  const long Ecap = G->E;
+  const long Ecap = G->E_room;  // edge capacity (>= the skin-list count)
   const float inv_nu = (float)(1.0 / c.avg_neighbors);
   const float rc = (float)c.cutoff;
   const int p_env = c.envelope_p;
@@ -1362,7 +1367,9 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
 
 size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
   const Config& c = M->cfg;
-  const size_t N = (size_t)std::max<int64_t>(n_atoms, 0), E = (size_t)std::max<int64_t>(n_edges, 0) + 1;
+  // edge buffers: the skin edges, plus the 1/8 room a rebuild that outgrows them adds
+  const size_t n_e = (size_t)std::max<int64_t>(n_edges, 0);
+  const size_t N = (size_t)std::max<int64_t>(n_atoms, 0), E = n_e + n_e / 8 + 65;
   const size_t C = c.channels, NC = (size_t)(c.lmax + 1) * (c.lmax + 1);
   size_t b = 0;
   b += E * (8 + 4 * 3) + E * (4 + 16 + 4 + 4 + 4);   // skin list + pruned list
@@ -1618,7 +1625,7 @@ void second_order(e3mi_model* M, e3mi_graph* G, const double* pos, const double*
   const Config& c = M->cfg;
   Allocator* a = &M->alloc;
   const int N = G->N, C = c.channels, T = c.layers, H = c.radial_hidden;
-  const long Ecap = G->E;
+  const long Ecap = G->E_room;  // edge capacity (>= the skin-list count)
   const int NC = (c.lmax + 1) * (c.lmax + 1);
   const float inv_nu = (float)(1.0 / c.avg_neighbors);
   const float rc = (float)c.cutoff;
