@@ -84,22 +84,75 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
   for (int q = 0; q < NA; ++q)
 #pragma unroll
     for (int c = 0; c < CH; ++c) acc[q][c] = 0.0f;
-  const int e1 = row_ptr[j + 1];
-  for (int e2 = row_ptr[j]; e2 < e1; ++e2) {
+  // Software pipeline over j's row (up to 128 channels): the indices of edge
+  // e2 + 2 and the R and dA rows of edge e2 + 1 are in flight while edge e2
+  // is processed (the rows of consecutive edges lie far apart, and a wave
+  // owns one sender). With 256 channels the prefetched rows would halve the
+  // waves per SIMD: each edge's rows are loaded when it is processed.
+  constexpr bool kPipe = CH <= 2;
+  const int eb = row_ptr[j], e1 = row_ptr[j + 1];
+  struct Idx {
+    int rev, i, row;
+    float4 d;
+  };
+  auto load_idx = [&](int e) {
+    Idx x;
+    x.rev = rev[e];
+    x.i = src[e];
+    x.row = r_row ? r_row[e] : e - e_first;
+    x.d = dvec[e];
+    return x;
+  };
+  auto load_rows = [&](const Idx& x, float (&oR)[NP][CH], float (&oA)[NP][CH]) {
+    if (x.rev < 0) return;
+    const RS* Re = R + (long)x.row * r_stride + k0;
+    const float* dAi = dA + (long)x.i * NP * C + k0;
+    static_for<NP>([&](auto pi) {
+      ldr_n<CH>(Re + pi * C, oR[pi]);
+      ldr_n<CH>(dAi + PS::T.rank[pi] * C, oA[pi]);
+    });
+  };
+  float nR[kPipe ? NP : 1][CH], nA[kPipe ? NP : 1][CH];
+  Idx nx{-1, 0, 0, make_float4(0.f, 0.f, 1.f, 1.f)}, nnx = nx;
+  if constexpr (kPipe) {
+    if (eb < e1) {
+      nx = load_idx(eb);
+      load_rows(nx, nR, nA);
+    }
+    if (eb + 1 < e1) nnx = load_idx(eb + 1);
+  }
+  for (int e2 = eb; e2 < e1; ++e2) {
+    Idx cx;
+    float cR[NP][CH], cA[NP][CH];
+    if constexpr (kPipe) {
+      cx = nx;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          cR[p][c] = nR[p][c];
+          cA[p][c] = nA[p][c];
+        }
+      if (e2 + 1 < e1) {
+        nx = nnx;
+        load_rows(nx, nR, nA);
+        if (e2 + 2 < e1) nnx = load_idx(e2 + 2);
+      }
+    } else {
+      cx = load_idx(e2);
+      load_rows(cx, cR, cA);
+    }
     RS* dRe = dR + (long)(e2 - e_first) * r_stride + k0;
-    if (rev[e2] < 0) {  // the edge i <- j is not in i's list
+    if (cx.rev < 0) {  // the edge i <- j is not in i's list
       const float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       static_for<NP>([&](auto pi) { str_nt<CH>(dRe + pi * C, z); });
       if (lane < 16) __builtin_nontemporal_store(0.0f, dY + (long)e2 * 16 + lane);
       continue;
     }
-    const int i = src[e2];
-    const float4 d = dvec[e2];
+    const float4 d = cx.d;
     const float ir = -1.0f / d.w;  // d_e = -d_e2
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const RS* Re = R + (long)(r_row ? r_row[e2] : e2 - e_first) * r_stride + k0;
-    const float* dAi = dA + (long)i * NP * C + k0;
     float dyp[NY];
 #pragma unroll
     for (int q = 0; q < NY; ++q) dyp[q] = 0.0f;
@@ -107,14 +160,11 @@ __global__ void __launch_bounds__(64) k_tps_bwd_sender(const int* __restrict__ r
       constexpr int g = PS::T.id[pi];
       constexpr int l1 = kL1[g], l2 = kL2[g];
       constexpr int z0 = kNzBegin[g], nz = kNzBegin[g + 1] - kNzBegin[g];
-      constexpr int rank = PS::T.rank[pi];
-      float rp[CH], da[CH], s[CH];
-      ldr_n<CH>(Re + pi * C, rp);
-      ldr_n<CH>(dAi + rank * C, da);
+      float s[CH];
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
-        const float dai = da[c] * inv_nu;
-        const float u = rp[c] * dai;
+        const float dai = cA[pi][c] * inv_nu;
+        const float u = cR[pi][c] * dai;
         float t = 0.0f;
         static_for<nz>([&](auto z) {
           constexpr int q = z0 + z;
