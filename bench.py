@@ -60,9 +60,13 @@ def layer_paths(cfg, t):
             if L1[g] <= l1max and L2[g] <= cfg.lmax and L3[g] <= l3max]
 
 
-def work_model(cfg, t, E, N):
-    """Algorithmic (flops, HBM bytes) of one launch of each stage of layer t."""
+def work_model(cfg, t, E, N, pairs=False):
+    """Algorithmic (flops, HBM bytes) of one launch of each stage of layer t.
+    pairs: the layer's radial MLP runs once per edge pair and R is stored once
+    per pair (an unchunked layer in an energy+forces evaluation); every pruned
+    edge has its reverse in the list, so there are E / 2 pairs."""
     C = cfg.channels
+    P = (E + 1) // 2 if pairs else E   # radial MLP evaluations = R rows
     ps = layer_paths(cfg, t)
     PC = len(ps) * C
     nc_in = 1 if t == 1 else (cfg.lmax + 1) ** 2
@@ -88,12 +92,16 @@ def work_model(cfg, t, E, N):
     out["last_bwd"] = (E * (mlp_hidden + 4 * H * NL * C + 2 * H * H + 2 * H * cfg.n_basis + 6 * C * NY),
                        E * (20 + 32) + N * 4 * (3 * NY * C + NL * C))
     # radial MLP: flops on the matrix cores; bytes = edge vectors in, R out
-    out["radial_fwd"] = (E * (mlp_hidden + 2 * H * PC), E * (16 + 4 * PC))
-    # adjoint: recompute hidden layers, dR W3^T, dH2 W2^T, dH1 W1^T; dR and dY in, g read+write
-    out["radial_bwd"] = (E * (mlp_hidden + 2 * H * PC + 2 * H * H + 2 * H * cfg.n_basis),
-                         E * (16 + 4 * PC + 64 + 32))
-    # tensor product + neighbour sum: R streamed once, h read and A written once per atom
-    out["tp_fwd"] = (E * tp_flops, E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
+    # (per pair: the owner's edge vector and its owner and reverse indices)
+    out["radial_fwd"] = (P * (mlp_hidden + 2 * H * PC), P * (16 + 4 * PC + (8 if pairs else 0)))
+    # adjoint: recompute hidden layers, dR W3^T, dH2 W2^T, dH1 W1^T; dR and dY
+    # of every edge in (summed per pair), g read+write
+    out["radial_bwd"] = (P * (mlp_hidden + 2 * H * PC + 2 * H * H + 2 * H * cfg.n_basis),
+                         E * (16 + 4 * PC + 64 + 32) + (P * 8 if pairs else 0))
+    # tensor product + neighbour sum: R streamed once (each pair's row, found
+    # through the edge's pair index), h read and A written once per atom
+    r_in = P * 4 * PC + (E * 4 if pairs else 0)
+    out["tp_fwd"] = (E * tp_flops, r_in + E * (16 + 4) + N * 4 * C * (nc_in + nout))
     edge_adj = E * (tp_flops + 2 * C * sum(nz for *_, nz in ps) + 2 * C * nout)
     node_adj = E * 2 * C * sum(nz + 2 * l3 + 1 for (_, _, l3, nz) in ps)
     if t == cfg.layers and C in (64, 128, 256) and getattr(cfg, "correlation", 1) != 2:
@@ -101,17 +109,18 @@ def work_model(cfg, t, E, N):
         # and dh in one pass: R read once, dR and dY written, edge vector, sender
         # and reverse index per edge; h, dA and dh (read and written) once per atom
         out["tp_bwd_edge"] = (edge_adj + (node_adj if t > 1 else 0),
-                              E * (8 * PC + 64 + 16 + 4 + 4) + N * 4 * C * (nc_in + nout + (2 * nc_in if t > 1 else 0)))
+                              r_in + E * (4 * PC + 64 + 16 + 4 + 4)
+                              + N * 4 * C * (nc_in + nout + (2 * nc_in if t > 1 else 0)))
     elif t > 1:
         # every path: the edge adjoint also writes each edge's sender-gradient
         # message (nc_in x C values); the node pass reads the messages of each
         # sender's edges (and the reverse index) and reads/writes dh once
         out["tp_bwd_edge"] = (edge_adj + 2 * E * C * sum(nz for *_, nz in ps),
-                              E * (8 * PC + 16 + 4 + 64 + 4 * nc_in * C) + N * 4 * C * (nc_in + nout))
+                              r_in + E * (4 * PC + 16 + 4 + 64 + 4 * nc_in * C) + N * 4 * C * (nc_in + nout))
         out["tp_bwd_node"] = (E * nc_in * C, E * (4 * nc_in * C + 8) + N * 4 * C * 2 * nc_in)
     else:
-        out["tp_bwd_edge"] = (edge_adj, E * (8 * PC + 16 + 4 + 64) + N * 4 * C * (nc_in + nout))
-        out["tp_bwd_node"] = (node_adj, E * (4 * PC + 16 + 4) + N * 4 * C * (nc_in + nout))
+        out["tp_bwd_edge"] = (edge_adj, r_in + E * (4 * PC + 16 + 4 + 64) + N * 4 * C * (nc_in + nout))
+        out["tp_bwd_node"] = (node_adj, r_in + E * (16 + 4) + N * 4 * C * (nc_in + nout))
     return out
 
 
@@ -827,7 +836,7 @@ def main():
     n_edges = g.last_edge_count()
     best = None
     for t in range(1, cfg.layers + 1):
-        wm = work_model(cfg, t, n_edges, b.n_atoms)
+        wm = work_model(cfg, t, n_edges, b.n_atoms, pairs=True)
         for s, (flops, nbytes) in wm.items():
             tot, n = m.stage_time(f"{s}@{t}")
             if n == 0:
@@ -873,7 +882,8 @@ def main():
     roof["traffic"] = measured_traffic("k_tps_bwd_sender" if (s, t) == ("tp_bwd_edge", cfg.layers) else "k_" + s)
     roof["kernel"] = f"{s} (layer {t})"
     roof["avg_launch_ms"] = tot / n
-    roof["algorithmic_per_launch"] = {"flops": flops, "bytes": nbytes, "edges": n_edges}
+    roof["algorithmic_per_launch"] = {"flops": flops, "bytes": nbytes, "edges": n_edges,
+                                      "edge_pairs": (n_edges + 1) // 2}
 
     md.close()
 
