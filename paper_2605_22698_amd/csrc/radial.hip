@@ -24,6 +24,8 @@
 // MFMA 32x32x2 operand layout (wave64): lane l supplies A[l%32][l/32] and
 // B[l/32][l%32]; accumulator register r of lane l holds
 // D[8 (r/4) + 4 (l/32) + r%4][l%32].
+#include <type_traits>
+
 #include "common.h"
 #include "runtime.h"
 
@@ -130,33 +132,34 @@ __device__ __forceinline__ void to_bf16_tile(const float (*X)[kLd], __bf16 (*Xb)
   for (int o = threadIdx.x; o < kTile * kH; o += 256) Xb[o >> 6][o & 63] = (__bf16)X[o >> 6][o & 63];
 }
 
-template <int NB, bool BF, class RS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1)))
-k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
+template <int NB, bool BF, class RS, int MODE>
+__global__ void __launch_bounds__(256) k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W3, int ld3, int PC,
                                                     RS* __restrict__ R, float rc, int p, int e_first, int e_end,
                                                     const __bf16* __restrict__ W2Tb,
                                                     const __bf16* __restrict__ W3Tb, const int* __restrict__ own,
-                                                    const int* __restrict__ n_own, const int* __restrict__ rev,
-                                                    int compact) {
+                                                    const int* __restrict__ n_own, const int* __restrict__ rev) {
   // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); R is
   // indexed from e_first. BF: W2Tb = W2^T and W3Tb = W3^T (used columns) in
-  // BF16. own: the tile's rows are pair owners (e_first = 0, e_end < 0),
-  // written to both edges' rows, or with `compact` to the pair's row
+  // BF16. MODE 0: the tile's rows are edges; 1: pair owners (e_first = 0,
+  // e_end < 0), R written to both edges' rows; 2: pair owners, R written to
+  // the pair's row
   __shared__ float Bs[kTile][NB + 1];
   __shared__ float H[kTile][kLd];
   __shared__ __align__(16) __bf16 Hb[BF ? kTile : 1][kLdb];
-  __shared__ int Es[kTile], Ps[kTile];  // the rows' edges and their pair partners (-1: none)
-  const int E = own ? *n_own : e_end >= 0 ? e_end : row_ptr_x[N];
-  const int e0 = (own ? 0 : e_first) + blockIdx.x * kTile;
+  __shared__ int Es[MODE == 1 ? kTile : 1], Ps[MODE == 1 ? kTile : 1];  // owners and partners (-1: none)
+  const int E = MODE ? *n_own : e_end >= 0 ? e_end : row_ptr_x[N];
+  const int e0 = (MODE ? 0 : e_first) + blockIdx.x * kTile;
   if (e0 >= E) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (t < kTile) {
     const int q = e0 + t;
-    const int e = q < E ? (own ? own[q] : q) : -1;
-    Es[t] = e;
-    Ps[t] = own && e >= 0 ? rev[e] : -1;
+    const int e = q < E ? (MODE ? own[q] : q) : -1;
+    if constexpr (MODE == 1) {
+      Es[t] = e;
+      Ps[t] = e >= 0 ? rev[e] : -1;
+    }
     const float r = e >= 0 ? dvec[e].w : rc;
     float b[NB];
     radial_basis<NB>(r, rc, p, b, nullptr);
@@ -196,16 +199,14 @@ k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = acc_row(r, lane);
-      if (compact) {
-        if (e0 + row < E) str(R + (long)(e0 + row) * PC + cc + (lane & 31), a0[r]);
-        if (e0 + 32 + row < E) str(R + (long)(e0 + 32 + row) * PC + cc + (lane & 31), a1[r]);
-        continue;
-      }
-      const int ea = Es[row], eb = Es[32 + row];
-      if (ea >= 0) str(R + (long)(ea - e_first) * PC + cc + (lane & 31), a0[r]);
-      if (eb >= 0) str(R + (long)(eb - e_first) * PC + cc + (lane & 31), a1[r]);
-      if (own) {
-        const int pa = Ps[row], pb = Ps[32 + row];
+      if constexpr (MODE != 1) {  // rows in order: edges, or pair indices
+        const int ea = e0 + row, eb = e0 + 32 + row;
+        if (ea < E) str(R + (long)(ea - e_first) * PC + cc + (lane & 31), a0[r]);
+        if (eb < E) str(R + (long)(eb - e_first) * PC + cc + (lane & 31), a1[r]);
+      } else {
+        const int ea = Es[row], eb = Es[32 + row], pa = Ps[row], pb = Ps[32 + row];
+        if (ea >= 0) str(R + (long)ea * PC + cc + (lane & 31), a0[r]);
+        if (eb >= 0) str(R + (long)eb * PC + cc + (lane & 31), a1[r]);
         if (pa >= 0) str(R + (long)pa * PC + cc + (lane & 31), a0[r]);
         if (pb >= 0) str(R + (long)pb * PC + cc + (lane & 31), a1[r]);
       }
@@ -213,7 +214,7 @@ k_radial_fwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
   }
 }
 
-template <int NB, int LMAX, bool BF, class RS>
+template <int NB, int LMAX, bool BF, class RS, bool PAIR>
 __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
                                                     int N, const float* __restrict__ W1, const float* __restrict__ W2,
                                                     const float* __restrict__ W2T, const float* __restrict__ W3T,
@@ -232,20 +233,25 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   __shared__ float Ds[BF ? 1 : kTile][33];
   __shared__ __align__(16) __bf16 Xb[BF ? kTile : 1][kLdb];
   __shared__ __align__(16) __bf16 Dsb[BF ? kTile : 1][40];
-  __shared__ int Es[kTile], Ps[kTile];  // the rows' edges and their pair partners (-1: none)
+  __shared__ int Es[PAIR ? kTile : 1], Ps[PAIR ? kTile : 1];  // owners and partners (-1: none)
   // edges [e_first, e_end) (e_end < 0: every edge inside the cutoff); dR is
-  // indexed from e_first, dY and g by edge. own: the tile's rows are pair
+  // indexed from e_first, dY and g by edge. PAIR: the tile's rows are pair
   // owners (e_first = 0, e_end < 0)
-  const int E = own ? *n_own : e_end >= 0 ? e_end : row_ptr_x[N];
-  const int e0 = (own ? 0 : e_first) + blockIdx.x * kTile;
+  const int E = PAIR ? *n_own : e_end >= 0 ? e_end : row_ptr_x[N];
+  const int e0 = (PAIR ? 0 : e_first) + blockIdx.x * kTile;
   if (e0 >= E) return;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+  // the row's edge and (pair mode) its partner
+  auto row_edge = [&](int row) { return PAIR ? Es[row] : (e0 + row < E ? e0 + row : -1); };
+  auto row_partner = [&](int row) { return PAIR ? Ps[row] : -1; };
   if (t < kTile) {
     const int q = e0 + t;
-    const int e = q < E ? (own ? own[q] : q) : -1;
-    Es[t] = e;
-    Ps[t] = own && e >= 0 ? rev[e] : -1;
+    const int e = q < E ? (PAIR ? own[q] : q) : -1;
+    if constexpr (PAIR) {
+      Es[t] = e;
+      Ps[t] = e >= 0 ? rev[e] : -1;
+    }
     const float r = e >= 0 ? dvec[e].w : rc;
     float b[NB], db[NB];
     radial_basis<NB>(r, rc, p, b, db);
@@ -278,7 +284,7 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   // slab is loaded beside the owner's and added when the slab is staged.
   f32x16 acc = {};
   const int srow = t >> 2, sc8 = (t & 3) * 8;
-  const int se = Es[srow], sp = Ps[srow];
+  const int se = row_edge(srow), sp = row_partner(srow);
   const bool sval = se >= 0;
   const RS* dRrow = dR + (long)(sval ? se - e_first : 0) * PC + sc8;
   const RS* dRpart = dR + (long)(sp >= 0 ? sp : 0) * PC + sc8;
@@ -379,10 +385,10 @@ __global__ void __launch_bounds__(256) k_radial_bwd(const float4* __restrict__ d
   __syncthreads();
   // threads 0-63: the rows' edges (length gradient and harmonics term);
   // threads 64-127 in pair mode: the partners (their harmonics term only)
-  if (t < 2 * kTile) {
+  if (t < (PAIR ? 2 : 1) * kTile) {
     const bool partner = t >= kTile;
     const int row = t & (kTile - 1);
-    const int e = partner ? Ps[row] : Es[row];
+    const int e = partner ? row_partner(row) : row_edge(row);
     if (e >= 0) {
       float dr = 0.0f;
       if (!partner) {
@@ -611,24 +617,30 @@ void launch_radial_fwd(int n_basis, const float4* dvec, const int* row_ptr_x, in
   if (bf16 && !(wb && wb->W2T && wb->W3T)) throw Error(E3MI_EINVAL, "BF16 mode: BF16 radial weights missing");
   if (pairs && (e_first != 0 || e_end >= 0 || !pairs->own || !pairs->n_own || !pairs->rev))
     throw Error(E3MI_EINVAL, "radial MLP per edge pair: needs the whole edge list and the pair owners");
+  const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
+  if (grid == 0) return;
+  const int mode = pairs ? (pairs->compact ? 2 : 1) : 0;
   const int* own = pairs ? pairs->own : nullptr;
   const int* n_own = pairs ? pairs->n_own : nullptr;
   const int* rev = pairs ? pairs->rev : nullptr;
-  const int compact = pairs ? pairs->compact : 0;
-  const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
-  if (grid == 0) return;
-  if (r_bf16)
-    k_radial_fwd<8, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
-                                                        static_cast<__bf16*>(R), rc, p, e_first, e_end, wb->W2T,
-                                                        wb->W3T, own, n_own, rev, compact);
-  else if (bf16)
-    k_radial_fwd<8, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
-                                                       static_cast<float*>(R), rc, p, e_first, e_end, wb->W2T,
-                                                       wb->W3T, own, n_own, rev, compact);
-  else
-    k_radial_fwd<8, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
-                                                        static_cast<float*>(R), rc, p, e_first, e_end, nullptr,
-                                                        nullptr, own, n_own, rev, compact);
+  auto go = [&](auto mc) {
+    constexpr int MODE = decltype(mc)::value;
+    if (r_bf16)
+      k_radial_fwd<8, true, __bf16, MODE><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
+                                                                static_cast<__bf16*>(R), rc, p, e_first, e_end,
+                                                                wb->W2T, wb->W3T, own, n_own, rev);
+    else if (bf16)
+      k_radial_fwd<8, true, float, MODE><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
+                                                               static_cast<float*>(R), rc, p, e_first, e_end,
+                                                               wb->W2T, wb->W3T, own, n_own, rev);
+    else
+      k_radial_fwd<8, false, float, MODE><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W3, ld3, PC,
+                                                                static_cast<float*>(R), rc, p, e_first, e_end,
+                                                                nullptr, nullptr, own, n_own, rev);
+  };
+  if (mode == 0) go(std::integral_constant<int, 0>{});
+  else if (mode == 1) go(std::integral_constant<int, 1>{});
+  else go(std::integral_constant<int, 2>{});
 }
 
 template <int LMAX>
@@ -638,21 +650,23 @@ static void radial_bwd_l(bool bf16, bool r_bf16, long e_cap, const float4* dvec,
                          int e_end, const RadialBf16* wb, const int* own, const int* n_own, const int* rev) {
   const int grid = tiles(e_end >= 0 ? (long)e_end - e_first : e_cap);
   if (grid == 0) return;
-  if (r_bf16)
-    k_radial_bwd<8, LMAX, true, __bf16><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
-                                                              static_cast<const __bf16*>(dR), dY, g, accumulate, rc,
-                                                              p, e_first, e_end, wb->W2T, wb->W2, wb->W3u, own, n_own,
-                                                              rev);
-  else if (bf16)
-    k_radial_bwd<8, LMAX, true, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
-                                                             static_cast<const float*>(dR), dY, g, accumulate, rc, p,
-                                                             e_first, e_end, wb->W2T, wb->W2, wb->W3u, own, n_own,
-                                                             rev);
-  else
-    k_radial_bwd<8, LMAX, false, float><<<grid, 256, 0, st>>>(dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC,
-                                                              static_cast<const float*>(dR), dY, g, accumulate, rc,
-                                                              p, e_first, e_end, nullptr, nullptr, nullptr, own,
-                                                              n_own, rev);
+  auto go = [&](auto pc) {
+    constexpr bool PAIR = decltype(pc)::value;
+    if (r_bf16)
+      k_radial_bwd<8, LMAX, true, __bf16, PAIR><<<grid, 256, 0, st>>>(
+          dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, static_cast<const __bf16*>(dR), dY, g, accumulate, rc, p,
+          e_first, e_end, wb->W2T, wb->W2, wb->W3u, own, n_own, rev);
+    else if (bf16)
+      k_radial_bwd<8, LMAX, true, float, PAIR><<<grid, 256, 0, st>>>(
+          dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, static_cast<const float*>(dR), dY, g, accumulate, rc, p,
+          e_first, e_end, wb->W2T, wb->W2, wb->W3u, own, n_own, rev);
+    else
+      k_radial_bwd<8, LMAX, false, float, PAIR><<<grid, 256, 0, st>>>(
+          dvec, row_ptr_x, N, W1, W2, W2T, W3T, PC, static_cast<const float*>(dR), dY, g, accumulate, rc, p,
+          e_first, e_end, nullptr, nullptr, nullptr, own, n_own, rev);
+  };
+  if (own) go(std::true_type{});
+  else go(std::false_type{});
 }
 
 void launch_radial_bwd(int n_basis, int lmax, const float4* dvec, const int* row_ptr_x, int N, long e_cap,

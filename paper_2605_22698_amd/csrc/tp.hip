@@ -35,7 +35,7 @@ __device__ __forceinline__ float group_sum(float v) {
 // of 72 (the hardware still holds five waves) and it runs faster (0.134 ms
 // against 0.141 on the 3,000-atom step). Holding residency at three or two
 // waves for real, by reserving LDS, is slower (0.167, 0.196 ms).
-template <int LMAX, int KIND, int CPT, class RS>
+template <int LMAX, int KIND, int CPT, class RS, bool IDX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIND == kLast ? 3 : 10))) k_tp_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                 const float4* __restrict__ dvec, const RS* __restrict__ R,
                                                 int r_stride, const float* __restrict__ h, int h_nc,
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIN
     const float ir = 1.0f / d.w;
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const RS* Re = R + (long)(r_row ? r_row[e] : e - e_first) * r_stride;
+    const RS* Re = R + (long)(IDX ? r_row[e] : e - e_first) * r_stride;
     const float* hj = h + (long)j * h_nc * C;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, KIN
 // Layers with every path hold 99 adjoint values per channel: the compiler is
 // asked for two waves per SIMD (at most 256 registers); one wave per SIMD
 // halves the kernel's speed.
-template <int LMAX, int KIND, int CPT, bool MSG, class RS>
+template <int LMAX, int KIND, int CPT, bool MSG, class RS, bool IDX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == kFull ? 2 : 1, 10))) k_tp_bwd_edge(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                      const float4* __restrict__ dvec, const RS* __restrict__ R,
                                                      int r_stride, const float* __restrict__ h, int h_nc,
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND =
     const float ir = 1.0f / d.w;
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const RS* Re = R + (long)(r_row ? r_row[e] : e - e_first) * r_stride;
+    const RS* Re = R + (long)(IDX ? r_row[e] : e - e_first) * r_stride;
     RS* dRe = dR + (long)(e - e_first) * r_stride;
     const float* hj = h + (long)j * h_nc * C;
     float dyp[NY];
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND =
   }
 }
 
-template <int LMAX, int KIND, int CPT, class RS>
+template <int LMAX, int KIND, int CPT, class RS, bool IDX>
 __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                      const float4* __restrict__ dvec, const RS* __restrict__ R,
                                                      int r_stride, const float* __restrict__ dA,
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(256) k_tp_bwd_node(const int* __restrict__ row
     const float ir = -1.0f / d.w;  // direction of the reverse edge
     float Y[NY];
     real_sh<LMAX>(d.x * ir, d.y * ir, d.z * ir, Y);
-    const RS* Re = R + (long)(r_row ? r_row[e] : e - e_first) * r_stride;
+    const RS* Re = R + (long)(IDX ? r_row[e] : e - e_first) * r_stride;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const int k = threadIdx.x + c * tpr;
@@ -678,6 +678,44 @@ __global__ void __launch_bounds__(256) k_tp_dual_geo(const int* __restrict__ row
 
 // ---- dispatch ---------------------------------------------------------------
 
+// the first-order passes (0 forward, 1 edge adjoint, 2 node adjoint); IDX:
+// R rows through the edges' pair indices
+template <int LMAX, int KIND, int CPT, bool IDX>
+static void first_order_launch(int which, const TpArgs& a, int nr, int tpr, hipStream_t st) {
+  const __bf16* Rb = reinterpret_cast<const __bf16*>(a.R);
+  __bf16* dRb = reinterpret_cast<__bf16*>(a.dR);
+  if (which == 0 && a.r_bf16)
+    k_tp_fwd<LMAX, KIND, CPT, __bf16, IDX><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h, a.h_nc,
+                                                                a.A, a.N, a.C, a.inv_nu, a.i0, a.e_first, a.r_row);
+  else if (which == 0)
+    k_tp_fwd<LMAX, KIND, CPT, float, IDX><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc,
+                                                               a.A, a.N, a.C, a.inv_nu, a.i0, a.e_first, a.r_row);
+  else if (which == 1 && a.r_bf16 && a.msg)
+    k_tp_bwd_edge<LMAX, KIND, CPT, true, __bf16, IDX><<<nr, tpr, 0, st>>>(
+        a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h, a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first,
+        a.msg, a.touched, a.tag, a.r_row);
+  else if (which == 1 && a.r_bf16)
+    k_tp_bwd_edge<LMAX, KIND, CPT, false, __bf16, IDX><<<nr, tpr, 0, st>>>(
+        a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h, a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first,
+        nullptr, nullptr, 0, a.r_row);
+  else if (which == 1 && a.msg)
+    k_tp_bwd_edge<LMAX, KIND, CPT, true, float, IDX><<<nr, tpr, 0, st>>>(
+        a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first,
+        a.msg, a.touched, a.tag, a.r_row);
+  else if (which == 1)
+    k_tp_bwd_edge<LMAX, KIND, CPT, false, float, IDX><<<nr, tpr, 0, st>>>(
+        a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu, a.i0, a.e_first,
+        nullptr, nullptr, 0, a.r_row);
+  else if (which == 2 && a.r_bf16)
+    k_tp_bwd_node<LMAX, KIND, CPT, __bf16, IDX><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.dA,
+                                                                     a.dh, a.dh_nc, a.N, a.C, a.inv_nu, a.i0,
+                                                                     a.e_first, a.dh_acc, a.r_row);
+  else if (which == 2)
+    k_tp_bwd_node<LMAX, KIND, CPT, float, IDX><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA,
+                                                                    a.dh, a.dh_nc, a.N, a.C, a.inv_nu, a.i0,
+                                                                    a.e_first, a.dh_acc, a.r_row);
+}
+
 template <int LMAX, int KIND, int CPT>
 static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
   const int tpr = a.C / CPT;
@@ -689,44 +727,18 @@ static void tp_launch(int which, const TpArgs& a, hipStream_t st) {
     throw Error(E3MI_EINVAL, "tensor product: BF16 radial weights only in the first-order passes");
   if (a.r_row && which > 2 && which != 7)
     throw Error(E3MI_EINVAL, "tensor product: R rows per edge pair only in the first-order passes");
-  const __bf16* Rb = reinterpret_cast<const __bf16*>(a.R);
-  __bf16* dRb = reinterpret_cast<__bf16*>(a.dR);
-  if (which == 0 && a.r_bf16)
-    k_tp_fwd<LMAX, KIND, CPT, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h, a.h_nc, a.A,
-                                                           a.N, a.C, a.inv_nu, a.i0, a.e_first, a.r_row);
-  else if (which == 0)
-    k_tp_fwd<LMAX, KIND, CPT, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h, a.h_nc, a.A,
-                                                          a.N, a.C, a.inv_nu, a.i0, a.e_first, a.r_row);
-  else if (which == 1 && a.r_bf16 && a.msg)
-    k_tp_bwd_edge<LMAX, KIND, CPT, true, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h,
-                                                                      a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu,
-                                                                      a.i0, a.e_first, a.msg, a.touched, a.tag, a.r_row);
-  else if (which == 1 && a.r_bf16)
-    k_tp_bwd_edge<LMAX, KIND, CPT, false, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.h,
-                                                                       a.h_nc, a.dA, dRb, a.dY, a.N, a.C, a.inv_nu,
-                                                                       a.i0, a.e_first, nullptr, nullptr, 0, a.r_row);
-  else if (which == 1 && a.msg)
-    k_tp_bwd_edge<LMAX, KIND, CPT, true, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
-                                                                     a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu,
-                                                                     a.i0, a.e_first, a.msg, a.touched, a.tag, a.r_row);
-  else if (which == 1)
-    k_tp_bwd_edge<LMAX, KIND, CPT, false, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.h,
-                                                                      a.h_nc, a.dA, a.dR, a.dY, a.N, a.C, a.inv_nu,
-                                                                      a.i0, a.e_first, nullptr, nullptr, 0, a.r_row);
+  if (which <= 2) {
+    if (a.r_row)
+      first_order_launch<LMAX, KIND, CPT, true>(which, a, nr, tpr, st);
+    else
+      first_order_launch<LMAX, KIND, CPT, false>(which, a, nr, tpr, st);
+  }
   else if (which == 7) {
     using PS = PathSet<LMAX, KIND>;
     const int c1 = a.n_recv > 0 ? a.i0 + a.n_recv : a.N;
     k_tp_msg_node<PS::NIN><<<a.N, 128, 0, st>>>(a.row_ptr, a.src, a.rev, a.msg, a.dh, a.dh_nc, a.C, a.i0, c1,
                                                  a.e_first, a.i0 == 0 ? 1 : 0, a.dh_acc, a.touched, a.tag);
   }
-  else if (which == 2 && a.r_bf16)
-    k_tp_bwd_node<LMAX, KIND, CPT, __bf16><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, Rb, a.r_stride, a.dA, a.dh,
-                                                                a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first,
-                                                                a.dh_acc, a.r_row);
-  else if (which == 2)
-    k_tp_bwd_node<LMAX, KIND, CPT, float><<<nr, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.R, a.r_stride, a.dA, a.dh,
-                                                               a.dh_nc, a.N, a.C, a.inv_nu, a.i0, a.e_first,
-                                                               a.dh_acc, a.r_row);
   else if (which == 3)
     k_tp_dual_fwd<LMAX, KIND, CPT><<<a.N, tpr, 0, st>>>(a.row_ptr, a.src, a.dvec, a.dd, a.R, a.Rd, a.r_stride, a.h,
                                                          a.hd, a.h_nc, a.Ad, a.N, a.C, a.inv_nu);
