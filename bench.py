@@ -130,10 +130,12 @@ def fp32_row_pattern(cfg, kern, t):
     layers (rows split by layer), the tensor-product kernels are per layer
     kind by their template arguments (1: every path, 2: scalar outputs)."""
     kind = 2 if t == cfg.layers else 1
+    # chunked layers run the per-edge instantiations (radial mode 0 / no
+    # pairs, R rows without the pair index)
     if kern.startswith("k_radial"):
-        return re.escape(kern) + r"<8, (\d+, )?false, float> \[layer %d\]" % t
+        return re.escape(kern) + r"<8, (\d+, )?false, float, (0|false)> \[layer %d\]" % t
     if kern in ("k_tp_fwd", "k_tp_bwd_edge", "k_tps_bwd_sender"):
-        return re.escape(kern) + r"<%d, %d, \d+(, (true|false))?, float>" % (cfg.lmax, kind)
+        return re.escape(kern) + r"<%d, %d, \d+(, (true|false))?, float(, false)?>" % (cfg.lmax, kind)
     return re.escape(kern) + r"(<.*>)?"
 
 
