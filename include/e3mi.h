@@ -263,9 +263,11 @@ int e3mi_model_set_flags(e3mi_model* model, int flags);
  * receivers (the adjoint then recomputes R per chunk), so a 100,000-atom,
  * 9-million-edge, 3-layer model (about 106 GB of R per layer in FP32, Section
  * 4's tensor product at scale) runs in bounded memory. The chunking reads the
- * pruned row pointer back to the host once per call. Results are bitwise
- * those of the unchunked evaluation (each receiver's and each sender's sums
- * run in the same order whatever the chunks). */
+ * pruned row pointer back to the host once per call. Chunked layers run the
+ * radial MLP edge by edge; results are bitwise those of the unchunked
+ * evaluation with E3MI_FLAG_RADIAL_PER_EDGE (each receiver's and each
+ * sender's sums run in the same order whatever the chunks), and agree with
+ * the default per-pair radial adjoint of an unchunked layer to rounding. */
 int e3mi_model_set_r_chunk_bytes(e3mi_model* model, size_t bytes);
 
 /* Most bytes of per-edge R kept for every edge inside the cutoff, summed
