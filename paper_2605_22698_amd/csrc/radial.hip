@@ -15,11 +15,14 @@
 // An edge and its reverse have exactly opposite vectors, so equal lengths and
 // equal R. With the pair owners of the pruned list given (own[0 .. P), P on
 // the device), a tile holds 64 owners instead of 64 edges: the forward pass
-// computes R once per pair and stores it in both edges' rows, and the adjoint
-// takes dR of the pair's two edges summed (E depends on the pair's length
-// through both) through the MLP once; the length gradient goes to the owner's
-// g and each edge keeps its own harmonics term. F_i sums g_e - g_rev(e) over
-// i's edges, so the forces are those of the edge-by-edge adjoint (to rounding).
+// computes R once per pair and stores it in the pair's row p (mode 2; the
+// tensor-product kernels find an edge's row through its pair index) or in
+// both edges' rows (mode 1), and the adjoint takes dR of the pair's two edges
+// summed (E depends on the pair's length through both) through the MLP once;
+// the length gradient goes to the owner's g and each edge keeps its own
+// harmonics term. F_i sums g_e - g_rev(e) over i's edges, so the forces are
+// those of the edge-by-edge adjoint (to rounding). The modes are template
+// arguments, so the edge-by-edge instantiations (mode 0) carry none of it.
 //
 // MFMA 32x32x2 operand layout (wave64): lane l supplies A[l%32][l/32] and
 // B[l/32][l%32]; accumulator register r of lane l holds

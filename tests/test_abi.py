@@ -74,6 +74,7 @@ def test_null_handles(lib):
     assert lib.e3mi_md_step(None, 1, 0.5, None, None) == -1
     assert lib.e3mi_graph_info(None, None, None) == -1
     assert lib.e3mi_footprint_bytes(None, 10, 10) == 0
+    assert lib.e3mi_model_set_flags(None, 8) == -1 and "null model" in lib.e3mi_last_error().decode()
     assert lib.e3mi_model_destroy(None) == 0
 
 
