@@ -208,6 +208,7 @@ struct Workspace {
   std::unique_ptr<DevBuf> dd, Bd, Prb, Prc, w2c, eb, xb, xc, Ab, Ac, hb_a, hb_b, hc_a, hc_b, Rb, Rc, P1g, P2g,
       partial, vf;
   std::unique_ptr<DevBuf> G1, dG1;  // first layer, [N, (l3+1)^2, S*64]
+  std::unique_ptr<DevBuf> P2f;      // first layer's second hidden pre-activation per edge pair (or edge), [., 64]
   std::unique_ptr<DevBuf> q_raw, q, pot, fc, pot_mean;  // electrostatics: charges, potential, forces
   std::vector<std::unique_ptr<DevBuf>> at;             // product block: A~ per layer
   std::unique_ptr<DevBuf> Ygb, Ygc, ghv, zeroE;        // Hessian-vector products
@@ -867,6 +868,10 @@ EdgePairs graph_pairs(const e3mi_graph* G, bool compact = false) {
 const EdgePairs* pairs_for(const e3mi_model* M, const RChunk& ch, const EdgePairs& p) {
   return M->edge_pairs && ch.e1 < 0 ? &p : nullptr;
 }
+// the first layer's hidden activations: row pair_of[e] per edge pair, or row e
+const int* first_pair_index(const e3mi_model* M, const e3mi_graph* G) {
+  return M->edge_pairs ? G->pair_of->as<int>() : nullptr;
+}
 // R of a layer once per edge pair: the pair mode on a single chunk, in a
 // first-order evaluation (the second-order passes read R per edge)
 bool r_compact_for(const e3mi_model* M, const std::vector<RChunk>& chunks, bool keep_A) {
@@ -966,6 +971,7 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
   const int S64 = c.n_species * c.radial_hidden;
   if (fact) {
     ensure(w.G1, a, sizeof(float) * (size_t)N * M->plans[0].nc_a * S64);
+    ensure(w.P2f, a, sizeof(float) * (size_t)c.radial_hidden * (size_t)(Ecap + 1));
     ensure(w.dG1, a, sizeof(float) * (size_t)N * M->plans[0].nc_a * S64);
   }
   // product block: the mix writes A~ (no self connection); B follows, then
@@ -994,9 +1000,15 @@ void forward_pass(e3mi_model* M, e3mi_graph* G, const double* pos, bool keep_A, 
     if (t == 1 && fact) {
       float* G1 = w.G1->as<float>();
       {
+        // the hidden layers once per edge pair (per edge with flag 8), then
+        // the per-species neighbour sums read them through the pair index
         ProfScope ps(&M->prof, stage_id(kFirstFwd, 1), st);
-        launch_first(true, c.lmax, L.l3max_used, row_ptr, src, dvec, species, N, S64, W.rad1.as<float>(),
-                     W.rad2.as<float>(), nullptr, G1, nullptr, nullptr, 0, rc, p_env, st);
+        const EdgePairs prs = graph_pairs(G);
+        launch_first_hidden(dvec, row_ptr, N, Ecap, M->edge_pairs ? prs.own : nullptr,
+                            M->edge_pairs ? prs.n_own : nullptr, W.rad1.as<float>(), W.rad2.as<float>(), rc, p_env,
+                            w.P2f->as<float>(), st);
+        launch_first(true, c.lmax, L.l3max_used, row_ptr, src, dvec, species, N, S64, W.rad1.as<float>(), nullptr,
+                     first_pair_index(M, G), w.P2f->as<float>(), G1, nullptr, nullptr, 0, rc, p_env, st);
       }
       float* ht = w.ht[1]->as<float>();
       float* mix_out = prod ? w.at[1]->as<float>() : ht;
@@ -1240,7 +1252,8 @@ void energy_forces(e3mi_model* M, e3mi_graph* G, const double* pos, double* ener
       {
         ProfScope ps(&M->prof, stage_id(kFirstBwd, 1), st);
         launch_first(false, c.lmax, L.l3max_used, row_ptr, src, dvec, species, N, S64, W.rad1.as<float>(),
-                     W.rad2.as<float>(), W.rad2T.as<float>(), nullptr, dG1, g, T != 1 ? 1 : 0, rc, p_env, st);
+                     W.rad2T.as<float>(), first_pair_index(M, G), w.P2f->as<float>(), nullptr, dG1, g,
+                     T != 1 ? 1 : 0, rc, p_env, st);
       }
       continue;
     }
@@ -1384,6 +1397,7 @@ size_t footprint(const e3mi_model* M, int64_t n_atoms, int64_t n_edges) {
     a_max = std::max(a_max, (size_t)L.a_per_atom);
     if (t == 1 && factorised_first(M)) {
       b += 2 * N * L.nc_out * (size_t)c.n_species * c.radial_hidden * 4;  // G and dG
+      b += E * (size_t)c.radial_hidden * 4;                                // hidden pre-activations
       continue;
     }
     if (fused_last(M, L, false, bf16)) continue;  // no per-edge R

@@ -13,7 +13,14 @@
 // hidden layers and a 64 x 16 outer product remain, and U_l is a weight
 // computed once per model.
 //
+// The hidden layers depend on the edge length only, so an edge and its
+// reverse share them: k_first_hidden computes the second hidden layer's
+// pre-activation P2 = silu(B W1) W2 once per edge pair (tiles of 64 pair
+// owners, or of 64 edges without the pair list), and both kernels below read
+// it through the edge's pair index.
+//
 // Kernels (one workgroup per receiver, its CSR row in tiles of 64 edges):
+//   k_first_hidden  P2 [pairs, 64]
 //   k_first_fwd  G_i [N, (L3+1)^2, S*64]
 //   k_first_bwd  from dG = dh~_l U_l^T: dH2_e = sum_c dG[c, z_j] (CY)_e[c],
 //                d(CY)_e = sum_q dG[c, z_j, q] H2_e[q], back through the MLP and
@@ -151,6 +158,62 @@ __device__ __forceinline__ void species_lists(const int* sp, int n_e, int S, int
   }
 }
 
+// X[row] = P2 row of the tile's edge e0 + row (its pair's, through pair_of,
+// or its own), or silu of it; rows past the tile's n_e edges zero. All 256
+// threads, 16-byte loads.
+__device__ __forceinline__ void load_p2_rows(const float* __restrict__ P2, const int* __restrict__ pair_of, int e0,
+                                             int n_e, float (*X)[kLd], bool silu = false) {
+  for (int o = threadIdx.x; o < kTile * (kH / 4); o += 256) {
+    const int row = o / (kH / 4), c4 = (o % (kH / 4)) * 4;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row < n_e) {
+      const int e = e0 + row;
+      v = *reinterpret_cast<const float4*>(P2 + (long)(pair_of ? pair_of[e] : e) * kH + c4);
+      if (silu) v = make_float4(siluf(v.x), siluf(v.y), siluf(v.z), siluf(v.w));
+    }
+    X[row][c4] = v.x;
+    X[row][c4 + 1] = v.y;
+    X[row][c4 + 2] = v.z;
+    X[row][c4 + 3] = v.w;
+  }
+}
+
+// P2 = silu(B W1) W2 of 64 pair owners (own: the pair list, P = *n_own) or
+// of 64 edges (own NULL: every edge inside the cutoff, row_ptr_x[N]), row q
+// of P2 for the tile's row q.
+template <int NB>
+__global__ void __launch_bounds__(256) k_first_hidden(const float4* __restrict__ dvec, const int* __restrict__ row_ptr_x,
+                                                      int N, const int* __restrict__ own,
+                                                      const int* __restrict__ n_own, const float* __restrict__ W1,
+                                                      const float* __restrict__ W2, float rc, int p,
+                                                      float* __restrict__ P2) {
+  __shared__ float Bs[kTile][NB + 1];
+  __shared__ float X[kTile][kLd];
+  const int n = own ? *n_own : row_ptr_x[N];
+  const int q0 = blockIdx.x * kTile;
+  if (q0 >= n) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t < kTile) {
+    const int q = q0 + t;
+    const int e = q < n ? (own ? own[q] : q) : -1;
+    const float r = e >= 0 ? dvec[e].w : rc;
+    float b[NB];
+    radial_basis<NB>(r, rc, p, b, nullptr);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) Bs[t][k] = b[k];
+  }
+  __syncthreads();
+  hidden1<NB>(Bs, W1, X);
+  __syncthreads();
+  const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
+  const f32x16 a = block_64(X, rb, W2, kH, cb);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int q = q0 + rb + acc_row(r, lane);
+    if (q < n) P2[(long)q * kH + cb + (lane & 31)] = a[r];
+  }
+}
+
 // Forward: G_i[n = (c, s), q] = sum_e [z_j(e) = s] (CY)_e[c] H2_e[q]. For each
 // species, a 16 (component) x 64 (q) product over that species' edges of the
 // tile on the matrix cores (16x16x4 steps over groups of 4 edges), accumulated
@@ -158,8 +221,9 @@ __device__ __forceinline__ void species_lists(const int* sp, int n_e, int S, int
 template <int LMAX, int L3>
 __global__ void __launch_bounds__(256) k_first_fwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                    const float4* __restrict__ dvec, const int* __restrict__ species,
-                                                   int S, const float* __restrict__ W1, const float* __restrict__ W2,
-                                                   float rc, int p, float* __restrict__ G) {
+                                                   int S, const int* __restrict__ pair_of,
+                                                   const float* __restrict__ P2, float rc, int p,
+                                                   float* __restrict__ G) {
   constexpr int NB = 8;
   constexpr int NC3 = (L3 + 1) * (L3 + 1);
   __shared__ float Bs[kTile][NB + 1];
@@ -183,15 +247,8 @@ __global__ void __launch_bounds__(256) k_first_fwd(const int* __restrict__ row_p
     tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, nullptr, Ys, sp);
     __syncthreads();
     species_lists(sp, n_e, S, perm, start, cnt);
-    hidden1<NB>(Bs, W1, X);
-    __syncthreads();
-    {
-      const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-      const f32x16 a = block_64(X, rb, W2, kH, cb);
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 16; ++r) X[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(a[r]);
-    }
+    // H2 = silu(P2) of the tile's edges (rows past them zero, never read)
+    load_p2_rows(P2, pair_of, e0, n_e, X, true);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -232,8 +289,9 @@ __global__ void __launch_bounds__(256) k_first_fwd(const int* __restrict__ row_p
 template <int LMAX, int L3>
 __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_ptr, const int* __restrict__ src,
                                                    const float4* __restrict__ dvec, const int* __restrict__ species,
-                                                   int S, const float* __restrict__ W1, const float* __restrict__ W2,
-                                                   const float* __restrict__ W2T, const float* __restrict__ dG,
+                                                   int S, const float* __restrict__ W1,
+                                                   const float* __restrict__ W2T, const int* __restrict__ pair_of,
+                                                   const float* __restrict__ P2, const float* __restrict__ dG,
                                                    float4* __restrict__ g, int accumulate, float rc, int p) {
   constexpr int NB = 8;
   constexpr int NC3 = (L3 + 1) * (L3 + 1);
@@ -269,19 +327,20 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
     tile_geometry<LMAX, L3, NB>(dvec, src, species, e0, e1, rc, p, Bs, nullptr, Ys, sp);
     __syncthreads();
     species_lists(sp, n_e, S, perm, start, cnt);
-    hidden1<NB>(Bs, W1, X);
-    __syncthreads();
-    // H2 = silu(P2) replaces H1 in LDS; silu'(P2) of this wave's block stays in
+    // the tile's P2 rows into LDS (rows past the tile's edges zero), then
+    // H2 = silu(P2) in place; silu'(P2) of this wave's block stays in
     // registers (the dH2 block below has the same rows and columns)
+    load_p2_rows(P2, pair_of, e0, n_e, X);
+    __syncthreads();
     f32x16 sg;
     {
       const int rb = (w >> 1) * 32, cb = (w & 1) * 32;
-      const f32x16 a = block_64(X, rb, W2, kH, cb);
-      __syncthreads();
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        X[rb + acc_row(r, lane)][cb + (lane & 31)] = siluf(a[r]);
-        sg[r] = silu_grad(a[r]);
+        float& x = X[rb + acc_row(r, lane)][cb + (lane & 31)];
+        const float pv = x;
+        sg[r] = silu_grad(pv);
+        x = siluf(pv);
       }
     }
     __syncthreads();
@@ -420,15 +479,15 @@ __global__ void __launch_bounds__(256) k_first_bwd(const int* __restrict__ row_p
 
 template <int LMAX, int L3>
 static void first_launch(bool fwd, const int* row_ptr, const int* src, const float4* dvec, const int* species, int N,
-                         int S, const float* W1, const float* W2, const float* W2T, float* G, const float* dG,
-                         float4* g, int accumulate, float rc, int p, hipStream_t st) {
+                         int S, const float* W1, const float* W2T, const int* pair_of, const float* P2, float* G,
+                         const float* dG, float4* g, int accumulate, float rc, int p, hipStream_t st) {
   constexpr int NC3 = (L3 + 1) * (L3 + 1);
   if (fwd) {
-    k_first_fwd<LMAX, L3><<<N, 256, 0, st>>>(row_ptr, src, dvec, species, S, W1, W2, rc, p, G);
+    k_first_fwd<LMAX, L3><<<N, 256, 0, st>>>(row_ptr, src, dvec, species, S, pair_of, P2, rc, p, G);
   } else {
     const size_t lds = sizeof(float) * (size_t)std::max(NC3 * S, kTile) * kLd;
-    k_first_bwd<LMAX, L3><<<N, 256, lds, st>>>(row_ptr, src, dvec, species, S, W1, W2, W2T, dG, g, accumulate, rc,
-                                               p);
+    k_first_bwd<LMAX, L3><<<N, 256, lds, st>>>(row_ptr, src, dvec, species, S, W1, W2T, pair_of, P2, dG, g,
+                                               accumulate, rc, p);
   }
 }
 
@@ -441,20 +500,35 @@ size_t first_lds_bytes(int l3max, int S64) {
   return fixed + std::max(nc3 * S, (size_t)kTile) * kLd * 4;
 }
 
+void launch_first_hidden(const float4* dvec, const int* row_ptr_x, int N, long e_cap, const int* own,
+                         const int* n_own, const float* W1, const float* W2, float rc, int p, float* P2,
+                         hipStream_t st) {
+  if (e_cap == 0) return;
+  E3MI_REQUIRE((own == nullptr) == (n_own == nullptr), E3MI_EINVAL, "first layer: pair list without its count");
+  k_first_hidden<8><<<(int)((e_cap + kTile - 1) / kTile), 256, 0, st>>>(dvec, row_ptr_x, N, own, n_own, W1, W2, rc,
+                                                                         p, P2);
+}
+
 void launch_first(bool fwd, int lmax, int l3max, const int* row_ptr, const int* src, const float4* dvec,
-                  const int* species, int N, int S64, const float* W1, const float* W2, const float* W2T, float* G,
-                  const float* dG, float4* g, int accumulate, float rc, int p, hipStream_t st) {
+                  const int* species, int N, int S64, const float* W1, const float* W2T, const int* pair_of,
+                  const float* P2, float* G, const float* dG, float4* g, int accumulate, float rc, int p,
+                  hipStream_t st) {
   if (N == 0) return;
+  E3MI_REQUIRE(P2, E3MI_EINVAL, "first layer: hidden pre-activations missing");
   if (S64 > kMaxS64 || first_lds_bytes(l3max, S64) > 65536)
     throw Error(E3MI_EUNSUPPORTED, "first-layer factorisation: too many species for the LDS budget");
   if (lmax == 3 && l3max == 3)
-    first_launch<3, 3>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
+    first_launch<3, 3>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2T, pair_of, P2, G, dG, g, accumulate,
+                       rc, p, st);
   else if (lmax == 3 && l3max == 0)
-    first_launch<3, 0>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
+    first_launch<3, 0>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2T, pair_of, P2, G, dG, g, accumulate,
+                       rc, p, st);
   else if (lmax == 2 && l3max == 2)
-    first_launch<2, 2>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
+    first_launch<2, 2>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2T, pair_of, P2, G, dG, g, accumulate,
+                       rc, p, st);
   else if (lmax == 2 && l3max == 0)
-    first_launch<2, 0>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2, W2T, G, dG, g, accumulate, rc, p, st);
+    first_launch<2, 0>(fwd, row_ptr, src, dvec, species, N, S64 / kH, W1, W2T, pair_of, P2, G, dG, g, accumulate,
+                       rc, p, st);
   else
     throw Error(E3MI_EUNSUPPORTED, "first-layer factorisation: unsupported orders");
 }

@@ -411,9 +411,17 @@ void launch_gemm_tn(RowMap x1, RowMap y1, RowMap x2, RowMap y2, long rows, const
 
 // ---- species-factorised first layer (first.hip) ---------------------------------------
 size_t first_lds_bytes(int l3max, int S64);
+// P2 = silu(B W1) W2 [rows, 64] of the first layer: per pair owner (own, P =
+// *n_own on the device) or per edge (own and n_own NULL); e_cap bounds the rows
+void launch_first_hidden(const float4* dvec, const int* row_ptr_x, int N, long e_cap, const int* own,
+                         const int* n_own, const float* W1, const float* W2, float rc, int p, float* P2,
+                         hipStream_t st);
+// forward (G) or adjoint (g) of the factorised first layer; edge e's P2 row is
+// pair_of[e] (or e when pair_of is NULL)
 void launch_first(bool fwd, int lmax, int l3max, const int* row_ptr, const int* src, const float4* dvec,
-                  const int* species, int N, int S64, const float* W1, const float* W2, const float* W2T, float* G,
-                  const float* dG, float4* g, int accumulate, float rc, int p, hipStream_t st);
+                  const int* species, int N, int S64, const float* W1, const float* W2T, const int* pair_of,
+                  const float* P2, float* G, const float* dG, float4* g, int accumulate, float rc, int p,
+                  hipStream_t st);
 
 // ---- fused last layer (last.hip) ----------------------------------------------------------
 struct LastArgs {
