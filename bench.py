@@ -75,12 +75,16 @@ def work_model(cfg, t, E, N, pairs=False):
     mlp_hidden = 2 * (cfg.n_basis * H + H * H)
     tp_flops = 2 * C * sum(nz + 2 * l3 + 1 for (_, _, l3, nz) in ps)
     out = {}
-    # species-factorised first layer: hidden MLP + outer product per edge; G per atom
+    # species-factorised first layer: the hidden MLP's pre-activation P2 once
+    # per edge pair (the first layer is never chunked; stored, 4 H bytes),
+    # the outer product per edge, G per atom; the adjoint reads P2 per edge
+    # (no hidden-layer recompute)
     nc3 = (cfg.lmax + 1) ** 2 if cfg.layers > 1 else 1
     s64 = cfg.n_species * H
-    out["first_fwd"] = (E * (mlp_hidden + 2 * H * nc3), E * 24 + N * 4 * nc3 * s64)
-    out["first_bwd"] = (E * (mlp_hidden + 2 * H * H + 2 * H * cfg.n_basis + 4 * H * nc3),
-                        E * (24 + 16) + N * 4 * nc3 * s64)
+    Ph = (E + 1) // 2
+    out["first_fwd"] = (Ph * mlp_hidden + E * 2 * H * nc3, Ph * (16 + 4 * H) + E * (24 + 4 * H) + N * 4 * nc3 * s64)
+    out["first_bwd"] = (E * (2 * H * H + 2 * H * cfg.n_basis + 4 * H * nc3),
+                        E * (24 + 16 + 4 * H) + N * 4 * nc3 * s64)
     # fused last layer (scalar outputs): hidden MLP, T = sum_e H2 s^T and its
     # W3 contraction forward; R recomputed, dH2 = W3 dR, MLP adjoint, and the
     # contracted-feature terms backward. Bytes: edge vectors, h once per atom,
