@@ -245,14 +245,17 @@ int e3mi_hessian_vectors(e3mi_model* model, e3mi_graph* graph, const double* pos
 #define E3MI_FLAG_FUSED_LAST_LAYER 4
 /*   An edge and its reverse have exactly opposite vectors (the same FP64
  *     difference of the two positions plus the image shift, negated), so
- *     equal lengths and equal radial weights R. By default a layer whose edges are all in
- *     memory at once (one receiver chunk) runs its radial MLP once per edge
- *     pair, writing R to both edges' rows (the same bits as edge by edge),
- *     and its adjoint once per pair on the sum of the two edges' dR (forces
- *     agree with the edge-by-edge adjoint to rounding).
- *   E3MI_FLAG_RADIAL_PER_EDGE (8) runs both per edge instead, as layers in
- *     receiver chunks always do; results are then bitwise those of any
- *     chunking. */
+ *     equal lengths and equal radial weights R. By default a layer whose
+ *     edges are all in memory at once (one receiver chunk) runs its radial
+ *     MLP once per edge pair. In an energy+forces call it stores R once per
+ *     pair (the same values as edge by edge; the second-order passes write
+ *     them to both edges' rows). Its adjoint runs once per pair on the sum of
+ *     the two edges' dR (forces agree with the edge-by-edge adjoint to
+ *     rounding). The species-factorised first layer's radial hidden layers
+ *     run once per pair likewise.
+ *   E3MI_FLAG_RADIAL_PER_EDGE (8) runs all of them per edge instead, as
+ *     layers in receiver chunks always do; results are then bitwise those of
+ *     any chunking. */
 #define E3MI_FLAG_RADIAL_PER_EDGE 8
 int e3mi_model_set_flags(e3mi_model* model, int flags);
 
